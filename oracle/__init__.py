@@ -1,0 +1,231 @@
+"""Python handle on the plain-C FP64 oracle (test infrastructure only).
+
+Only the test-suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The GPU library never does.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcteno_oracle.so")
+SRC_PATH = os.path.join(HERE, "cteno_oracle.c")
+
+PERIODIC, WALL, TRANSMISSIVE = 0, 1, 2
+ADVECTION, EULER = 0, 1
+CTENO, CTENOZ = 0, 1
+GAMMA_PAPER, GAMMA_LAMBDA = 0, 1
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, no FMA contraction, OpenMP)."""
+    if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC_PATH):
+        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
+               "-Wall", "-o", LIB_PATH + ".tmp", SRC_PATH, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(LIB_PATH + ".tmp", LIB_PATH)
+    return LIB_PATH
+
+
+class _Scheme(C.Structure):
+    _fields_ = [("physics", C.c_int), ("ax", C.c_double), ("ay", C.c_double), ("gamma", C.c_double),
+                ("scheme", C.c_int), ("degree", C.c_int), ("gamma_form", C.c_int),
+                ("lambda1_prime", C.c_double), ("c_t", C.c_double), ("eps", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        L.or_create.restype = P
+        L.or_create.argtypes = [C.c_int, P, C.c_int, P, P, P, C.POINTER(_Scheme)]
+        L.or_destroy.argtypes = [P]
+        L.or_last_error.restype = C.c_char_p
+        L.or_dims.argtypes = [P] + [C.POINTER(C.c_int)] * 6
+        L.or_prepare.argtypes = [P]
+        L.or_geometry.argtypes = [P, P, P, P, P, P]
+        L.or_stencils.argtypes = [P, C.c_int, P, P, P, P]
+        L.or_pinv.argtypes = [P, C.c_int, P, P, P]
+        L.or_ls_matrix.argtypes = [P, C.c_int, P, P]
+        L.or_smoothness.restype = C.c_double
+        L.or_smoothness.argtypes = [P, P, C.c_int, C.c_int]
+        L.or_select.argtypes = [P, P, P]
+        L.or_hllc.argtypes = [C.c_double, P, P, C.c_double, C.c_double, P]
+        L.or_euler_flux.argtypes = [C.c_double, P, C.c_double, C.c_double, P]
+        L.or_reconstruct.argtypes = [P, P, P, P, P, P]
+        L.or_reconstruct_cells.argtypes = [P, P, C.c_int, P, P, P]
+        L.or_face_fluxes.argtypes = [P, P, P]
+        L.or_residual.argtypes = [P, P, P]
+        L.or_dt_bound.restype = C.c_double
+        L.or_dt_bound.argtypes = [P, P]
+        L.or_rk3_step.argtypes = [P, P, C.c_double]
+        L.or_solve.argtypes = [P, P, C.c_double, C.c_double, C.c_int, C.c_double,
+                               C.POINTER(C.c_int), C.POINTER(C.c_double)]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+class Oracle:
+    """One mesh + scheme in the oracle.  Arrays follow the input cell order."""
+
+    def __init__(self, xy, tri, box, bc, physics=EULER, scheme=CTENOZ, degree=3,
+                 lambda1_prime=1e4, c_t=1e-6, eps=1e-12, gamma=1.4, ax=1.0, ay=1.0,
+                 gamma_form=GAMMA_PAPER):
+        L = lib()
+        self._xy = np.ascontiguousarray(xy, dtype=np.float64)
+        self._tri = np.ascontiguousarray(tri, dtype=np.int32)
+        box = np.ascontiguousarray(box, dtype=np.float64)
+        bc = np.ascontiguousarray(bc, dtype=np.int32)
+        s = _Scheme(physics, ax, ay, gamma, scheme, degree, gamma_form, lambda1_prime, c_t, eps)
+        h = L.or_create(self._xy.shape[0], _p(self._xy), self._tri.shape[0], _p(self._tri), _p(box), _p(bc),
+                        C.byref(s))
+        if not h:
+            raise OracleError(L.or_last_error().decode())
+        self.h = h
+        self.N = int(self._tri.shape[0])
+        d = [C.c_int() for _ in range(6)]
+        L.or_dims(h, *[C.byref(x) for x in d])
+        self.K, self.M, self.Kd, self.Md, self.Nq, self.nv = [x.value for x in d]
+        self.physics, self.scheme, self.degree = physics, scheme, degree
+
+    @classmethod
+    def from_mesh(cls, mesh, **kw):
+        return cls(mesh.xy, mesh.tri, mesh.box, mesh.bc, **kw)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            lib().or_destroy(h)
+            self.h = None
+
+    def _check(self, rc):
+        if rc:
+            raise OracleError(f"{lib().or_last_error().decode()} [rc={rc}]")
+
+    def prepare(self):
+        self._check(lib().or_prepare(self.h))
+
+    def geometry(self):
+        N = self.N
+        cxy = np.empty((N, 2)); area = np.empty(N)
+        fnb = np.empty((N, 3), np.int32); fnbf = np.empty((N, 3), np.int32); fn = np.empty((N, 3, 3))
+        lib().or_geometry(self.h, _p(cxy), _p(area), _p(fnb), _p(fnbf), _p(fn))
+        return dict(centroid=cxy, area=area, nbr=fnb, nbr_face=fnbf, normal=fn[..., :2], length=fn[..., 2])
+
+    def stencils(self, cells=None):
+        cells = np.arange(self.N, dtype=np.int32) if cells is None else np.ascontiguousarray(cells, np.int32)
+        n = cells.shape[0]
+        cen = np.empty((n, self.M), np.int32)
+        dr = np.empty((n, 3, self.Md), np.int32)
+        dn = np.empty((n, 3), np.int32)
+        self._check(lib().or_stencils(self.h, n, _p(cells), _p(cen), _p(dr), _p(dn)))
+        return cen, dr, dn
+
+    def pinv(self, cells):
+        cells = np.ascontiguousarray(cells, np.int32)
+        n = cells.shape[0]
+        pc = np.empty((n, self.K, self.M))
+        pd = np.empty((n, 3, self.Kd, self.Md))
+        self._check(lib().or_pinv(self.h, n, _p(cells), _p(pc), _p(pd)))
+        return pc, pd
+
+    def ls_matrix(self, i):
+        A = np.empty((self.K, self.M))
+        w = np.empty(self.M)
+        self._check(lib().or_ls_matrix(self.h, int(i), _p(A), _p(w)))
+        return A.T.copy(), w
+
+    def smoothness(self, a, r):
+        a = np.ascontiguousarray(a, np.float64)
+        return lib().or_smoothness(self.h, _p(a), a.shape[0], r)
+
+    def select(self, si, adm=(1, 1, 1, 1)):
+        si = np.ascontiguousarray(si, np.float64)
+        adm = np.ascontiguousarray(adm, np.int32)
+        return lib().or_select(self.h, _p(si), _p(adm))
+
+    def reconstruct(self, U, forced=None, want_coef=False):
+        U = np.ascontiguousarray(U, np.float64).reshape(self.nv, self.N)
+        fv = np.empty((self.N, 3, self.Nq, self.nv))
+        dl = np.empty((self.N, self.nv), np.uint8)
+        coef = np.empty((self.N, self.nv, self.K)) if want_coef else None
+        f = None if forced is None else np.ascontiguousarray(forced, np.uint8)
+        self._check(lib().or_reconstruct(self.h, _p(U), _p(f), _p(fv), _p(dl), _p(coef)))
+        return (fv, dl, coef) if want_coef else (fv, dl)
+
+    def reconstruct_cells(self, U, cells):
+        U = np.ascontiguousarray(U, np.float64).reshape(self.nv, self.N)
+        cells = np.ascontiguousarray(cells, np.int32)
+        n = cells.shape[0]
+        fv = np.empty((n, 3, self.Nq, self.nv))
+        dl = np.empty((n, self.nv), np.uint8)
+        self._check(lib().or_reconstruct_cells(self.h, _p(U), n, _p(cells), _p(fv), _p(dl)))
+        return fv, dl
+
+    def face_fluxes(self, fv):
+        fv = np.ascontiguousarray(fv, np.float64)
+        fo = np.empty((self.N, 3, self.nv))
+        self._check(lib().or_face_fluxes(self.h, _p(fv), _p(fo)))
+        return fo
+
+    def residual(self, U):
+        U = np.ascontiguousarray(U, np.float64).reshape(self.nv, self.N)
+        R = np.empty((self.nv, self.N))
+        self._check(lib().or_residual(self.h, _p(U), _p(R)))
+        return R
+
+    def dt_bound(self, U):
+        U = np.ascontiguousarray(U, np.float64).reshape(self.nv, self.N)
+        return lib().or_dt_bound(self.h, _p(U))
+
+    def rk3_step(self, U, dt):
+        U = np.array(U, dtype=np.float64, order="C").reshape(self.nv, self.N)
+        self._check(lib().or_rk3_step(self.h, _p(U), float(dt)))
+        return U
+
+    def solve(self, U, t_final, cfl=0.3, t0=0.0, max_steps=1 << 30):
+        U = np.array(U, dtype=np.float64, order="C").reshape(self.nv, self.N)
+        steps = C.c_int()
+        t = C.c_double()
+        self._check(lib().or_solve(self.h, _p(U), float(t0), float(t_final), int(max_steps), float(cfl),
+                                   C.byref(steps), C.byref(t)))
+        return U, steps.value, t.value
+
+
+def hllc(UL, UR, n, gamma=1.4):
+    UL = np.ascontiguousarray(UL, np.float64)
+    UR = np.ascontiguousarray(UR, np.float64)
+    F = np.empty(4)
+    rc = lib().or_hllc(gamma, _p(UL), _p(UR), float(n[0]), float(n[1]), _p(F))
+    if rc:
+        raise OracleError("non-physical state")
+    return F
+
+
+def euler_flux(U, n, gamma=1.4):
+    U = np.ascontiguousarray(U, np.float64)
+    F = np.empty(4)
+    lib().or_euler_flux(gamma, _p(U), float(n[0]), float(n[1]), _p(F))
+    return F
+
+
+def threads() -> int:
+    return int(lib().or_threads())
