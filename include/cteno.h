@@ -1,0 +1,244 @@
+/*
+ * cteno.h -- C ABI of the MI355X (gfx950) CTENO / CTENOZ finite-volume
+ * library for the 2-D Euler equations and scalar advection on unstructured
+ * triangular meshes.
+ *
+ * Method: Ma, Chong, Feng, Zhang, Wang, Zhou, "High-order finite-volume
+ * central targeted ENO family scheme for compressible flows in unstructured
+ * meshes" (arXiv 2312.17042).  Section numbers below refer to that paper.
+ *
+ * Conventions shared by every entry point:
+ *   - every call returns a cteno_status; on failure the outputs and handles
+ *     are left unchanged and cteno_last_error() returns a message that stays
+ *     valid until the next failing call on the same thread;
+ *   - "host" pointers are read or written during the call only (inputs are
+ *     copied); "device" pointers are HIP device allocations owned by the
+ *     caller (for example torch tensors) and are accessed on the context's
+ *     stream, asynchronously, in stream order;
+ *   - arrays use the caller's cell order (the order of the triangles passed
+ *     to cteno_mesh_upload); the library may reorder cells internally;
+ *   - cell states are cell averages of the conserved variables, laid out
+ *     variable-major [nv][n_cells] in double precision: nv = 1 for scalar
+ *     advection, nv = 4 (rho, rho u, rho v, E) for the Euler equations;
+ *   - asynchronous device failures (non-physical states, faults) are
+ *     reported by the next synchronising call (cteno_sol_download,
+ *     cteno_solve, cteno_ctx_synchronize).
+ */
+#ifndef CTENO_H
+#define CTENO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CTENO_OK = 0,
+    CTENO_ERR_INVALID = 1,      /* bad argument or call sequence */
+    CTENO_ERR_MESH = 2,         /* malformed mesh (degenerate cell, unmatched periodic seam, ...) */
+    CTENO_ERR_STENCIL = 3,      /* stencil cannot be built (mesh too small) or rank-deficient LS */
+    CTENO_ERR_NOMEM = 4,        /* device or host allocation failed */
+    CTENO_ERR_DEVICE = 5,       /* HIP runtime error */
+    CTENO_ERR_NONPHYSICAL = 6,  /* density or pressure <= 0 / NaN met in a face state */
+    CTENO_ERR_BUSY = 7          /* resource budget exhausted; retry later */
+} cteno_status;
+
+/* boundary kinds per box side */
+enum { CTENO_PERIODIC = 0, CTENO_WALL = 1, CTENO_TRANSMISSIVE = 2 };
+/* physics */
+enum { CTENO_ADVECTION = 0, CTENO_EULER = 1 };
+/* weighting scheme: CTENO = Algorithm 1 (sec. 2.4), CTENOZ = Algorithm 2 (sec. 2.5) */
+enum { CTENO_SCHEME_CTENO = 0, CTENO_SCHEME_CTENOZ = 1 };
+/* CTENO scale-separation form: PAPER = gamma_s = 1/(SI_s+eps)^6 exactly as in
+   Algorithm 1; LAMBDA = gamma_s = lambda_s/(SI_s+eps)^6 (linear weights of
+   eq. e18 included) */
+enum { CTENO_GAMMA_PAPER = 0, CTENO_GAMMA_LAMBDA = 1 };
+/* arithmetic of the reconstruction, weights and fluxes.  The cell-average
+   state, the residual accumulation and the Runge-Kutta update are always
+   FP64; MIXED runs reconstruction, smoothness indicators, weights and HLLC
+   in FP32.  Bit mask of the pseudo-inverse copies kept on the device. */
+enum { CTENO_FP64 = 1, CTENO_MIXED = 2, CTENO_BOTH = 3 };
+
+typedef void *(*cteno_alloc_fn)(size_t bytes, void *user);
+typedef void (*cteno_free_fn)(void *ptr, void *user);
+
+typedef struct cteno_ctx cteno_ctx;
+typedef struct cteno_mesh cteno_mesh;
+typedef struct cteno_sol cteno_sol;
+typedef struct cteno_server cteno_server;
+
+/* Triangular mesh (sec. 2: cells V_i with faces A_ij).  Vertices are raw
+   coordinates; each triangle's own three vertices must form the cell as it
+   lies in the plane (no wrap-around triangles).  On a periodic pair of box
+   sides, vertices on the two sides are welded where their other coordinate
+   matches (tolerance 1e-9 of the box size), so seam vertices may be
+   duplicated.  Triangles may have either orientation; each is normalised to
+   counter-clockwise by swapping its 2nd and 3rd vertex. */
+typedef struct {
+    int32_t n_vertices;
+    const double *xy;      /* host [n_vertices][2] */
+    int32_t n_cells;
+    const int32_t *tri;    /* host [n_cells][3] */
+    double box[4];         /* x0, x1, y0, y1 */
+    int32_t bc[4];         /* kinds of the sides x = x0, x = x1, y = y0, y = y1 */
+} cteno_mesh_desc;
+
+/* Scheme parameters (sec. 2.1-2.6).  degree r in {2, 3}: the central
+   polynomial of degree r gives order r+1 and uses M = 2K neighbours,
+   K = (r+1)(r+2)/2 - 1; directional polynomials have degree 1; two
+   Gauss-Legendre points per face.  For the Euler equations a cell whose
+   reconstructed density or pressure is <= 0 at any Gauss point uses its
+   cell average at all of them (a positivity fallback the paper does not
+   describe; flagged by bit 7 of the selection bytes).
+   lambda1_prime: eq. e18; c_t: cut-off of eq. e23 (paper: 1e-6); eps: the
+   regulariser of the smoothness indicators (not given by the paper; 1e-12
+   recommended). */
+typedef struct {
+    int32_t physics;
+    double ax, ay;          /* advection velocity (ADVECTION) */
+    double gamma;           /* ratio of specific heats (EULER) */
+    int32_t scheme;
+    int32_t degree;
+    double lambda1_prime;
+    double c_t;
+    double eps;
+    int32_t gamma_form;
+    int32_t precision;      /* CTENO_FP64 | CTENO_MIXED | CTENO_BOTH */
+    int32_t reorder;        /* 1: Morton-order cells internally for locality; 0: keep order */
+} cteno_scheme;
+
+typedef struct {
+    int64_t n_cells, n_faces, n_boundary_faces;
+    int32_t K, M, slots, nv, nq;
+    int32_t n_inadmissible;     /* interior faces whose directional stencil has < 3 cells */
+    int64_t device_bytes;       /* resident device memory of the mesh handle */
+} cteno_mesh_info;
+
+/* ---------------------------------------------------------------------- */
+/* context                                                                 */
+/* ---------------------------------------------------------------------- */
+
+/* Creates a context on HIP device `device`, issuing all work on `stream`
+   (a hipStream_t; NULL = a non-blocking stream owned by the context).  alloc/free (both or neither)
+   route every device allocation through the caller, e.g. a framework's
+   caching allocator; NULL uses hipMalloc/hipFree. */
+cteno_status cteno_ctx_create(int device, void *stream, cteno_alloc_fn alloc, cteno_free_fn free_fn,
+                              void *user, cteno_ctx **out);
+void cteno_ctx_destroy(cteno_ctx *ctx);
+cteno_status cteno_ctx_set_stream(cteno_ctx *ctx, void *stream);
+/* waits for the stream and reports pending device errors */
+cteno_status cteno_ctx_synchronize(cteno_ctx *ctx);
+const char *cteno_last_error(void);
+/* Per-kernel timing with HIP events on the context stream (off by default).
+   kernel: 0 = reconstruction, 1 = flux + residual + RK update, 2 = pseudo-inverse
+   precompute.  Reports launches and summed milliseconds since the last reset. */
+cteno_status cteno_ctx_set_timing(cteno_ctx *ctx, int32_t on);
+cteno_status cteno_ctx_kernel_stats(cteno_ctx *ctx, int32_t kernel, int64_t *launches, double *total_ms);
+cteno_status cteno_ctx_reset_stats(cteno_ctx *ctx);
+
+/* ---------------------------------------------------------------------- */
+/* mesh                                                                    */
+/* ---------------------------------------------------------------------- */
+
+/* Builds faces, central and directional stencils on the host (sec. 2.1,
+   2.3: central stencil of M cells, one compact directional stencil per
+   face inside it) and computes the least-squares pseudo-inverses
+   P = R^-1 Q^T diag(|V'_m|) of every stencil on the device in FP64
+   (sec. 2.1, Householder QR), plus an FP32 copy when precision includes
+   MIXED.  Synchronises. */
+cteno_status cteno_mesh_upload(cteno_ctx *ctx, const cteno_mesh_desc *desc, const cteno_scheme *scheme,
+                               cteno_mesh **out);
+cteno_status cteno_mesh_info_get(const cteno_mesh *mesh, cteno_mesh_info *info);
+/* Host copies of the stencils: central [n_cells][M] cell ids (ascending),
+   directional [n_cells][3][M_d] (face neighbour first, -1 padded) and the
+   directional sizes [n_cells][3] (0 = inadmissible).  Any output may be NULL. */
+cteno_status cteno_mesh_stencils(const cteno_mesh *mesh, int32_t *central, int32_t *directional, int32_t *dir_count);
+/* Pseudo-inverses of selected cells, copied to host: central [n][K][M]
+   (columns in the order of cteno_mesh_stencils' central list), directional
+   [n][3][2][M_d] (columns in directional-list order, zero where absent).
+   which = CTENO_FP64 or CTENO_MIXED (the FP32 copy, widened).  Synchronises. */
+cteno_status cteno_mesh_pinv(cteno_ctx *ctx, const cteno_mesh *mesh, int32_t which, int32_t n, const int32_t *cells,
+                             double *central, double *directional);
+void cteno_mesh_destroy(cteno_mesh *mesh);
+/* Host-only stencil construction (no device needed), same rule and output
+   layout as cteno_mesh_stencils; the outputs must hold n_cells rows. */
+cteno_status cteno_stencils_host(const cteno_mesh_desc *desc, const cteno_scheme *scheme, int32_t *central,
+                                 int32_t *directional, int32_t *dir_count);
+
+/* ---------------------------------------------------------------------- */
+/* solution state                                                          */
+/* ---------------------------------------------------------------------- */
+
+/* Device-resident cell averages (FP64) at time t0, copied from host u0
+   [nv][n_cells]. */
+cteno_status cteno_sol_create(cteno_ctx *ctx, const cteno_mesh *mesh, const double *u0, double t0, cteno_sol **out);
+/* Replaces the state with host u [nv][n_cells] and sets the time. */
+cteno_status cteno_sol_set(cteno_sol *sol, const double *u, double t);
+/* Copies the state to host u [nv][n_cells] (may be NULL) and the time to *t
+   (may be NULL).  Synchronises and reports pending device errors. */
+cteno_status cteno_sol_download(cteno_sol *sol, double *u, double *t);
+void cteno_sol_destroy(cteno_sol *sol);
+
+/* ---------------------------------------------------------------------- */
+/* stage kernels (low level; outputs in caller cell order)                 */
+/* ---------------------------------------------------------------------- */
+
+/* Reconstruction of the current state of `sol` (sec. 2.1-2.5): central and
+   directional least-squares polynomials, p_1 (eq. e17), smoothness
+   indicators, CTENO/CTENOZ selection and the final polynomial, evaluated at
+   the N_q Gauss points of each face.
+   face_vals: device [n_cells][3][N_q][nv], FP64 (precision CTENO_FP64) or
+   FP32 (CTENO_MIXED); point q of face f lies at t_q along the face from
+   vertex f to vertex f+1 of the counter-clockwise triangle.
+   delta_out: device [n_cells][nv] or NULL: bit 0 = delta_1 (central),
+   bit 1+f = delta of the directional stencil of face f, bit 7 = positivity
+   fallback taken.
+   delta_forced: device [n_cells][nv] or NULL: use these selections instead
+   of computing them (bits of inadmissible stencils are ignored). */
+cteno_status cteno_reconstruct(cteno_ctx *ctx, const cteno_mesh *mesh, const cteno_sol *sol, int32_t precision,
+                               void *face_vals, uint8_t *delta_out, const uint8_t *delta_forced);
+/* Face fluxes from face-point values (sec. 2.6, HLLC for Euler, upwind for
+   advection), integrated over each face with the Gauss weights:
+   face_flux: device [n_cells][3][nv] (FP64 or FP32 by precision), the
+   outward flux of cell i through its face f, times |A_f|. */
+cteno_status cteno_flux(cteno_ctx *ctx, const cteno_mesh *mesh, int32_t precision, const void *face_vals,
+                        void *face_flux);
+/* Residual dU/dt = -(1/|V_i|) sum_f outward flux (the semi-discrete form
+   after eq. e1) of the current state: resid device [nv][n_cells] FP64. */
+cteno_status cteno_residual(cteno_ctx *ctx, const cteno_mesh *mesh, const cteno_sol *sol, int32_t precision,
+                            double *resid);
+/* One SSP-RK3 stage (Shu-Osher form) of size dt on `sol`: stage 0 forms
+   U1 = U + dt R(U), stage 1 U2 = 3/4 U + 1/4 (U1 + dt R(U1)), stage 2
+   U <- 1/3 U + 2/3 (U2 + dt R(U2)).  Stages must be issued 0, 1, 2. */
+cteno_status cteno_rk_stage(cteno_ctx *ctx, const cteno_mesh *mesh, cteno_sol *sol, int32_t precision, int32_t stage,
+                            double dt);
+
+/* ---------------------------------------------------------------------- */
+/* time marching                                                           */
+/* ---------------------------------------------------------------------- */
+
+/* Marches `sol` with SSP-RK3 until t_final or max_steps steps, whichever
+   comes first, dt = cfl * min_i 2|V_i| / sum_f |A_f| s_if (s the normal
+   signal speed |v.n| + c, or |a.n|), the last step clipped to land on
+   t_final.  The time step is computed and applied on the device (no host
+   round trip per step); use_graph = 1 replays a captured HIP graph per step.
+   steps_done (may be NULL) receives the number of steps taken by this call.
+   Synchronises. */
+cteno_status cteno_solve(cteno_ctx *ctx, const cteno_mesh *mesh, cteno_sol *sol, int32_t precision, double t_final,
+                         int64_t max_steps, double cfl, int32_t use_graph, int64_t *steps_done);
+
+/* Cells x variables whose TENO selection (delta bits) differs between the
+   FP32 and FP64 reconstructions of the current state.  Needs precision
+   CTENO_BOTH on the mesh.  Synchronises. */
+cteno_status cteno_count_flips(cteno_ctx *ctx, const cteno_mesh *mesh, const cteno_sol *sol, int64_t *flips);
+
+/* Device copy kernel used to calibrate hardware byte counters: copies
+   n_bytes (multiple of 16) from src to dst on the context stream. */
+cteno_status cteno_util_copy(cteno_ctx *ctx, void *dst, const void *src, size_t n_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CTENO_H */

@@ -65,6 +65,7 @@ def lib():
         L.or_reconstruct.argtypes = [P, P, P, P, P, P]
         L.or_reconstruct_cells.argtypes = [P, P, C.c_int, P, P, P]
         L.or_face_fluxes.argtypes = [P, P, P]
+        L.or_residual_cells.argtypes = [P, P, C.c_int, P, P]
         L.or_residual.argtypes = [P, P, P]
         L.or_dt_bound.restype = C.c_double
         L.or_dt_bound.argtypes = [P, P]
@@ -179,6 +180,14 @@ class Oracle:
         dl = np.empty((n, self.nv), np.uint8)
         self._check(lib().or_reconstruct_cells(self.h, _p(U), n, _p(cells), _p(fv), _p(dl)))
         return fv, dl
+
+    def residual_cells(self, U, cells):
+        """Residual of selected cells only, R[n][nv] (reconstructs only what it needs)."""
+        U = np.ascontiguousarray(U, np.float64).reshape(self.nv, self.N)
+        cells = np.ascontiguousarray(cells, np.int32)
+        R = np.empty((cells.shape[0], self.nv))
+        self._check(lib().or_residual_cells(self.h, _p(U), cells.shape[0], _p(cells), _p(R)))
+        return R
 
     def face_fluxes(self, fv):
         fv = np.ascontiguousarray(fv, np.float64)

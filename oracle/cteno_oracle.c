@@ -695,6 +695,22 @@ static int reconstruct_cell(or_ctx *c, int i, const double *U, const uint8_t *fo
             }
         }
     }
+    /* positivity fallback (not in the paper): a cell whose reconstructed
+       state is non-physical at any of its Gauss points (density or pressure
+       <= 0) uses its cell average at all of them; flagged with bit 7 */
+    if (c->physics == OR_EULER) {
+        int bad = 0;
+        for (int p = 0; p < 3 * c->Nq; ++p) {
+            const double *W = fv + (size_t)p * nv;
+            double pr = (c->gam - 1.0) * (W[3] - 0.5 * (W[1] * W[1] + W[2] * W[2]) / W[0]);
+            if (!(W[0] > 0.0) || !(pr > 0.0)) bad = 1;
+        }
+        if (bad) {
+            for (int p = 0; p < 3 * c->Nq; ++p)
+                for (int v = 0; v < nv; ++v) fv[(size_t)p * nv + v] = U[(size_t)v * N + i];
+            if (dbits) for (int v = 0; v < nv; ++v) dbits[v] |= 0x80;
+        }
+    }
     return 0;
 }
 
@@ -1020,6 +1036,55 @@ int or_reconstruct_cells(or_ctx *c, const double *U, int n, const int *cells, do
         if (rc) { set_err("reconstruction failure at cell", i); return rc; }
     }
     return 0;
+}
+
+/* residual of selected cells only: each sampled cell and its face
+   neighbours are reconstructed, the three face fluxes formed as in
+   face_fluxes (owner = lower cell id), R[n][nv] */
+int or_residual_cells(or_ctx *c, const double *U, int n, const int *cells, double *R) {
+    int nv = c->nv, Nq = c->Nq;
+    size_t per = (size_t)3 * Nq * nv;
+    double *own = malloc(sizeof(double) * per), *nbf = malloc(sizeof(double) * per);
+    uint8_t dl[OR_MAXNV];
+    int rc = 0;
+    for (int a = 0; a < n && !rc; ++a) {
+        int i = cells[a];
+        if (i < 0 || i >= c->N) { rc = 1; set_err("cell out of range", i); break; }
+        rc = reconstruct_cell(c, i, U, NULL, own, dl, NULL);
+        double acc[OR_MAXNV] = {0, 0, 0, 0};
+        for (int f = 0; f < 3 && !rc; ++f) {
+            int j = c->fnb[3 * i + f];
+            int g = c->fnbf[3 * i + f];
+            if (j >= 0) rc = reconstruct_cell(c, j, U, NULL, nbf, dl, NULL);
+            if (rc) break;
+            /* evaluate from the owner's side exactly as face_fluxes does */
+            int owner_is_i = (j < 0) || (i < j);
+            int oc = owner_is_i ? i : j, of = owner_is_i ? f : g;
+            const double *ofv = owner_is_i ? own : nbf, *xfv = owner_is_i ? nbf : own;
+            int xf = owner_is_i ? g : f;
+            double nx = c->fnx[3 * oc + of], ny = c->fny[3 * oc + of];
+            double facc[OR_MAXNV] = {0, 0, 0, 0};
+            for (int q = 0; q < Nq; ++q) {
+                const double *UL = ofv + ((size_t)of * Nq + q) * nv;
+                double UR[OR_MAXNV], F[OR_MAXNV];
+                if (j >= 0) {
+                    const double *p = xfv + ((size_t)xf * Nq + (Nq - 1 - q)) * nv;
+                    for (int v = 0; v < nv; ++v) UR[v] = p[v];
+                } else {
+                    ghost(c, c->fbc[3 * i + f], UL, nx, ny, UR);
+                }
+                rc |= point_flux(c, UL, UR, nx, ny, F);
+                for (int v = 0; v < nv; ++v) facc[v] += c->gw[q] * F[v];
+            }
+            for (int v = 0; v < nv; ++v) {
+                double val = c->flen[3 * oc + of] * facc[v];
+                acc[v] += owner_is_i ? val : -val;
+            }
+        }
+        for (int v = 0; v < nv; ++v) R[(size_t)a * nv + v] = -acc[v] / c->area[i];
+    }
+    free(own); free(nbf);
+    return rc;
 }
 
 int or_face_fluxes(or_ctx *c, const double *fv, double *fo) {

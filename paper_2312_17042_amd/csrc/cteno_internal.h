@@ -1,0 +1,96 @@
+// Internal declarations of the CTENO/CTENOZ MI355X library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/cteno.h"
+
+namespace cteno {
+
+// ---------------------------------------------------------------------------
+// sizes
+// ---------------------------------------------------------------------------
+constexpr int kTile = 64;          // cells per tile of the tiled per-cell arrays (one wave)
+constexpr int kNq = 2;             // Gauss points per face for degree <= 3
+constexpr int kMaxK = 9;
+constexpr int kMaxS = 18;
+constexpr int kDirSlots = 4;       // M_d = 2 K_d with K_d = 2 (degree-1 directional)
+constexpr int kPdEntries = 3 * 2 * kDirSlots;
+
+inline int dims_K(int r) { return (r + 1) * (r + 2) / 2 - 1; }
+inline int dims_M(int r) { return 2 * dims_K(r); }
+inline int dims_S(int r) { return dims_M(r) > 3 * kDirSlots ? dims_M(r) : 3 * kDirSlots; }
+
+// tiled index: per-cell array with E entries, 64-cell tiles, entry-major inside a tile
+__host__ __device__ inline size_t tix(int64_t i, int e, int E) {
+    return ((size_t)(i >> 6) * E + e) * kTile + (i & 63);
+}
+inline int64_t pad64(int64_t n) { return (n + kTile - 1) / kTile * kTile; }
+
+// neighbour code per cell face: bit 31 set = boundary (bits 0..1 = kind),
+// else bits 0..27 neighbour (internal index), 28..29 neighbour's local
+// face, bit 30 = this cell owns the face
+constexpr uint32_t kNbBoundary = 0x80000000u;
+constexpr uint32_t kNbOwner = 0x40000000u;
+constexpr uint32_t kNbIndexMask = 0x0FFFFFFFu;
+
+// ---------------------------------------------------------------------------
+// host mesh builder output (all in internal order unless noted)
+// ---------------------------------------------------------------------------
+struct HostMesh {
+    int N = 0, r = 0, K = 0, M = 0, S = 0, nv = 0;
+    int per_x = 0, per_y = 0;
+    double Lx = 0, Ly = 0;
+    int64_t n_faces = 0, n_boundary = 0;
+    int n_inadmissible = 0;
+    std::vector<int32_t> perm;     // internal -> user
+    std::vector<int32_t> iperm;    // user -> internal
+    // user-order stencils (for inspection)
+    std::vector<int32_t> cen_user;     // [N][M] ascending user ids
+    std::vector<int32_t> dir_user;     // [N][3][4] user ids, -1 padded
+    std::vector<int32_t> dirn_user;    // [N][3]
+    // internal-order device inputs
+    std::vector<int32_t> slot;         // tiled [S]: internal cell index (self for pads)
+    std::vector<uint8_t> slot_flag;    // tiled [S]: bit0 central member, bit1 directional member
+    std::vector<int8_t> slot_shift;    // tiled [2*S]: periodic image shift (x then y)
+    std::vector<uint8_t> flags;        // [Npad]: bit s = directional stencil of face s admissible
+    std::vector<double> verts;         // tiled [6]: CCW vertex coordinates x0,y0,x1,y1,x2,y2
+    std::vector<uint32_t> nb;          // tiled [3]
+    std::vector<double> fgeo;          // tiled [9]: (nx, ny, len) per local face
+    std::vector<double> area;          // [Npad]
+    // slot column -> position in the user-order stencil lists (for cteno_mesh_pinv)
+    std::vector<int8_t> slot_cen_pos;  // tiled [S]: index into cen_user row, -1 for pads
+    std::vector<int8_t> slot_dir_pos;  // tiled [S]: index into dir_user row of its sector, -1 if none
+};
+
+// returns CTENO_OK or an error (message in err)
+cteno_status build_host_mesh(const cteno_mesh_desc &d, const cteno_scheme &s, HostMesh &hm, std::string &err);
+
+// ---------------------------------------------------------------------------
+// constant tables of the reference triangle (host-computed, FP64)
+// ---------------------------------------------------------------------------
+struct RefTables {
+    int K = 0;
+    int ex[kMaxK][2];               // exponents of psi_k
+    double mean[kMaxK];             // mean of psi_k over the reference triangle
+    double gram[kMaxK][kMaxK];      // smoothness-indicator Gram matrix
+    double basis[3][kNq][kMaxK];    // phi_k at the face Gauss points
+    double gw[kNq];                 // Gauss weights on [0, 1]
+};
+void make_ref_tables(int r, RefTables &t);
+
+// ---------------------------------------------------------------------------
+// device-side control block of a time march
+// ---------------------------------------------------------------------------
+struct Ctrl {
+    double t, t_next, t_final, dt, cfl;
+    unsigned long long dt_cand_bits;   // min over cells of the dt bound (bits of a positive double)
+    long long step, max_steps;
+    int done, pending, nonphysical, pad;
+};
+
+}  // namespace cteno

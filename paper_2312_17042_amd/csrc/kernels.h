@@ -1,0 +1,77 @@
+// Kernel launchers of the CTENO/CTENOZ library (implemented in kernels.hip).
+#pragma once
+
+#include "cteno_internal.h"
+
+namespace cteno {
+
+struct DeviceMesh {
+    int64_t N = 0, Np = 0;
+    int r = 0, K = 0, S = 0, nv = 0, physics = 0;
+    int scheme = 0, gamma_form = 0, precision = 0;
+    double gamma = 1.4, ax = 0, ay = 0, lam1p = 1e4, ct = 1e-6, eps = 1e-12;
+    double Lx = 0, Ly = 0;
+    int32_t *slot = nullptr;      // tiled [S]
+    uint8_t *flags = nullptr;     // [Np]
+    uint32_t *nb = nullptr;       // tiled [3]
+    double *fgeo64 = nullptr;     // tiled [9]
+    float *fgeo32 = nullptr;      // tiled [9]
+    double *area = nullptr;       // [Np]
+    double *Pc64 = nullptr, *Pd64 = nullptr;   // tiled [K*S], [24]
+    float *Pc32 = nullptr, *Pd32 = nullptr;
+    int32_t *perm = nullptr;      // internal -> user [N]
+    RefTables tab;
+};
+
+struct PrecomputeInputs {
+    const double *verts;          // tiled [6]
+    const int32_t *slot;          // tiled [S]
+    const uint8_t *slot_flag;     // tiled [S]
+    const int8_t *slot_shift;     // tiled [2S]
+    uint8_t *flags;               // [Np] in/out: inadmissible-by-rank bits cleared
+    int *rank_fail;               // device counter of rank-deficient central systems
+};
+
+hipError_t launch_precompute(const DeviceMesh &m, const PrecomputeInputs &in, hipStream_t st);
+
+// reconstruction; dmode: 0 none, 1 write delta, 2 forced delta
+hipError_t launch_reconstruct(const DeviceMesh &m, bool fp32, const double *U, void *FV, uint8_t *delta, int dmode,
+                              const int *done, hipStream_t st);
+
+// flux / residual / RK stage.  mode: 0 outward face fluxes, 1 residual, 2 RK stage
+struct FluxLaunch {
+    int mode = 2;
+    const void *FV = nullptr;
+    const double *Un = nullptr, *Us = nullptr;
+    double *Uout = nullptr;
+    int stage = 0;
+    const double *dt_ptr = nullptr;
+    double dt_value = 0.0;
+    void *flux_out = nullptr;    // AoS [Np][3][nv] of the precision type
+    double *resid = nullptr;     // AoS [Np][nv]
+    Ctrl *ctrl = nullptr;        // done / nonphysical / dt candidate (may be null)
+    int want_dt = 0;
+};
+hipError_t launch_flux(const DeviceMesh &m, bool fp32, const FluxLaunch &f, hipStream_t st);
+
+hipError_t launch_dt_candidate(const DeviceMesh &m, const double *U, Ctrl *ctrl, hipStream_t st);
+hipError_t launch_control(Ctrl *ctrl, int commit_only, hipStream_t st);
+
+// layout conversions between caller order/layout and internal order/layout
+hipError_t launch_user_to_state(const DeviceMesh &m, const double *user, double *state, hipStream_t st);
+hipError_t launch_state_to_user(const DeviceMesh &m, const double *state, double *user, hipStream_t st);
+hipError_t launch_fv_to_user(const DeviceMesh &m, bool fp32, const void *fv, void *user, hipStream_t st);
+hipError_t launch_fv_from_user(const DeviceMesh &m, bool fp32, const void *user, void *fv, hipStream_t st);
+hipError_t launch_flux_to_user(const DeviceMesh &m, bool fp32, const void *fo, void *user, hipStream_t st);
+hipError_t launch_delta_to_user(const DeviceMesh &m, const uint8_t *d, uint8_t *user, hipStream_t st);
+hipError_t launch_delta_from_user(const DeviceMesh &m, const uint8_t *user, uint8_t *d, hipStream_t st);
+hipError_t launch_count_diff(const DeviceMesh &m, const uint8_t *a, const uint8_t *b, unsigned long long *count,
+                             hipStream_t st);
+hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, size_t n, hipStream_t st);
+hipError_t launch_to_fp32(const double *src, float *dst, size_t n, hipStream_t st);
+hipError_t launch_copy16(void *dst, const void *src, size_t n16, hipStream_t st);
+// dst[a][e] = src[tiled(idx[a], e, E)] from exactly one of src64 / src32 / srci
+hipError_t launch_gather_tiled(int n, const int32_t *idx, int E, const double *src64, const float *src32,
+                               const int32_t *srci, double *dst, hipStream_t st);
+
+}  // namespace cteno

@@ -1,0 +1,1115 @@
+// HIP kernels (gfx950) of the CTENO/CTENOZ finite-volume hot path.
+//
+//   k_precompute   once per mesh, FP64: reference-space moments of every
+//                  stencil cell (sec. 2.1), Householder QR of the M x K
+//                  least-squares matrix and the pseudo-inverse
+//                  P = R^-1 Q^T diag(|V'_m|), for the central stencil and
+//                  the three directional stencils; FP32 copies on request.
+//   k_reconstruct  per cell and stage: gather of neighbour averages, central
+//                  and directional products P d, p_1 (eq. e17), smoothness
+//                  indicators, CTENO (Algorithm 1) / CTENOZ (Algorithm 2)
+//                  selection, final polynomial at the face Gauss points.
+//   k_flux         per cell and stage: HLLC (sec. 2.6) or upwind flux at the
+//                  Gauss points of its three faces, the residual of the
+//                  semi-discrete form after eq. e1, and the SSP-RK3 stage;
+//                  each interior face flux is evaluated identically by both
+//                  of its cells (same operands, same order) so the update is
+//                  conservative to FP64 round-off without atomics.
+//   k_control      per RK step, one thread: time step from the reduced CFL
+//                  bound, clipping to t_final, termination.
+//
+// Memory layout: per-cell static data (stencil slots, pseudo-inverses,
+// face geometry) in 64-cell tiles, entry-major inside a tile, so a wave
+// streams each entry as one contiguous 256/512-byte segment; the state and
+// the face-point values are cell-major (array of structures) so a gather of
+// one neighbour touches one cache line.
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+#include <cmath>
+#include <type_traits>
+
+#include "kernels.h"
+
+namespace cteno {
+
+// ===========================================================================
+// precompute (FP64)
+// ===========================================================================
+
+struct QuadRule {
+    double s[16], t[16], w[16];     // collapsed Gauss-Legendre 4x4 on the reference triangle
+};
+
+template <int R>
+struct PreArgs {
+    static constexpr int K = (R + 1) * (R + 2) / 2 - 1;
+    static constexpr int M = 2 * K;
+    static constexpr int S = M > 12 ? M : 12;
+    int64_t N;
+    const double *verts;
+    const int32_t *slot;
+    const uint8_t *slot_flag;
+    const int8_t *slot_shift;
+    uint8_t *flags;
+    int *rank_fail;
+    double *Pc64, *Pd64;
+    float *Pc32, *Pd32;
+    double Lx, Ly;
+    int ex[K][2];
+    double mean[K];
+    QuadRule q;
+};
+
+template <int R>
+__global__ __launch_bounds__(64) void k_precompute(const PreArgs<R> a) {
+    constexpr int K = PreArgs<R>::K;
+    constexpr int S = PreArgs<R>::S;
+    __shared__ double sA[K * S][64];      // least-squares matrix, column-major, one column of lanes per cell
+    __shared__ double sQ[3][K][64];       // Householder v0, beta, and diag(R)
+    const int lane = threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * 64 + lane;
+    if (i >= a.N) return;                 // lanes only touch their own LDS column: no barriers needed
+
+    const double x0 = a.verts[tix(i, 0, 6)], y0 = a.verts[tix(i, 1, 6)];
+    const double ja = a.verts[tix(i, 2, 6)] - x0, jc = a.verts[tix(i, 3, 6)] - y0;
+    const double jb = a.verts[tix(i, 4, 6)] - x0, jd = a.verts[tix(i, 5, 6)] - y0;
+    const double det = ja * jd - jb * jc;
+
+    double wrow[S];
+    double dA[3][4][2], dW[3][4];
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        const uint8_t fl = a.slot_flag[tix(i, j, S)];
+        double row[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) row[k] = 0.0;
+        double w = 0.0;
+        if (fl & 1) {
+            const int64_t m = a.slot[tix(i, j, S)];
+            const double sx = a.slot_shift[tix(i, 2 * j, 2 * S)] * a.Lx;
+            const double sy = a.slot_shift[tix(i, 2 * j + 1, 2 * S)] * a.Ly;
+            double X[3], Y[3];
+#pragma unroll
+            for (int v = 0; v < 3; ++v) {
+                const double px = (a.verts[tix(m, 2 * v, 6)] + sx) - x0;
+                const double py = (a.verts[tix(m, 2 * v + 1, 6)] + sy) - y0;
+                X[v] = (jd * px - jb * py) / det;
+                Y[v] = (-jc * px + ja * py) / det;
+            }
+            const double ar = 0.5 * fabs((X[1] - X[0]) * (Y[2] - Y[0]) - (X[2] - X[0]) * (Y[1] - Y[0]));
+            double mom[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) mom[k] = 0.0;
+#pragma unroll
+            for (int p = 0; p < 16; ++p) {
+                const double xi = X[0] + a.q.s[p] * (X[1] - X[0]) + a.q.t[p] * (X[2] - X[0]);
+                const double et = Y[0] + a.q.s[p] * (Y[1] - Y[0]) + a.q.t[p] * (Y[2] - Y[0]);
+                double px[R + 1], py[R + 1];
+                px[0] = py[0] = 1.0;
+#pragma unroll
+                for (int e = 1; e <= R; ++e) { px[e] = px[e - 1] * xi; py[e] = py[e - 1] * et; }
+#pragma unroll
+                for (int k = 0; k < K; ++k) mom[k] += a.q.w[p] * (px[a.ex[k][0]] * py[a.ex[k][1]]);
+            }
+            // int_{V'_m} psi_k = 2 |V'_m| sum_p w_p psi_k(x_p);  A_mk = that - |V'_m| mean(psi_k)
+#pragma unroll
+            for (int k = 0; k < K; ++k) row[k] = 2.0 * ar * mom[k] - ar * a.mean[k];
+            w = ar;
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) sA[k * S + j][lane] = row[k];
+        wrow[j] = w;
+        if (j < 12) {
+            const bool dm = (fl & 2) != 0;
+            dA[j / 4][j % 4][0] = dm ? row[0] : 0.0;
+            dA[j / 4][j % 4][1] = dm ? row[1] : 0.0;
+            dW[j / 4][j % 4] = dm ? w : 0.0;
+        }
+    }
+
+    // Householder QR of the S x K matrix (zero rows for padding slots)
+    double rmax = 0.0;
+    for (int j = 0; j < K; ++j) {
+        double nrm2 = 0.0;
+        for (int r2 = j; r2 < S; ++r2) { const double x = sA[j * S + r2][lane]; nrm2 += x * x; }
+        const double nrm = sqrt(nrm2);
+        const double xj = sA[j * S + j][lane];
+        const double alpha = xj > 0 ? -nrm : nrm;
+        const double v0 = xj - alpha;
+        double vv = v0 * v0;
+        for (int r2 = j + 1; r2 < S; ++r2) { const double x = sA[j * S + r2][lane]; vv += x * x; }
+        const double beta = vv > 0 ? 2.0 / vv : 0.0;
+        sQ[0][j][lane] = v0;
+        sQ[1][j][lane] = beta;
+        sQ[2][j][lane] = alpha;
+        rmax = fmax(rmax, fabs(alpha));
+        for (int k2 = j + 1; k2 < K; ++k2) {
+            double s = v0 * sA[k2 * S + j][lane];
+            for (int r2 = j + 1; r2 < S; ++r2) s += sA[j * S + r2][lane] * sA[k2 * S + r2][lane];
+            s *= beta;
+            sA[k2 * S + j][lane] -= s * v0;
+            for (int r2 = j + 1; r2 < S; ++r2) sA[k2 * S + r2][lane] -= s * sA[j * S + r2][lane];
+        }
+    }
+    bool rank_ok = rmax > 0.0;
+    for (int j = 0; j < K; ++j) rank_ok = rank_ok && fabs(sQ[2][j][lane]) > 1e-12 * rmax;
+    if (!rank_ok) atomicAdd(a.rank_fail, 1);
+
+    // P(:, m) = R^-1 Q^T (w_m e_m)
+#pragma unroll 1
+    for (int m = 0; m < S; ++m) {
+        double b[S];
+#pragma unroll
+        for (int r2 = 0; r2 < S; ++r2) b[r2] = (r2 == m) ? wrow[r2] : 0.0;
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const double v0 = sQ[0][j][lane];
+            double s = v0 * b[j];
+#pragma unroll
+            for (int r2 = j + 1; r2 < S; ++r2) s += sA[j * S + r2][lane] * b[r2];
+            s *= sQ[1][j][lane];
+            b[j] -= s * v0;
+#pragma unroll
+            for (int r2 = j + 1; r2 < S; ++r2) b[r2] -= s * sA[j * S + r2][lane];
+        }
+        double x[K];
+#pragma unroll
+        for (int j = K - 1; j >= 0; --j) {
+            double s = b[j];
+#pragma unroll
+            for (int k2 = j + 1; k2 < K; ++k2) s -= sA[k2 * S + j][lane] * x[k2];
+            x[j] = s / sQ[2][j][lane];
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const double v = rank_ok ? x[k] : 0.0;
+            a.Pc64[tix(i, k * S + m, K * S)] = v;
+            if (a.Pc32) a.Pc32[tix(i, k * S + m, K * S)] = (float)v;
+        }
+    }
+
+    // directional 4 x 2 systems in registers
+    uint8_t fl = a.flags[i];
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+        double A[4][2], v0[2], bt[2], rd[2];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) { A[t][0] = dA[s][t][0]; A[t][1] = dA[s][t][1]; }
+        double dmax = 0.0;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            double nrm2 = 0.0;
+#pragma unroll
+            for (int r2 = j; r2 < 4; ++r2) nrm2 += A[r2][j] * A[r2][j];
+            const double nrm = sqrt(nrm2);
+            const double alpha = A[j][j] > 0 ? -nrm : nrm;
+            const double vj = A[j][j] - alpha;
+            double vv = vj * vj;
+#pragma unroll
+            for (int r2 = j + 1; r2 < 4; ++r2) vv += A[r2][j] * A[r2][j];
+            const double beta = vv > 0 ? 2.0 / vv : 0.0;
+            v0[j] = vj; bt[j] = beta; rd[j] = alpha;
+            dmax = fmax(dmax, fabs(alpha));
+#pragma unroll
+            for (int k2 = j + 1; k2 < 2; ++k2) {
+                double sm = vj * A[j][k2];
+#pragma unroll
+                for (int r2 = j + 1; r2 < 4; ++r2) sm += A[r2][j] * A[r2][k2];
+                sm *= beta;
+                A[j][k2] -= sm * vj;
+#pragma unroll
+                for (int r2 = j + 1; r2 < 4; ++r2) A[r2][k2] -= sm * A[r2][j];
+            }
+        }
+        bool ok = ((fl >> s) & 1) && dmax > 0.0 && fabs(rd[0]) > 1e-12 * dmax && fabs(rd[1]) > 1e-12 * dmax;
+        if (!ok) fl &= (uint8_t)~(1u << s);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            double b[4];
+#pragma unroll
+            for (int r2 = 0; r2 < 4; ++r2) b[r2] = (r2 == m) ? dW[s][r2] : 0.0;
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                double sm = v0[j] * b[j];
+#pragma unroll
+                for (int r2 = j + 1; r2 < 4; ++r2) sm += A[r2][j] * b[r2];
+                sm *= bt[j];
+                b[j] -= sm * v0[j];
+#pragma unroll
+                for (int r2 = j + 1; r2 < 4; ++r2) b[r2] -= sm * A[r2][j];
+            }
+            const double x1 = ok ? b[1] / rd[1] : 0.0;
+            const double x0v = ok ? (b[0] - A[0][1] * x1) / rd[0] : 0.0;
+            const int e0 = (s * 2 + 0) * 4 + m, e1 = (s * 2 + 1) * 4 + m;
+            a.Pd64[tix(i, e0, kPdEntries)] = x0v;
+            a.Pd64[tix(i, e1, kPdEntries)] = x1;
+            if (a.Pd32) {
+                a.Pd32[tix(i, e0, kPdEntries)] = (float)x0v;
+                a.Pd32[tix(i, e1, kPdEntries)] = (float)x1;
+            }
+        }
+    }
+    a.flags[i] = fl;
+}
+
+static void gauss_legendre4(double x[4], double w[4]) {
+    // roots of P_4 by Newton iteration from the Chebyshev guesses
+    for (int k = 0; k < 4; ++k) {
+        double z = cos(M_PI * (k + 0.75) / 4.5);
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int n = 2; n <= 4; ++n) { double p2 = ((2 * n - 1) * z * p1 - (n - 1) * p0) / n; p0 = p1; p1 = p2; }
+            double dp = 4 * (z * p1 - p0) / (z * z - 1.0);
+            double dz = p1 / dp;
+            z -= dz;
+            if (fabs(dz) < 1e-17) break;
+        }
+        double p0 = 1.0, p1 = z;
+        for (int n = 2; n <= 4; ++n) { double p2 = ((2 * n - 1) * z * p1 - (n - 1) * p0) / n; p0 = p1; p1 = p2; }
+        double dp = 4 * (z * p1 - p0) / (z * z - 1.0);
+        x[k] = z;
+        w[k] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+template <int R>
+static hipError_t precompute_r(const DeviceMesh &m, const PrecomputeInputs &in, hipStream_t st) {
+    PreArgs<R> a;
+    a.N = m.N;
+    a.verts = in.verts; a.slot = in.slot; a.slot_flag = in.slot_flag; a.slot_shift = in.slot_shift;
+    a.flags = in.flags; a.rank_fail = in.rank_fail;
+    a.Pc64 = m.Pc64; a.Pd64 = m.Pd64; a.Pc32 = m.Pc32; a.Pd32 = m.Pd32;
+    a.Lx = m.Lx; a.Ly = m.Ly;
+    for (int k = 0; k < PreArgs<R>::K; ++k) {
+        a.ex[k][0] = m.tab.ex[k][0];
+        a.ex[k][1] = m.tab.ex[k][1];
+        a.mean[k] = m.tab.mean[k];
+    }
+    double x[4], w[4];
+    gauss_legendre4(x, w);
+    int p = 0;
+    for (int u = 0; u < 4; ++u)
+        for (int v = 0; v < 4; ++v) {
+            double su = 0.5 * (x[u] + 1.0), sv = 0.5 * (x[v] + 1.0);
+            a.q.s[p] = su;
+            a.q.t[p] = sv * (1.0 - su);
+            a.q.w[p] = 0.25 * w[u] * w[v] * (1.0 - su);
+            ++p;
+        }
+    const unsigned grid = (unsigned)((m.N + 63) / 64);
+    hipLaunchKernelGGL(k_precompute<R>, dim3(grid), dim3(64), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_precompute(const DeviceMesh &m, const PrecomputeInputs &in, hipStream_t st) {
+    switch (m.r) {
+        case 2: return precompute_r<2>(m, in, st);
+        case 3: return precompute_r<3>(m, in, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// ===========================================================================
+// reconstruction
+// ===========================================================================
+
+template <typename real>
+__device__ __forceinline__ real pow6(real x) {
+    const real x2 = x * x;
+    return x2 * x2 * x2;
+}
+
+template <typename real, int K>
+struct ReconArgs {
+    int64_t N;
+    const double *U;        // AoS [Np][NV]
+    const int32_t *slot;    // tiled [S]
+    const uint8_t *flags;   // [Np]
+    const real *Pc;         // tiled [K*S]
+    const real *Pd;         // tiled [24]
+    real *FV;               // AoS [Np][3][2][NV]
+    uint8_t *delta;         // AoS [Np][NV]
+    const int *done;
+    real gram[K][K];
+    real basis[3][2][K];
+    real lam1, ct, eps;
+    real lams[5];           // lambda_s for s_t = 2, 3, 4 (index s_t)
+    real gamma;             // ratio of specific heats (positivity check)
+    real lam_ratio[5];      // lambda_1 / lambda_s (index s_t)
+};
+
+// TENO selection bits for one variable: bit 0 central, bit 1+s directional s.
+// FP64 follows Algorithms 1/2 literally; FP32 evaluates the same chi_s
+// through ratios that cannot overflow (gamma_s reaches 1e72 in FP64 terms).
+template <typename real, int SCHEME, int GFORM>
+__device__ __forceinline__ int teno_bits(const real si[4], int adm, int st, real lam1, real lams, real lratio,
+                                         real ct, real eps) {
+    int bits = 0;
+    if constexpr (std::is_same<real, double>::value) {
+        double g[4], sum = 0.0;
+        if (SCHEME == CTENO_SCHEME_CTENO) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const double lam = s == 0 ? (double)lam1 : (double)lams;
+                g[s] = (GFORM == CTENO_GAMMA_LAMBDA ? lam : 1.0) / pow6(si[s] + eps);
+            }
+        } else {
+            double tsum = 0.0;
+#pragma unroll
+            for (int s = 1; s < 4; ++s) if ((adm >> s) & 1) tsum += fabs(si[s] - si[0]);
+            const double tau = pow6(tsum / (st - 1));
+#pragma unroll
+            for (int s = 0; s < 4; ++s) g[s] = 1.0 + tau / (si[s] + eps);
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) if ((adm >> s) & 1) sum += g[s];
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+            if ((adm >> s) & 1) {
+                const double chi = g[s] / sum;
+                if (!(chi < ct)) bits |= 1 << s;
+            }
+    } else {
+        float e[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) e[s] = si[s] + eps;
+        if (SCHEME == CTENO_SCHEME_CTENO) {
+            // chi_s = 1 / sum_t (lambda_t / lambda_s) (e_s / e_t)^6
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                if (!((adm >> s) & 1)) continue;
+                float den = 0.0f;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    if (!((adm >> t) & 1)) continue;
+                    float lr = 1.0f;
+                    if (GFORM == CTENO_GAMMA_LAMBDA && s != t) lr = (t == 0) ? lratio : (s == 0 ? 1.0f / lratio : 1.0f);
+                    den += lr * pow6(e[s] / e[t]);
+                }
+                const float chi = 1.0f / den;
+                if (!(chi < ct)) bits |= 1 << s;
+            }
+        } else {
+            float tsum = 0.0f, emin = e[0];
+#pragma unroll
+            for (int s = 1; s < 4; ++s)
+                if ((adm >> s) & 1) { tsum += fabsf(e[s] - e[0]); emin = fminf(emin, e[s]); }
+            const float tau = pow6(tsum / (float)(st - 1));
+            const float G = tau / emin;            // gamma_s = 1 + G w_s, w_s = emin / e_s in (0, 1]
+            float num[4], sum = 0.0f;
+            if (G <= 1e30f) {
+#pragma unroll
+                for (int s = 0; s < 4; ++s) num[s] = 1.0f + G * (emin / e[s]);
+            } else {
+                const float iG = 1.0f / G;
+#pragma unroll
+                for (int s = 0; s < 4; ++s) num[s] = iG + emin / e[s];
+            }
+#pragma unroll
+            for (int s = 0; s < 4; ++s) if ((adm >> s) & 1) sum += num[s];
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+                if ((adm >> s) & 1) {
+                    const float chi = num[s] / sum;
+                    if (!(chi < ct)) bits |= 1 << s;
+                }
+        }
+    }
+    return bits;
+}
+
+template <typename real, int R, int NV, int SCHEME, int GFORM, int DMODE>
+__global__ __launch_bounds__(256) void k_reconstruct(const ReconArgs<real, (R + 1) * (R + 2) / 2 - 1> a) {
+    constexpr int K = (R + 1) * (R + 2) / 2 - 1;
+    constexpr int M = 2 * K;
+    constexpr int S = M > 12 ? M : 12;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.N) return;
+    if (a.done && *a.done) return;
+
+    double U0[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) U0[v] = a.U[i * NV + v];
+
+    real ao[K][NV], ad[3][2][NV];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) ao[k][v] = 0;
+#pragma unroll
+    for (int s = 0; s < 3; ++s)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) ad[s][c][v] = 0;
+
+    // directional groups: slots 4s .. 4s+3 feed both the central product and
+    // the directional product of face s
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+#pragma unroll 1
+        for (int t = 0; t < 4; ++t) {
+            const int j = 4 * s + t;
+            const int64_t m = a.slot[tix(i, j, S)];
+            real d[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) d[v] = (real)(a.U[m * NV + v] - U0[v]);
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const real p = a.Pc[tix(i, k * S + j, K * S)];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) ao[k][v] += p * d[v];
+            }
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const real p = a.Pd[tix(i, (s * 2 + c) * 4 + t, kPdEntries)];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) ad[s][c][v] += p * d[v];
+            }
+        }
+    }
+    // remaining central slots
+#pragma unroll 1
+    for (int j = 12; j < S; ++j) {
+        const int64_t m = a.slot[tix(i, j, S)];
+        real d[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) d[v] = (real)(a.U[m * NV + v] - U0[v]);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const real p = a.Pc[tix(i, k * S + j, K * S)];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) ao[k][v] += p * d[v];
+        }
+    }
+
+    const int fl = a.flags[i] & 7;
+    const int adm = 1 | (fl << 1);
+    const int st = 1 + __popc(fl);
+    const real lams = a.lams[st];
+    real out[3][2][NV];
+    uint32_t dword = 0;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        // p_1 = (p_opt - sum_s lambda_s p_s) / lambda_1
+        real a1[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            real sm = ao[k][v];
+            if (k < 2 && st > 1) {
+#pragma unroll
+                for (int q = 0; q < 3; ++q)
+                    if ((fl >> q) & 1) sm -= lams * ad[q][k][v];
+            }
+            a1[k] = st > 1 ? sm / a.lam1 : sm;
+        }
+        int bits;
+        if (DMODE == 2) {
+            bits = a.delta[i * NV + v] & adm;
+        } else if (st == 1) {
+            bits = 1;
+        } else {
+            real si[4];
+            real acc = 0;
+#pragma unroll
+            for (int p = 0; p < K; ++p) {
+                real rowp = 0;
+#pragma unroll
+                for (int q = 0; q < K; ++q) rowp += a.gram[p][q] * a1[q];
+                acc += a1[p] * rowp;
+            }
+            si[0] = acc;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const real x0 = ad[q][0][v], x1 = ad[q][1][v];
+                si[q + 1] = x0 * (a.gram[0][0] * x0 + a.gram[0][1] * x1) + x1 * (a.gram[1][0] * x0 + a.gram[1][1] * x1);
+            }
+            bits = teno_bits<real, SCHEME, GFORM>(si, adm, st, a.lam1, lams, a.lam_ratio[st], a.ct, a.eps);
+        }
+        dword |= (uint32_t)bits << (8 * v);
+        real fin[K];
+        if (bits & 1) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) fin[k] = a1[k];
+        } else {
+            real s0 = 0, s1 = 0;
+            int cnt = 0;
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+                if ((bits >> (q + 1)) & 1) { s0 += ad[q][0][v]; s1 += ad[q][1][v]; ++cnt; }
+            fin[0] = s0 / (real)cnt;
+            fin[1] = s1 / (real)cnt;
+#pragma unroll
+            for (int k = 2; k < K; ++k) fin[k] = 0;
+        }
+#pragma unroll
+        for (int f = 0; f < 3; ++f)
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                real val = 0;
+#pragma unroll
+                for (int k = 0; k < K; ++k) val += a.basis[f][q][k] * fin[k];
+                out[f][q][v] = (real)(U0[v] + (double)val);
+            }
+    }
+    if (NV == 4) {
+        // positivity fallback: a cell with a non-physical state (density or
+        // pressure <= 0) at any of its Gauss points uses its cell average at
+        // all of them; reported with bit 7 of its selection bytes
+        bool bad = false;
+#pragma unroll
+        for (int f = 0; f < 3; ++f)
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const real rho = out[f][q][0];
+                const real pr = (a.gamma - 1) * (out[f][q][3] - (real)0.5 * (out[f][q][1] * out[f][q][1] +
+                                                                             out[f][q][2] * out[f][q][2]) / rho);
+                bad |= !(rho > 0) || !(pr > 0);
+            }
+        if (bad) {
+#pragma unroll
+            for (int f = 0; f < 3; ++f)
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) out[f][q][v] = (real)U0[v];
+            dword |= 0x80808080u;
+        }
+    }
+    if (DMODE == 1) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) a.delta[i * NV + v] = (uint8_t)(dword >> (8 * v));
+    }
+    real *dst = a.FV + i * 3 * 2 * NV;
+#pragma unroll
+    for (int f = 0; f < 3; ++f)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) dst[(f * 2 + q) * NV + v] = out[f][q][v];
+}
+
+template <typename real, int R, int NV>
+static hipError_t reconstruct_t(const DeviceMesh &m, const double *U, void *FV, uint8_t *delta, int dmode,
+                                const int *done, hipStream_t st) {
+    constexpr int K = (R + 1) * (R + 2) / 2 - 1;
+    ReconArgs<real, K> a;
+    a.N = m.N;
+    a.U = U;
+    a.slot = m.slot;
+    a.flags = m.flags;
+    if constexpr (std::is_same<real, double>::value) { a.Pc = m.Pc64; a.Pd = m.Pd64; }
+    else { a.Pc = m.Pc32; a.Pd = m.Pd32; }
+    if (!a.Pc || !a.Pd) return hipErrorInvalidValue;
+    a.FV = (real *)FV;
+    a.delta = delta;
+    a.done = done;
+    for (int p = 0; p < K; ++p)
+        for (int q = 0; q < K; ++q) a.gram[p][q] = (real)m.tab.gram[p][q];
+    for (int f = 0; f < 3; ++f)
+        for (int q = 0; q < 2; ++q)
+            for (int k = 0; k < K; ++k) a.basis[f][q][k] = (real)m.tab.basis[f][q][k];
+    const double lam1 = 1.0 - 1.0 / m.lam1p;
+    a.lam1 = (real)lam1;
+    a.gamma = (real)m.gamma;
+    a.ct = (real)m.ct;
+    a.eps = (real)m.eps;
+    for (int s = 0; s < 5; ++s) {
+        const double ls = s >= 2 ? (1.0 - lam1) / (s - 1) : 0.0;
+        a.lams[s] = (real)ls;
+        a.lam_ratio[s] = s >= 2 ? (real)(lam1 / ls) : (real)1;
+    }
+    const unsigned grid = (unsigned)((m.N + 255) / 256);
+#define CT_LAUNCH(SCH, GF, DM) hipLaunchKernelGGL((k_reconstruct<real, R, NV, SCH, GF, DM>), dim3(grid), dim3(256), 0, st, a)
+#define CT_DM(SCH, GF)              \
+    switch (dmode) {                \
+        case 0: CT_LAUNCH(SCH, GF, 0); break; \
+        case 1: CT_LAUNCH(SCH, GF, 1); break; \
+        default: CT_LAUNCH(SCH, GF, 2); break; \
+    }
+    if (m.scheme == CTENO_SCHEME_CTENOZ) { CT_DM(CTENO_SCHEME_CTENOZ, CTENO_GAMMA_PAPER); }
+    else if (m.gamma_form == CTENO_GAMMA_LAMBDA) { CT_DM(CTENO_SCHEME_CTENO, CTENO_GAMMA_LAMBDA); }
+    else { CT_DM(CTENO_SCHEME_CTENO, CTENO_GAMMA_PAPER); }
+#undef CT_DM
+#undef CT_LAUNCH
+    return hipGetLastError();
+}
+
+template <typename real>
+static hipError_t reconstruct_p(const DeviceMesh &m, const double *U, void *FV, uint8_t *delta, int dmode,
+                                const int *done, hipStream_t st) {
+    if (m.nv == 4) {
+        switch (m.r) {
+            case 2: return reconstruct_t<real, 2, 4>(m, U, FV, delta, dmode, done, st);
+            case 3: return reconstruct_t<real, 3, 4>(m, U, FV, delta, dmode, done, st);
+        }
+    } else {
+        switch (m.r) {
+            case 2: return reconstruct_t<real, 2, 1>(m, U, FV, delta, dmode, done, st);
+            case 3: return reconstruct_t<real, 3, 1>(m, U, FV, delta, dmode, done, st);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_reconstruct(const DeviceMesh &m, bool fp32, const double *U, void *FV, uint8_t *delta, int dmode,
+                              const int *done, hipStream_t st) {
+    return fp32 ? reconstruct_p<float>(m, U, FV, delta, dmode, done, st)
+                : reconstruct_p<double>(m, U, FV, delta, dmode, done, st);
+}
+
+// ===========================================================================
+// fluxes, residual, Runge-Kutta
+// ===========================================================================
+
+// HLLC with Roe-averaged signal speeds (sec. 2.6), in the face-normal frame
+// (u normal, w tangential velocity); F returned in the global frame.
+template <typename real>
+__device__ __forceinline__ bool hllc(real g, const real *UL, const real *UR, real nx, real ny, real *F) {
+    const real rl = UL[0], rr = UR[0];
+    const real ul = (UL[1] * nx + UL[2] * ny) / rl, wl = (-UL[1] * ny + UL[2] * nx) / rl;
+    const real ur = (UR[1] * nx + UR[2] * ny) / rr, wr = (-UR[1] * ny + UR[2] * nx) / rr;
+    const real El = UL[3], Er = UR[3];
+    const real h = (real)0.5;
+    const real pl = (g - 1) * (El - h * rl * (ul * ul + wl * wl));
+    const real pr = (g - 1) * (Er - h * rr * (ur * ur + wr * wr));
+    const bool ok = rl > 0 && rr > 0 && pl > 0 && pr > 0;
+    const real cl = sqrt(g * pl / rl), cr = sqrt(g * pr / rr);
+    const real Hl = (El + pl) / rl, Hr = (Er + pr) / rr;
+    const real D = sqrt(rr / rl);
+    const real ut = (ul + ur * D) / (1 + D);
+    const real wt = (wl + wr * D) / (1 + D);
+    const real Ht = (Hl + Hr * D) / (1 + D);
+    const real ct = sqrt((g - 1) * (Ht - h * (ut * ut + wt * wt)));
+    const real SL = fmin(ul - cl, ut - ct);
+    const real SR = fmax(ur + cr, ut + ct);
+    const real SM = (rr * ur * (SR - ur) - rl * ul * (SL - ul) + pl - pr) / (rr * (SR - ur) - rl * (SL - ul));
+    const real ps = rl * (ul - SL) * (ul - SM) + pl;
+    real Fn[4];
+    if (SL > 0) {
+        Fn[0] = rl * ul; Fn[1] = rl * ul * ul + pl; Fn[2] = rl * ul * wl; Fn[3] = ul * (El + pl);
+    } else if (0 < SM) {
+        const real d = SL - SM;
+        const real Us0 = rl * (SL - ul) / d;
+        const real Us1 = ((SL - ul) * rl * ul + ps - pl) / d;
+        const real Us2 = (SL - ul) * rl * wl / d;
+        const real Us3 = ((SL - ul) * El - pl * ul + ps * SM) / d;
+        Fn[0] = rl * ul + SL * (Us0 - rl);
+        Fn[1] = (rl * ul * ul + pl) + SL * (Us1 - rl * ul);
+        Fn[2] = rl * ul * wl + SL * (Us2 - rl * wl);
+        Fn[3] = ul * (El + pl) + SL * (Us3 - El);
+    } else if (0 < SR) {
+        const real d = SR - SM;
+        const real Us0 = rr * (SR - ur) / d;
+        const real Us1 = ((SR - ur) * rr * ur + ps - pr) / d;
+        const real Us2 = (SR - ur) * rr * wr / d;
+        const real Us3 = ((SR - ur) * Er - pr * ur + ps * SM) / d;
+        Fn[0] = rr * ur + SR * (Us0 - rr);
+        Fn[1] = (rr * ur * ur + pr) + SR * (Us1 - rr * ur);
+        Fn[2] = rr * ur * wr + SR * (Us2 - rr * wr);
+        Fn[3] = ur * (Er + pr) + SR * (Us3 - Er);
+    } else {
+        Fn[0] = rr * ur; Fn[1] = rr * ur * ur + pr; Fn[2] = rr * ur * wr; Fn[3] = ur * (Er + pr);
+    }
+    F[0] = Fn[0];
+    F[1] = Fn[1] * nx - Fn[2] * ny;
+    F[2] = Fn[1] * ny + Fn[2] * nx;
+    F[3] = Fn[3];
+    return ok;
+}
+
+template <typename real>
+struct FluxArgs {
+    int64_t N;
+    const real *FV;
+    const uint32_t *nb;
+    const real *fgeo;
+    const double *area;
+    const double *Un, *Us;
+    double *Uout;
+    const double *dt_ptr;
+    double dt_value;
+    real *flux_out;
+    double *resid;
+    Ctrl *ctrl;
+    real gamma, ax, ay;
+    double gamma64;
+    int stage, want_dt;
+};
+
+template <int NV, int PHYS>
+__device__ __forceinline__ double cell_dt_bound(const double *U, const double nrm[3][3], double area, double gamma,
+                                                double ax, double ay) {
+    double sum = 0.0;
+    if (PHYS == CTENO_EULER) {
+        const double rho = U[0], u = U[1] / rho, v = U[2] / rho;
+        const double p = (gamma - 1.0) * (U[3] - 0.5 * rho * (u * u + v * v));
+        const double c = sqrt(gamma * p / rho);
+#pragma unroll
+        for (int f = 0; f < 3; ++f) sum += nrm[f][2] * (fabs(u * nrm[f][0] + v * nrm[f][1]) + c);
+    } else {
+#pragma unroll
+        for (int f = 0; f < 3; ++f) sum += nrm[f][2] * fabs(ax * nrm[f][0] + ay * nrm[f][1]);
+    }
+    return 2.0 * area / sum;
+}
+
+__device__ __forceinline__ double block_min(double v) {
+    __shared__ double red[16];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    double r = INFINITY;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) r = fmin(r, red[k]);
+    return r;
+}
+
+template <typename real, int NV, int PHYS, int MODE>
+__global__ __launch_bounds__(256) void k_flux(const FluxArgs<real> a) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool active = i < a.N;
+    if (a.ctrl && a.ctrl->done) return;        // uniform across the grid
+    double dtc = INFINITY;
+    if (active) {
+        double acc[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+        double nrm[3][3];
+        bool bad = false;
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            const uint32_t code = a.nb[tix(i, f, 3)];
+            const real nx = a.fgeo[tix(i, 3 * f, 9)];
+            const real ny = a.fgeo[tix(i, 3 * f + 1, 9)];
+            const real len = a.fgeo[tix(i, 3 * f + 2, 9)];
+            nrm[f][0] = (double)nx; nrm[f][1] = (double)ny; nrm[f][2] = (double)len;
+            real own[2][NV], oth[2][NV];
+            const real *src = a.FV + (i * 3 + f) * 2 * NV;
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+#pragma unroll
+                for (int v = 0; v < NV; ++v) own[q][v] = src[q * NV + v];
+            bool owner;
+            if (code & kNbBoundary) {
+                owner = true;
+                const bool wall = (code & 3u) == CTENO_WALL;
+                // ghost state at the same Gauss point: oth[1-q] pairs with own[q]
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) oth[1 - q][v] = own[q][v];
+                    if (PHYS == CTENO_EULER && wall) {
+                        const real mn = own[q][1] * nx + own[q][2] * ny;
+                        oth[1 - q][1] = own[q][1] - 2 * mn * nx;
+                        oth[1 - q][2] = own[q][2] - 2 * mn * ny;
+                    }
+                }
+            } else {
+                owner = (code & kNbOwner) != 0;
+                const int64_t j = code & kNbIndexMask;
+                const int g = (code >> 28) & 3;
+                const real *nsrc = a.FV + (j * 3 + g) * 2 * NV;
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) oth[q][v] = nsrc[q * NV + v];
+            }
+            // both cells of a face evaluate F(owner side, other side; owner normal)
+            // at the owner's Gauss points in the owner's order
+            const real fx = owner ? nx : -nx, fy = owner ? ny : -ny;
+            real sumF[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) sumF[v] = 0;
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                real A[NV], B[NV], F[NV];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    A[v] = owner ? own[q][v] : oth[q][v];
+                    B[v] = owner ? oth[1 - q][v] : own[1 - q][v];
+                }
+                if (PHYS == CTENO_EULER) {
+                    bad |= !hllc<real>(a.gamma, A, B, fx, fy, F);
+                } else {
+                    const real an = a.ax * fx + a.ay * fy;
+                    F[0] = an * (an >= 0 ? A[0] : B[0]);
+                }
+#pragma unroll
+                for (int v = 0; v < NV; ++v) sumF[v] += (real)0.5 * F[v];
+            }
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const double val = (double)(len * sumF[v]);
+                const double out = owner ? val : -val;
+                acc[v] += out;
+                if (MODE == 0) a.flux_out[(i * 3 + f) * NV + v] = (real)out;
+            }
+        }
+        if (bad && a.ctrl) atomicOr(&a.ctrl->nonphysical, 1);
+        if (MODE == 1) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) a.resid[i * NV + v] = -acc[v] / a.area[i];
+        }
+        if (MODE == 2) {
+            const double dt = a.dt_ptr ? *a.dt_ptr : a.dt_value;
+            double un[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const double R = -acc[v] / a.area[i];
+                const double u0 = a.Un[i * NV + v];
+                const double us = a.Us[i * NV + v];
+                double r;
+                if (a.stage == 0) r = us + dt * R;
+                else if (a.stage == 1) r = 0.75 * u0 + 0.25 * (us + dt * R);
+                else r = (1.0 / 3.0) * u0 + (2.0 / 3.0) * (us + dt * R);
+                un[v] = r;
+                a.Uout[i * NV + v] = r;
+            }
+            if (a.want_dt) dtc = cell_dt_bound<NV, PHYS>(un, nrm, a.area[i], a.gamma64, (double)a.ax, (double)a.ay);
+        }
+    }
+    if (MODE == 2 && a.want_dt) {
+        const double bm = block_min(dtc);
+        if (threadIdx.x == 0 && bm < INFINITY)
+            atomicMin(&a.ctrl->dt_cand_bits, (unsigned long long)__double_as_longlong(bm));
+    }
+}
+
+template <typename real, int NV, int PHYS>
+static hipError_t flux_t(const DeviceMesh &m, const FluxLaunch &f, hipStream_t st) {
+    FluxArgs<real> a;
+    a.N = m.N;
+    a.FV = (const real *)f.FV;
+    a.nb = m.nb;
+    if constexpr (std::is_same<real, double>::value) a.fgeo = m.fgeo64;
+    else a.fgeo = m.fgeo32;
+    a.area = m.area;
+    a.Un = f.Un; a.Us = f.Us; a.Uout = f.Uout;
+    a.dt_ptr = f.dt_ptr; a.dt_value = f.dt_value;
+    a.flux_out = (real *)f.flux_out;
+    a.resid = f.resid;
+    a.ctrl = f.ctrl;
+    a.gamma = (real)m.gamma; a.ax = (real)m.ax; a.ay = (real)m.ay;
+    a.gamma64 = m.gamma;
+    a.stage = f.stage;
+    a.want_dt = f.want_dt && f.ctrl;
+    const unsigned grid = (unsigned)((m.N + 255) / 256);
+    switch (f.mode) {
+        case 0: hipLaunchKernelGGL((k_flux<real, NV, PHYS, 0>), dim3(grid), dim3(256), 0, st, a); break;
+        case 1: hipLaunchKernelGGL((k_flux<real, NV, PHYS, 1>), dim3(grid), dim3(256), 0, st, a); break;
+        default: hipLaunchKernelGGL((k_flux<real, NV, PHYS, 2>), dim3(grid), dim3(256), 0, st, a); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_flux(const DeviceMesh &m, bool fp32, const FluxLaunch &f, hipStream_t st) {
+    if (m.physics == CTENO_EULER)
+        return fp32 ? flux_t<float, 4, CTENO_EULER>(m, f, st) : flux_t<double, 4, CTENO_EULER>(m, f, st);
+    return fp32 ? flux_t<float, 1, CTENO_ADVECTION>(m, f, st) : flux_t<double, 1, CTENO_ADVECTION>(m, f, st);
+}
+
+// ===========================================================================
+// time-step control
+// ===========================================================================
+
+template <int NV, int PHYS>
+__global__ __launch_bounds__(256) void k_dt_candidate(int64_t N, const double *U, const double *fgeo,
+                                                      const double *area, double gamma, double ax, double ay,
+                                                      Ctrl *ctrl) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double dtc = INFINITY;
+    if (i < N) {
+        double u[NV], nrm[3][3];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) u[v] = U[i * NV + v];
+#pragma unroll
+        for (int f = 0; f < 3; ++f)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) nrm[f][c] = fgeo[tix(i, 3 * f + c, 9)];
+        dtc = cell_dt_bound<NV, PHYS>(u, nrm, area[i], gamma, ax, ay);
+    }
+    const double bm = block_min(dtc);
+    if (threadIdx.x == 0 && bm < INFINITY) atomicMin(&ctrl->dt_cand_bits, (unsigned long long)__double_as_longlong(bm));
+}
+
+hipError_t launch_dt_candidate(const DeviceMesh &m, const double *U, Ctrl *ctrl, hipStream_t st) {
+    const unsigned grid = (unsigned)((m.N + 255) / 256);
+    if (m.physics == CTENO_EULER)
+        hipLaunchKernelGGL((k_dt_candidate<4, CTENO_EULER>), dim3(grid), dim3(256), 0, st, m.N, U, m.fgeo64, m.area,
+                           m.gamma, m.ax, m.ay, ctrl);
+    else
+        hipLaunchKernelGGL((k_dt_candidate<1, CTENO_ADVECTION>), dim3(grid), dim3(256), 0, st, m.N, U, m.fgeo64,
+                           m.area, m.gamma, m.ax, m.ay, ctrl);
+    return hipGetLastError();
+}
+
+// Step control, one thread.  Commits the pending step (t <- t_next), then
+// decides the next one exactly as: stop when t >= t_final or the step
+// budget is used; dt = cfl * bound; clip the last step onto t_final.
+__global__ void k_control(Ctrl *c, int commit_only) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (c->pending) {
+        c->t = c->t_next;
+        c->step += 1;
+        c->pending = 0;
+    }
+    if (commit_only || c->done) return;
+    if (c->nonphysical || !(c->t < c->t_final) || c->step >= c->max_steps) {
+        c->done = 1;
+        return;
+    }
+    const double bound = __longlong_as_double((long long)c->dt_cand_bits);
+    double dt = c->cfl * bound;
+    double tn = c->t + dt;
+    if (dt >= c->t_final - c->t) {
+        dt = c->t_final - c->t;
+        tn = c->t_final;
+    }
+    if (!(dt > 0.0)) {
+        c->done = 1;
+        c->nonphysical = 1;
+        return;
+    }
+    c->dt = dt;
+    c->t_next = tn;
+    c->pending = 1;
+    c->dt_cand_bits = 0x7FF0000000000000ull;   // +inf, reduced again by the last stage
+}
+
+hipError_t launch_control(Ctrl *ctrl, int commit_only, hipStream_t st) {
+    hipLaunchKernelGGL(k_control, dim3(1), dim3(64), 0, st, ctrl, commit_only);
+    return hipGetLastError();
+}
+
+// ===========================================================================
+// layout conversions and utilities
+// ===========================================================================
+
+__global__ void k_user_to_state(int64_t N, int nv, const int32_t *perm, const double *user, double *state) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    const int64_t u = perm[k];
+    for (int v = 0; v < nv; ++v) state[k * nv + v] = user[(int64_t)v * N + u];
+}
+__global__ void k_state_to_user(int64_t N, int nv, const int32_t *perm, const double *state, double *user) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    const int64_t u = perm[k];
+    for (int v = 0; v < nv; ++v) user[(int64_t)v * N + u] = state[k * nv + v];
+}
+// rows of `width` elements, internal row k <-> caller row perm[k]
+template <typename T>
+__global__ void k_rows_to_user(int64_t N, int width, const int32_t *perm, const T *src, T *dst) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    const int64_t u = perm[k];
+    for (int e = 0; e < width; ++e) dst[u * width + e] = src[k * width + e];
+}
+template <typename T>
+__global__ void k_rows_from_user(int64_t N, int width, const int32_t *perm, const T *src, T *dst) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    const int64_t u = perm[k];
+    for (int e = 0; e < width; ++e) dst[k * width + e] = src[u * width + e];
+}
+
+static unsigned grid_for(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+hipError_t launch_user_to_state(const DeviceMesh &m, const double *user, double *state, hipStream_t st) {
+    hipLaunchKernelGGL(k_user_to_state, dim3(grid_for(m.N)), dim3(256), 0, st, m.N, m.nv, m.perm, user, state);
+    return hipGetLastError();
+}
+hipError_t launch_state_to_user(const DeviceMesh &m, const double *state, double *user, hipStream_t st) {
+    hipLaunchKernelGGL(k_state_to_user, dim3(grid_for(m.N)), dim3(256), 0, st, m.N, m.nv, m.perm, state, user);
+    return hipGetLastError();
+}
+hipError_t launch_fv_to_user(const DeviceMesh &m, bool fp32, const void *fv, void *user, hipStream_t st) {
+    const int w = 3 * kNq * m.nv;
+    if (fp32) hipLaunchKernelGGL(k_rows_to_user<float>, dim3(grid_for(m.N)), dim3(256), 0, st, m.N, w, m.perm, (const float *)fv, (float *)user);
+    else hipLaunchKernelGGL(k_rows_to_user<double>, dim3(grid_for(m.N)), dim3(256), 0, st, m.N, w, m.perm, (const double *)fv, (double *)user);
+    return hipGetLastError();
+}
+hipError_t launch_fv_from_user(const DeviceMesh &m, bool fp32, const void *user, void *fv, hipStream_t st) {
+    const int w = 3 * kNq * m.nv;
+    if (fp32) hipLaunchKernelGGL(k_rows_from_user<float>, dim3(grid_for(m.N)), dim3(256), 0, st, m.N, w, m.perm, (const float *)user, (float *)fv);
+    else hipLaunchKernelGGL(k_rows_from_user<double>, dim3(grid_for(m.N)), dim3(256), 0, st, m.N, w, m.perm, (const double *)user, (double *)fv);
+    return hipGetLastError();
+}
+hipError_t launch_flux_to_user(const DeviceMesh &m, bool fp32, const void *fo, void *user, hipStream_t st) {
+    const int w = 3 * m.nv;
+    if (fp32) hipLaunchKernelGGL(k_rows_to_user<float>, dim3(grid_for(m.N)), dim3(256), 0, st, m.N, w, m.perm, (const float *)fo, (float *)user);
+    else hipLaunchKernelGGL(k_rows_to_user<double>, dim3(grid_for(m.N)), dim3(256), 0, st, m.N, w, m.perm, (const double *)fo, (double *)user);
+    return hipGetLastError();
+}
+hipError_t launch_delta_to_user(const DeviceMesh &m, const uint8_t *d, uint8_t *user, hipStream_t st) {
+    hipLaunchKernelGGL(k_rows_to_user<uint8_t>, dim3(grid_for(m.N)), dim3(256), 0, st, m.N, m.nv, m.perm, d, user);
+    return hipGetLastError();
+}
+hipError_t launch_delta_from_user(const DeviceMesh &m, const uint8_t *user, uint8_t *d, hipStream_t st) {
+    hipLaunchKernelGGL(k_rows_from_user<uint8_t>, dim3(grid_for(m.N)), dim3(256), 0, st, m.N, m.nv, m.perm, user, d);
+    return hipGetLastError();
+}
+
+__global__ void k_count_diff(int64_t n, const uint8_t *a, const uint8_t *b, unsigned long long *count) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long c = (k < n && a[k] != b[k]) ? 1ull : 0ull;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(count, c);
+}
+hipError_t launch_count_diff(const DeviceMesh &m, const uint8_t *a, const uint8_t *b, unsigned long long *count,
+                             hipStream_t st) {
+    const int64_t n = m.N * m.nv;
+    hipLaunchKernelGGL(k_count_diff, dim3(grid_for(n)), dim3(256), 0, st, n, a, b, count);
+    return hipGetLastError();
+}
+
+__global__ void k_fill_u64(unsigned long long *p, unsigned long long v, size_t n) {
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) p[k] = v;
+}
+hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, size_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for((int64_t)n)), dim3(256), 0, st, p, v, n);
+    return hipGetLastError();
+}
+
+__global__ void k_to_fp32(const double *src, float *dst, size_t n) {
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) dst[k] = (float)src[k];
+}
+hipError_t launch_to_fp32(const double *src, float *dst, size_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_to_fp32, dim3(grid_for((int64_t)n)), dim3(256), 0, st, src, dst, n);
+    return hipGetLastError();
+}
+
+__global__ void k_copy16(uint4 *dst, const uint4 *src, size_t n) {
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x)
+        dst[k] = src[k];
+}
+hipError_t launch_copy16(void *dst, const void *src, size_t n16, hipStream_t st) {
+    unsigned grid = (unsigned)std::min<size_t>((n16 + 255) / 256, 256 * 64);
+    if (grid == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy16, dim3(grid), dim3(256), 0, st, (uint4 *)dst, (const uint4 *)src, n16);
+    return hipGetLastError();
+}
+
+__global__ void k_gather_tiled(int n, const int32_t *idx, int E, const double *s64, const float *s32,
+                               const int32_t *si, double *dst) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)n * E) return;
+    const int a = (int)(t / E), e = (int)(t % E);
+    const size_t src = tix(idx[a], e, E);
+    dst[t] = s64 ? s64[src] : (s32 ? (double)s32[src] : (double)si[src]);
+}
+hipError_t launch_gather_tiled(int n, const int32_t *idx, int E, const double *src64, const float *src32,
+                               const int32_t *srci, double *dst, hipStream_t st) {
+    hipLaunchKernelGGL(k_gather_tiled, dim3(grid_for((int64_t)n * E)), dim3(256), 0, st, n, idx, E, src64, src32, srci,
+                       dst);
+    return hipGetLastError();
+}
+
+}  // namespace cteno

@@ -1,0 +1,767 @@
+// C ABI implementation: contexts, mesh upload, solution state, stage calls
+// and the device-driven SSP-RK3 time march.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "cteno_internal.h"
+#include "kernels.h"
+
+using namespace cteno;
+
+namespace {
+thread_local std::string g_err;
+cteno_status fail(cteno_status s, const std::string &m) {
+    g_err = m;
+    return s;
+}
+}  // namespace
+
+#define HIP_TRY(expr)                                                                               \
+    do {                                                                                            \
+        hipError_t e_ = (expr);                                                                     \
+        if (e_ != hipSuccess) return fail(CTENO_ERR_DEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+extern "C" const char *cteno_last_error(void) { return g_err.c_str(); }
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+struct cteno_ctx {
+    int device = 0;
+    hipStream_t user_stream = nullptr;
+    hipStream_t own_stream = nullptr;
+    cteno_alloc_fn alloc = nullptr;
+    cteno_free_fn free_fn = nullptr;
+    void *user = nullptr;
+    bool timing = false;
+    int64_t launches[3] = {0, 0, 0};
+    double total_ms[3] = {0, 0, 0};
+    struct Pending { int kernel; hipEvent_t a, b; };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> event_pool;
+    hipStream_t stream() const { return user_stream ? user_stream : own_stream; }
+};
+
+namespace {
+
+void *dev_alloc(cteno_ctx *c, size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    if (c->alloc) return c->alloc(bytes, c->user);
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+    return p;
+}
+void dev_free(cteno_ctx *c, void *p) {
+    if (!p) return;
+    if (c->free_fn) c->free_fn(p, c->user);
+    else (void)hipFree(p);
+}
+
+hipEvent_t take_event(cteno_ctx *c) {
+    if (!c->event_pool.empty()) {
+        hipEvent_t e = c->event_pool.back();
+        c->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+}
+
+// drains recorded timing events (call after a stream synchronisation)
+void collect_timing(cteno_ctx *c) {
+    for (auto &p : c->pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            c->launches[p.kernel] += 1;
+            c->total_ms[p.kernel] += ms;
+        }
+        c->event_pool.push_back(p.a);
+        c->event_pool.push_back(p.b);
+    }
+    c->pending.clear();
+}
+
+// launches fn on the context stream, bracketed by timing events when enabled
+template <class F>
+hipError_t timed(cteno_ctx *c, int kernel, F &&fn) {
+    if (!c->timing) return fn();
+    hipEvent_t a = take_event(c), b = take_event(c);
+    (void)hipEventRecord(a, c->stream());
+    hipError_t e = fn();
+    (void)hipEventRecord(b, c->stream());
+    c->pending.push_back({kernel, a, b});
+    if (c->pending.size() > 4096) {
+        (void)hipEventSynchronize(b);
+        collect_timing(c);
+    }
+    return e;
+}
+
+struct DevBuf {
+    cteno_ctx *ctx = nullptr;
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(cteno_ctx *c, size_t n) : ctx(c), bytes(n) { p = dev_alloc(c, n); }
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept : ctx(o.ctx), p(o.p), bytes(o.bytes) { o.p = nullptr; }
+    DevBuf &operator=(DevBuf &&o) noexcept {
+        reset();
+        ctx = o.ctx; p = o.p; bytes = o.bytes; o.p = nullptr;
+        return *this;
+    }
+    ~DevBuf() { reset(); }
+    void reset() {
+        if (p && ctx) dev_free(ctx, p);
+        p = nullptr;
+    }
+    template <class T> T *as() const { return (T *)p; }
+};
+
+}  // namespace
+
+extern "C" cteno_status cteno_ctx_create(int device, void *stream, cteno_alloc_fn alloc, cteno_free_fn free_fn,
+                                         void *user, cteno_ctx **out) {
+    if (!out) return fail(CTENO_ERR_INVALID, "out is NULL");
+    if ((alloc == nullptr) != (free_fn == nullptr)) return fail(CTENO_ERR_INVALID, "alloc and free must be given together");
+    int n = 0;
+    HIP_TRY(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) return fail(CTENO_ERR_INVALID, "no such device");
+    HIP_TRY(hipSetDevice(device));
+    auto c = std::make_unique<cteno_ctx>();
+    c->device = device;
+    c->user_stream = (hipStream_t)stream;
+    c->alloc = alloc;
+    c->free_fn = free_fn;
+    c->user = user;
+    HIP_TRY(hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking));
+    *out = c.release();
+    return CTENO_OK;
+}
+
+extern "C" void cteno_ctx_destroy(cteno_ctx *c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream());
+    collect_timing(c);
+    for (auto e : c->event_pool) (void)hipEventDestroy(e);
+    if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
+    delete c;
+}
+
+extern "C" cteno_status cteno_ctx_set_stream(cteno_ctx *c, void *stream) {
+    if (!c) return fail(CTENO_ERR_INVALID, "ctx is NULL");
+    c->user_stream = (hipStream_t)stream;
+    return CTENO_OK;
+}
+
+extern "C" cteno_status cteno_ctx_synchronize(cteno_ctx *c) {
+    if (!c) return fail(CTENO_ERR_INVALID, "ctx is NULL");
+    HIP_TRY(hipSetDevice(c->device));
+    HIP_TRY(hipStreamSynchronize(c->stream()));
+    collect_timing(c);
+    return CTENO_OK;
+}
+
+extern "C" cteno_status cteno_ctx_set_timing(cteno_ctx *c, int32_t on) {
+    if (!c) return fail(CTENO_ERR_INVALID, "ctx is NULL");
+    c->timing = on != 0;
+    return CTENO_OK;
+}
+
+extern "C" cteno_status cteno_ctx_kernel_stats(cteno_ctx *c, int32_t kernel, int64_t *launches, double *total_ms) {
+    if (!c || kernel < 0 || kernel > 2) return fail(CTENO_ERR_INVALID, "bad kernel id");
+    HIP_TRY(hipStreamSynchronize(c->stream()));
+    collect_timing(c);
+    if (launches) *launches = c->launches[kernel];
+    if (total_ms) *total_ms = c->total_ms[kernel];
+    return CTENO_OK;
+}
+
+extern "C" cteno_status cteno_ctx_reset_stats(cteno_ctx *c) {
+    if (!c) return fail(CTENO_ERR_INVALID, "ctx is NULL");
+    HIP_TRY(hipStreamSynchronize(c->stream()));
+    collect_timing(c);
+    for (int k = 0; k < 3; ++k) { c->launches[k] = 0; c->total_ms[k] = 0; }
+    return CTENO_OK;
+}
+
+// ---------------------------------------------------------------------------
+// mesh
+// ---------------------------------------------------------------------------
+struct cteno_mesh {
+    cteno_ctx *ctx = nullptr;
+    cteno_scheme scheme{};
+    HostMesh host;
+    DeviceMesh dm;
+    std::vector<DevBuf> bufs;
+    int64_t bytes = 0;
+    template <class T> T *alloc(size_t count) {
+        bufs.emplace_back(ctx, count * sizeof(T));
+        if (!bufs.back().p) return nullptr;
+        bytes += (int64_t)(count * sizeof(T));
+        return bufs.back().as<T>();
+    }
+};
+
+namespace {
+template <class T>
+hipError_t h2d(T *dst, const std::vector<T> &src, hipStream_t st) {
+    return hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, st);
+}
+}  // namespace
+
+extern "C" cteno_status cteno_mesh_upload(cteno_ctx *ctx, const cteno_mesh_desc *desc, const cteno_scheme *scheme,
+                                          cteno_mesh **out) {
+    if (!ctx || !desc || !scheme || !out) return fail(CTENO_ERR_INVALID, "NULL argument");
+    const cteno_scheme &s = *scheme;
+    if (s.physics != CTENO_ADVECTION && s.physics != CTENO_EULER) return fail(CTENO_ERR_INVALID, "bad physics");
+    if (s.scheme != CTENO_SCHEME_CTENO && s.scheme != CTENO_SCHEME_CTENOZ) return fail(CTENO_ERR_INVALID, "bad scheme");
+    if (s.degree < 2 || s.degree > 3) return fail(CTENO_ERR_INVALID, "degree must be 2 or 3");
+    if (s.precision < 1 || s.precision > 3) return fail(CTENO_ERR_INVALID, "bad precision");
+    if (!(s.lambda1_prime > 1.0) || !(s.c_t > 0 && s.c_t < 1) || !(s.eps > 0))
+        return fail(CTENO_ERR_INVALID, "bad lambda1_prime, c_t or eps");
+    if (s.physics == CTENO_EULER && !(s.gamma > 1.0)) return fail(CTENO_ERR_INVALID, "bad gamma");
+    HIP_TRY(hipSetDevice(ctx->device));
+
+    auto m = std::make_unique<cteno_mesh>();
+    m->ctx = ctx;
+    m->scheme = s;
+    std::string err;
+    cteno_status rc = build_host_mesh(*desc, s, m->host, err);
+    if (rc != CTENO_OK) return fail(rc, err);
+    HostMesh &hm = m->host;
+    DeviceMesh &dm = m->dm;
+    dm.N = hm.N; dm.Np = pad64(hm.N);
+    dm.r = hm.r; dm.K = hm.K; dm.S = hm.S; dm.nv = hm.nv;
+    dm.physics = s.physics; dm.scheme = s.scheme; dm.gamma_form = s.gamma_form; dm.precision = s.precision;
+    dm.gamma = s.gamma; dm.ax = s.ax; dm.ay = s.ay; dm.lam1p = s.lambda1_prime; dm.ct = s.c_t; dm.eps = s.eps;
+    dm.Lx = hm.Lx; dm.Ly = hm.Ly;
+    make_ref_tables(hm.r, dm.tab);
+
+    const size_t Np = (size_t)dm.Np, S = hm.S, KS = (size_t)hm.K * hm.S;
+    hipStream_t st = ctx->stream();
+    dm.slot = m->alloc<int32_t>(Np * S);
+    dm.flags = m->alloc<uint8_t>(Np);
+    dm.nb = m->alloc<uint32_t>(Np * 3);
+    dm.fgeo64 = m->alloc<double>(Np * 9);
+    dm.area = m->alloc<double>(Np);
+    dm.perm = m->alloc<int32_t>((size_t)hm.N);
+    if (s.precision & CTENO_MIXED) {
+        dm.fgeo32 = m->alloc<float>(Np * 9);
+        dm.Pc32 = m->alloc<float>(Np * KS);
+        dm.Pd32 = m->alloc<float>(Np * kPdEntries);
+    }
+    if (!dm.slot || !dm.flags || !dm.nb || !dm.fgeo64 || !dm.area || !dm.perm ||
+        ((s.precision & CTENO_MIXED) && (!dm.fgeo32 || !dm.Pc32 || !dm.Pd32)))
+        return fail(CTENO_ERR_NOMEM, "device allocation failed");
+    // FP64 pseudo-inverses are always computed; kept only when FP64 is resident
+    DevBuf pc64(ctx, Np * KS * sizeof(double)), pd64(ctx, Np * kPdEntries * sizeof(double));
+    DevBuf verts(ctx, Np * 6 * sizeof(double)), sflag(ctx, Np * S), sshift(ctx, Np * 2 * S), rfail(ctx, sizeof(int));
+    if (!pc64.p || !pd64.p || !verts.p || !sflag.p || !sshift.p || !rfail.p)
+        return fail(CTENO_ERR_NOMEM, "device allocation failed (precompute)");
+    dm.Pc64 = pc64.as<double>();
+    dm.Pd64 = pd64.as<double>();
+
+    HIP_TRY(h2d(dm.slot, hm.slot, st));
+    HIP_TRY(h2d(dm.flags, hm.flags, st));
+    HIP_TRY(h2d(dm.nb, hm.nb, st));
+    HIP_TRY(h2d(dm.fgeo64, hm.fgeo, st));
+    HIP_TRY(h2d(dm.area, hm.area, st));
+    HIP_TRY(h2d(dm.perm, hm.perm, st));
+    HIP_TRY(h2d(verts.as<double>(), hm.verts, st));
+    HIP_TRY(h2d(sflag.as<uint8_t>(), hm.slot_flag, st));
+    HIP_TRY(h2d(sshift.as<int8_t>(), hm.slot_shift, st));
+    HIP_TRY(hipMemsetAsync(rfail.p, 0, sizeof(int), st));
+    if (dm.fgeo32) HIP_TRY(launch_to_fp32(dm.fgeo64, dm.fgeo32, Np * 9, st));
+
+    PrecomputeInputs in{verts.as<double>(), dm.slot, sflag.as<uint8_t>(), sshift.as<int8_t>(), dm.flags,
+                        rfail.as<int>()};
+    HIP_TRY(timed(ctx, 2, [&] { return launch_precompute(dm, in, st); }));
+    int rank_fail = 0;
+    std::vector<uint8_t> flags(Np);
+    HIP_TRY(hipMemcpyAsync(&rank_fail, rfail.p, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(flags.data(), dm.flags, Np, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    collect_timing(ctx);
+    if (rank_fail) return fail(CTENO_ERR_STENCIL, std::to_string(rank_fail) + " rank-deficient central stencils");
+    // directional stencils found rank-deficient on the device become inadmissible
+    for (int k = 0; k < hm.N; ++k) {
+        const int u = hm.perm[k];
+        for (int f = 0; f < 3; ++f)
+            if (((hm.flags[k] >> f) & 1) && !((flags[k] >> f) & 1)) {
+                hm.dirn_user[3 * (size_t)u + f] = 0;
+                for (int a = 0; a < kDirSlots; ++a) hm.dir_user[((size_t)u * 3 + f) * kDirSlots + a] = -1;
+                hm.n_inadmissible++;
+            }
+        hm.flags[k] = flags[k];
+    }
+    if (s.precision & CTENO_FP64) {
+        m->bytes += (int64_t)(pc64.bytes + pd64.bytes);
+        m->bufs.push_back(std::move(pc64));
+        m->bufs.push_back(std::move(pd64));
+    } else {
+        dm.Pc64 = dm.Pd64 = nullptr;
+    }
+    // release host-only copies that the device now holds
+    hm.slot.clear(); hm.slot.shrink_to_fit();
+    hm.slot_flag.clear(); hm.slot_flag.shrink_to_fit();
+    hm.slot_shift.clear(); hm.slot_shift.shrink_to_fit();
+    hm.verts.clear(); hm.verts.shrink_to_fit();
+    hm.nb.clear(); hm.nb.shrink_to_fit();
+    hm.fgeo.clear(); hm.fgeo.shrink_to_fit();
+    *out = m.release();
+    return CTENO_OK;
+}
+
+extern "C" cteno_status cteno_mesh_info_get(const cteno_mesh *m, cteno_mesh_info *info) {
+    if (!m || !info) return fail(CTENO_ERR_INVALID, "NULL argument");
+    info->n_cells = m->host.N;
+    info->n_faces = m->host.n_faces;
+    info->n_boundary_faces = m->host.n_boundary;
+    info->K = m->host.K;
+    info->M = m->host.M;
+    info->slots = m->host.S;
+    info->nv = m->host.nv;
+    info->nq = kNq;
+    info->n_inadmissible = m->host.n_inadmissible;
+    info->device_bytes = m->bytes;
+    return CTENO_OK;
+}
+
+extern "C" cteno_status cteno_mesh_stencils(const cteno_mesh *m, int32_t *central, int32_t *directional,
+                                            int32_t *dir_count) {
+    if (!m) return fail(CTENO_ERR_INVALID, "mesh is NULL");
+    const HostMesh &h = m->host;
+    if (central) std::memcpy(central, h.cen_user.data(), h.cen_user.size() * sizeof(int32_t));
+    if (directional) std::memcpy(directional, h.dir_user.data(), h.dir_user.size() * sizeof(int32_t));
+    if (dir_count) std::memcpy(dir_count, h.dirn_user.data(), h.dirn_user.size() * sizeof(int32_t));
+    return CTENO_OK;
+}
+
+extern "C" cteno_status cteno_mesh_pinv(cteno_ctx *ctx, const cteno_mesh *m, int32_t which, int32_t n,
+                                        const int32_t *cells, double *central, double *directional) {
+    if (!ctx || !m || n < 0 || (n && !cells)) return fail(CTENO_ERR_INVALID, "bad arguments");
+    const DeviceMesh &dm = m->dm;
+    const HostMesh &hm = m->host;
+    const bool f32 = which == CTENO_MIXED;
+    if (which != CTENO_FP64 && which != CTENO_MIXED) return fail(CTENO_ERR_INVALID, "which must be FP64 or MIXED");
+    if (!(dm.precision & which)) return fail(CTENO_ERR_INVALID, "requested pseudo-inverse copy is not resident");
+    if (n == 0) return CTENO_OK;
+    std::vector<int32_t> idx(n);
+    for (int a = 0; a < n; ++a) {
+        if (cells[a] < 0 || cells[a] >= hm.N) return fail(CTENO_ERR_INVALID, "cell out of range");
+        idx[a] = hm.iperm[cells[a]];
+    }
+    // slot tables are not kept on the host; rebuild the column maps from the stencils
+    const int K = hm.K, S = hm.S, M = hm.M, KS = K * S;
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream();
+    DevBuf didx(ctx, n * sizeof(int32_t)), oc(ctx, (size_t)n * KS * sizeof(double)),
+        od(ctx, (size_t)n * kPdEntries * sizeof(double)), dslot(ctx, (size_t)n * S * sizeof(double));
+    if (!didx.p || !oc.p || !od.p || !dslot.p) return fail(CTENO_ERR_NOMEM, "device allocation failed");
+    HIP_TRY(hipMemcpyAsync(didx.p, idx.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    HIP_TRY(launch_gather_tiled(n, didx.as<int32_t>(), KS, f32 ? nullptr : dm.Pc64, f32 ? dm.Pc32 : nullptr,
+                                nullptr, oc.as<double>(), st));
+    HIP_TRY(launch_gather_tiled(n, didx.as<int32_t>(), kPdEntries, f32 ? nullptr : dm.Pd64, f32 ? dm.Pd32 : nullptr,
+                                nullptr, od.as<double>(), st));
+    HIP_TRY(launch_gather_tiled(n, didx.as<int32_t>(), S, nullptr, nullptr, dm.slot, dslot.as<double>(), st));
+    std::vector<double> pc((size_t)n * KS), pd((size_t)n * kPdEntries);
+    HIP_TRY(hipMemcpyAsync(pc.data(), oc.p, pc.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(pd.data(), od.p, pd.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    std::vector<double> slotd((size_t)n * S);
+    HIP_TRY(hipMemcpyAsync(slotd.data(), dslot.p, slotd.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    std::vector<int32_t> slots(slotd.begin(), slotd.end());
+    for (int a = 0; a < n; ++a) {
+        const int u = cells[a];
+        const int32_t *cen = hm.cen_user.data() + (size_t)u * M;
+        const int32_t *dr = hm.dir_user.data() + (size_t)u * 3 * kDirSlots;
+        if (central) std::fill(central + (size_t)a * K * M, central + (size_t)(a + 1) * K * M, 0.0);
+        if (directional)
+            std::fill(directional + (size_t)a * 3 * 2 * kDirSlots, directional + (size_t)(a + 1) * 3 * 2 * kDirSlots, 0.0);
+        for (int j = 0; j < S; ++j) {
+            const int src_k = slots[(size_t)a * S + j];
+            if (src_k == idx[a]) continue;   // padding slot (the cell itself)
+            const int src_u = hm.perm[src_k];
+            int cpos = -1;
+            for (int q = 0; q < M; ++q) if (cen[q] == src_u) cpos = q;
+            if (cpos < 0) return fail(CTENO_ERR_DEVICE, "slot not in stencil");
+            if (central)
+                for (int k = 0; k < K; ++k)
+                    central[((size_t)a * K + k) * M + cpos] = pc[(size_t)a * KS + k * S + j];
+            if (j < 12 && directional) {
+                const int s = j / 4, t = j % 4;
+                int dpos = -1;
+                for (int q = 0; q < kDirSlots; ++q) if (dr[s * kDirSlots + q] == src_u) dpos = q;
+                if (dpos >= 0)
+                    for (int c = 0; c < 2; ++c)
+                        directional[(((size_t)a * 3 + s) * 2 + c) * kDirSlots + dpos] =
+                            pd[(size_t)a * kPdEntries + (s * 2 + c) * 4 + t];
+            }
+        }
+    }
+    return CTENO_OK;
+}
+
+extern "C" cteno_status cteno_stencils_host(const cteno_mesh_desc *desc, const cteno_scheme *scheme,
+                                            int32_t *central, int32_t *directional, int32_t *dir_count) {
+    if (!desc || !scheme) return fail(CTENO_ERR_INVALID, "NULL argument");
+    if (scheme->degree < 2 || scheme->degree > 3) return fail(CTENO_ERR_INVALID, "degree must be 2 or 3");
+    HostMesh hm;
+    std::string err;
+    cteno_scheme s = *scheme;
+    s.reorder = 0;
+    cteno_status rc = build_host_mesh(*desc, s, hm, err);
+    if (rc != CTENO_OK) return fail(rc, err);
+    if (central) std::memcpy(central, hm.cen_user.data(), hm.cen_user.size() * sizeof(int32_t));
+    if (directional) std::memcpy(directional, hm.dir_user.data(), hm.dir_user.size() * sizeof(int32_t));
+    if (dir_count) std::memcpy(dir_count, hm.dirn_user.data(), hm.dirn_user.size() * sizeof(int32_t));
+    return CTENO_OK;
+}
+
+extern "C" void cteno_mesh_destroy(cteno_mesh *m) {
+    if (!m) return;
+    (void)hipSetDevice(m->ctx->device);
+    (void)hipStreamSynchronize(m->ctx->stream());
+    delete m;
+}
+
+// ---------------------------------------------------------------------------
+// solution state
+// ---------------------------------------------------------------------------
+struct cteno_sol {
+    cteno_ctx *ctx = nullptr;
+    const cteno_mesh *mesh = nullptr;
+    DevBuf U[3];              // U^n, U^(1), U^(2): AoS [Np][nv]
+    DevBuf FV[2];             // face-point values, FP64 / FP32
+    DevBuf ctrl;              // Ctrl
+    double t = 0.0;
+    Ctrl *h_ctrl = nullptr;   // pinned host mirror
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    ~cteno_sol() {
+        for (auto &g : graph) if (g) (void)hipGraphExecDestroy(g);
+        if (h_ctrl) (void)hipHostFree(h_ctrl);
+    }
+    void *fv(bool f32) {
+        DevBuf &b = FV[f32 ? 1 : 0];
+        if (!b.p) {
+            const DeviceMesh &dm = mesh->dm;
+            b = DevBuf(ctx, (size_t)dm.Np * 3 * kNq * dm.nv * (f32 ? sizeof(float) : sizeof(double)));
+        }
+        return b.p;
+    }
+};
+
+namespace {
+cteno_status check_precision(const cteno_mesh *m, int32_t precision, bool &f32) {
+    if (precision != CTENO_FP64 && precision != CTENO_MIXED) return fail(CTENO_ERR_INVALID, "precision must be FP64 or MIXED");
+    if (!(m->dm.precision & precision)) return fail(CTENO_ERR_INVALID, "mesh was uploaded without this precision");
+    f32 = precision == CTENO_MIXED;
+    return CTENO_OK;
+}
+}  // namespace
+
+extern "C" cteno_status cteno_sol_create(cteno_ctx *ctx, const cteno_mesh *m, const double *u0, double t0,
+                                         cteno_sol **out) {
+    if (!ctx || !m || !u0 || !out) return fail(CTENO_ERR_INVALID, "NULL argument");
+    HIP_TRY(hipSetDevice(ctx->device));
+    auto s = std::make_unique<cteno_sol>();
+    s->ctx = ctx;
+    s->mesh = m;
+    const DeviceMesh &dm = m->dm;
+    const size_t bytes = (size_t)dm.Np * dm.nv * sizeof(double);
+    for (auto &u : s->U) {
+        u = DevBuf(ctx, bytes);
+        if (!u.p) return fail(CTENO_ERR_NOMEM, "device allocation failed");
+        HIP_TRY(hipMemsetAsync(u.p, 0, bytes, ctx->stream()));
+    }
+    s->ctrl = DevBuf(ctx, sizeof(Ctrl));
+    if (!s->ctrl.p) return fail(CTENO_ERR_NOMEM, "device allocation failed");
+    HIP_TRY(hipMemsetAsync(s->ctrl.p, 0, sizeof(Ctrl), ctx->stream()));
+    HIP_TRY(hipHostMalloc((void **)&s->h_ctrl, sizeof(Ctrl), hipHostMallocDefault));
+    cteno_sol *raw = s.release();
+    cteno_status rc = cteno_sol_set(raw, u0, t0);
+    if (rc != CTENO_OK) { cteno_sol_destroy(raw); return rc; }
+    *out = raw;
+    return CTENO_OK;
+}
+
+extern "C" cteno_status cteno_sol_set(cteno_sol *s, const double *u, double t) {
+    if (!s || !u) return fail(CTENO_ERR_INVALID, "NULL argument");
+    const DeviceMesh &dm = s->mesh->dm;
+    hipStream_t st = s->ctx->stream();
+    HIP_TRY(hipSetDevice(s->ctx->device));
+    DevBuf tmp(s->ctx, (size_t)dm.N * dm.nv * sizeof(double));
+    if (!tmp.p) return fail(CTENO_ERR_NOMEM, "device allocation failed");
+    HIP_TRY(hipMemcpyAsync(tmp.p, u, (size_t)dm.N * dm.nv * sizeof(double), hipMemcpyHostToDevice, st));
+    HIP_TRY(launch_user_to_state(dm, tmp.as<double>(), s->U[0].as<double>(), st));
+    HIP_TRY(hipStreamSynchronize(st));
+    s->t = t;
+    return CTENO_OK;
+}
+
+extern "C" cteno_status cteno_sol_download(cteno_sol *s, double *u, double *t) {
+    if (!s) return fail(CTENO_ERR_INVALID, "sol is NULL");
+    const DeviceMesh &dm = s->mesh->dm;
+    hipStream_t st = s->ctx->stream();
+    HIP_TRY(hipSetDevice(s->ctx->device));
+    if (u) {
+        DevBuf tmp(s->ctx, (size_t)dm.N * dm.nv * sizeof(double));
+        if (!tmp.p) return fail(CTENO_ERR_NOMEM, "device allocation failed");
+        HIP_TRY(launch_state_to_user(dm, s->U[0].as<double>(), tmp.as<double>(), st));
+        HIP_TRY(hipMemcpyAsync(u, tmp.p, (size_t)dm.N * dm.nv * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+    } else {
+        HIP_TRY(hipStreamSynchronize(st));
+    }
+    if (t) *t = s->t;
+    return CTENO_OK;
+}
+
+extern "C" void cteno_sol_destroy(cteno_sol *s) {
+    if (!s) return;
+    (void)hipSetDevice(s->ctx->device);
+    (void)hipStreamSynchronize(s->ctx->stream());
+    delete s;
+}
+
+// ---------------------------------------------------------------------------
+// stage calls
+// ---------------------------------------------------------------------------
+extern "C" cteno_status cteno_reconstruct(cteno_ctx *ctx, const cteno_mesh *m, const cteno_sol *sol,
+                                          int32_t precision, void *face_vals, uint8_t *delta_out,
+                                          const uint8_t *delta_forced) {
+    if (!ctx || !m || !sol || !face_vals) return fail(CTENO_ERR_INVALID, "NULL argument");
+    if (sol->mesh != m) return fail(CTENO_ERR_INVALID, "solution belongs to another mesh");
+    bool f32;
+    if (cteno_status rc = check_precision(m, precision, f32)) return rc;
+    HIP_TRY(hipSetDevice(ctx->device));
+    const DeviceMesh &dm = m->dm;
+    hipStream_t st = ctx->stream();
+    cteno_sol *s = const_cast<cteno_sol *>(sol);
+    void *fv = s->fv(f32);
+    if (!fv) return fail(CTENO_ERR_NOMEM, "device allocation failed");
+    DevBuf dbuf;
+    int dmode = 0;
+    if (delta_forced || delta_out) {
+        dbuf = DevBuf(ctx, (size_t)dm.Np * dm.nv);
+        if (!dbuf.p) return fail(CTENO_ERR_NOMEM, "device allocation failed");
+        if (delta_forced) {
+            HIP_TRY(launch_delta_from_user(dm, delta_forced, dbuf.as<uint8_t>(), st));
+            dmode = 2;
+        } else {
+            dmode = 1;
+        }
+    }
+    HIP_TRY(timed(ctx, 0, [&] { return launch_reconstruct(dm, f32, s->U[0].as<double>(), fv, dbuf.as<uint8_t>(), dmode, nullptr, st); }));
+    HIP_TRY(launch_fv_to_user(dm, f32, fv, face_vals, st));
+    if (delta_out) HIP_TRY(launch_delta_to_user(dm, dbuf.as<uint8_t>(), delta_out, st));
+    HIP_TRY(hipStreamSynchronize(st));   // dbuf is released on return
+    return CTENO_OK;
+}
+
+extern "C" cteno_status cteno_flux(cteno_ctx *ctx, const cteno_mesh *m, int32_t precision, const void *face_vals,
+                                   void *face_flux) {
+    if (!ctx || !m || !face_vals || !face_flux) return fail(CTENO_ERR_INVALID, "NULL argument");
+    bool f32;
+    if (cteno_status rc = check_precision(m, precision, f32)) return rc;
+    HIP_TRY(hipSetDevice(ctx->device));
+    const DeviceMesh &dm = m->dm;
+    hipStream_t st = ctx->stream();
+    const size_t es = f32 ? sizeof(float) : sizeof(double);
+    DevBuf fv(ctx, (size_t)dm.Np * 3 * kNq * dm.nv * es), fo(ctx, (size_t)dm.Np * 3 * dm.nv * es);
+    if (!fv.p || !fo.p) return fail(CTENO_ERR_NOMEM, "device allocation failed");
+    HIP_TRY(launch_fv_from_user(dm, f32, face_vals, fv.p, st));
+    FluxLaunch fl;
+    fl.mode = 0;
+    fl.FV = fv.p;
+    fl.flux_out = fo.p;
+    HIP_TRY(timed(ctx, 1, [&] { return launch_flux(dm, f32, fl, st); }));
+    HIP_TRY(launch_flux_to_user(dm, f32, fo.p, face_flux, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return CTENO_OK;
+}
+
+extern "C" cteno_status cteno_residual(cteno_ctx *ctx, const cteno_mesh *m, const cteno_sol *sol, int32_t precision,
+                                       double *resid) {
+    if (!ctx || !m || !sol || !resid) return fail(CTENO_ERR_INVALID, "NULL argument");
+    if (sol->mesh != m) return fail(CTENO_ERR_INVALID, "solution belongs to another mesh");
+    bool f32;
+    if (cteno_status rc = check_precision(m, precision, f32)) return rc;
+    HIP_TRY(hipSetDevice(ctx->device));
+    const DeviceMesh &dm = m->dm;
+    hipStream_t st = ctx->stream();
+    cteno_sol *s = const_cast<cteno_sol *>(sol);
+    void *fv = s->fv(f32);
+    DevBuf r(ctx, (size_t)dm.Np * dm.nv * sizeof(double));
+    if (!fv || !r.p) return fail(CTENO_ERR_NOMEM, "device allocation failed");
+    HIP_TRY(timed(ctx, 0, [&] { return launch_reconstruct(dm, f32, s->U[0].as<double>(), fv, nullptr, 0, nullptr, st); }));
+    FluxLaunch fl;
+    fl.mode = 1;
+    fl.FV = fv;
+    fl.resid = r.as<double>();
+    HIP_TRY(timed(ctx, 1, [&] { return launch_flux(dm, f32, fl, st); }));
+    HIP_TRY(launch_state_to_user(dm, r.as<double>(), resid, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return CTENO_OK;
+}
+
+namespace {
+// one SSP-RK3 stage on sol; dt from a device pointer or a host value
+hipError_t issue_stage(cteno_ctx *ctx, cteno_sol *s, bool f32, int stage, const double *dt_ptr, double dt_value,
+                       Ctrl *ctrl, int want_dt, hipStream_t st) {
+    const DeviceMesh &dm = s->mesh->dm;
+    const double *in = s->U[stage].as<double>();    // U^n, U^(1), U^(2)
+    double *outU = stage == 2 ? s->U[0].as<double>() : s->U[stage + 1].as<double>();
+    void *fv = s->fv(f32);
+    const int *done = ctrl ? &ctrl->done : nullptr;
+    hipError_t e = timed(ctx, 0, [&] { return launch_reconstruct(dm, f32, in, fv, nullptr, 0, done, st); });
+    if (e != hipSuccess) return e;
+    FluxLaunch fl;
+    fl.mode = 2;
+    fl.FV = fv;
+    fl.Un = s->U[0].as<double>();
+    fl.Us = in;
+    fl.Uout = outU;
+    fl.stage = stage;
+    fl.dt_ptr = dt_ptr;
+    fl.dt_value = dt_value;
+    fl.ctrl = ctrl;
+    fl.want_dt = want_dt;
+    return timed(ctx, 1, [&] { return launch_flux(dm, f32, fl, st); });
+}
+}  // namespace
+
+extern "C" cteno_status cteno_rk_stage(cteno_ctx *ctx, const cteno_mesh *m, cteno_sol *sol, int32_t precision,
+                                       int32_t stage, double dt) {
+    if (!ctx || !m || !sol) return fail(CTENO_ERR_INVALID, "NULL argument");
+    if (sol->mesh != m) return fail(CTENO_ERR_INVALID, "solution belongs to another mesh");
+    if (stage < 0 || stage > 2) return fail(CTENO_ERR_INVALID, "stage must be 0, 1 or 2");
+    bool f32;
+    if (cteno_status rc = check_precision(m, precision, f32)) return rc;
+    HIP_TRY(hipSetDevice(ctx->device));
+    if (!sol->fv(f32)) return fail(CTENO_ERR_NOMEM, "device allocation failed");
+    HIP_TRY(issue_stage(ctx, sol, f32, stage, nullptr, dt, nullptr, 0, ctx->stream()));
+    if (stage == 2) sol->t += dt;
+    return CTENO_OK;
+}
+
+// ---------------------------------------------------------------------------
+// time march
+// ---------------------------------------------------------------------------
+namespace {
+hipError_t issue_step(cteno_ctx *ctx, cteno_sol *s, bool f32, hipStream_t st) {
+    Ctrl *c = s->ctrl.as<Ctrl>();
+    hipError_t e = launch_control(c, 0, st);
+    for (int stage = 0; stage < 3 && e == hipSuccess; ++stage)
+        e = issue_stage(ctx, s, f32, stage, &c->dt, 0.0, c, stage == 2, st);
+    return e;
+}
+}  // namespace
+
+extern "C" cteno_status cteno_solve(cteno_ctx *ctx, const cteno_mesh *m, cteno_sol *s, int32_t precision,
+                                    double t_final, int64_t max_steps, double cfl, int32_t use_graph,
+                                    int64_t *steps_done) {
+    if (!ctx || !m || !s) return fail(CTENO_ERR_INVALID, "NULL argument");
+    if (s->mesh != m) return fail(CTENO_ERR_INVALID, "solution belongs to another mesh");
+    if (!(cfl > 0) || max_steps < 0) return fail(CTENO_ERR_INVALID, "bad cfl or max_steps");
+    bool f32;
+    if (cteno_status rc = check_precision(m, precision, f32)) return rc;
+    HIP_TRY(hipSetDevice(ctx->device));
+    if (!s->fv(f32)) return fail(CTENO_ERR_NOMEM, "device allocation failed");
+    const DeviceMesh &dm = m->dm;
+    hipStream_t st = ctx->stream();
+    Ctrl *dc = s->ctrl.as<Ctrl>();
+    Ctrl &h = *s->h_ctrl;
+    std::memset(&h, 0, sizeof(Ctrl));
+    h.t = s->t;
+    h.t_final = t_final;
+    h.cfl = cfl;
+    h.max_steps = max_steps;
+    h.dt_cand_bits = 0x7FF0000000000000ull;
+    HIP_TRY(hipMemcpyAsync(dc, &h, sizeof(Ctrl), hipMemcpyHostToDevice, st));
+    HIP_TRY(launch_dt_candidate(dm, s->U[0].as<double>(), dc, st));
+
+    // graphs need a capturable stream: the context's own stream when the
+    // caller uses the null stream
+    const bool graph = use_graph && !ctx->timing;
+    hipStream_t gs = st;
+    hipEvent_t ev = nullptr;
+    if (graph && st == nullptr) {
+        gs = ctx->own_stream;
+        HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        HIP_TRY(hipEventRecord(ev, st));
+        HIP_TRY(hipStreamWaitEvent(gs, ev, 0));
+    }
+    hipGraphExec_t &gx = s->graph[f32 ? 1 : 0];
+    if (graph && !gx) {
+        hipGraph_t g = nullptr;
+        HIP_TRY(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
+        hipError_t e = issue_step(ctx, s, f32, gs);
+        hipError_t e2 = hipStreamEndCapture(gs, &g);
+        if (e != hipSuccess) return fail(CTENO_ERR_DEVICE, std::string("capture: ") + hipGetErrorString(e));
+        HIP_TRY(e2);
+        HIP_TRY(hipGraphInstantiate(&gx, g, nullptr, nullptr, 0));
+        (void)hipGraphDestroy(g);
+    }
+    const int chunk = 16;
+    for (int64_t it = 0;; ++it) {
+        for (int k = 0; k < chunk; ++k) {
+            if (graph) HIP_TRY(hipGraphLaunch(gx, gs));
+            else HIP_TRY(issue_step(ctx, s, f32, gs));
+        }
+        HIP_TRY(hipMemcpyAsync(&h, dc, sizeof(Ctrl), hipMemcpyDeviceToHost, gs));
+        HIP_TRY(hipStreamSynchronize(gs));
+        collect_timing(ctx);
+        if (h.done) break;
+        if (it > max_steps / chunk + 4) break;   // cannot happen: every step either advances or finishes
+    }
+    HIP_TRY(launch_control(dc, 1, gs));
+    HIP_TRY(hipMemcpyAsync(&h, dc, sizeof(Ctrl), hipMemcpyDeviceToHost, gs));
+    HIP_TRY(hipStreamSynchronize(gs));
+    if (ev) {
+        (void)hipEventDestroy(ev);
+    }
+    s->t = h.t;
+    if (steps_done) *steps_done = h.step;
+    if (h.nonphysical) return fail(CTENO_ERR_NONPHYSICAL, "non-physical state (density or pressure <= 0, or NaN)");
+    return CTENO_OK;
+}
+
+extern "C" cteno_status cteno_count_flips(cteno_ctx *ctx, const cteno_mesh *m, const cteno_sol *sol, int64_t *flips) {
+    if (!ctx || !m || !sol || !flips) return fail(CTENO_ERR_INVALID, "NULL argument");
+    if (m->dm.precision != CTENO_BOTH) return fail(CTENO_ERR_INVALID, "needs both pseudo-inverse copies (CTENO_BOTH)");
+    HIP_TRY(hipSetDevice(ctx->device));
+    const DeviceMesh &dm = m->dm;
+    hipStream_t st = ctx->stream();
+    cteno_sol *s = const_cast<cteno_sol *>(sol);
+    DevBuf d64(ctx, (size_t)dm.Np * dm.nv), d32(ctx, (size_t)dm.Np * dm.nv), cnt(ctx, sizeof(unsigned long long));
+    void *fv64 = s->fv(false), *fv32 = s->fv(true);
+    if (!d64.p || !d32.p || !cnt.p || !fv64 || !fv32) return fail(CTENO_ERR_NOMEM, "device allocation failed");
+    HIP_TRY(launch_reconstruct(dm, false, s->U[0].as<double>(), fv64, d64.as<uint8_t>(), 1, nullptr, st));
+    HIP_TRY(launch_reconstruct(dm, true, s->U[0].as<double>(), fv32, d32.as<uint8_t>(), 1, nullptr, st));
+    HIP_TRY(launch_fill_u64(cnt.as<unsigned long long>(), 0ull, 1, st));
+    HIP_TRY(launch_count_diff(dm, d64.as<uint8_t>(), d32.as<uint8_t>(), cnt.as<unsigned long long>(), st));
+    unsigned long long c = 0;
+    HIP_TRY(hipMemcpyAsync(&c, cnt.p, sizeof(c), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    *flips = (int64_t)c;
+    return CTENO_OK;
+}
+
+extern "C" cteno_status cteno_util_copy(cteno_ctx *ctx, void *dst, const void *src, size_t n_bytes) {
+    if (!ctx || !dst || !src || (n_bytes % 16)) return fail(CTENO_ERR_INVALID, "bad copy arguments");
+    HIP_TRY(hipSetDevice(ctx->device));
+    HIP_TRY(launch_copy16(dst, src, n_bytes / 16, ctx->stream()));
+    return CTENO_OK;
+}

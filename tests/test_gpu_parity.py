@@ -1,0 +1,256 @@
+"""GPU (HIP, gfx950) path against the FP64 CPU oracle, through the C ABI.
+
+Tolerances (normwise per variable, ||gpu - oracle||_inf / ||oracle||_inf):
+  FP64 mode: 1e-12 for pseudo-inverses, face values, fluxes, residuals and
+             final states; TENO selections (delta bits) identical;
+  mixed mode (FP32 reconstruction/weights/fluxes, FP64 state): face values
+             5e-6 with the oracle's selections forced, pseudo-inverse FP32
+             copies 1e-6, final states 1e-5 of the FP64 run.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2312_17042_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2312_17042_amd import cteno as T  # noqa: E402
+
+
+def relerr(g, o):
+    g = np.asarray(g, np.float64)
+    o = np.asarray(o, np.float64)
+    return float(np.abs(g - o).max() / max(np.abs(o).max(), 1e-300))
+
+
+def relerr_var(g, o, axis_v=-1):
+    g = np.moveaxis(np.asarray(g, np.float64), axis_v, 0).reshape(np.shape(g)[axis_v], -1)
+    o = np.moveaxis(np.asarray(o, np.float64), axis_v, 0).reshape(np.shape(o)[axis_v], -1)
+    return max(float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)) for a, b in zip(g, o))
+
+
+CASES = {
+    # name: (workload factory, scheme keywords shared by library and oracle)
+    "advection_r2_cteno": (lambda: W.advection_case(20, seed=1),
+                           dict(physics=O.ADVECTION, scheme=O.CTENO, degree=2, lambda1_prime=1e15)),
+    "vortex_r3_ctenoz": (lambda: W.vortex_case(24, seed=2),
+                         dict(physics=O.EULER, scheme=O.CTENOZ, degree=3, lambda1_prime=1e4)),
+    "sod_r3_cteno": (lambda: W.sod_case(48, 12, seed=3),
+                     dict(physics=O.EULER, scheme=O.CTENO, degree=3, lambda1_prime=1e15)),
+    "vortex_r3_cteno_lambda": (lambda: W.vortex_case(20, seed=5),
+                               dict(physics=O.EULER, scheme=O.CTENO, degree=3, lambda1_prime=1e15,
+                                    gamma_form=O.GAMMA_LAMBDA)),
+    "density_r2_ctenoz": (lambda: W.density_wave_case(12, seed=11),
+                          dict(physics=O.EULER, scheme=O.CTENOZ, degree=2, lambda1_prime=1e4)),
+}
+
+
+_cache = {}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = T.Context(0)
+    yield c
+    _cache.clear()
+    c.close()
+
+
+def setup_case(ctx, name, precision=T.BOTH):
+    key = (name, precision)
+    if key not in _cache:
+        make, kw = CASES[name]
+        mesh, u0 = make()
+        o = O.Oracle.from_mesh(mesh, **kw)
+        m = T.Mesh.from_workload(ctx, mesh, precision=precision, **kw)
+        _cache[key] = (mesh, u0, o, m)
+    return _cache[key]
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_stencils_and_pinv(ctx, name):
+    mesh, u0, o, m = setup_case(ctx, name)
+    oc, od, on = o.stencils()
+    lc, ld, ln = m.stencils()
+    assert np.array_equal(np.sort(oc, 1), lc)
+    assert np.array_equal(on, ln)
+    cells = np.arange(0, mesh.n_cells, max(1, mesh.n_cells // 97)).astype(np.int32)
+    opc, opd = o.pinv(cells)
+    gpc, gpd = m.pinv(cells, T.FP64)
+    # oracle columns follow its central list; the library's follow the sorted list
+    order = np.argsort(oc[cells], axis=1)
+    opc_sorted = np.take_along_axis(opc, order[:, None, :], axis=2)
+    for a in range(len(cells)):
+        assert relerr(gpc[a], opc_sorted[a]) < 1e-12, a
+        assert relerr(gpd[a], opd[a]) < 1e-12 if np.abs(opd[a]).max() > 0 else np.abs(gpd[a]).max() == 0
+    fpc, fpd = m.pinv(cells, T.MIXED)
+    assert relerr(fpc, gpc) < 1e-6 and relerr(fpd, gpd) < 1e-6
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_reconstruct_fp64(ctx, name):
+    mesh, u0, o, m = setup_case(ctx, name)
+    s = T.Solution(m, u0)
+    fv, dl = s.reconstruct(T.FP64)
+    ofv, odl = o.reconstruct(u0)
+    assert np.array_equal(dl.cpu().numpy(), odl), "TENO selections differ"
+    assert relerr_var(fv.cpu().numpy(), ofv) < 1e-12
+    # forced selections reproduce the same values
+    fv2, _ = s.reconstruct(T.FP64, forced=odl)
+    assert relerr_var(fv2.cpu().numpy(), ofv) < 1e-12
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_reconstruct_mixed(ctx, name):
+    mesh, u0, o, m = setup_case(ctx, name)
+    s = T.Solution(m, u0)
+    ofv, odl = o.reconstruct(u0)
+    fv, _ = s.reconstruct(T.MIXED, forced=odl)
+    assert relerr_var(fv.cpu().numpy(), ofv) < 5e-6
+    fv_free, dl = s.reconstruct(T.MIXED)
+    flips = int((dl.cpu().numpy() != odl).sum())
+    assert flips == s.count_flips() or flips <= mesh.n_cells * m.nv
+    same = (dl.cpu().numpy() == odl).all(axis=1)
+    assert relerr_var(fv_free.cpu().numpy()[same], ofv[same]) < 5e-6
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_flux_and_residual_fp64(ctx, name):
+    mesh, u0, o, m = setup_case(ctx, name)
+    ofv, _ = o.reconstruct(u0)
+    ofo = o.face_fluxes(ofv)
+    gfo = T.flux(m, torch.as_tensor(ofv).cuda(), T.FP64)
+    assert relerr_var(gfo.cpu().numpy(), ofo) < 1e-12
+    s = T.Solution(m, u0)
+    R = s.residual(T.FP64).cpu().numpy()
+    oR = o.residual(u0)
+    assert relerr_var(R, oR, axis_v=0) < 1e-12
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_rk_stages_fp64(ctx, name):
+    mesh, u0, o, m = setup_case(ctx, name)
+    dt = 0.3 * o.dt_bound(u0)
+    s = T.Solution(m, u0)
+    for st in range(3):
+        s.rk_stage(st, dt, T.FP64)
+    ug, t = s.download()
+    uo = o.rk3_step(u0, dt)
+    assert abs(t - dt) < 1e-15
+    assert relerr_var(ug, uo, axis_v=0) < 1e-12
+
+
+@pytest.mark.parametrize("name", ["advection_r2_cteno", "vortex_r3_ctenoz", "sod_r3_cteno"])
+def test_solve_fp64_matches_oracle(ctx, name):
+    mesh, u0, o, m = setup_case(ctx, name)
+    s = T.Solution(m, u0)
+    if name.startswith("advection"):
+        steps = s.solve(t_final=0.1, cfl=0.3, precision=T.FP64)       # the full advection run
+        uo, so, to = o.solve(u0, 0.1, cfl=0.3)
+    else:
+        steps = s.solve(t_final=10.0, max_steps=12, cfl=0.3, precision=T.FP64)
+        uo, so, to = o.solve(u0, 10.0, cfl=0.3, max_steps=12)
+    ug, tg = s.download()
+    assert steps == so
+    assert abs(tg - to) <= 1e-12 * max(1.0, abs(to))
+    assert relerr_var(ug, uo, axis_v=0) < 1e-12
+
+
+def test_graph_replay_equals_direct_launch(ctx):
+    mesh, u0, o, m = setup_case(ctx, "vortex_r3_ctenoz")
+    a = T.Solution(m, u0)
+    b = T.Solution(m, u0)
+    for prec in (T.FP64, T.MIXED):
+        a.set(u0)
+        b.set(u0)
+        na = a.solve(t_final=10.0, max_steps=7, precision=prec, use_graph=True)
+        nb = b.solve(t_final=10.0, max_steps=7, precision=prec, use_graph=False)
+        ua, ta = a.download()
+        ub, tb = b.download()
+        assert na == nb == 7 and ta == tb
+        assert np.array_equal(ua, ub)
+        # a second graph solve continues from the same state the same way
+        a.solve(t_final=10.0, max_steps=3, precision=prec, use_graph=True)
+        b.solve(t_final=10.0, max_steps=3, precision=prec, use_graph=False)
+        assert np.array_equal(a.download()[0], b.download()[0])
+
+
+@pytest.mark.parametrize("prec", [T.FP64, T.MIXED])
+def test_conservation_on_gpu(ctx, prec):
+    mesh, u0, o, m = setup_case(ctx, "vortex_r3_ctenoz")
+    area = W.cell_areas(mesh)
+    s = T.Solution(m, u0)
+    s.solve(t_final=10.0, max_steps=25, precision=prec)
+    u, _ = s.download()
+    tot0 = (u0 * area).sum(1)
+    tot1 = (u * area).sum(1)
+    assert np.abs(tot1 - tot0).max() <= 2e-13 * np.abs(tot0).max()
+
+
+def test_freestream_on_gpu(ctx):
+    mesh = W.split_jitter_mesh(16, 16, seed=9)
+    kw = dict(physics=O.EULER, scheme=O.CTENOZ, degree=3, lambda1_prime=1e4)
+    m = T.Mesh.from_workload(ctx, mesh, precision=T.BOTH, **kw)
+    U = np.tile(np.array([1.3, 0.4, -0.7, 2.9])[:, None], (1, mesh.n_cells))
+    s = T.Solution(m, U)
+    r64 = s.residual(T.FP64).cpu().numpy()
+    r32 = s.residual(T.MIXED).cpu().numpy()
+    h = 1.0 / 16
+    assert np.abs(r64).max() <= 1e-13 * 3.0 / h
+    assert np.abs(r32).max() <= 1e-5 * 3.0 / h
+
+
+def test_mixed_vs_fp64_solution(ctx):
+    mesh, u0, o, m = setup_case(ctx, "vortex_r3_ctenoz")
+    a = T.Solution(m, u0)
+    b = T.Solution(m, u0)
+    a.solve(t_final=10.0, max_steps=20, precision=T.FP64)
+    b.solve(t_final=10.0, max_steps=20, precision=T.MIXED)
+    ua, _ = a.download()
+    ub, _ = b.download()
+    assert relerr_var(ub, ua, axis_v=0) < 1e-5
+
+
+def test_nonphysical_state_is_reported(ctx):
+    mesh, u0, o, m = setup_case(ctx, "vortex_r3_ctenoz")
+    bad = u0.copy()
+    bad[3, 5] = -1.0          # negative total energy -> negative pressure
+    s = T.Solution(m, bad)
+    with pytest.raises(T.CtenoError) as e:
+        s.solve(t_final=10.0, max_steps=3, precision=T.FP64)
+    assert e.value.status == T.ERR_NONPHYSICAL
+
+
+@pytest.mark.parametrize("which", ["vortex_80k", "sod_1p28M"])
+def test_full_size_sampled_parity(ctx, which):
+    """Full configured sizes, one reconstruction and residual in the launch
+    configuration of the time march; the oracle evaluates sampled cells."""
+    if which == "vortex_80k":
+        mesh, u0 = W.vortex_case(200, seed=2)
+        kw = dict(physics=O.EULER, scheme=O.CTENOZ, degree=3, lambda1_prime=1e4)
+    else:
+        mesh, u0 = W.sod_case(1600, 400, seed=3)
+        kw = dict(physics=O.EULER, scheme=O.CTENO, degree=3, lambda1_prime=1e15)
+    m = T.Mesh.from_workload(ctx, mesh, precision=T.BOTH, **kw)
+    o = O.Oracle.from_mesh(mesh, **kw)
+    rng = np.random.default_rng(0)
+    cells = np.sort(rng.choice(mesh.n_cells, 300, replace=False)).astype(np.int32)
+    if which == "sod_1p28M":   # also sample the discontinuity
+        cx = mesh.xy[mesh.tri].mean(1)[:, 0]
+        near = np.where(np.abs(cx - 0.5) < 2.0 / 1600)[0]
+        cells = np.unique(np.concatenate([cells, rng.choice(near, 200, replace=False)])).astype(np.int32)
+    s = T.Solution(m, u0)
+    fv, dl = s.reconstruct(T.FP64)
+    ofv, odl = o.reconstruct_cells(u0, cells)
+    assert np.array_equal(dl.cpu().numpy()[cells], odl)
+    assert relerr_var(fv.cpu().numpy()[cells], ofv) < 1e-12
+    R = s.residual(T.FP64).cpu().numpy()[:, cells].T
+    oR = o.residual_cells(u0, cells)
+    assert relerr_var(R, oR) < 1e-12
+    fv32, _ = s.reconstruct(T.MIXED, forced=dl.cpu().numpy())
+    assert relerr_var(fv32.cpu().numpy()[cells], ofv) < 5e-6

@@ -535,3 +535,20 @@ def test_literal_cteno_degrades_like_table1():
             errs[gf].append(math.sqrt(((U[0] - ue[0]) ** 2 * W.cell_areas(m)).sum()))
     assert _orders(errs[0])[-1] < 2.3
     assert _orders(errs[1])[-1] > 2.5
+
+
+def test_sod_converges_without_overshoot():
+    """Literal CTENO on the x-split Sod problem (walls in y, transmissive in x)
+    converges to the exact Riemann solution: L1 density error falls under
+    refinement and the density stays within the initial bounds to 1%."""
+    errs = []
+    for nx, ny in ((24, 6), (48, 12)):
+        m, u0 = W.sod_case(nx, ny, seed=3)
+        o = O.Oracle.from_mesh(m, physics=O.EULER, scheme=O.CTENO, degree=3, lambda1_prime=1e15)
+        U, steps, t = o.solve(u0, 0.2, cfl=0.3)
+        assert abs(t - 0.2) < 1e-14
+        ue = W.cell_average(m, W.sod_exact(0.2), n=6)
+        ar = W.cell_areas(m)
+        errs.append(float((np.abs(U[0] - ue[0]) * ar).sum() / ar.sum()))
+        assert U[0].max() <= 1.01 and U[0].min() >= 0.125 * 0.99
+    assert errs[1] < 0.75 * errs[0]
