@@ -1,0 +1,186 @@
+"""Throughput benchmark: cell-stage updates/s of the CTENOZ hot path on one MI355X.
+
+Workload: isentropic vortex (strength 5, centred at (5,5)) on the periodic
+[0,10]^2 box, 2000 x 2000 squares split into 8,000,000 jittered triangles
+(seed 5), cubic CTENOZ (lambda1' = 1e4), SSP-RK3 at CFL 0.3.  The mixed
+path (FP32 reconstruction / weights / HLLC, FP64 state and update) gives
+`value`; the all-FP64 path is reported beside it, with the error of each
+against the exact solution and against each other, and the TENO-cutoff
+flip count.  Inputs are resident in HBM before the timed region.
+
+Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 2]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per cell and stage of the dominant kernel (reconstruction):
+# pseudo-inverses (162 central + 24 directional entries), 18 slot indices,
+# 1 flag byte, the cell's FP64 state (4 x 8) and its 24 face-point values
+RECON_BYTES = {"mixed": 162 * 4 + 24 * 4 + 18 * 4 + 1 + 32 + 24 * 4,
+               "fp64": 162 * 8 + 24 * 8 + 18 * 4 + 1 + 32 + 24 * 8}
+# flux + residual + RK kernel: own face values, neighbour codes, face
+# geometry, area, U^n / stage input / output
+FLUX_BYTES = {"mixed": 24 * 4 + 12 + 9 * 4 + 8 + 3 * 32,
+              "fp64": 24 * 8 + 12 + 9 * 8 + 8 + 3 * 32}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def run_precision(T, ctx, mesh, sol, u0, prec, steps, warmup):
+    import torch
+    sol.set(u0, 0.0)
+    # warm-up: also captures the step graph
+    sol.solve(max_steps=warmup, cfl=0.3, precision=prec, use_graph=True)
+    ctx.set_timing(True)
+    ctx.reset_stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n = sol.solve(max_steps=steps, cfl=0.3, precision=prec, use_graph=False)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    kr = ctx.kernel_stats(T.KERNEL_RECONSTRUCT)
+    kf = ctx.kernel_stats(T.KERNEL_FLUX)
+    ctx.set_timing(False)
+    assert n == steps, (n, steps)
+    u, t = sol.download()
+    return dict(elapsed=el, recon=kr, flux=kf, u=u, t=t)
+
+
+def cpu_baseline(W):
+    """The FP64 oracle on a bounded sample of the same workload family."""
+    import oracle as O
+    n = 400
+    mesh, u0 = W.vortex_case(n, seed=5)
+    o = O.Oracle.from_mesh(mesh, physics=O.EULER, scheme=O.CTENOZ, degree=3, lambda1_prime=1e4)
+    o.prepare()                      # stencils + least-squares factors: excluded, as on the GPU
+    dt = 0.3 * o.dt_bound(u0)
+    steps = 2
+    t0 = time.perf_counter()
+    U = u0
+    for _ in range(steps):
+        U = o.rk3_step(U, dt)
+    el = time.perf_counter() - t0
+    return {"value": mesh.n_cells * 3 * steps / el, "unit": "cell-stage updates/s", "cores": O.threads(),
+            "kind": "oracle",
+            "sample": f"isentropic vortex on {n}x{n} split/jittered periodic [0,10]^2 ({mesh.n_cells} cells, same "
+                      f"per-cell work as the 8M-cell case), cubic CTENOZ FP64, {steps} SSP-RK3 steps, "
+                      f"{el:.2f} s wall, precompute excluded"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=2000, help="squares per side (2000 -> 8M cells)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); multi-GPU sharding is a design "
+              f"note, not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2312_17042_amd import cteno as T
+    from paper_2312_17042_amd import workloads as W
+
+    t0 = time.perf_counter()
+    mesh = W.split_jitter_mesh(args.n, args.n, (0.0, 10.0, 0.0, 10.0), seed=5)
+    u0 = W.cell_average(mesh, W.isentropic_vortex(0.0), n=3)
+    log(f"mesh {mesh.n_cells} cells, initial data {time.perf_counter() - t0:.1f}s")
+
+    ctx = T.Context(0)
+    t0 = time.perf_counter()
+    m = T.Mesh.from_workload(ctx, mesh, physics=T.EULER, scheme=T.CTENOZ, degree=3, lambda1_prime=1e4,
+                             precision=T.BOTH)
+    log(f"upload + FP64 precompute {time.perf_counter() - t0:.1f}s, device bytes {m.info.device_bytes / 1e9:.2f} GB")
+    sol = T.Solution(m, u0)
+    N = mesh.n_cells
+
+    res = {}
+    precs = [("mixed", T.MIXED)] + ([] if args.no_fp64 else [("fp64", T.FP64)])
+    for name, prec in precs:
+        log(f"timing {name}: {args.warmup} warm-up + {args.steps} steps")
+        r = run_precision(T, ctx, m, sol, u0, prec, args.steps, args.warmup)
+        r["value"] = N * 3 * args.steps / r["elapsed"]
+        res[name] = r
+        log(f"{name}: {r['value']:.3e} cell-stage/s, {1e3 * r['elapsed'] / args.steps:.3f} ms/step, "
+            f"recon {r['recon'][1] / max(1, r['recon'][0]):.3f} ms/launch, flux {r['flux'][1] / max(1, r['flux'][0]):.3f} ms/launch")
+
+    # accuracy at the end of the timed run, on a sample of cells
+    mx = res["mixed"]
+    sample = np.arange(0, N, 97)
+    T_end = mx["t"]
+    sub = W.Mesh(mesh.xy, mesh.tri[sample], mesh.box, mesh.bc, mesh.nx, mesh.ny, mesh.seed)
+    ue = W.cell_average(sub, W.isentropic_vortex(T_end), n=4)
+    err = {"t_end": T_end, "mixed_vs_exact_rho_linf": float(np.abs(mx["u"][0, sample] - ue[0]).max())}
+    if "fp64" in res:
+        f = res["fp64"]
+        err["fp64_vs_exact_rho_linf"] = float(np.abs(f["u"][0, sample] - ue[0]).max())
+        err["mixed_vs_fp64_rel_linf"] = float(np.abs(mx["u"] - f["u"]).max() / np.abs(f["u"]).max())
+        sol.set(mx["u"], T_end)
+        err["teno_flips_fp32_vs_fp64"] = int(sol.count_flips())
+        err["flip_unit"] = "cells x variables, final mixed state"
+
+    nrec, msrec = mx["recon"]
+    avg_ms = msrec / max(1, nrec)
+    achieved = RECON_BYTES["mixed"] * N / (avg_ms * 1e-3) / 1e9
+    nfl, msfl = mx["flux"]
+    avg_fl = msfl / max(1, nfl)
+    out = {
+        "metric": "cell-stage updates/s (mixed FP32 vs FP64) at stated error; serving p50/p99",
+        "value": mx["value"],
+        "unit": "cell-stage updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * mx["elapsed"] / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32/f64 mixed",
+        "data": "synthetic",
+        "config": {"workload": f"isentropic vortex, {args.n}x{args.n} split/jittered periodic [0,10]^2 "
+                               f"({N} cells), cubic CTENOZ lambda1'=1e4, SSP-RK3 CFL 0.3",
+                   "cells": N, "scheme": "CTENOZ", "degree": 3, "precision": "mixed"},
+        "error": err,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_reconstruct (FP32)", "bytes_per_cell": RECON_BYTES["mixed"],
+                     "avg_launch_ms": avg_ms},
+        "kernels": {"reconstruct_ms": avg_ms, "flux_rk_ms": avg_fl,
+                    "flux_rk_GBs": FLUX_BYTES["mixed"] * N / (avg_fl * 1e-3) / 1e9},
+    }
+    if "fp64" in res:
+        f = res["fp64"]
+        n64, ms64 = f["recon"]
+        a64 = ms64 / max(1, n64)
+        nf64, msf64 = f["flux"]
+        out["fp64"] = {"value": f["value"], "ms_per_step": 1e3 * f["elapsed"] / args.steps,
+                       "reconstruct_ms": a64, "flux_rk_ms": msf64 / max(1, nf64),
+                       "reconstruct_GBs": RECON_BYTES["fp64"] * N / (a64 * 1e-3) / 1e9}
+        out["mixed_over_fp64"] = mx["value"] / f["value"]
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(W)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -29,7 +29,23 @@ inline int dims_S(int r) { return dims_M(r) > 3 * kDirSlots ? dims_M(r) : 3 * kD
 __host__ __device__ inline size_t tix(int64_t i, int e, int E) {
     return ((size_t)(i >> 6) * E + e) * kTile + (i & 63);
 }
+// vector-tiled index (array of structures of arrays): entries are grouped in
+// vectors of VW consecutive entries per cell, vectors tiled like tix; a lane
+// reads VW entries with one 16-byte load and a wave reads 1 KiB contiguously.
+// E must be a multiple of VW.  Returns the scalar index of entry e.
+__host__ __device__ inline size_t avix(int64_t i, int e, int E, int VW) {
+    return ((((size_t)(i >> 6) * (E / VW) + e / VW) * kTile + (i & 63)) * VW) + (e % VW);
+}
 inline int64_t pad64(int64_t n) { return (n + kTile - 1) / kTile * kTile; }
+inline int round_up(int a, int b) { return (a + b - 1) / b * b; }
+
+// pseudo-inverse stream of one cell, consumed slot by slot: for slot j the K
+// central entries P_c[k][j], then (j < 12) the two directional entries
+// P_d[j/4][c][j%4]
+__host__ __device__ constexpr int pinv_offset(int j, int K) {
+    return j <= 12 ? j * (K + 2) : 12 * (K + 2) + (j - 12) * K;
+}
+inline int pinv_entries(int r) { return pinv_offset(dims_S(r), dims_K(r)); }
 
 // neighbour code per cell face: bit 31 set = boundary (bits 0..1 = kind),
 // else bits 0..27 neighbour (internal index), 28..29 neighbour's local
@@ -54,17 +70,16 @@ struct HostMesh {
     std::vector<int32_t> dir_user;     // [N][3][4] user ids, -1 padded
     std::vector<int32_t> dirn_user;    // [N][3]
     // internal-order device inputs
-    std::vector<int32_t> slot;         // tiled [S]: internal cell index (self for pads)
+    int SP = 0;                        // slots padded to a multiple of 4
+    std::vector<int32_t> slot;         // vector-tiled [SP] (VW 4): internal cell index (self for pads)
     std::vector<uint8_t> slot_flag;    // tiled [S]: bit0 central member, bit1 directional member
     std::vector<int8_t> slot_shift;    // tiled [2*S]: periodic image shift (x then y)
     std::vector<uint8_t> flags;        // [Npad]: bit s = directional stencil of face s admissible
     std::vector<double> verts;         // tiled [6]: CCW vertex coordinates x0,y0,x1,y1,x2,y2
-    std::vector<uint32_t> nb;          // tiled [3]
-    std::vector<double> fgeo;          // tiled [9]: (nx, ny, len) per local face
+    // face records: per local face (nx, ny, |A|, neighbour code), vector-tiled
+    std::vector<double> fr64;          // [12] entries, VW 2; code stored in the low bits of the double
+    std::vector<float> fr32;           // [12] entries, VW 4; code stored as the float's bits
     std::vector<double> area;          // [Npad]
-    // slot column -> position in the user-order stencil lists (for cteno_mesh_pinv)
-    std::vector<int8_t> slot_cen_pos;  // tiled [S]: index into cen_user row, -1 for pads
-    std::vector<int8_t> slot_dir_pos;  // tiled [S]: index into dir_user row of its sector, -1 if none
 };
 
 // returns CTENO_OK or an error (message in err)

@@ -7,25 +7,25 @@ namespace cteno {
 
 struct DeviceMesh {
     int64_t N = 0, Np = 0;
-    int r = 0, K = 0, S = 0, nv = 0, physics = 0;
+    int r = 0, K = 0, S = 0, SP = 0, nv = 0, physics = 0;
     int scheme = 0, gamma_form = 0, precision = 0;
+    int E64 = 0, E32 = 0;          // pseudo-inverse entries per cell (padded to the vector width)
     double gamma = 1.4, ax = 0, ay = 0, lam1p = 1e4, ct = 1e-6, eps = 1e-12;
     double Lx = 0, Ly = 0;
-    int32_t *slot = nullptr;      // tiled [S]
-    uint8_t *flags = nullptr;     // [Np]
-    uint32_t *nb = nullptr;       // tiled [3]
-    double *fgeo64 = nullptr;     // tiled [9]
-    float *fgeo32 = nullptr;      // tiled [9]
-    double *area = nullptr;       // [Np]
-    double *Pc64 = nullptr, *Pd64 = nullptr;   // tiled [K*S], [24]
-    float *Pc32 = nullptr, *Pd32 = nullptr;
-    int32_t *perm = nullptr;      // internal -> user [N]
+    int32_t *slot = nullptr;       // vector-tiled [SP], VW 4
+    uint8_t *flags = nullptr;      // [Np]
+    double *fr64 = nullptr;        // face records, vector-tiled [12], VW 2
+    float *fr32 = nullptr;         // face records, vector-tiled [12], VW 4
+    double *area = nullptr;        // [Np]
+    double *P64 = nullptr;         // pseudo-inverse stream, vector-tiled [E64], VW 2
+    float *P32 = nullptr;          // pseudo-inverse stream, vector-tiled [E32], VW 4
+    int32_t *perm = nullptr;       // internal -> user [N]
     RefTables tab;
+    int64_t blocks() const { return (N + 255) / 256; }
 };
 
 struct PrecomputeInputs {
     const double *verts;          // tiled [6]
-    const int32_t *slot;          // tiled [S]
     const uint8_t *slot_flag;     // tiled [S]
     const int8_t *slot_shift;     // tiled [2S]
     uint8_t *flags;               // [Np] in/out: inadmissible-by-rank bits cleared
@@ -49,13 +49,15 @@ struct FluxLaunch {
     double dt_value = 0.0;
     void *flux_out = nullptr;    // AoS [Np][3][nv] of the precision type
     double *resid = nullptr;     // AoS [Np][nv]
-    Ctrl *ctrl = nullptr;        // done / nonphysical / dt candidate (may be null)
-    int want_dt = 0;
+    Ctrl *ctrl = nullptr;        // done / nonphysical (may be null)
+    double *dt_part = nullptr;   // per-block minima of the CFL bound (stage 2 of a march), or null
 };
 hipError_t launch_flux(const DeviceMesh &m, bool fp32, const FluxLaunch &f, hipStream_t st);
 
-hipError_t launch_dt_candidate(const DeviceMesh &m, const double *U, Ctrl *ctrl, hipStream_t st);
-hipError_t launch_control(Ctrl *ctrl, int commit_only, hipStream_t st);
+// per-block minima of the CFL bound of state U into dt_part[blocks()]
+hipError_t launch_dt_partials(const DeviceMesh &m, const double *U, double *dt_part, hipStream_t st);
+// step control; reduces dt_part[n_part] unless commit_only
+hipError_t launch_control(Ctrl *ctrl, const double *dt_part, int64_t n_part, int commit_only, hipStream_t st);
 
 // layout conversions between caller order/layout and internal order/layout
 hipError_t launch_user_to_state(const DeviceMesh &m, const double *user, double *state, hipStream_t st);
@@ -68,10 +70,9 @@ hipError_t launch_delta_from_user(const DeviceMesh &m, const uint8_t *user, uint
 hipError_t launch_count_diff(const DeviceMesh &m, const uint8_t *a, const uint8_t *b, unsigned long long *count,
                              hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, size_t n, hipStream_t st);
-hipError_t launch_to_fp32(const double *src, float *dst, size_t n, hipStream_t st);
 hipError_t launch_copy16(void *dst, const void *src, size_t n16, hipStream_t st);
-// dst[a][e] = src[tiled(idx[a], e, E)] from exactly one of src64 / src32 / srci
-hipError_t launch_gather_tiled(int n, const int32_t *idx, int E, const double *src64, const float *src32,
-                               const int32_t *srci, double *dst, hipStream_t st);
+// dst[a][e] = src[avix(idx[a], e, E, VW)] from exactly one of src64 / src32 / srci
+hipError_t launch_gather_entries(int n, const int32_t *idx, int E, int VW, const double *src64, const float *src32,
+                                 const int32_t *srci, double *dst, hipStream_t st);
 
 }  // namespace cteno

@@ -34,6 +34,69 @@
 namespace cteno {
 
 // ===========================================================================
+// small helpers
+// ===========================================================================
+
+template <typename real> struct Vec;
+template <> struct Vec<float> { using T = float4; static constexpr int W = 4; };
+template <> struct Vec<double> { using T = double2; static constexpr int W = 2; };
+
+__device__ __forceinline__ float comp(const float4 &v, int c) { return c == 0 ? v.x : c == 1 ? v.y : c == 2 ? v.z : v.w; }
+__device__ __forceinline__ double comp(const double2 &v, int c) { return c == 0 ? v.x : v.y; }
+__device__ __forceinline__ int comp(const int4 &v, int c) { return c == 0 ? v.x : c == 1 ? v.y : c == 2 ? v.z : v.w; }
+
+// n consecutive reals from/to an aligned address with the widest vector the
+// row size allows (16 bytes, else 8 bytes)
+template <typename real, int n>
+__device__ __forceinline__ void load_row(const real *__restrict__ p, real *out) {
+    if constexpr ((n * sizeof(real)) % 16 == 0) {
+        using V = typename Vec<real>::T;
+        constexpr int W = Vec<real>::W;
+#pragma unroll
+        for (int k = 0; k < n / W; ++k) {
+            const V v = reinterpret_cast<const V *>(p)[k];
+#pragma unroll
+            for (int c = 0; c < W; ++c) out[k * W + c] = comp(v, c);
+        }
+    } else {
+        static_assert(std::is_same<real, float>::value && n % 2 == 0, "row must be a multiple of 8 bytes");
+#pragma unroll
+        for (int k = 0; k < n / 2; ++k) {
+            const float2 v = reinterpret_cast<const float2 *>(p)[k];
+            out[2 * k] = v.x;
+            out[2 * k + 1] = v.y;
+        }
+    }
+}
+template <typename real, int n>
+__device__ __forceinline__ void store_row(real *__restrict__ p, const real *in) {
+    if constexpr ((n * sizeof(real)) % 16 == 0) {
+        if constexpr (std::is_same<real, float>::value) {
+#pragma unroll
+            for (int k = 0; k < n / 4; ++k)
+                reinterpret_cast<float4 *>(p)[k] = make_float4(in[4 * k], in[4 * k + 1], in[4 * k + 2], in[4 * k + 3]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < n / 2; ++k) reinterpret_cast<double2 *>(p)[k] = make_double2(in[2 * k], in[2 * k + 1]);
+        }
+    } else {
+        static_assert(std::is_same<real, float>::value && n % 2 == 0, "row must be a multiple of 8 bytes");
+#pragma unroll
+        for (int k = 0; k < n / 2; ++k) reinterpret_cast<float2 *>(p)[k] = make_float2(in[2 * k], in[2 * k + 1]);
+    }
+}
+
+// Work-groups are dispatched round-robin over the 8 XCDs; remap them so that
+// each XCD (and its L2) works on one contiguous range of cells, which keeps
+// the neighbour gathers of adjacent blocks in the same L2.
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
+    if (nb < 8) return b;
+    const int64_t per = nb / 8, rem = nb % 8;
+    const int64_t x = b % 8, pos = b / 8;
+    return x < rem ? x * (per + 1) + pos : rem * (per + 1) + (x - rem) * per + pos;
+}
+
+// ===========================================================================
 // precompute (FP64)
 // ===========================================================================
 
@@ -46,6 +109,7 @@ struct PreArgs {
     static constexpr int K = (R + 1) * (R + 2) / 2 - 1;
     static constexpr int M = 2 * K;
     static constexpr int S = M > 12 ? M : 12;
+    static constexpr int SP = (S + 3) / 4 * 4;
     int64_t N;
     const double *verts;
     const int32_t *slot;
@@ -53,8 +117,9 @@ struct PreArgs {
     const int8_t *slot_shift;
     uint8_t *flags;
     int *rank_fail;
-    double *Pc64, *Pd64;
-    float *Pc32, *Pd32;
+    double *P64;
+    float *P32;
+    int E64, E32;
     double Lx, Ly;
     int ex[K][2];
     double mean[K];
@@ -65,11 +130,16 @@ template <int R>
 __global__ __launch_bounds__(64) void k_precompute(const PreArgs<R> a) {
     constexpr int K = PreArgs<R>::K;
     constexpr int S = PreArgs<R>::S;
+    constexpr int SP = PreArgs<R>::SP;
     __shared__ double sA[K * S][64];      // least-squares matrix, column-major, one column of lanes per cell
     __shared__ double sQ[3][K][64];       // Householder v0, beta, and diag(R)
     const int lane = threadIdx.x;
     const int64_t i = (int64_t)blockIdx.x * 64 + lane;
     if (i >= a.N) return;                 // lanes only touch their own LDS column: no barriers needed
+    auto put = [&](int e, double v) {
+        a.P64[avix(i, e, a.E64, 2)] = v;
+        if (a.P32) a.P32[avix(i, e, a.E32, 4)] = (float)v;
+    };
 
     const double x0 = a.verts[tix(i, 0, 6)], y0 = a.verts[tix(i, 1, 6)];
     const double ja = a.verts[tix(i, 2, 6)] - x0, jc = a.verts[tix(i, 3, 6)] - y0;
@@ -86,7 +156,7 @@ __global__ __launch_bounds__(64) void k_precompute(const PreArgs<R> a) {
         for (int k = 0; k < K; ++k) row[k] = 0.0;
         double w = 0.0;
         if (fl & 1) {
-            const int64_t m = a.slot[tix(i, j, S)];
+            const int64_t m = a.slot[avix(i, j, SP, 4)];
             const double sx = a.slot_shift[tix(i, 2 * j, 2 * S)] * a.Lx;
             const double sy = a.slot_shift[tix(i, 2 * j + 1, 2 * S)] * a.Ly;
             double X[3], Y[3];
@@ -181,12 +251,9 @@ __global__ __launch_bounds__(64) void k_precompute(const PreArgs<R> a) {
             for (int k2 = j + 1; k2 < K; ++k2) s -= sA[k2 * S + j][lane] * x[k2];
             x[j] = s / sQ[2][j][lane];
         }
+        const int off = pinv_offset(m, K);
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const double v = rank_ok ? x[k] : 0.0;
-            a.Pc64[tix(i, k * S + m, K * S)] = v;
-            if (a.Pc32) a.Pc32[tix(i, k * S + m, K * S)] = (float)v;
-        }
+        for (int k = 0; k < K; ++k) put(off + k, rank_ok ? x[k] : 0.0);
     }
 
     // directional 4 x 2 systems in registers
@@ -241,13 +308,9 @@ __global__ __launch_bounds__(64) void k_precompute(const PreArgs<R> a) {
             }
             const double x1 = ok ? b[1] / rd[1] : 0.0;
             const double x0v = ok ? (b[0] - A[0][1] * x1) / rd[0] : 0.0;
-            const int e0 = (s * 2 + 0) * 4 + m, e1 = (s * 2 + 1) * 4 + m;
-            a.Pd64[tix(i, e0, kPdEntries)] = x0v;
-            a.Pd64[tix(i, e1, kPdEntries)] = x1;
-            if (a.Pd32) {
-                a.Pd32[tix(i, e0, kPdEntries)] = (float)x0v;
-                a.Pd32[tix(i, e1, kPdEntries)] = (float)x1;
-            }
+            const int off = pinv_offset(4 * s + m, K) + K;
+            put(off, x0v);
+            put(off + 1, x1);
         }
     }
     a.flags[i] = fl;
@@ -277,9 +340,9 @@ template <int R>
 static hipError_t precompute_r(const DeviceMesh &m, const PrecomputeInputs &in, hipStream_t st) {
     PreArgs<R> a;
     a.N = m.N;
-    a.verts = in.verts; a.slot = in.slot; a.slot_flag = in.slot_flag; a.slot_shift = in.slot_shift;
+    a.verts = in.verts; a.slot = m.slot; a.slot_flag = in.slot_flag; a.slot_shift = in.slot_shift;
     a.flags = in.flags; a.rank_fail = in.rank_fail;
-    a.Pc64 = m.Pc64; a.Pd64 = m.Pd64; a.Pc32 = m.Pc32; a.Pd32 = m.Pd32;
+    a.P64 = m.P64; a.P32 = m.P32; a.E64 = m.E64; a.E32 = m.E32;
     a.Lx = m.Lx; a.Ly = m.Ly;
     for (int k = 0; k < PreArgs<R>::K; ++k) {
         a.ex[k][0] = m.tab.ex[k][0];
@@ -320,14 +383,27 @@ __device__ __forceinline__ real pow6(real x) {
     return x2 * x2 * x2;
 }
 
+// d[v] = U[m][v] - U0[v], rounded to the working precision
+template <int NV, typename real>
+__device__ __forceinline__ void gather_diff(const double *__restrict__ U, int64_t m, const double *U0, real *d) {
+    if constexpr (NV == 4) {
+        const double2 u01 = reinterpret_cast<const double2 *>(U)[2 * m];
+        const double2 u23 = reinterpret_cast<const double2 *>(U)[2 * m + 1];
+        d[0] = (real)(u01.x - U0[0]); d[1] = (real)(u01.y - U0[1]);
+        d[2] = (real)(u23.x - U0[2]); d[3] = (real)(u23.y - U0[3]);
+    } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) d[v] = (real)(U[m * NV + v] - U0[v]);
+    }
+}
+
 template <typename real, int K>
 struct ReconArgs {
     int64_t N;
     const double *U;        // AoS [Np][NV]
-    const int32_t *slot;    // tiled [S]
+    const int32_t *slot;    // vector-tiled [SP], VW 4
     const uint8_t *flags;   // [Np]
-    const real *Pc;         // tiled [K*S]
-    const real *Pd;         // tiled [24]
+    const real *P;          // vector-tiled pseudo-inverse stream
     real *FV;               // AoS [Np][3][2][NV]
     uint8_t *delta;         // AoS [Np][NV]
     const int *done;
@@ -424,9 +500,17 @@ __global__ __launch_bounds__(256) void k_reconstruct(const ReconArgs<real, (R + 
     constexpr int K = (R + 1) * (R + 2) / 2 - 1;
     constexpr int M = 2 * K;
     constexpr int S = M > 12 ? M : 12;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    constexpr int SP = (S + 3) / 4 * 4;
+    using V = typename Vec<real>::T;
+    constexpr int VW = Vec<real>::W;
+    constexpr int E = (pinv_offset(S, K) + VW - 1) / VW * VW;
+    const int64_t i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= a.N) return;
     if (a.done && *a.done) return;
+
+    // this cell's streams: vector g of the pseudo-inverse at Pv[g * 64]
+    const V *__restrict__ Pv = reinterpret_cast<const V *>(a.P) + (size_t)(i >> 6) * (E / VW) * 64 + (i & 63);
+    const int4 *__restrict__ Sv = reinterpret_cast<const int4 *>(a.slot) + (size_t)(i >> 6) * (SP / 4) * 64 + (i & 63);
 
     double U0[NV];
 #pragma unroll
@@ -444,43 +528,86 @@ __global__ __launch_bounds__(256) void k_reconstruct(const ReconArgs<real, (R + 
 #pragma unroll
             for (int v = 0; v < NV; ++v) ad[s][c][v] = 0;
 
-    // directional groups: slots 4s .. 4s+3 feed both the central product and
-    // the directional product of face s
+    // a_opt = P_c d and a_s = P_s d.  Slots 4s..4s+3 (directional group s)
+    // hold K central and 2 directional entries each: 4 (K + 2) entries, a
+    // whole number of vectors, loaded at once per group; then the remaining
+    // slots with K central entries each.
+    constexpr int GE = 4 * (K + 2);
+    constexpr int GV = GE / VW;
+    // all slot indices up front, so each group's gathers issue with its loads
+    int4 slv[SP / 4];
 #pragma unroll
-    for (int s = 0; s < 3; ++s) {
+    for (int g = 0; g < SP / 4; ++g) slv[g] = Sv[g * 64];
 #pragma unroll 1
+    for (int s = 0; s < 3; ++s) {
+        int4 sl = slv[0];
+#pragma unroll
+        for (int s2 = 1; s2 < 3; ++s2)
+            if (s2 == s) sl = slv[s2];
+        V pv[GV];
+#pragma unroll
+        for (int g = 0; g < GV; ++g) pv[g] = Pv[(s * GV + g) * 64];
+        real adt[2][NV];
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) adt[c][v] = 0;
+#pragma unroll
         for (int t = 0; t < 4; ++t) {
-            const int j = 4 * s + t;
-            const int64_t m = a.slot[tix(i, j, S)];
+            const int64_t m = comp(sl, t);
             real d[NV];
+            gather_diff<NV>(a.U, m, U0, d);
 #pragma unroll
-            for (int v = 0; v < NV; ++v) d[v] = (real)(a.U[m * NV + v] - U0[v]);
+            for (int q = 0; q < K + 2; ++q) {
+                const int el = t * (K + 2) + q;
+                const real p = comp(pv[el / VW], el % VW);
+                if (q < K) {
 #pragma unroll
-            for (int k = 0; k < K; ++k) {
-                const real p = a.Pc[tix(i, k * S + j, K * S)];
+                    for (int v = 0; v < NV; ++v) ao[q][v] += p * d[v];
+                } else {
 #pragma unroll
-                for (int v = 0; v < NV; ++v) ao[k][v] += p * d[v];
-            }
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                const real p = a.Pd[tix(i, (s * 2 + c) * 4 + t, kPdEntries)];
-#pragma unroll
-                for (int v = 0; v < NV; ++v) ad[s][c][v] += p * d[v];
+                    for (int v = 0; v < NV; ++v) adt[q - K][v] += p * d[v];
+                }
             }
         }
+#pragma unroll
+        for (int s2 = 0; s2 < 3; ++s2)
+            if (s2 == s)
+#pragma unroll
+                for (int c = 0; c < 2; ++c)
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) ad[s2][c][v] = adt[c][v];
+        __builtin_amdgcn_sched_barrier(0);   // keep the phases apart: bounded live registers
     }
-    // remaining central slots
-#pragma unroll 1
-    for (int j = 12; j < S; ++j) {
-        const int64_t m = a.slot[tix(i, j, S)];
-        real d[NV];
+    if constexpr (S > 12) {
+        // remaining slots in two halves (bounded register footprint); a
+        // vector straddling the halves is loaded by both
+        constexpr int T0 = 12 * (K + 2);          // first tail entry (a multiple of VW)
+        constexpr int NT = S - 12;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) d[v] = (real)(a.U[m * NV + v] - U0[v]);
+        for (int h = 0; h < 2; ++h) {
+            constexpr int HS = (NT + 1) / 2;      // slots per half
+            const int t0 = h * HS, t1 = h == 0 ? HS : NT;
+            const int e0 = T0 + t0 * K, e1 = T0 + t1 * K;      // entries [e0, e1)
+            const int g0 = e0 / VW, g1 = (e1 + VW - 1) / VW;   // vectors [g0, g1)
+            V pv[(HS * K + 2 * VW - 2) / VW + 1];
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const real p = a.Pc[tix(i, k * S + j, K * S)];
+            for (int g = 0; g < g1 - g0; ++g) pv[g] = Pv[(g0 + g) * 64];
 #pragma unroll
-            for (int v = 0; v < NV; ++v) ao[k][v] += p * d[v];
+            for (int t = t0; t < t1; ++t) {
+                const int j = 12 + t;
+                const int64_t m = comp(slv[j / 4], j % 4);
+                real d[NV];
+                gather_diff<NV>(a.U, m, U0, d);
+#pragma unroll
+                for (int q = 0; q < K; ++q) {
+                    const int e = T0 + t * K + q;
+                    const real p = comp(pv[e / VW - g0], e % VW);
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) ao[q][v] += p * d[v];
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
         }
     }
 
@@ -581,13 +708,7 @@ __global__ __launch_bounds__(256) void k_reconstruct(const ReconArgs<real, (R + 
 #pragma unroll
         for (int v = 0; v < NV; ++v) a.delta[i * NV + v] = (uint8_t)(dword >> (8 * v));
     }
-    real *dst = a.FV + i * 3 * 2 * NV;
-#pragma unroll
-    for (int f = 0; f < 3; ++f)
-#pragma unroll
-        for (int q = 0; q < 2; ++q)
-#pragma unroll
-            for (int v = 0; v < NV; ++v) dst[(f * 2 + q) * NV + v] = out[f][q][v];
+    store_row<real, 3 * 2 * NV>(a.FV + i * 3 * 2 * NV, &out[0][0][0]);
 }
 
 template <typename real, int R, int NV>
@@ -599,9 +720,9 @@ static hipError_t reconstruct_t(const DeviceMesh &m, const double *U, void *FV, 
     a.U = U;
     a.slot = m.slot;
     a.flags = m.flags;
-    if constexpr (std::is_same<real, double>::value) { a.Pc = m.Pc64; a.Pd = m.Pd64; }
-    else { a.Pc = m.Pc32; a.Pd = m.Pd32; }
-    if (!a.Pc || !a.Pd) return hipErrorInvalidValue;
+    if constexpr (std::is_same<real, double>::value) a.P = m.P64;
+    else a.P = m.P32;
+    if (!a.P) return hipErrorInvalidValue;
     a.FV = (real *)FV;
     a.delta = delta;
     a.done = done;
@@ -620,7 +741,7 @@ static hipError_t reconstruct_t(const DeviceMesh &m, const double *U, void *FV, 
         a.lams[s] = (real)ls;
         a.lam_ratio[s] = s >= 2 ? (real)(lam1 / ls) : (real)1;
     }
-    const unsigned grid = (unsigned)((m.N + 255) / 256);
+    const unsigned grid = (unsigned)m.blocks();
 #define CT_LAUNCH(SCH, GF, DM) hipLaunchKernelGGL((k_reconstruct<real, R, NV, SCH, GF, DM>), dim3(grid), dim3(256), 0, st, a)
 #define CT_DM(SCH, GF)              \
     switch (dmode) {                \
@@ -723,8 +844,7 @@ template <typename real>
 struct FluxArgs {
     int64_t N;
     const real *FV;
-    const uint32_t *nb;
-    const real *fgeo;
+    const real *fr;         // face records (nx, ny, |A|, code), vector-tiled
     const double *area;
     const double *Un, *Us;
     double *Uout;
@@ -733,10 +853,27 @@ struct FluxArgs {
     real *flux_out;
     double *resid;
     Ctrl *ctrl;
+    double *dt_part;
     real gamma, ax, ay;
     double gamma64;
-    int stage, want_dt;
+    int stage;
 };
+
+// face record of local face f: unit normal, length, neighbour code
+template <typename real>
+__device__ __forceinline__ void face_record(const real *fr, int64_t i, int f, real &nx, real &ny, real &len,
+                                            uint32_t &code) {
+    if constexpr (std::is_same<real, float>::value) {
+        const float4 r = reinterpret_cast<const float4 *>(fr)[(size_t)(i >> 6) * 3 * 64 + f * 64 + (i & 63)];
+        nx = r.x; ny = r.y; len = r.z;
+        code = (uint32_t)__float_as_int(r.w);
+    } else {
+        const double2 *b = reinterpret_cast<const double2 *>(fr) + (size_t)(i >> 6) * 6 * 64 + (i & 63);
+        const double2 r0 = b[(2 * f) * 64], r1 = b[(2 * f + 1) * 64];
+        nx = r0.x; ny = r0.y; len = r1.x;
+        code = (uint32_t)__double_as_longlong(r1.y);
+    }
+}
 
 template <int NV, int PHYS>
 __device__ __forceinline__ double cell_dt_bound(const double *U, const double nrm[3][3], double area, double gamma,
@@ -755,6 +892,7 @@ __device__ __forceinline__ double cell_dt_bound(const double *U, const double nr
     return 2.0 * area / sum;
 }
 
+// minimum over the block (all threads call it; result valid in thread 0)
 __device__ __forceinline__ double block_min(double v) {
     __shared__ double red[16];
 #pragma unroll
@@ -770,7 +908,7 @@ __device__ __forceinline__ double block_min(double v) {
 
 template <typename real, int NV, int PHYS, int MODE>
 __global__ __launch_bounds__(256) void k_flux(const FluxArgs<real> a) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     const bool active = i < a.N;
     if (a.ctrl && a.ctrl->done) return;        // uniform across the grid
     double dtc = INFINITY;
@@ -780,19 +918,15 @@ __global__ __launch_bounds__(256) void k_flux(const FluxArgs<real> a) {
         for (int v = 0; v < NV; ++v) acc[v] = 0.0;
         double nrm[3][3];
         bool bad = false;
+        real own[3][2][NV];
+        load_row<real, 3 * 2 * NV>(a.FV + i * 3 * 2 * NV, &own[0][0][0]);
 #pragma unroll
         for (int f = 0; f < 3; ++f) {
-            const uint32_t code = a.nb[tix(i, f, 3)];
-            const real nx = a.fgeo[tix(i, 3 * f, 9)];
-            const real ny = a.fgeo[tix(i, 3 * f + 1, 9)];
-            const real len = a.fgeo[tix(i, 3 * f + 2, 9)];
+            real nx, ny, len;
+            uint32_t code;
+            face_record<real>(a.fr, i, f, nx, ny, len, code);
             nrm[f][0] = (double)nx; nrm[f][1] = (double)ny; nrm[f][2] = (double)len;
-            real own[2][NV], oth[2][NV];
-            const real *src = a.FV + (i * 3 + f) * 2 * NV;
-#pragma unroll
-            for (int q = 0; q < 2; ++q)
-#pragma unroll
-                for (int v = 0; v < NV; ++v) own[q][v] = src[q * NV + v];
+            real oth[2][NV];
             bool owner;
             if (code & kNbBoundary) {
                 owner = true;
@@ -801,22 +935,18 @@ __global__ __launch_bounds__(256) void k_flux(const FluxArgs<real> a) {
 #pragma unroll
                 for (int q = 0; q < 2; ++q) {
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) oth[1 - q][v] = own[q][v];
+                    for (int v = 0; v < NV; ++v) oth[1 - q][v] = own[f][q][v];
                     if (PHYS == CTENO_EULER && wall) {
-                        const real mn = own[q][1] * nx + own[q][2] * ny;
-                        oth[1 - q][1] = own[q][1] - 2 * mn * nx;
-                        oth[1 - q][2] = own[q][2] - 2 * mn * ny;
+                        const real mn = own[f][q][1] * nx + own[f][q][2] * ny;
+                        oth[1 - q][1] = own[f][q][1] - 2 * mn * nx;
+                        oth[1 - q][2] = own[f][q][2] - 2 * mn * ny;
                     }
                 }
             } else {
                 owner = (code & kNbOwner) != 0;
                 const int64_t j = code & kNbIndexMask;
                 const int g = (code >> 28) & 3;
-                const real *nsrc = a.FV + (j * 3 + g) * 2 * NV;
-#pragma unroll
-                for (int q = 0; q < 2; ++q)
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) oth[q][v] = nsrc[q * NV + v];
+                load_row<real, 2 * NV>(a.FV + (j * 3 + g) * 2 * NV, &oth[0][0]);
             }
             // both cells of a face evaluate F(owner side, other side; owner normal)
             // at the owner's Gauss points in the owner's order
@@ -829,8 +959,8 @@ __global__ __launch_bounds__(256) void k_flux(const FluxArgs<real> a) {
                 real A[NV], B[NV], F[NV];
 #pragma unroll
                 for (int v = 0; v < NV; ++v) {
-                    A[v] = owner ? own[q][v] : oth[q][v];
-                    B[v] = owner ? oth[1 - q][v] : own[1 - q][v];
+                    A[v] = owner ? own[f][q][v] : oth[q][v];
+                    B[v] = owner ? oth[1 - q][v] : own[f][1 - q][v];
                 }
                 if (PHYS == CTENO_EULER) {
                     bad |= !hllc<real>(a.gamma, A, B, fx, fy, F);
@@ -856,26 +986,41 @@ __global__ __launch_bounds__(256) void k_flux(const FluxArgs<real> a) {
         }
         if (MODE == 2) {
             const double dt = a.dt_ptr ? *a.dt_ptr : a.dt_value;
-            double un[NV];
+            const double ar = a.area[i];
+            double u0[NV], us[NV], un[NV];
+            if constexpr (NV == 4) {
+                const double2 *U2 = reinterpret_cast<const double2 *>(a.Un);
+                const double2 *S2 = reinterpret_cast<const double2 *>(a.Us);
+                const double2 x0 = U2[2 * i], x1 = U2[2 * i + 1], y0 = S2[2 * i], y1 = S2[2 * i + 1];
+                u0[0] = x0.x; u0[1] = x0.y; u0[2] = x1.x; u0[3] = x1.y;
+                us[0] = y0.x; us[1] = y0.y; us[2] = y1.x; us[3] = y1.y;
+            } else {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) { u0[v] = a.Un[i * NV + v]; us[v] = a.Us[i * NV + v]; }
+            }
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                const double R = -acc[v] / a.area[i];
-                const double u0 = a.Un[i * NV + v];
-                const double us = a.Us[i * NV + v];
+                const double R = -acc[v] / ar;
                 double r;
-                if (a.stage == 0) r = us + dt * R;
-                else if (a.stage == 1) r = 0.75 * u0 + 0.25 * (us + dt * R);
-                else r = (1.0 / 3.0) * u0 + (2.0 / 3.0) * (us + dt * R);
+                if (a.stage == 0) r = us[v] + dt * R;
+                else if (a.stage == 1) r = 0.75 * u0[v] + 0.25 * (us[v] + dt * R);
+                else r = (1.0 / 3.0) * u0[v] + (2.0 / 3.0) * (us[v] + dt * R);
                 un[v] = r;
-                a.Uout[i * NV + v] = r;
             }
-            if (a.want_dt) dtc = cell_dt_bound<NV, PHYS>(un, nrm, a.area[i], a.gamma64, (double)a.ax, (double)a.ay);
+            if constexpr (NV == 4) {
+                double2 *O2 = reinterpret_cast<double2 *>(a.Uout);
+                O2[2 * i] = make_double2(un[0], un[1]);
+                O2[2 * i + 1] = make_double2(un[2], un[3]);
+            } else {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) a.Uout[i * NV + v] = un[v];
+            }
+            if (a.dt_part) dtc = cell_dt_bound<NV, PHYS>(un, nrm, ar, a.gamma64, (double)a.ax, (double)a.ay);
         }
     }
-    if (MODE == 2 && a.want_dt) {
+    if (MODE == 2 && a.dt_part) {
         const double bm = block_min(dtc);
-        if (threadIdx.x == 0 && bm < INFINITY)
-            atomicMin(&a.ctrl->dt_cand_bits, (unsigned long long)__double_as_longlong(bm));
+        if (threadIdx.x == 0) a.dt_part[blockIdx.x] = bm;
     }
 }
 
@@ -884,20 +1029,19 @@ static hipError_t flux_t(const DeviceMesh &m, const FluxLaunch &f, hipStream_t s
     FluxArgs<real> a;
     a.N = m.N;
     a.FV = (const real *)f.FV;
-    a.nb = m.nb;
-    if constexpr (std::is_same<real, double>::value) a.fgeo = m.fgeo64;
-    else a.fgeo = m.fgeo32;
+    if constexpr (std::is_same<real, double>::value) a.fr = m.fr64;
+    else a.fr = m.fr32;
     a.area = m.area;
     a.Un = f.Un; a.Us = f.Us; a.Uout = f.Uout;
     a.dt_ptr = f.dt_ptr; a.dt_value = f.dt_value;
     a.flux_out = (real *)f.flux_out;
     a.resid = f.resid;
     a.ctrl = f.ctrl;
+    a.dt_part = f.dt_part;
     a.gamma = (real)m.gamma; a.ax = (real)m.ax; a.ay = (real)m.ay;
     a.gamma64 = m.gamma;
     a.stage = f.stage;
-    a.want_dt = f.want_dt && f.ctrl;
-    const unsigned grid = (unsigned)((m.N + 255) / 256);
+    const unsigned grid = (unsigned)m.blocks();
     switch (f.mode) {
         case 0: hipLaunchKernelGGL((k_flux<real, NV, PHYS, 0>), dim3(grid), dim3(256), 0, st, a); break;
         case 1: hipLaunchKernelGGL((k_flux<real, NV, PHYS, 1>), dim3(grid), dim3(256), 0, st, a); break;
@@ -917,9 +1061,8 @@ hipError_t launch_flux(const DeviceMesh &m, bool fp32, const FluxLaunch &f, hipS
 // ===========================================================================
 
 template <int NV, int PHYS>
-__global__ __launch_bounds__(256) void k_dt_candidate(int64_t N, const double *U, const double *fgeo,
-                                                      const double *area, double gamma, double ax, double ay,
-                                                      Ctrl *ctrl) {
+__global__ __launch_bounds__(256) void k_dt_partials(int64_t N, const double *U, const double *fr, const double *area,
+                                                     double gamma, double ax, double ay, double *part) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double dtc = INFINITY;
     if (i < N) {
@@ -927,31 +1070,46 @@ __global__ __launch_bounds__(256) void k_dt_candidate(int64_t N, const double *U
 #pragma unroll
         for (int v = 0; v < NV; ++v) u[v] = U[i * NV + v];
 #pragma unroll
-        for (int f = 0; f < 3; ++f)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) nrm[f][c] = fgeo[tix(i, 3 * f + c, 9)];
+        for (int f = 0; f < 3; ++f) {
+            double nx, ny, len;
+            uint32_t code;
+            face_record<double>(fr, i, f, nx, ny, len, code);
+            nrm[f][0] = nx; nrm[f][1] = ny; nrm[f][2] = len;
+        }
         dtc = cell_dt_bound<NV, PHYS>(u, nrm, area[i], gamma, ax, ay);
     }
     const double bm = block_min(dtc);
-    if (threadIdx.x == 0 && bm < INFINITY) atomicMin(&ctrl->dt_cand_bits, (unsigned long long)__double_as_longlong(bm));
+    if (threadIdx.x == 0) part[blockIdx.x] = bm;
 }
 
-hipError_t launch_dt_candidate(const DeviceMesh &m, const double *U, Ctrl *ctrl, hipStream_t st) {
-    const unsigned grid = (unsigned)((m.N + 255) / 256);
+hipError_t launch_dt_partials(const DeviceMesh &m, const double *U, double *part, hipStream_t st) {
+    const unsigned grid = (unsigned)m.blocks();
     if (m.physics == CTENO_EULER)
-        hipLaunchKernelGGL((k_dt_candidate<4, CTENO_EULER>), dim3(grid), dim3(256), 0, st, m.N, U, m.fgeo64, m.area,
-                           m.gamma, m.ax, m.ay, ctrl);
+        hipLaunchKernelGGL((k_dt_partials<4, CTENO_EULER>), dim3(grid), dim3(256), 0, st, m.N, U, m.fr64, m.area,
+                           m.gamma, m.ax, m.ay, part);
     else
-        hipLaunchKernelGGL((k_dt_candidate<1, CTENO_ADVECTION>), dim3(grid), dim3(256), 0, st, m.N, U, m.fgeo64,
-                           m.area, m.gamma, m.ax, m.ay, ctrl);
+        hipLaunchKernelGGL((k_dt_partials<1, CTENO_ADVECTION>), dim3(grid), dim3(256), 0, st, m.N, U, m.fr64,
+                           m.area, m.gamma, m.ax, m.ay, part);
     return hipGetLastError();
 }
 
-// Step control, one thread.  Commits the pending step (t <- t_next), then
+// Step control, one block.  Commits the pending step (t <- t_next), then
 // decides the next one exactly as: stop when t >= t_final or the step
-// budget is used; dt = cfl * bound; clip the last step onto t_final.
-__global__ void k_control(Ctrl *c, int commit_only) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// budget is used; dt = cfl * (minimum over cells of the bound, reduced from
+// the per-block minima); clip the last step onto t_final.
+__global__ __launch_bounds__(1024) void k_control(Ctrl *c, const double *part, int64_t n_part, int commit_only) {
+    __shared__ double red[16];
+    const bool reduce = !commit_only && !c->done;
+    double v = INFINITY;
+    if (reduce)
+        for (int64_t k = threadIdx.x; k < n_part; k += blockDim.x) v = fmin(v, part[k]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double bound = INFINITY;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) bound = fmin(bound, red[k]);
     if (c->pending) {
         c->t = c->t_next;
         c->step += 1;
@@ -962,7 +1120,6 @@ __global__ void k_control(Ctrl *c, int commit_only) {
         c->done = 1;
         return;
     }
-    const double bound = __longlong_as_double((long long)c->dt_cand_bits);
     double dt = c->cfl * bound;
     double tn = c->t + dt;
     if (dt >= c->t_final - c->t) {
@@ -977,11 +1134,10 @@ __global__ void k_control(Ctrl *c, int commit_only) {
     c->dt = dt;
     c->t_next = tn;
     c->pending = 1;
-    c->dt_cand_bits = 0x7FF0000000000000ull;   // +inf, reduced again by the last stage
 }
 
-hipError_t launch_control(Ctrl *ctrl, int commit_only, hipStream_t st) {
-    hipLaunchKernelGGL(k_control, dim3(1), dim3(64), 0, st, ctrl, commit_only);
+hipError_t launch_control(Ctrl *ctrl, const double *part, int64_t n_part, int commit_only, hipStream_t st) {
+    hipLaunchKernelGGL(k_control, dim3(1), dim3(1024), 0, st, ctrl, part, n_part, commit_only);
     return hipGetLastError();
 }
 
@@ -1077,15 +1233,6 @@ hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, size_t n
     return hipGetLastError();
 }
 
-__global__ void k_to_fp32(const double *src, float *dst, size_t n) {
-    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < n) dst[k] = (float)src[k];
-}
-hipError_t launch_to_fp32(const double *src, float *dst, size_t n, hipStream_t st) {
-    hipLaunchKernelGGL(k_to_fp32, dim3(grid_for((int64_t)n)), dim3(256), 0, st, src, dst, n);
-    return hipGetLastError();
-}
-
 __global__ void k_copy16(uint4 *dst, const uint4 *src, size_t n) {
     for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x)
         dst[k] = src[k];
@@ -1097,18 +1244,18 @@ hipError_t launch_copy16(void *dst, const void *src, size_t n16, hipStream_t st)
     return hipGetLastError();
 }
 
-__global__ void k_gather_tiled(int n, const int32_t *idx, int E, const double *s64, const float *s32,
-                               const int32_t *si, double *dst) {
+__global__ void k_gather_entries(int n, const int32_t *idx, int E, int VW, const double *s64, const float *s32,
+                                 const int32_t *si, double *dst) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (int64_t)n * E) return;
     const int a = (int)(t / E), e = (int)(t % E);
-    const size_t src = tix(idx[a], e, E);
+    const size_t src = avix(idx[a], e, E, VW);
     dst[t] = s64 ? s64[src] : (s32 ? (double)s32[src] : (double)si[src]);
 }
-hipError_t launch_gather_tiled(int n, const int32_t *idx, int E, const double *src64, const float *src32,
-                               const int32_t *srci, double *dst, hipStream_t st) {
-    hipLaunchKernelGGL(k_gather_tiled, dim3(grid_for((int64_t)n * E)), dim3(256), 0, st, n, idx, E, src64, src32, srci,
-                       dst);
+hipError_t launch_gather_entries(int n, const int32_t *idx, int E, int VW, const double *src64, const float *src32,
+                                 const int32_t *srci, double *dst, hipStream_t st) {
+    hipLaunchKernelGGL(k_gather_entries, dim3(grid_for((int64_t)n * E)), dim3(256), 0, st, n, idx, E, VW, src64,
+                       src32, srci, dst);
     return hipGetLastError();
 }
 

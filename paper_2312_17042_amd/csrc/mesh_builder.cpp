@@ -373,23 +373,36 @@ cteno_status build_host_mesh(const cteno_mesh_desc &d, const cteno_scheme &s, Ho
     hm.dirn_user = b.dirn;
 
     const int64_t Np = pad64(N);
-    hm.slot.assign((size_t)Np * S, 0);
+    const int SP = round_up(S, 4);
+    hm.SP = SP;
+    hm.slot.assign((size_t)Np * SP, 0);
     hm.slot_flag.assign((size_t)Np * S, 0);
     hm.slot_shift.assign((size_t)Np * 2 * S, 0);
-    hm.slot_cen_pos.assign((size_t)Np * S, -1);
-    hm.slot_dir_pos.assign((size_t)Np * S, -1);
     hm.flags.assign(Np, 0);
     hm.verts.assign((size_t)Np * 6, 0.0);
-    hm.nb.assign((size_t)Np * 3, kNbBoundary);
-    hm.fgeo.assign((size_t)Np * 9, 0.0);
+    hm.fr64.assign((size_t)Np * 12, 0.0);
+    hm.fr32.assign((size_t)Np * 12, 0.0f);
     hm.area.assign(Np, 1.0);
+
+    auto put_face = [&](int64_t k, int f, double nx, double ny, double len, uint32_t code) {
+        hm.fr64[avix(k, 4 * f + 0, 12, 2)] = nx;
+        hm.fr64[avix(k, 4 * f + 1, 12, 2)] = ny;
+        hm.fr64[avix(k, 4 * f + 2, 12, 2)] = len;
+        uint64_t c64 = code;
+        std::memcpy(&hm.fr64[avix(k, 4 * f + 3, 12, 2)], &c64, sizeof c64);
+        hm.fr32[avix(k, 4 * f + 0, 12, 4)] = (float)nx;
+        hm.fr32[avix(k, 4 * f + 1, 12, 4)] = (float)ny;
+        hm.fr32[avix(k, 4 * f + 2, 12, 4)] = (float)len;
+        std::memcpy(&hm.fr32[avix(k, 4 * f + 3, 12, 4)], &code, sizeof code);
+    };
 
     std::atomic<int64_t> nfaces{0}, nbnd{0};
     std::atomic<int> ninad{0};
     parallel_for(Np, [&](int64_t k, int) {
         if (k >= N) {
             // padding cells: self slots, unit area, boundary faces; never written back
-            for (int j = 0; j < S; ++j) hm.slot[tix(k, j, S)] = (int32_t)k;
+            for (int j = 0; j < SP; ++j) hm.slot[avix(k, j, SP, 4)] = (int32_t)k;
+            for (int f = 0; f < 3; ++f) put_face(k, f, 1.0, 0.0, 0.0, kNbBoundary | CTENO_TRANSMISSIVE);
             return;
         }
         const int u = hm.perm[k];
@@ -406,7 +419,6 @@ cteno_status build_host_mesh(const cteno_mesh_desc &d, const cteno_scheme &s, Ho
         std::vector<int> used(M, 0);
         std::vector<int32_t> sl(S, -1);
         std::vector<uint8_t> fl(S, 0);
-        std::vector<int8_t> dpos(S, -1);
         uint8_t adm = 0;
         for (int f = 0; f < 3; ++f) {
             if (dn[f] > 0) {
@@ -414,7 +426,6 @@ cteno_status build_host_mesh(const cteno_mesh_desc &d, const cteno_scheme &s, Ho
                 for (int a = 0; a < dn[f]; ++a) {
                     sl[f * kDirSlots + a] = dr[f * kDirSlots + a];
                     fl[f * kDirSlots + a] = 3;
-                    dpos[f * kDirSlots + a] = (int8_t)a;
                     for (int m = 0; m < M; ++m) if (cen[m] == dr[f * kDirSlots + a]) used[m] = 1;
                 }
             } else if (b.fnb[3 * (size_t)u + f] >= 0) {
@@ -428,21 +439,15 @@ cteno_status build_host_mesh(const cteno_mesh_desc &d, const cteno_scheme &s, Ho
             if (m < M) { sl[j] = cen[m]; fl[j] = 1; used[m] = 1; }
         }
         hm.flags[k] = adm;
-        for (int j = 0; j < S; ++j) {
-            int src = sl[j];
-            int cpos = -1;
-            if (src >= 0)
-                for (int q = 0; q < M; ++q) if (cen[q] == src) cpos = q;
-            hm.slot_cen_pos[tix(k, j, S)] = (int8_t)cpos;
-            hm.slot_dir_pos[tix(k, j, S)] = dpos[j];
+        for (int j = 0; j < SP; ++j) {
+            const int src = j < S ? sl[j] : -1;
             if (src < 0) {   // pad: the cell itself, zero weight
-                hm.slot[tix(k, j, S)] = (int32_t)k;
-                hm.slot_flag[tix(k, j, S)] = 0;
+                hm.slot[avix(k, j, SP, 4)] = (int32_t)k;
                 continue;
             }
             int sx, sy; double dx, dy;
             b.offset(u, src, sx, sy, dx, dy);
-            hm.slot[tix(k, j, S)] = hm.iperm[src];
+            hm.slot[avix(k, j, SP, 4)] = hm.iperm[src];
             hm.slot_flag[tix(k, j, S)] = fl[j];
             hm.slot_shift[tix(k, 2 * j, 2 * S)] = (int8_t)sx;
             hm.slot_shift[tix(k, 2 * j + 1, 2 * S)] = (int8_t)sy;
@@ -460,10 +465,10 @@ cteno_status build_host_mesh(const cteno_mesh_desc &d, const cteno_scheme &s, Ho
                 ny = -ex / len;
             };
             double nx, ny, len;
+            uint32_t code;
             if (j < 0) {
                 edge_normal(u, f, nx, ny, len);
-                int kind = b.fbc[3 * (size_t)u + f];
-                hm.nb[tix(k, f, 3)] = kNbBoundary | (uint32_t)kind;
+                code = kNbBoundary | (uint32_t)b.fbc[3 * (size_t)u + f];
                 nbnd++;
                 nfaces++;
             } else {
@@ -474,12 +479,10 @@ cteno_status build_host_mesh(const cteno_mesh_desc &d, const cteno_scheme &s, Ho
                 // the other cell stores the exact negation
                 if (owner) edge_normal(u, f, nx, ny, len);
                 else { edge_normal(j, g, nx, ny, len); nx = -nx; ny = -ny; }
-                hm.nb[tix(k, f, 3)] = (uint32_t)kj | ((uint32_t)g << 28) | (owner ? kNbOwner : 0u);
+                code = (uint32_t)kj | ((uint32_t)g << 28) | (owner ? kNbOwner : 0u);
                 if (owner) nfaces++;
             }
-            hm.fgeo[tix(k, 3 * f, 9)] = nx;
-            hm.fgeo[tix(k, 3 * f + 1, 9)] = ny;
-            hm.fgeo[tix(k, 3 * f + 2, 9)] = len;
+            put_face(k, f, nx, ny, len, code);
         }
     });
     hm.n_faces = nfaces;

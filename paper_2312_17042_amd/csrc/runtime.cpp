@@ -248,44 +248,45 @@ extern "C" cteno_status cteno_mesh_upload(cteno_ctx *ctx, const cteno_mesh_desc 
     dm.Lx = hm.Lx; dm.Ly = hm.Ly;
     make_ref_tables(hm.r, dm.tab);
 
-    const size_t Np = (size_t)dm.Np, S = hm.S, KS = (size_t)hm.K * hm.S;
+    const size_t Np = (size_t)dm.Np, S = hm.S;
+    dm.SP = hm.SP;
+    dm.E64 = round_up(pinv_entries(hm.r), 2);
+    dm.E32 = round_up(pinv_entries(hm.r), 4);
     hipStream_t st = ctx->stream();
-    dm.slot = m->alloc<int32_t>(Np * S);
+    dm.slot = m->alloc<int32_t>(Np * hm.SP);
     dm.flags = m->alloc<uint8_t>(Np);
-    dm.nb = m->alloc<uint32_t>(Np * 3);
-    dm.fgeo64 = m->alloc<double>(Np * 9);
+    dm.fr64 = m->alloc<double>(Np * 12);
     dm.area = m->alloc<double>(Np);
     dm.perm = m->alloc<int32_t>((size_t)hm.N);
     if (s.precision & CTENO_MIXED) {
-        dm.fgeo32 = m->alloc<float>(Np * 9);
-        dm.Pc32 = m->alloc<float>(Np * KS);
-        dm.Pd32 = m->alloc<float>(Np * kPdEntries);
+        dm.fr32 = m->alloc<float>(Np * 12);
+        dm.P32 = m->alloc<float>(Np * dm.E32);
     }
-    if (!dm.slot || !dm.flags || !dm.nb || !dm.fgeo64 || !dm.area || !dm.perm ||
-        ((s.precision & CTENO_MIXED) && (!dm.fgeo32 || !dm.Pc32 || !dm.Pd32)))
+    if (!dm.slot || !dm.flags || !dm.fr64 || !dm.area || !dm.perm ||
+        ((s.precision & CTENO_MIXED) && (!dm.fr32 || !dm.P32)))
         return fail(CTENO_ERR_NOMEM, "device allocation failed");
     // FP64 pseudo-inverses are always computed; kept only when FP64 is resident
-    DevBuf pc64(ctx, Np * KS * sizeof(double)), pd64(ctx, Np * kPdEntries * sizeof(double));
+    DevBuf p64(ctx, Np * dm.E64 * sizeof(double));
     DevBuf verts(ctx, Np * 6 * sizeof(double)), sflag(ctx, Np * S), sshift(ctx, Np * 2 * S), rfail(ctx, sizeof(int));
-    if (!pc64.p || !pd64.p || !verts.p || !sflag.p || !sshift.p || !rfail.p)
+    if (!p64.p || !verts.p || !sflag.p || !sshift.p || !rfail.p)
         return fail(CTENO_ERR_NOMEM, "device allocation failed (precompute)");
-    dm.Pc64 = pc64.as<double>();
-    dm.Pd64 = pd64.as<double>();
+    dm.P64 = p64.as<double>();
 
     HIP_TRY(h2d(dm.slot, hm.slot, st));
     HIP_TRY(h2d(dm.flags, hm.flags, st));
-    HIP_TRY(h2d(dm.nb, hm.nb, st));
-    HIP_TRY(h2d(dm.fgeo64, hm.fgeo, st));
+    HIP_TRY(h2d(dm.fr64, hm.fr64, st));
+    if (dm.fr32) HIP_TRY(h2d(dm.fr32, hm.fr32, st));
     HIP_TRY(h2d(dm.area, hm.area, st));
     HIP_TRY(h2d(dm.perm, hm.perm, st));
     HIP_TRY(h2d(verts.as<double>(), hm.verts, st));
     HIP_TRY(h2d(sflag.as<uint8_t>(), hm.slot_flag, st));
     HIP_TRY(h2d(sshift.as<int8_t>(), hm.slot_shift, st));
     HIP_TRY(hipMemsetAsync(rfail.p, 0, sizeof(int), st));
-    if (dm.fgeo32) HIP_TRY(launch_to_fp32(dm.fgeo64, dm.fgeo32, Np * 9, st));
+    // padding entries of the streams stay zero
+    HIP_TRY(hipMemsetAsync(dm.P64, 0, Np * dm.E64 * sizeof(double), st));
+    if (dm.P32) HIP_TRY(hipMemsetAsync(dm.P32, 0, Np * dm.E32 * sizeof(float), st));
 
-    PrecomputeInputs in{verts.as<double>(), dm.slot, sflag.as<uint8_t>(), sshift.as<int8_t>(), dm.flags,
-                        rfail.as<int>()};
+    PrecomputeInputs in{verts.as<double>(), sflag.as<uint8_t>(), sshift.as<int8_t>(), dm.flags, rfail.as<int>()};
     HIP_TRY(timed(ctx, 2, [&] { return launch_precompute(dm, in, st); }));
     int rank_fail = 0;
     std::vector<uint8_t> flags(Np);
@@ -306,19 +307,18 @@ extern "C" cteno_status cteno_mesh_upload(cteno_ctx *ctx, const cteno_mesh_desc 
         hm.flags[k] = flags[k];
     }
     if (s.precision & CTENO_FP64) {
-        m->bytes += (int64_t)(pc64.bytes + pd64.bytes);
-        m->bufs.push_back(std::move(pc64));
-        m->bufs.push_back(std::move(pd64));
+        m->bytes += (int64_t)p64.bytes;
+        m->bufs.push_back(std::move(p64));
     } else {
-        dm.Pc64 = dm.Pd64 = nullptr;
+        dm.P64 = nullptr;
     }
     // release host-only copies that the device now holds
     hm.slot.clear(); hm.slot.shrink_to_fit();
     hm.slot_flag.clear(); hm.slot_flag.shrink_to_fit();
     hm.slot_shift.clear(); hm.slot_shift.shrink_to_fit();
     hm.verts.clear(); hm.verts.shrink_to_fit();
-    hm.nb.clear(); hm.nb.shrink_to_fit();
-    hm.fgeo.clear(); hm.fgeo.shrink_to_fit();
+    hm.fr64.clear(); hm.fr64.shrink_to_fit();
+    hm.fr32.clear(); hm.fr32.shrink_to_fit();
     *out = m.release();
     return CTENO_OK;
 }
@@ -363,25 +363,21 @@ extern "C" cteno_status cteno_mesh_pinv(cteno_ctx *ctx, const cteno_mesh *m, int
         idx[a] = hm.iperm[cells[a]];
     }
     // slot tables are not kept on the host; rebuild the column maps from the stencils
-    const int K = hm.K, S = hm.S, M = hm.M, KS = K * S;
+    const int K = hm.K, S = hm.S, M = hm.M;
+    const int E = f32 ? dm.E32 : dm.E64, VW = f32 ? 4 : 2;
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t st = ctx->stream();
-    DevBuf didx(ctx, n * sizeof(int32_t)), oc(ctx, (size_t)n * KS * sizeof(double)),
-        od(ctx, (size_t)n * kPdEntries * sizeof(double)), dslot(ctx, (size_t)n * S * sizeof(double));
-    if (!didx.p || !oc.p || !od.p || !dslot.p) return fail(CTENO_ERR_NOMEM, "device allocation failed");
+    DevBuf didx(ctx, n * sizeof(int32_t)), op(ctx, (size_t)n * E * sizeof(double)),
+        dslot(ctx, (size_t)n * dm.SP * sizeof(double));
+    if (!didx.p || !op.p || !dslot.p) return fail(CTENO_ERR_NOMEM, "device allocation failed");
     HIP_TRY(hipMemcpyAsync(didx.p, idx.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, st));
-    HIP_TRY(launch_gather_tiled(n, didx.as<int32_t>(), KS, f32 ? nullptr : dm.Pc64, f32 ? dm.Pc32 : nullptr,
-                                nullptr, oc.as<double>(), st));
-    HIP_TRY(launch_gather_tiled(n, didx.as<int32_t>(), kPdEntries, f32 ? nullptr : dm.Pd64, f32 ? dm.Pd32 : nullptr,
-                                nullptr, od.as<double>(), st));
-    HIP_TRY(launch_gather_tiled(n, didx.as<int32_t>(), S, nullptr, nullptr, dm.slot, dslot.as<double>(), st));
-    std::vector<double> pc((size_t)n * KS), pd((size_t)n * kPdEntries);
-    HIP_TRY(hipMemcpyAsync(pc.data(), oc.p, pc.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(pd.data(), od.p, pd.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-    std::vector<double> slotd((size_t)n * S);
+    HIP_TRY(launch_gather_entries(n, didx.as<int32_t>(), E, VW, f32 ? nullptr : dm.P64, f32 ? dm.P32 : nullptr,
+                                  nullptr, op.as<double>(), st));
+    HIP_TRY(launch_gather_entries(n, didx.as<int32_t>(), dm.SP, 4, nullptr, nullptr, dm.slot, dslot.as<double>(), st));
+    std::vector<double> pe((size_t)n * E), slotd((size_t)n * dm.SP);
+    HIP_TRY(hipMemcpyAsync(pe.data(), op.p, pe.size() * sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(slotd.data(), dslot.p, slotd.size() * sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    std::vector<int32_t> slots(slotd.begin(), slotd.end());
     for (int a = 0; a < n; ++a) {
         const int u = cells[a];
         const int32_t *cen = hm.cen_user.data() + (size_t)u * M;
@@ -390,23 +386,22 @@ extern "C" cteno_status cteno_mesh_pinv(cteno_ctx *ctx, const cteno_mesh *m, int
         if (directional)
             std::fill(directional + (size_t)a * 3 * 2 * kDirSlots, directional + (size_t)(a + 1) * 3 * 2 * kDirSlots, 0.0);
         for (int j = 0; j < S; ++j) {
-            const int src_k = slots[(size_t)a * S + j];
+            const int src_k = (int)slotd[(size_t)a * dm.SP + j];
             if (src_k == idx[a]) continue;   // padding slot (the cell itself)
             const int src_u = hm.perm[src_k];
             int cpos = -1;
             for (int q = 0; q < M; ++q) if (cen[q] == src_u) cpos = q;
             if (cpos < 0) return fail(CTENO_ERR_DEVICE, "slot not in stencil");
+            const int off = pinv_offset(j, K);
             if (central)
-                for (int k = 0; k < K; ++k)
-                    central[((size_t)a * K + k) * M + cpos] = pc[(size_t)a * KS + k * S + j];
+                for (int k = 0; k < K; ++k) central[((size_t)a * K + k) * M + cpos] = pe[(size_t)a * E + off + k];
             if (j < 12 && directional) {
-                const int s = j / 4, t = j % 4;
+                const int s = j / 4;
                 int dpos = -1;
                 for (int q = 0; q < kDirSlots; ++q) if (dr[s * kDirSlots + q] == src_u) dpos = q;
                 if (dpos >= 0)
                     for (int c = 0; c < 2; ++c)
-                        directional[(((size_t)a * 3 + s) * 2 + c) * kDirSlots + dpos] =
-                            pd[(size_t)a * kPdEntries + (s * 2 + c) * 4 + t];
+                        directional[(((size_t)a * 3 + s) * 2 + c) * kDirSlots + dpos] = pe[(size_t)a * E + off + K + c];
             }
         }
     }
@@ -445,6 +440,7 @@ struct cteno_sol {
     DevBuf U[3];              // U^n, U^(1), U^(2): AoS [Np][nv]
     DevBuf FV[2];             // face-point values, FP64 / FP32
     DevBuf ctrl;              // Ctrl
+    DevBuf dt_part;           // per-block minima of the CFL bound
     double t = 0.0;
     Ctrl *h_ctrl = nullptr;   // pinned host mirror
     hipGraphExec_t graph[2] = {nullptr, nullptr};
@@ -486,7 +482,8 @@ extern "C" cteno_status cteno_sol_create(cteno_ctx *ctx, const cteno_mesh *m, co
         HIP_TRY(hipMemsetAsync(u.p, 0, bytes, ctx->stream()));
     }
     s->ctrl = DevBuf(ctx, sizeof(Ctrl));
-    if (!s->ctrl.p) return fail(CTENO_ERR_NOMEM, "device allocation failed");
+    s->dt_part = DevBuf(ctx, (size_t)dm.blocks() * sizeof(double));
+    if (!s->ctrl.p || !s->dt_part.p) return fail(CTENO_ERR_NOMEM, "device allocation failed");
     HIP_TRY(hipMemsetAsync(s->ctrl.p, 0, sizeof(Ctrl), ctx->stream()));
     HIP_TRY(hipHostMalloc((void **)&s->h_ctrl, sizeof(Ctrl), hipHostMallocDefault));
     cteno_sol *raw = s.release();
@@ -619,7 +616,7 @@ extern "C" cteno_status cteno_residual(cteno_ctx *ctx, const cteno_mesh *m, cons
 namespace {
 // one SSP-RK3 stage on sol; dt from a device pointer or a host value
 hipError_t issue_stage(cteno_ctx *ctx, cteno_sol *s, bool f32, int stage, const double *dt_ptr, double dt_value,
-                       Ctrl *ctrl, int want_dt, hipStream_t st) {
+                       Ctrl *ctrl, double *dt_part, hipStream_t st) {
     const DeviceMesh &dm = s->mesh->dm;
     const double *in = s->U[stage].as<double>();    // U^n, U^(1), U^(2)
     double *outU = stage == 2 ? s->U[0].as<double>() : s->U[stage + 1].as<double>();
@@ -637,7 +634,7 @@ hipError_t issue_stage(cteno_ctx *ctx, cteno_sol *s, bool f32, int stage, const 
     fl.dt_ptr = dt_ptr;
     fl.dt_value = dt_value;
     fl.ctrl = ctrl;
-    fl.want_dt = want_dt;
+    fl.dt_part = dt_part;
     return timed(ctx, 1, [&] { return launch_flux(dm, f32, fl, st); });
 }
 }  // namespace
@@ -651,7 +648,7 @@ extern "C" cteno_status cteno_rk_stage(cteno_ctx *ctx, const cteno_mesh *m, cten
     if (cteno_status rc = check_precision(m, precision, f32)) return rc;
     HIP_TRY(hipSetDevice(ctx->device));
     if (!sol->fv(f32)) return fail(CTENO_ERR_NOMEM, "device allocation failed");
-    HIP_TRY(issue_stage(ctx, sol, f32, stage, nullptr, dt, nullptr, 0, ctx->stream()));
+    HIP_TRY(issue_stage(ctx, sol, f32, stage, nullptr, dt, nullptr, nullptr, ctx->stream()));
     if (stage == 2) sol->t += dt;
     return CTENO_OK;
 }
@@ -662,9 +659,10 @@ extern "C" cteno_status cteno_rk_stage(cteno_ctx *ctx, const cteno_mesh *m, cten
 namespace {
 hipError_t issue_step(cteno_ctx *ctx, cteno_sol *s, bool f32, hipStream_t st) {
     Ctrl *c = s->ctrl.as<Ctrl>();
-    hipError_t e = launch_control(c, 0, st);
+    double *part = s->dt_part.as<double>();
+    hipError_t e = launch_control(c, part, s->mesh->dm.blocks(), 0, st);
     for (int stage = 0; stage < 3 && e == hipSuccess; ++stage)
-        e = issue_stage(ctx, s, f32, stage, &c->dt, 0.0, c, stage == 2, st);
+        e = issue_stage(ctx, s, f32, stage, &c->dt, 0.0, c, stage == 2 ? part : nullptr, st);
     return e;
 }
 }  // namespace
@@ -690,7 +688,7 @@ extern "C" cteno_status cteno_solve(cteno_ctx *ctx, const cteno_mesh *m, cteno_s
     h.max_steps = max_steps;
     h.dt_cand_bits = 0x7FF0000000000000ull;
     HIP_TRY(hipMemcpyAsync(dc, &h, sizeof(Ctrl), hipMemcpyHostToDevice, st));
-    HIP_TRY(launch_dt_candidate(dm, s->U[0].as<double>(), dc, st));
+    HIP_TRY(launch_dt_partials(dm, s->U[0].as<double>(), s->dt_part.as<double>(), st));
 
     // graphs need a capturable stream: the context's own stream when the
     // caller uses the null stream
@@ -714,19 +712,23 @@ extern "C" cteno_status cteno_solve(cteno_ctx *ctx, const cteno_mesh *m, cteno_s
         HIP_TRY(hipGraphInstantiate(&gx, g, nullptr, nullptr, 0));
         (void)hipGraphDestroy(g);
     }
-    const int chunk = 16;
-    for (int64_t it = 0;; ++it) {
-        for (int k = 0; k < chunk; ++k) {
+    // steps are issued in chunks between host checks of the done flag; a
+    // step issued after the march has reached t_final exits at once on the
+    // device.  No more steps than the budget are issued.
+    int64_t issued = 0;
+    while (issued < max_steps) {
+        const int64_t chunk = std::min<int64_t>(16, max_steps - issued);
+        for (int64_t k = 0; k < chunk; ++k) {
             if (graph) HIP_TRY(hipGraphLaunch(gx, gs));
             else HIP_TRY(issue_step(ctx, s, f32, gs));
         }
+        issued += chunk;
         HIP_TRY(hipMemcpyAsync(&h, dc, sizeof(Ctrl), hipMemcpyDeviceToHost, gs));
         HIP_TRY(hipStreamSynchronize(gs));
         collect_timing(ctx);
         if (h.done) break;
-        if (it > max_steps / chunk + 4) break;   // cannot happen: every step either advances or finishes
     }
-    HIP_TRY(launch_control(dc, 1, gs));
+    HIP_TRY(launch_control(dc, nullptr, 0, 1, gs));
     HIP_TRY(hipMemcpyAsync(&h, dc, sizeof(Ctrl), hipMemcpyDeviceToHost, gs));
     HIP_TRY(hipStreamSynchronize(gs));
     if (ev) {
