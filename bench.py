@@ -37,6 +37,18 @@ FLUX_BYTES = {"mixed": 24 * 4 + 12 + 9 * 4 + 8 + 3 * 32,
               "fp64": 24 * 8 + 12 + 9 * 8 + 8 + 3 * 32}
 
 
+# HBM bytes per cell and launch of the mixed reconstruction kernel measured
+# with the FETCH_SIZE / WRITE_SIZE counters (scaled by the copy-kernel
+# calibration), valid only for the kernel source they were taken on
+MEASURED_TRAFFIC = {"kernels_sha256_prefix": "34a6b442f9baea1b", "recon_mixed_bytes_per_cell": 966.7}
+
+
+def kernels_hash():
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2312_17042_amd", "csrc", "kernels.hip"), "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -143,6 +155,9 @@ def main():
     achieved = RECON_BYTES["mixed"] * N / (avg_ms * 1e-3) / 1e9
     nfl, msfl = mx["flux"]
     avg_fl = msfl / max(1, nfl)
+    traffic = None
+    if kernels_hash() == MEASURED_TRAFFIC["kernels_sha256_prefix"]:
+        traffic = MEASURED_TRAFFIC["recon_mixed_bytes_per_cell"] * N
     out = {
         "metric": "cell-stage updates/s (mixed FP32 vs FP64) at stated error; serving p50/p99",
         "value": mx["value"],
@@ -161,7 +176,7 @@ def main():
                    "cells": N, "scheme": "CTENOZ", "degree": 3, "precision": "mixed"},
         "error": err,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_reconstruct (FP32)", "bytes_per_cell": RECON_BYTES["mixed"],
                      "avg_launch_ms": avg_ms},
         "kernels": {"reconstruct_ms": avg_ms, "flux_rk_ms": avg_fl,
@@ -176,6 +191,22 @@ def main():
                        "reconstruct_ms": a64, "flux_rk_ms": msf64 / max(1, nf64),
                        "reconstruct_GBs": RECON_BYTES["fp64"] * N / (a64 * 1e-3) / 1e9}
         out["mixed_over_fp64"] = mx["value"] / f["value"]
+    # plain device copy of a known size: practical HBM ceiling, and the
+    # calibration kernel for the hardware byte counters
+    nbytes = 4 << 30
+    src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda:0").fill_(1.0)
+    dst = torch.empty_like(src)
+    ctx.copy(dst, src, nbytes)
+    torch.cuda.synchronize()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.copy(dst, src, nbytes)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / reps
+    out["copy_calibration"] = {"bytes_read": nbytes, "bytes_written": nbytes, "GBs": 2 * nbytes / el / 1e9,
+                               "kernel": "k_copy16"}
+    del src, dst
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(W)
