@@ -94,6 +94,65 @@ def cpu_baseline(W):
                       f"{el:.2f} s wall, precompute excluded"}
 
 
+def serving_bench(T, W, ctx, n_requests=256, budget_gb=4.0, max_slots=128, steps=100):
+    """Poisson stream of independent Euler solves through the continuous-batching server."""
+    import statistics
+    t0 = time.perf_counter()
+    reqs = W.serving_requests(n_requests, rate_hz=1.0, seed=4)
+    items = [W.build_request(r) for r in reqs]
+    cells = [m.n_cells for m, _ in items]
+    log(f"serving: {n_requests} requests generated ({sum(cells)} cells, {time.perf_counter() - t0:.1f}s)")
+    scheme = T.make_scheme(physics=T.EULER, scheme=T.CTENOZ, degree=3, lambda1_prime=1e4, precision=T.MIXED)
+
+    def run(arrivals):
+        srv = T.Server(ctx, scheme, budget_bytes=int(budget_gb * (1 << 30)), max_slots=max_slots)
+        tickets = []
+        start = time.perf_counter()
+        for (mesh, u0), at in zip(items, arrivals):
+            now = time.perf_counter() - start
+            if at > now:
+                time.sleep(at - now)
+            tickets.append(srv.submit(mesh, u0, steps))
+        srv.drain()
+        wall = time.perf_counter() - start
+        lat, failed = [], 0
+        for t in tickets:
+            try:
+                st, _, _, l = srv.poll(t)
+                lat.append(l)
+                srv.poll(t, take=True)
+            except T.CtenoError:
+                failed += 1
+        stats = srv.stats()
+        srv.close()
+        return wall, lat, failed, stats
+
+    wall, lat, failed, st = run([0.0] * n_requests)
+    sat = n_requests / wall
+    log(f"serving: closed loop {wall:.2f}s -> {sat:.1f} req/s, peak {st['peak_active']} resident")
+    rate = 0.7 * sat
+    arrivals = [r.arrival_s / rate for r in reqs]
+    wall, lat, failed, st = run(arrivals)
+    lat_sorted = sorted(lat)
+
+    def pct(p):
+        if not lat_sorted:
+            return None
+        k = min(len(lat_sorted) - 1, max(0, int(math.ceil(p / 100.0 * len(lat_sorted))) - 1))
+        return lat_sorted[k]
+    out = {"requests": n_requests, "steps_per_request": steps, "scheme": "CTENOZ r=3, FP32-mixed",
+           "cells_total": int(sum(cells)), "budget_bytes": int(budget_gb * (1 << 30)), "max_slots": max_slots,
+           "saturation_req_per_s": sat, "rate_hz": rate, "wall_s": wall,
+           "throughput_req_per_s": n_requests / wall,
+           "cell_stages_per_s": st["cell_stages"] / wall,
+           "p50_s": pct(50), "p99_s": pct(99),
+           "mean_s": statistics.fmean(lat) if lat else None,
+           "peak_active": st["peak_active"], "peak_bytes": st["peak_bytes"], "failed": failed,
+           "latency": "submission to result on the host (mesh/stencil build, FP64 precompute, queueing, 100 steps)"}
+    log(f"serving: Poisson {rate:.1f}/s -> p50 {out['p50_s']:.3f}s p99 {out['p99_s']:.3f}s, {failed} failed")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,6 +161,8 @@ def main():
     ap.add_argument("--n", type=int, default=2000, help="squares per side (2000 -> 8M cells)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=256)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); multi-GPU sharding is a design "
@@ -207,6 +268,8 @@ def main():
     out["copy_calibration"] = {"bytes_read": nbytes, "bytes_written": nbytes, "GBs": 2 * nbytes / el / 1e9,
                                "kernel": "k_copy16"}
     del src, dst
+    if not args.no_serving:
+        out["serving"] = serving_bench(T, W, ctx, n_requests=args.serving_requests)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(W)

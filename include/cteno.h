@@ -234,6 +234,52 @@ cteno_status cteno_solve(cteno_ctx *ctx, const cteno_mesh *mesh, cteno_sol *sol,
    CTENO_BOTH on the mesh.  Synchronises. */
 cteno_status cteno_count_flips(cteno_ctx *ctx, const cteno_mesh *mesh, const cteno_sol *sol, int64_t *flips);
 
+/* ---------------------------------------------------------------------- */
+/* serving: continuous batching of independent solves                     */
+/* ---------------------------------------------------------------------- */
+
+typedef struct {
+    int64_t submitted, finished;
+    int32_t active, peak_active;    /* solves resident on the device now / at most */
+    int64_t ticks;                  /* batched SSP-RK3 steps launched */
+    int64_t cell_stages;            /* cells x stages of finished solves */
+    int64_t bytes_in_use, peak_bytes, budget_bytes;
+} cteno_server_stats;
+
+enum { CTENO_REQ_QUEUED = 0, CTENO_REQ_READY = 1, CTENO_REQ_RUNNING = 2, CTENO_REQ_DONE = 3, CTENO_REQ_FAILED = 4 };
+
+/* Starts a server for independent 2-D Euler solves with one scheme (FP32
+   reconstruction / weights / HLLC, FP64 state; degree 2 or 3).  A host
+   thread builds each request's mesh and stencils; a scheduler thread admits
+   built requests in arrival order while at most max_slots are resident and
+   their device footprint (pseudo-inverses, geometry, state, face values,
+   plus the transient FP64 precompute of a newcomer) fits in
+   hbm_budget_bytes, runs one batched SSP-RK3 step of every resident solve per
+   tick (one launch per kernel for all of them, replayed from a HIP graph;
+   each solve keeps its own CFL time step), and returns finished solves'
+   memory so waiting requests join between ticks.  Work is issued on a
+   stream owned by the server. */
+cteno_status cteno_server_create(cteno_ctx *ctx, const cteno_scheme *scheme, size_t hbm_budget_bytes,
+                                 int32_t max_slots, cteno_server **out);
+/* Queues a solve of n_steps SSP-RK3 steps at the given CFL number from the
+   initial cell averages u0 (host [4][n_cells]); copies every input and
+   returns at once with a ticket. */
+cteno_status cteno_server_submit(cteno_server *server, const cteno_mesh_desc *desc, const double *u0,
+                                 int32_t n_steps, double cfl, uint64_t *ticket);
+/* Reports a request's state (CTENO_REQ_*).  When it is DONE: steps_done,
+   latency_s (submission to result on the host) are set and, if u_out
+   (host [4][n_cells]) is not NULL, the result is copied and the ticket is
+   released.  A FAILED request returns its error status (message in
+   cteno_last_error); polling it with u_out != NULL releases it.  Any output
+   may be NULL. */
+cteno_status cteno_server_poll(cteno_server *server, uint64_t ticket, int32_t *state, double *u_out,
+                               int64_t *steps_done, double *latency_s);
+/* Blocks until every submitted request has finished or failed. */
+cteno_status cteno_server_drain(cteno_server *server);
+cteno_status cteno_server_get_stats(cteno_server *server, cteno_server_stats *stats);
+/* Stops the threads (queued requests are dropped) and frees everything. */
+void cteno_server_destroy(cteno_server *server);
+
 /* Device copy kernel used to calibrate hardware byte counters: copies
    n_bytes (multiple of 16) from src to dst on the context stream. */
 cteno_status cteno_util_copy(cteno_ctx *ctx, void *dst, const void *src, size_t n_bytes);

@@ -54,10 +54,31 @@ struct FluxLaunch {
 };
 hipError_t launch_flux(const DeviceMesh &m, bool fp32, const FluxLaunch &f, hipStream_t st);
 
-// per-block minima of the CFL bound of state U into dt_part[blocks()]
-hipError_t launch_dt_partials(const DeviceMesh &m, const double *U, double *dt_part, hipStream_t st);
+// per-block minima of the CFL bound of state U into dt_part[blocks()], from the
+// face records of the stage kernels' precision (fp32) so a march's first step
+// uses the same geometry as its later steps
+hipError_t launch_dt_partials(const DeviceMesh &m, bool fp32, const double *U, double *dt_part, hipStream_t st);
 // step control; reduces dt_part[n_part] unless commit_only
 hipError_t launch_control(Ctrl *ctrl, const double *dt_part, int64_t n_part, int commit_only, hipStream_t st);
+
+// device descriptor of one active serving slot (one independent solve)
+struct BatchSlot {
+    int64_t N, block0, nblocks;     // cells; first global block; blocks of 256 cells
+    const int32_t *slot;
+    const uint8_t *flags;
+    const float *P;                 // FP32 pseudo-inverse stream
+    const float *fr;                // FP32 face records
+    const double *area;
+    double *U[3];                   // U^n, U^(1), U^(2)
+    float *FV;
+    double *dt_part;                // [nblocks]
+    Ctrl *ctrl;
+};
+// one SSP-RK3 step (control + 3 x (reconstruction, flux/RK)) of every slot in
+// tab[0 .. *n_slots); grids of max_slots and max_blocks blocks (blocks past the
+// active range exit at once).  FP32 reconstruction/flux, Euler, r = 2 or 3.
+hipError_t launch_batch_step(const DeviceMesh &proto, const BatchSlot *tab, const int *n_slots, int max_slots,
+                             int64_t max_blocks, hipStream_t st);
 
 // layout conversions between caller order/layout and internal order/layout
 hipError_t launch_user_to_state(const DeviceMesh &m, const double *user, double *state, hipStream_t st);

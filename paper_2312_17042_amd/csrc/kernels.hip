@@ -26,6 +26,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cfloat>
+#include <cstring>
 #include <cmath>
 #include <type_traits>
 
@@ -495,8 +496,22 @@ __device__ __forceinline__ int teno_bits(const real si[4], int adm, int st, real
     return bits;
 }
 
+// per-mesh arrays of one reconstruction (the constants stay in ReconArgs)
+template <typename real>
+struct ReconPtrs {
+    const double *U;
+    const int32_t *slot;
+    const uint8_t *flags;
+    const real *P;
+    real *FV;
+    uint8_t *delta;
+};
+
 template <typename real, int R, int NV, int SCHEME, int GFORM, int DMODE>
-__global__ __launch_bounds__(256) void k_reconstruct(const ReconArgs<real, (R + 1) * (R + 2) / 2 - 1> a) {
+__device__ __forceinline__ void recon_body(const ReconArgs<real, (R + 1) * (R + 2) / 2 - 1> a,
+                                           const ReconPtrs<real> ptr, int64_t i) {
+    // a and ptr by value: a reference to the kernel-argument struct would make
+    // the compiler copy it to scratch memory
     constexpr int K = (R + 1) * (R + 2) / 2 - 1;
     constexpr int M = 2 * K;
     constexpr int S = M > 12 ? M : 12;
@@ -504,17 +519,14 @@ __global__ __launch_bounds__(256) void k_reconstruct(const ReconArgs<real, (R + 
     using V = typename Vec<real>::T;
     constexpr int VW = Vec<real>::W;
     constexpr int E = (pinv_offset(S, K) + VW - 1) / VW * VW;
-    const int64_t i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (i >= a.N) return;
-    if (a.done && *a.done) return;
 
     // this cell's streams: vector g of the pseudo-inverse at Pv[g * 64]
-    const V *__restrict__ Pv = reinterpret_cast<const V *>(a.P) + (size_t)(i >> 6) * (E / VW) * 64 + (i & 63);
-    const int4 *__restrict__ Sv = reinterpret_cast<const int4 *>(a.slot) + (size_t)(i >> 6) * (SP / 4) * 64 + (i & 63);
+    const V *__restrict__ Pv = reinterpret_cast<const V *>(ptr.P) + (size_t)(i >> 6) * (E / VW) * 64 + (i & 63);
+    const int4 *__restrict__ Sv = reinterpret_cast<const int4 *>(ptr.slot) + (size_t)(i >> 6) * (SP / 4) * 64 + (i & 63);
 
     double U0[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) U0[v] = a.U[i * NV + v];
+    for (int v = 0; v < NV; ++v) U0[v] = ptr.U[i * NV + v];
 
     real ao[K][NV], ad[3][2][NV];
 #pragma unroll
@@ -556,7 +568,7 @@ __global__ __launch_bounds__(256) void k_reconstruct(const ReconArgs<real, (R + 
         for (int t = 0; t < 4; ++t) {
             const int64_t m = comp(sl, t);
             real d[NV];
-            gather_diff<NV>(a.U, m, U0, d);
+            gather_diff<NV>(ptr.U, m, U0, d);
 #pragma unroll
             for (int q = 0; q < K + 2; ++q) {
                 const int el = t * (K + 2) + q;
@@ -598,7 +610,7 @@ __global__ __launch_bounds__(256) void k_reconstruct(const ReconArgs<real, (R + 
                 const int j = 12 + t;
                 const int64_t m = comp(slv[j / 4], j % 4);
                 real d[NV];
-                gather_diff<NV>(a.U, m, U0, d);
+                gather_diff<NV>(ptr.U, m, U0, d);
 #pragma unroll
                 for (int q = 0; q < K; ++q) {
                     const int e = T0 + t * K + q;
@@ -611,10 +623,13 @@ __global__ __launch_bounds__(256) void k_reconstruct(const ReconArgs<real, (R + 
         }
     }
 
-    const int fl = a.flags[i] & 7;
+    const int fl = ptr.flags[i] & 7;
     const int adm = 1 | (fl << 1);
     const int st = 1 + __popc(fl);
-    const real lams = a.lams[st];
+    // static indices only: a dynamic index into the argument struct would
+    // force it into scratch memory
+    const real lams = st == 2 ? a.lams[2] : (st == 3 ? a.lams[3] : a.lams[4]);
+    const real lratio = st == 2 ? a.lam_ratio[2] : (st == 3 ? a.lam_ratio[3] : a.lam_ratio[4]);
     real out[3][2][NV];
     uint32_t dword = 0;
 #pragma unroll
@@ -633,7 +648,7 @@ __global__ __launch_bounds__(256) void k_reconstruct(const ReconArgs<real, (R + 
         }
         int bits;
         if (DMODE == 2) {
-            bits = a.delta[i * NV + v] & adm;
+            bits = ptr.delta[i * NV + v] & adm;
         } else if (st == 1) {
             bits = 1;
         } else {
@@ -652,7 +667,7 @@ __global__ __launch_bounds__(256) void k_reconstruct(const ReconArgs<real, (R + 
                 const real x0 = ad[q][0][v], x1 = ad[q][1][v];
                 si[q + 1] = x0 * (a.gram[0][0] * x0 + a.gram[0][1] * x1) + x1 * (a.gram[1][0] * x0 + a.gram[1][1] * x1);
             }
-            bits = teno_bits<real, SCHEME, GFORM>(si, adm, st, a.lam1, lams, a.lam_ratio[st], a.ct, a.eps);
+            bits = teno_bits<real, SCHEME, GFORM>(si, adm, st, a.lam1, lams, lratio, a.ct, a.eps);
         }
         dword |= (uint32_t)bits << (8 * v);
         real fin[K];
@@ -680,7 +695,7 @@ __global__ __launch_bounds__(256) void k_reconstruct(const ReconArgs<real, (R + 
                 out[f][q][v] = (real)(U0[v] + (double)val);
             }
     }
-    if (NV == 4) {
+    if constexpr (NV == 4) {
         // positivity fallback: a cell with a non-physical state (density or
         // pressure <= 0) at any of its Gauss points uses its cell average at
         // all of them; reported with bit 7 of its selection bytes
@@ -706,9 +721,40 @@ __global__ __launch_bounds__(256) void k_reconstruct(const ReconArgs<real, (R + 
     }
     if (DMODE == 1) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) a.delta[i * NV + v] = (uint8_t)(dword >> (8 * v));
+        for (int v = 0; v < NV; ++v) ptr.delta[i * NV + v] = (uint8_t)(dword >> (8 * v));
     }
-    store_row<real, 3 * 2 * NV>(a.FV + i * 3 * 2 * NV, &out[0][0][0]);
+    store_row<real, 3 * 2 * NV>(ptr.FV + i * 3 * 2 * NV, &out[0][0][0]);
+}
+
+template <typename real, int R, int NV, int SCHEME, int GFORM, int DMODE>
+__global__ __launch_bounds__(256) void k_reconstruct(const ReconArgs<real, (R + 1) * (R + 2) / 2 - 1> a) {
+    const int64_t i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (i >= a.N) return;
+    if (a.done && *a.done) return;
+    const ReconPtrs<real> ptr{a.U, a.slot, a.flags, a.P, a.FV, a.delta};
+    recon_body<real, R, NV, SCHEME, GFORM, DMODE>(a, ptr, i);
+}
+
+// scheme constants of the reconstruction (tables of the reference triangle,
+// linear weights of eq. e18 for every admissible-stencil count)
+template <typename real, int K>
+static void fill_recon_constants(const DeviceMesh &m, ReconArgs<real, K> &a) {
+    a.N = m.N;
+    for (int p = 0; p < K; ++p)
+        for (int q = 0; q < K; ++q) a.gram[p][q] = (real)m.tab.gram[p][q];
+    for (int f = 0; f < 3; ++f)
+        for (int q = 0; q < 2; ++q)
+            for (int k = 0; k < K; ++k) a.basis[f][q][k] = (real)m.tab.basis[f][q][k];
+    const double lam1 = 1.0 - 1.0 / m.lam1p;
+    a.lam1 = (real)lam1;
+    a.gamma = (real)m.gamma;
+    a.ct = (real)m.ct;
+    a.eps = (real)m.eps;
+    for (int s = 0; s < 5; ++s) {
+        const double ls = s >= 2 ? (1.0 - lam1) / (s - 1) : 0.0;
+        a.lams[s] = (real)ls;
+        a.lam_ratio[s] = s >= 2 ? (real)(lam1 / ls) : (real)1;
+    }
 }
 
 template <typename real, int R, int NV>
@@ -726,21 +772,7 @@ static hipError_t reconstruct_t(const DeviceMesh &m, const double *U, void *FV, 
     a.FV = (real *)FV;
     a.delta = delta;
     a.done = done;
-    for (int p = 0; p < K; ++p)
-        for (int q = 0; q < K; ++q) a.gram[p][q] = (real)m.tab.gram[p][q];
-    for (int f = 0; f < 3; ++f)
-        for (int q = 0; q < 2; ++q)
-            for (int k = 0; k < K; ++k) a.basis[f][q][k] = (real)m.tab.basis[f][q][k];
-    const double lam1 = 1.0 - 1.0 / m.lam1p;
-    a.lam1 = (real)lam1;
-    a.gamma = (real)m.gamma;
-    a.ct = (real)m.ct;
-    a.eps = (real)m.eps;
-    for (int s = 0; s < 5; ++s) {
-        const double ls = s >= 2 ? (1.0 - lam1) / (s - 1) : 0.0;
-        a.lams[s] = (real)ls;
-        a.lam_ratio[s] = s >= 2 ? (real)(lam1 / ls) : (real)1;
-    }
+    fill_recon_constants<real, K>(m, a);
     const unsigned grid = (unsigned)m.blocks();
 #define CT_LAUNCH(SCH, GF, DM) hipLaunchKernelGGL((k_reconstruct<real, R, NV, SCH, GF, DM>), dim3(grid), dim3(256), 0, st, a)
 #define CT_DM(SCH, GF)              \
@@ -906,25 +938,39 @@ __device__ __forceinline__ double block_min(double v) {
     return r;
 }
 
+// per-mesh arrays of one flux / residual / RK launch (constants stay in FluxArgs)
+template <typename real>
+struct FluxPtrs {
+    const real *FV;
+    const real *fr;
+    const double *area;
+    const double *Un, *Us;
+    double *Uout;
+    const double *dt_ptr;
+    real *flux_out;
+    double *resid;
+    Ctrl *ctrl;
+    bool want_dt;
+};
+
+// one cell's three faces, residual and (MODE 2) RK stage; returns the cell's
+// CFL bound of the new state when requested, else +inf
 template <typename real, int NV, int PHYS, int MODE>
-__global__ __launch_bounds__(256) void k_flux(const FluxArgs<real> a) {
-    const int64_t i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    const bool active = i < a.N;
-    if (a.ctrl && a.ctrl->done) return;        // uniform across the grid
+__device__ __forceinline__ double flux_body(const FluxArgs<real> a, const FluxPtrs<real> ptr, int64_t i) {
     double dtc = INFINITY;
-    if (active) {
+    {
         double acc[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) acc[v] = 0.0;
         double nrm[3][3];
         bool bad = false;
         real own[3][2][NV];
-        load_row<real, 3 * 2 * NV>(a.FV + i * 3 * 2 * NV, &own[0][0][0]);
+        load_row<real, 3 * 2 * NV>(ptr.FV + i * 3 * 2 * NV, &own[0][0][0]);
 #pragma unroll
         for (int f = 0; f < 3; ++f) {
             real nx, ny, len;
             uint32_t code;
-            face_record<real>(a.fr, i, f, nx, ny, len, code);
+            face_record<real>(ptr.fr, i, f, nx, ny, len, code);
             nrm[f][0] = (double)nx; nrm[f][1] = (double)ny; nrm[f][2] = (double)len;
             real oth[2][NV];
             bool owner;
@@ -946,7 +992,7 @@ __global__ __launch_bounds__(256) void k_flux(const FluxArgs<real> a) {
                 owner = (code & kNbOwner) != 0;
                 const int64_t j = code & kNbIndexMask;
                 const int g = (code >> 28) & 3;
-                load_row<real, 2 * NV>(a.FV + (j * 3 + g) * 2 * NV, &oth[0][0]);
+                load_row<real, 2 * NV>(ptr.FV + (j * 3 + g) * 2 * NV, &oth[0][0]);
             }
             // both cells of a face evaluate F(owner side, other side; owner normal)
             // at the owner's Gauss points in the owner's order
@@ -976,27 +1022,27 @@ __global__ __launch_bounds__(256) void k_flux(const FluxArgs<real> a) {
                 const double val = (double)(len * sumF[v]);
                 const double out = owner ? val : -val;
                 acc[v] += out;
-                if (MODE == 0) a.flux_out[(i * 3 + f) * NV + v] = (real)out;
+                if (MODE == 0) ptr.flux_out[(i * 3 + f) * NV + v] = (real)out;
             }
         }
-        if (bad && a.ctrl) atomicOr(&a.ctrl->nonphysical, 1);
+        if (bad && ptr.ctrl) atomicOr(&ptr.ctrl->nonphysical, 1);
         if (MODE == 1) {
 #pragma unroll
-            for (int v = 0; v < NV; ++v) a.resid[i * NV + v] = -acc[v] / a.area[i];
+            for (int v = 0; v < NV; ++v) ptr.resid[i * NV + v] = -acc[v] / ptr.area[i];
         }
         if (MODE == 2) {
-            const double dt = a.dt_ptr ? *a.dt_ptr : a.dt_value;
-            const double ar = a.area[i];
+            const double dt = ptr.dt_ptr ? *ptr.dt_ptr : a.dt_value;
+            const double ar = ptr.area[i];
             double u0[NV], us[NV], un[NV];
             if constexpr (NV == 4) {
-                const double2 *U2 = reinterpret_cast<const double2 *>(a.Un);
-                const double2 *S2 = reinterpret_cast<const double2 *>(a.Us);
+                const double2 *U2 = reinterpret_cast<const double2 *>(ptr.Un);
+                const double2 *S2 = reinterpret_cast<const double2 *>(ptr.Us);
                 const double2 x0 = U2[2 * i], x1 = U2[2 * i + 1], y0 = S2[2 * i], y1 = S2[2 * i + 1];
                 u0[0] = x0.x; u0[1] = x0.y; u0[2] = x1.x; u0[3] = x1.y;
                 us[0] = y0.x; us[1] = y0.y; us[2] = y1.x; us[3] = y1.y;
             } else {
 #pragma unroll
-                for (int v = 0; v < NV; ++v) { u0[v] = a.Un[i * NV + v]; us[v] = a.Us[i * NV + v]; }
+                for (int v = 0; v < NV; ++v) { u0[v] = ptr.Un[i * NV + v]; us[v] = ptr.Us[i * NV + v]; }
             }
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
@@ -1008,16 +1054,27 @@ __global__ __launch_bounds__(256) void k_flux(const FluxArgs<real> a) {
                 un[v] = r;
             }
             if constexpr (NV == 4) {
-                double2 *O2 = reinterpret_cast<double2 *>(a.Uout);
+                double2 *O2 = reinterpret_cast<double2 *>(ptr.Uout);
                 O2[2 * i] = make_double2(un[0], un[1]);
                 O2[2 * i + 1] = make_double2(un[2], un[3]);
             } else {
 #pragma unroll
-                for (int v = 0; v < NV; ++v) a.Uout[i * NV + v] = un[v];
+                for (int v = 0; v < NV; ++v) ptr.Uout[i * NV + v] = un[v];
             }
-            if (a.dt_part) dtc = cell_dt_bound<NV, PHYS>(un, nrm, ar, a.gamma64, (double)a.ax, (double)a.ay);
+            if (ptr.want_dt) dtc = cell_dt_bound<NV, PHYS>(un, nrm, ar, a.gamma64, (double)a.ax, (double)a.ay);
         }
     }
+    return dtc;
+}
+
+template <typename real, int NV, int PHYS, int MODE>
+__global__ __launch_bounds__(256) void k_flux(const FluxArgs<real> a) {
+    const int64_t i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (a.ctrl && a.ctrl->done) return;        // uniform across the grid
+    const FluxPtrs<real> ptr{a.FV, a.fr, a.area, a.Un, a.Us, a.Uout, a.dt_ptr, a.flux_out, a.resid, a.ctrl,
+                             a.dt_part != nullptr};
+    double dtc = INFINITY;
+    if (i < a.N) dtc = flux_body<real, NV, PHYS, MODE>(a, ptr, i);
     if (MODE == 2 && a.dt_part) {
         const double bm = block_min(dtc);
         if (threadIdx.x == 0) a.dt_part[blockIdx.x] = bm;
@@ -1060,8 +1117,8 @@ hipError_t launch_flux(const DeviceMesh &m, bool fp32, const FluxLaunch &f, hipS
 // time-step control
 // ===========================================================================
 
-template <int NV, int PHYS>
-__global__ __launch_bounds__(256) void k_dt_partials(int64_t N, const double *U, const double *fr, const double *area,
+template <typename real, int NV, int PHYS>
+__global__ __launch_bounds__(256) void k_dt_partials(int64_t N, const double *U, const real *fr, const double *area,
                                                      double gamma, double ax, double ay, double *part) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double dtc = INFINITY;
@@ -1071,9 +1128,9 @@ __global__ __launch_bounds__(256) void k_dt_partials(int64_t N, const double *U,
         for (int v = 0; v < NV; ++v) u[v] = U[i * NV + v];
 #pragma unroll
         for (int f = 0; f < 3; ++f) {
-            double nx, ny, len;
+            real nx, ny, len;
             uint32_t code;
-            face_record<double>(fr, i, f, nx, ny, len, code);
+            face_record<real>(fr, i, f, nx, ny, len, code);
             nrm[f][0] = nx; nrm[f][1] = ny; nrm[f][2] = len;
         }
         dtc = cell_dt_bound<NV, PHYS>(u, nrm, area[i], gamma, ax, ay);
@@ -1082,34 +1139,27 @@ __global__ __launch_bounds__(256) void k_dt_partials(int64_t N, const double *U,
     if (threadIdx.x == 0) part[blockIdx.x] = bm;
 }
 
-hipError_t launch_dt_partials(const DeviceMesh &m, const double *U, double *part, hipStream_t st) {
+hipError_t launch_dt_partials(const DeviceMesh &m, bool fp32, const double *U, double *part, hipStream_t st) {
     const unsigned grid = (unsigned)m.blocks();
-    if (m.physics == CTENO_EULER)
-        hipLaunchKernelGGL((k_dt_partials<4, CTENO_EULER>), dim3(grid), dim3(256), 0, st, m.N, U, m.fr64, m.area,
-                           m.gamma, m.ax, m.ay, part);
-    else
-        hipLaunchKernelGGL((k_dt_partials<1, CTENO_ADVECTION>), dim3(grid), dim3(256), 0, st, m.N, U, m.fr64,
-                           m.area, m.gamma, m.ax, m.ay, part);
+    const bool f32 = (fp32 && m.fr32) || m.fr64 == nullptr;
+    if (m.physics == CTENO_EULER) {
+        if (f32) hipLaunchKernelGGL((k_dt_partials<float, 4, CTENO_EULER>), dim3(grid), dim3(256), 0, st, m.N, U,
+                                    m.fr32, m.area, m.gamma, m.ax, m.ay, part);
+        else hipLaunchKernelGGL((k_dt_partials<double, 4, CTENO_EULER>), dim3(grid), dim3(256), 0, st, m.N, U,
+                                m.fr64, m.area, m.gamma, m.ax, m.ay, part);
+    } else {
+        if (f32) hipLaunchKernelGGL((k_dt_partials<float, 1, CTENO_ADVECTION>), dim3(grid), dim3(256), 0, st, m.N, U,
+                                    m.fr32, m.area, m.gamma, m.ax, m.ay, part);
+        else hipLaunchKernelGGL((k_dt_partials<double, 1, CTENO_ADVECTION>), dim3(grid), dim3(256), 0, st, m.N, U,
+                                m.fr64, m.area, m.gamma, m.ax, m.ay, part);
+    }
     return hipGetLastError();
 }
 
-// Step control, one block.  Commits the pending step (t <- t_next), then
-// decides the next one exactly as: stop when t >= t_final or the step
-// budget is used; dt = cfl * (minimum over cells of the bound, reduced from
-// the per-block minima); clip the last step onto t_final.
-__global__ __launch_bounds__(1024) void k_control(Ctrl *c, const double *part, int64_t n_part, int commit_only) {
-    __shared__ double red[16];
-    const bool reduce = !commit_only && !c->done;
-    double v = INFINITY;
-    if (reduce)
-        for (int64_t k = threadIdx.x; k < n_part; k += blockDim.x) v = fmin(v, part[k]);
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    double bound = INFINITY;
-    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) bound = fmin(bound, red[k]);
+// Commits the pending step (t <- t_next), then decides the next one exactly
+// as: stop when t >= t_final or the step budget is used; dt = cfl * bound;
+// clip the last step onto t_final.
+__device__ void control_logic(Ctrl *c, double bound, int commit_only) {
     if (c->pending) {
         c->t = c->t_next;
         c->step += 1;
@@ -1136,9 +1186,122 @@ __global__ __launch_bounds__(1024) void k_control(Ctrl *c, const double *part, i
     c->pending = 1;
 }
 
+// minimum of part[0..n) over the block (valid in thread 0)
+__device__ __forceinline__ double block_min_array(const double *part, int64_t n, bool reduce) {
+    __shared__ double red[16];
+    double v = INFINITY;
+    if (reduce)
+        for (int64_t k = threadIdx.x; k < n; k += blockDim.x) v = fmin(v, part[k]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double bound = INFINITY;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) bound = fmin(bound, red[k]);
+    return bound;
+}
+
+// Step control of one march, one block: the bound is the minimum of the
+// per-block minima left by the last stage (or by k_dt_partials).
+__global__ __launch_bounds__(1024) void k_control(Ctrl *c, const double *part, int64_t n_part, int commit_only) {
+    const bool reduce = !commit_only && !c->done;
+    const double bound = block_min_array(part, n_part, reduce);
+    if (threadIdx.x == 0) control_logic(c, bound, commit_only);
+}
+
 hipError_t launch_control(Ctrl *ctrl, const double *part, int64_t n_part, int commit_only, hipStream_t st) {
     hipLaunchKernelGGL(k_control, dim3(1), dim3(1024), 0, st, ctrl, part, n_part, commit_only);
     return hipGetLastError();
+}
+
+// ===========================================================================
+// batched serving kernels: one launch covers every active solve (slot)
+// ===========================================================================
+
+// slot of global block b: slots hold consecutive block ranges in table order
+__device__ __forceinline__ int find_slot(const BatchSlot *tab, int n, int64_t b) {
+    for (int k = 0; k < n; ++k)
+        if (b < tab[k].block0 + tab[k].nblocks) return b >= tab[k].block0 ? k : -1;
+    return -1;
+}
+
+template <int R, int SCHEME, int GFORM>
+__global__ __launch_bounds__(256) void k_reconstruct_batch(const ReconArgs<float, (R + 1) * (R + 2) / 2 - 1> a,
+                                                           const BatchSlot *tab, const int *n_slots, int stage) {
+    const int64_t b = blockIdx.x;
+    const int s = find_slot(tab, *n_slots, b);
+    if (s < 0) return;
+    const BatchSlot &t = tab[s];
+    if (t.ctrl->done) return;
+    const int64_t i = (b - t.block0) * blockDim.x + threadIdx.x;
+    if (i >= t.N) return;
+    const ReconPtrs<float> ptr{t.U[stage], t.slot, t.flags, t.P, t.FV, nullptr};
+    recon_body<float, R, 4, SCHEME, GFORM, 0>(a, ptr, i);
+}
+
+__global__ __launch_bounds__(256) void k_flux_batch(const FluxArgs<float> a, const BatchSlot *tab, const int *n_slots) {
+    const int64_t b = blockIdx.x;
+    const int s = find_slot(tab, *n_slots, b);
+    if (s < 0) return;
+    const BatchSlot &t = tab[s];
+    if (t.ctrl->done) return;                 // uniform across the block
+    const int stage = a.stage;
+    const int64_t local = b - t.block0;
+    const int64_t i = local * blockDim.x + threadIdx.x;
+    const FluxPtrs<float> ptr{t.FV, t.fr, t.area, t.U[0], t.U[stage], stage == 2 ? t.U[0] : t.U[stage + 1],
+                              &t.ctrl->dt, nullptr, nullptr, t.ctrl, stage == 2};
+    double dtc = INFINITY;
+    if (i < t.N) dtc = flux_body<float, 4, CTENO_EULER, 2>(a, ptr, i);
+    if (stage == 2) {
+        const double bm = block_min(dtc);
+        if (threadIdx.x == 0) t.dt_part[local] = bm;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_control_batch(const BatchSlot *tab, const int *n_slots) {
+    if ((int)blockIdx.x >= *n_slots) return;
+    const BatchSlot &t = tab[blockIdx.x];
+    const bool reduce = !t.ctrl->done;
+    const double bound = block_min_array(t.dt_part, t.nblocks, reduce);
+    if (threadIdx.x == 0) control_logic(t.ctrl, bound, 0);
+}
+
+template <int R>
+static hipError_t batch_step_r(const DeviceMesh &proto, const BatchSlot *tab, const int *n_slots, int max_slots,
+                               int64_t max_blocks, hipStream_t st) {
+    constexpr int K = (R + 1) * (R + 2) / 2 - 1;
+    ReconArgs<float, K> ra;
+    std::memset(&ra, 0, sizeof ra);
+    fill_recon_constants<float, K>(proto, ra);
+    FluxArgs<float> fa;
+    std::memset(&fa, 0, sizeof fa);
+    fa.gamma = (float)proto.gamma; fa.ax = (float)proto.ax; fa.ay = (float)proto.ay; fa.gamma64 = proto.gamma;
+    hipLaunchKernelGGL(k_control_batch, dim3(max_slots), dim3(1024), 0, st, tab, n_slots);
+    for (int stage = 0; stage < 3; ++stage) {
+        if (proto.scheme == CTENO_SCHEME_CTENOZ)
+            hipLaunchKernelGGL((k_reconstruct_batch<R, CTENO_SCHEME_CTENOZ, CTENO_GAMMA_PAPER>), dim3(max_blocks),
+                               dim3(256), 0, st, ra, tab, n_slots, stage);
+        else if (proto.gamma_form == CTENO_GAMMA_LAMBDA)
+            hipLaunchKernelGGL((k_reconstruct_batch<R, CTENO_SCHEME_CTENO, CTENO_GAMMA_LAMBDA>), dim3(max_blocks),
+                               dim3(256), 0, st, ra, tab, n_slots, stage);
+        else
+            hipLaunchKernelGGL((k_reconstruct_batch<R, CTENO_SCHEME_CTENO, CTENO_GAMMA_PAPER>), dim3(max_blocks),
+                               dim3(256), 0, st, ra, tab, n_slots, stage);
+        fa.stage = stage;
+        hipLaunchKernelGGL(k_flux_batch, dim3(max_blocks), dim3(256), 0, st, fa, tab, n_slots);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_step(const DeviceMesh &proto, const BatchSlot *tab, const int *n_slots, int max_slots,
+                             int64_t max_blocks, hipStream_t st) {
+    if (proto.nv != 4 || proto.physics != CTENO_EULER) return hipErrorInvalidValue;
+    switch (proto.r) {
+        case 2: return batch_step_r<2>(proto, tab, n_slots, max_slots, max_blocks, st);
+        case 3: return batch_step_r<3>(proto, tab, n_slots, max_slots, max_blocks, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 // ===========================================================================

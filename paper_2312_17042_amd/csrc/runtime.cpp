@@ -3,6 +3,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -220,10 +226,7 @@ hipError_t h2d(T *dst, const std::vector<T> &src, hipStream_t st) {
 }
 }  // namespace
 
-extern "C" cteno_status cteno_mesh_upload(cteno_ctx *ctx, const cteno_mesh_desc *desc, const cteno_scheme *scheme,
-                                          cteno_mesh **out) {
-    if (!ctx || !desc || !scheme || !out) return fail(CTENO_ERR_INVALID, "NULL argument");
-    const cteno_scheme &s = *scheme;
+static cteno_status check_scheme(const cteno_scheme &s) {
     if (s.physics != CTENO_ADVECTION && s.physics != CTENO_EULER) return fail(CTENO_ERR_INVALID, "bad physics");
     if (s.scheme != CTENO_SCHEME_CTENO && s.scheme != CTENO_SCHEME_CTENOZ) return fail(CTENO_ERR_INVALID, "bad scheme");
     if (s.degree < 2 || s.degree > 3) return fail(CTENO_ERR_INVALID, "degree must be 2 or 3");
@@ -231,38 +234,42 @@ extern "C" cteno_status cteno_mesh_upload(cteno_ctx *ctx, const cteno_mesh_desc 
     if (!(s.lambda1_prime > 1.0) || !(s.c_t > 0 && s.c_t < 1) || !(s.eps > 0))
         return fail(CTENO_ERR_INVALID, "bad lambda1_prime, c_t or eps");
     if (s.physics == CTENO_EULER && !(s.gamma > 1.0)) return fail(CTENO_ERR_INVALID, "bad gamma");
-    HIP_TRY(hipSetDevice(ctx->device));
+    return CTENO_OK;
+}
 
-    auto m = std::make_unique<cteno_mesh>();
-    m->ctx = ctx;
-    m->scheme = s;
-    std::string err;
-    cteno_status rc = build_host_mesh(*desc, s, m->host, err);
-    if (rc != CTENO_OK) return fail(rc, err);
-    HostMesh &hm = m->host;
-    DeviceMesh &dm = m->dm;
+// Uploads a host-built mesh: device arrays, FP64 precompute of the
+// pseudo-inverses (plus the FP32 copy for MIXED), admissibility fix-up.
+// Allocations are appended to bufs; their size is added to bytes.
+static cteno_status upload_device_mesh(cteno_ctx *ctx, hipStream_t st, HostMesh &hm, const cteno_scheme &s,
+                                       DeviceMesh &dm, std::vector<DevBuf> &bufs, int64_t &bytes, bool keep_fr64) {
+    auto alloc_raw = [&](size_t n) -> void * {
+        bufs.emplace_back(ctx, n);
+        if (!bufs.back().p) return nullptr;
+        bytes += (int64_t)n;
+        return bufs.back().p;
+    };
+    auto allocator = [&](auto *tag, size_t count) { return (decltype(tag))alloc_raw(count * sizeof(*tag)); };
+#define alloc_T(T, n) allocator((T *)nullptr, (n))
     dm.N = hm.N; dm.Np = pad64(hm.N);
     dm.r = hm.r; dm.K = hm.K; dm.S = hm.S; dm.nv = hm.nv;
     dm.physics = s.physics; dm.scheme = s.scheme; dm.gamma_form = s.gamma_form; dm.precision = s.precision;
     dm.gamma = s.gamma; dm.ax = s.ax; dm.ay = s.ay; dm.lam1p = s.lambda1_prime; dm.ct = s.c_t; dm.eps = s.eps;
     dm.Lx = hm.Lx; dm.Ly = hm.Ly;
     make_ref_tables(hm.r, dm.tab);
-
     const size_t Np = (size_t)dm.Np, S = hm.S;
     dm.SP = hm.SP;
     dm.E64 = round_up(pinv_entries(hm.r), 2);
     dm.E32 = round_up(pinv_entries(hm.r), 4);
-    hipStream_t st = ctx->stream();
-    dm.slot = m->alloc<int32_t>(Np * hm.SP);
-    dm.flags = m->alloc<uint8_t>(Np);
-    dm.fr64 = m->alloc<double>(Np * 12);
-    dm.area = m->alloc<double>(Np);
-    dm.perm = m->alloc<int32_t>((size_t)hm.N);
+    dm.slot = alloc_T(int32_t, Np * hm.SP);
+    dm.flags = alloc_T(uint8_t, Np);
+    dm.fr64 = keep_fr64 ? alloc_T(double, Np * 12) : nullptr;
+    dm.area = alloc_T(double, Np);
+    dm.perm = alloc_T(int32_t, (size_t)hm.N);
     if (s.precision & CTENO_MIXED) {
-        dm.fr32 = m->alloc<float>(Np * 12);
-        dm.P32 = m->alloc<float>(Np * dm.E32);
+        dm.fr32 = alloc_T(float, Np * 12);
+        dm.P32 = alloc_T(float, Np * dm.E32);
     }
-    if (!dm.slot || !dm.flags || !dm.fr64 || !dm.area || !dm.perm ||
+    if (!dm.slot || !dm.flags || (keep_fr64 && !dm.fr64) || !dm.area || !dm.perm ||
         ((s.precision & CTENO_MIXED) && (!dm.fr32 || !dm.P32)))
         return fail(CTENO_ERR_NOMEM, "device allocation failed");
     // FP64 pseudo-inverses are always computed; kept only when FP64 is resident
@@ -274,7 +281,7 @@ extern "C" cteno_status cteno_mesh_upload(cteno_ctx *ctx, const cteno_mesh_desc 
 
     HIP_TRY(h2d(dm.slot, hm.slot, st));
     HIP_TRY(h2d(dm.flags, hm.flags, st));
-    HIP_TRY(h2d(dm.fr64, hm.fr64, st));
+    if (dm.fr64) HIP_TRY(h2d(dm.fr64, hm.fr64, st));
     if (dm.fr32) HIP_TRY(h2d(dm.fr32, hm.fr32, st));
     HIP_TRY(h2d(dm.area, hm.area, st));
     HIP_TRY(h2d(dm.perm, hm.perm, st));
@@ -287,13 +294,15 @@ extern "C" cteno_status cteno_mesh_upload(cteno_ctx *ctx, const cteno_mesh_desc 
     if (dm.P32) HIP_TRY(hipMemsetAsync(dm.P32, 0, Np * dm.E32 * sizeof(float), st));
 
     PrecomputeInputs in{verts.as<double>(), sflag.as<uint8_t>(), sshift.as<int8_t>(), dm.flags, rfail.as<int>()};
-    HIP_TRY(timed(ctx, 2, [&] { return launch_precompute(dm, in, st); }));
+    // kernel timing belongs to the context's own stream and thread
+    if (st == ctx->stream()) HIP_TRY(timed(ctx, 2, [&] { return launch_precompute(dm, in, st); }));
+    else HIP_TRY(launch_precompute(dm, in, st));
     int rank_fail = 0;
     std::vector<uint8_t> flags(Np);
     HIP_TRY(hipMemcpyAsync(&rank_fail, rfail.p, sizeof(int), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(flags.data(), dm.flags, Np, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    collect_timing(ctx);
+    if (st == ctx->stream()) collect_timing(ctx);
     if (rank_fail) return fail(CTENO_ERR_STENCIL, std::to_string(rank_fail) + " rank-deficient central stencils");
     // directional stencils found rank-deficient on the device become inadmissible
     for (int k = 0; k < hm.N; ++k) {
@@ -307,8 +316,8 @@ extern "C" cteno_status cteno_mesh_upload(cteno_ctx *ctx, const cteno_mesh_desc 
         hm.flags[k] = flags[k];
     }
     if (s.precision & CTENO_FP64) {
-        m->bytes += (int64_t)p64.bytes;
-        m->bufs.push_back(std::move(p64));
+        bytes += (int64_t)p64.bytes;
+        bufs.push_back(std::move(p64));
     } else {
         dm.P64 = nullptr;
     }
@@ -319,6 +328,24 @@ extern "C" cteno_status cteno_mesh_upload(cteno_ctx *ctx, const cteno_mesh_desc 
     hm.verts.clear(); hm.verts.shrink_to_fit();
     hm.fr64.clear(); hm.fr64.shrink_to_fit();
     hm.fr32.clear(); hm.fr32.shrink_to_fit();
+#undef alloc_T
+    return CTENO_OK;
+}
+
+extern "C" cteno_status cteno_mesh_upload(cteno_ctx *ctx, const cteno_mesh_desc *desc, const cteno_scheme *scheme,
+                                          cteno_mesh **out) {
+    if (!ctx || !desc || !scheme || !out) return fail(CTENO_ERR_INVALID, "NULL argument");
+    const cteno_scheme &s = *scheme;
+    if (cteno_status rc = check_scheme(s)) return rc;
+    HIP_TRY(hipSetDevice(ctx->device));
+    auto m = std::make_unique<cteno_mesh>();
+    m->ctx = ctx;
+    m->scheme = s;
+    std::string err;
+    cteno_status rc = build_host_mesh(*desc, s, m->host, err);
+    if (rc != CTENO_OK) return fail(rc, err);
+    rc = upload_device_mesh(ctx, ctx->stream(), m->host, s, m->dm, m->bufs, m->bytes, true);
+    if (rc != CTENO_OK) return rc;
     *out = m.release();
     return CTENO_OK;
 }
@@ -688,7 +715,7 @@ extern "C" cteno_status cteno_solve(cteno_ctx *ctx, const cteno_mesh *m, cteno_s
     h.max_steps = max_steps;
     h.dt_cand_bits = 0x7FF0000000000000ull;
     HIP_TRY(hipMemcpyAsync(dc, &h, sizeof(Ctrl), hipMemcpyHostToDevice, st));
-    HIP_TRY(launch_dt_partials(dm, s->U[0].as<double>(), s->dt_part.as<double>(), st));
+    HIP_TRY(launch_dt_partials(dm, f32, s->U[0].as<double>(), s->dt_part.as<double>(), st));
 
     // graphs need a capturable stream: the context's own stream when the
     // caller uses the null stream
@@ -766,4 +793,461 @@ extern "C" cteno_status cteno_util_copy(cteno_ctx *ctx, void *dst, const void *s
     HIP_TRY(hipSetDevice(ctx->device));
     HIP_TRY(launch_copy16(dst, src, n_bytes / 16, ctx->stream()));
     return CTENO_OK;
+}
+
+// ---------------------------------------------------------------------------
+// serving: continuous batching of independent solves
+// ---------------------------------------------------------------------------
+namespace {
+using Clock = std::chrono::steady_clock;
+
+enum { REQ_QUEUED = 0, REQ_READY = 1, REQ_RUNNING = 2, REQ_DONE = 3, REQ_FAILED = 4 };
+
+struct ServerRequest {
+    uint64_t ticket = 0;
+    std::vector<double> xy;
+    std::vector<int32_t> tri;
+    cteno_mesh_desc desc{};
+    std::vector<double> u0;
+    int32_t n_steps = 0;
+    double cfl = 0.3;
+    Clock::time_point t_submit, t_admit, t_done;
+    int state = REQ_QUEUED;
+    HostMesh hm;
+    std::string err;
+    cteno_status fail_status = CTENO_OK;
+    std::vector<double> result;
+    double t_end = 0.0;
+    int64_t steps = 0;
+};
+
+struct ServerSlot {
+    std::shared_ptr<ServerRequest> req;
+    DeviceMesh dm;
+    std::vector<DevBuf> bufs;
+    DevBuf U[3], FV, dt_part;
+    int ctrl_index = -1;
+    int64_t bytes = 0;
+};
+}  // namespace
+
+struct cteno_server {
+    cteno_ctx *ctx = nullptr;
+    cteno_scheme scheme{};
+    int64_t budget = 0;
+    int max_slots = 0;
+    int64_t max_blocks = 0;
+    hipStream_t stream = nullptr;
+    DeviceMesh proto;              // scheme constants shared by every slot
+    // device slot table, slot count, control pool
+    DevBuf d_table, d_nslots, d_ctrl;
+    BatchSlot *h_table = nullptr;
+    int *h_nslots = nullptr;
+    Ctrl *h_ctrl = nullptr;
+    hipGraphExec_t graph = nullptr;
+    // host side
+    std::mutex mu;
+    std::condition_variable cv_build, cv_sched, cv_done;
+    std::deque<std::shared_ptr<ServerRequest>> to_build, ready;
+    std::map<uint64_t, std::shared_ptr<ServerRequest>> requests;
+    std::vector<std::unique_ptr<ServerSlot>> active;
+    std::vector<int> free_ctrl;
+    uint64_t next_ticket = 1;
+    int64_t bytes_used = 0, peak_bytes = 0;
+    int peak_active = 0;
+    int64_t ticks = 0, cell_stages = 0, n_submitted = 0, n_finished = 0;
+    bool stop = false;
+    std::string sched_error;
+    std::thread builder, scheduler;
+};
+
+namespace {
+
+// steady and transient device bytes of a slot with N cells
+void slot_footprint(const cteno_server *sv, int64_t N, int64_t &steady, int64_t &transient) {
+    const int r = sv->scheme.degree;
+    const int64_t Np = pad64(N);
+    const int64_t E32 = round_up(pinv_entries(r), 4), E64 = round_up(pinv_entries(r), 2);
+    const int S = dims_S(r), SP = round_up(S, 4);
+    steady = Np * (E32 * 4 + SP * 4 + 1 + 12 * 4 + 8 + 3 * 32 + 3 * kNq * 4 * 4) + N * 4 + ((N + 255) / 256) * 8;
+    transient = Np * (E64 * 8 + 6 * 8 + S + 2 * S) + 64;
+}
+
+void builder_main(cteno_server *sv) {
+    for (;;) {
+        std::shared_ptr<ServerRequest> rq;
+        {
+            std::unique_lock<std::mutex> lk(sv->mu);
+            sv->cv_build.wait(lk, [&] { return sv->stop || !sv->to_build.empty(); });
+            if (sv->to_build.empty()) return;
+            rq = sv->to_build.front();
+            sv->to_build.pop_front();
+        }
+        std::string err;
+        cteno_status rc = build_host_mesh(rq->desc, sv->scheme, rq->hm, err);
+        int64_t steady = 0, transient = 0;
+        if (rc == CTENO_OK) {
+            slot_footprint(sv, rq->hm.N, steady, transient);
+            if (steady + transient > sv->budget) { rc = CTENO_ERR_BUSY; err = "request exceeds the HBM budget"; }
+        }
+        std::lock_guard<std::mutex> lk(sv->mu);
+        if (rc != CTENO_OK) {
+            rq->state = REQ_FAILED;
+            rq->err = err;
+            rq->fail_status = rc;
+            rq->t_done = Clock::now();
+            sv->n_finished++;
+            sv->cv_done.notify_all();
+        } else {
+            rq->state = REQ_READY;
+            sv->ready.push_back(rq);
+            sv->cv_sched.notify_all();
+        }
+    }
+}
+
+cteno_status admit(cteno_server *sv, const std::shared_ptr<ServerRequest> &rq, std::unique_ptr<ServerSlot> &sl) {
+    sl = std::make_unique<ServerSlot>();
+    sl->req = rq;
+    cteno_scheme s = sv->scheme;
+    s.precision = CTENO_MIXED;
+    int64_t bytes = 0;
+    cteno_status rc = upload_device_mesh(sv->ctx, sv->stream, rq->hm, s, sl->dm, sl->bufs, bytes, false);
+    if (rc != CTENO_OK) return rc;
+    const DeviceMesh &dm = sl->dm;
+    const size_t sb = (size_t)dm.Np * dm.nv * sizeof(double);
+    for (auto &u : sl->U) {
+        u = DevBuf(sv->ctx, sb);
+        if (!u.p) return fail(CTENO_ERR_NOMEM, "device allocation failed");
+        HIP_TRY(hipMemsetAsync(u.p, 0, sb, sv->stream));
+    }
+    sl->FV = DevBuf(sv->ctx, (size_t)dm.Np * 3 * kNq * dm.nv * sizeof(float));
+    sl->dt_part = DevBuf(sv->ctx, (size_t)dm.blocks() * sizeof(double));
+    if (!sl->FV.p || !sl->dt_part.p) return fail(CTENO_ERR_NOMEM, "device allocation failed");
+    bytes += (int64_t)(3 * sb + sl->FV.bytes + sl->dt_part.bytes);
+    // initial state: caller order -> internal order
+    DevBuf tmp(sv->ctx, (size_t)dm.N * dm.nv * sizeof(double));
+    if (!tmp.p) return fail(CTENO_ERR_NOMEM, "device allocation failed");
+    HIP_TRY(hipMemcpyAsync(tmp.p, rq->u0.data(), (size_t)dm.N * dm.nv * sizeof(double), hipMemcpyHostToDevice,
+                           sv->stream));
+    HIP_TRY(launch_user_to_state(dm, tmp.as<double>(), sl->U[0].as<double>(), sv->stream));
+    HIP_TRY(launch_dt_partials(dm, true, sl->U[0].as<double>(), sl->dt_part.as<double>(), sv->stream));
+    // control block
+    sl->ctrl_index = sv->free_ctrl.back();
+    sv->free_ctrl.pop_back();
+    Ctrl c{};
+    c.t = 0.0;
+    c.t_final = INFINITY;
+    c.cfl = rq->cfl;
+    c.max_steps = rq->n_steps;
+    Ctrl *dc = sv->d_ctrl.as<Ctrl>() + sl->ctrl_index;
+    HIP_TRY(hipMemcpyAsync(dc, &c, sizeof(Ctrl), hipMemcpyHostToDevice, sv->stream));
+    HIP_TRY(hipStreamSynchronize(sv->stream));     // host buffers (u0, c) are released after this
+    rq->u0.clear();
+    rq->u0.shrink_to_fit();
+    sl->bytes = bytes;
+    return CTENO_OK;
+}
+
+cteno_status retire(cteno_server *sv, ServerSlot &sl, const Ctrl &c) {
+    auto &rq = sl.req;
+    rq->steps = c.step;
+    rq->t_end = c.t;
+    if (c.nonphysical) {
+        rq->state = REQ_FAILED;
+        rq->fail_status = CTENO_ERR_NONPHYSICAL;
+        rq->err = "non-physical state (density or pressure <= 0, or NaN)";
+    } else {
+        const DeviceMesh &dm = sl.dm;
+        DevBuf tmp(sv->ctx, (size_t)dm.N * dm.nv * sizeof(double));
+        if (!tmp.p) return fail(CTENO_ERR_NOMEM, "device allocation failed");
+        rq->result.resize((size_t)dm.N * dm.nv);
+        HIP_TRY(launch_state_to_user(dm, sl.U[0].as<double>(), tmp.as<double>(), sv->stream));
+        HIP_TRY(hipMemcpyAsync(rq->result.data(), tmp.p, rq->result.size() * sizeof(double), hipMemcpyDeviceToHost,
+                               sv->stream));
+        HIP_TRY(hipStreamSynchronize(sv->stream));
+        rq->state = REQ_DONE;
+    }
+    rq->hm = HostMesh();
+    rq->t_done = Clock::now();
+    return CTENO_OK;
+}
+
+void scheduler_fail(cteno_server *sv, const std::string &m) {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->sched_error = m;
+    for (auto &kv : sv->requests)
+        if (kv.second->state != REQ_DONE && kv.second->state != REQ_FAILED) {
+            kv.second->state = REQ_FAILED;
+            kv.second->fail_status = CTENO_ERR_DEVICE;
+            kv.second->err = "server stopped: " + m;
+            kv.second->t_done = Clock::now();
+            sv->n_finished++;
+        }
+    sv->ready.clear();
+    sv->to_build.clear();
+    sv->cv_done.notify_all();
+}
+
+void scheduler_main(cteno_server *sv) {
+    if (hipSetDevice(sv->ctx->device) != hipSuccess) { scheduler_fail(sv, "hipSetDevice failed"); return; }
+    bool dirty = true;
+    for (;;) {
+        // admissions: ready requests, in arrival order, while slots and memory allow
+        std::deque<std::shared_ptr<ServerRequest>> cand;
+        {
+            std::unique_lock<std::mutex> lk(sv->mu);
+            if (sv->active.empty())
+                sv->cv_sched.wait(lk, [&] { return sv->stop || !sv->ready.empty(); });
+            if (sv->stop && sv->active.empty() && sv->ready.empty()) return;
+            while (!sv->ready.empty() && (int)(sv->active.size() + cand.size()) < sv->max_slots) {
+                int64_t steady, transient;
+                slot_footprint(sv, sv->ready.front()->hm.N, steady, transient);
+                int64_t pending = 0;
+                for (auto &c : cand) { int64_t a, b; slot_footprint(sv, c->hm.N, a, b); pending += a; }
+                if (sv->bytes_used + pending + steady + transient > sv->budget) break;
+                cand.push_back(sv->ready.front());
+                sv->ready.pop_front();
+            }
+        }
+        for (auto &rq : cand) {
+            std::unique_ptr<ServerSlot> sl;
+            cteno_status rc = admit(sv, rq, sl);
+            if (rc != CTENO_OK && sl && sl->ctrl_index >= 0) sv->free_ctrl.push_back(sl->ctrl_index);
+            std::lock_guard<std::mutex> lk(sv->mu);
+            if (rc != CTENO_OK) {
+                rq->state = REQ_FAILED;
+                rq->fail_status = rc;
+                rq->err = g_err;
+                rq->t_done = Clock::now();
+                rq->hm = HostMesh();
+                sv->n_finished++;
+                sv->cv_done.notify_all();
+                continue;
+            }
+            rq->state = REQ_RUNNING;
+            rq->t_admit = Clock::now();
+            sv->bytes_used += sl->bytes;
+            sv->peak_bytes = std::max(sv->peak_bytes, sv->bytes_used);
+            sv->active.push_back(std::move(sl));
+            sv->peak_active = std::max(sv->peak_active, (int)sv->active.size());
+            dirty = true;
+        }
+        if (sv->active.empty()) continue;
+        if (dirty) {
+            int64_t b0 = 0;
+            for (size_t k = 0; k < sv->active.size(); ++k) {
+                ServerSlot &sl = *sv->active[k];
+                BatchSlot &t = sv->h_table[k];
+                t.N = sl.dm.N;
+                t.block0 = b0;
+                t.nblocks = sl.dm.blocks();
+                t.slot = sl.dm.slot;
+                t.flags = sl.dm.flags;
+                t.P = sl.dm.P32;
+                t.fr = sl.dm.fr32;
+                t.area = sl.dm.area;
+                for (int q = 0; q < 3; ++q) t.U[q] = sl.U[q].as<double>();
+                t.FV = sl.FV.as<float>();
+                t.dt_part = sl.dt_part.as<double>();
+                t.ctrl = sv->d_ctrl.as<Ctrl>() + sl.ctrl_index;
+                b0 += t.nblocks;
+            }
+            *sv->h_nslots = (int)sv->active.size();
+            if (b0 > sv->max_blocks) { scheduler_fail(sv, "block budget exceeded"); return; }
+            if (hipMemcpyAsync(sv->d_table.p, sv->h_table, sizeof(BatchSlot) * sv->active.size(),
+                               hipMemcpyHostToDevice, sv->stream) != hipSuccess ||
+                hipMemcpyAsync(sv->d_nslots.p, sv->h_nslots, sizeof(int), hipMemcpyHostToDevice, sv->stream) !=
+                    hipSuccess) {
+                scheduler_fail(sv, "slot table upload failed");
+                return;
+            }
+            dirty = false;
+        }
+        // one SSP-RK3 step of every active solve
+        if (hipGraphLaunch(sv->graph, sv->stream) != hipSuccess) { scheduler_fail(sv, "graph launch failed"); return; }
+        sv->ticks++;
+        // read back the control blocks of the active slots
+        for (size_t k = 0; k < sv->active.size(); ++k) {
+            const int ci = sv->active[k]->ctrl_index;
+            if (hipMemcpyAsync(sv->h_ctrl + ci, sv->d_ctrl.as<Ctrl>() + ci, sizeof(Ctrl), hipMemcpyDeviceToHost,
+                               sv->stream) != hipSuccess) { scheduler_fail(sv, "control read-back failed"); return; }
+        }
+        if (hipStreamSynchronize(sv->stream) != hipSuccess) { scheduler_fail(sv, "device error during a step"); return; }
+        for (size_t k = 0; k < sv->active.size();) {
+            ServerSlot &sl = *sv->active[k];
+            const Ctrl &c = sv->h_ctrl[sl.ctrl_index];
+            if (!c.done) { ++k; continue; }
+            cteno_status rc = retire(sv, sl, c);
+            std::lock_guard<std::mutex> lk(sv->mu);
+            if (rc != CTENO_OK) {
+                sl.req->state = REQ_FAILED;
+                sl.req->fail_status = rc;
+                sl.req->err = g_err;
+                sl.req->t_done = Clock::now();
+            }
+            sv->cell_stages += sl.dm.N * 3 * c.step;
+            sv->bytes_used -= sl.bytes;
+            sv->free_ctrl.push_back(sl.ctrl_index);
+            sv->n_finished++;
+            sv->active.erase(sv->active.begin() + k);
+            dirty = true;
+            sv->cv_done.notify_all();
+        }
+    }
+}
+}  // namespace
+
+extern "C" cteno_status cteno_server_create(cteno_ctx *ctx, const cteno_scheme *scheme, size_t hbm_budget_bytes,
+                                            int32_t max_slots, cteno_server **out) {
+    if (!ctx || !scheme || !out) return fail(CTENO_ERR_INVALID, "NULL argument");
+    if (cteno_status rc = check_scheme(*scheme)) return rc;
+    if (scheme->physics != CTENO_EULER) return fail(CTENO_ERR_INVALID, "serving runs the Euler equations");
+    if (max_slots < 1 || max_slots > 1024) return fail(CTENO_ERR_INVALID, "max_slots must be 1..1024");
+    if (hbm_budget_bytes < (1u << 20)) return fail(CTENO_ERR_INVALID, "budget too small");
+    HIP_TRY(hipSetDevice(ctx->device));
+    auto sv = std::make_unique<cteno_server>();
+    sv->ctx = ctx;
+    sv->scheme = *scheme;
+    sv->scheme.precision = CTENO_MIXED;
+    sv->budget = (int64_t)hbm_budget_bytes;
+    sv->max_slots = max_slots;
+    // the batched grid covers the most cells the budget can hold, plus one
+    // partial block per slot
+    int64_t steady, transient;
+    slot_footprint(sv.get(), 1 << 20, steady, transient);
+    const double per_cell = (double)steady / (1 << 20);
+    sv->max_blocks = (int64_t)(sv->budget / per_cell) / 256 + max_slots + 1;
+    HIP_TRY(hipStreamCreateWithFlags(&sv->stream, hipStreamNonBlocking));
+    sv->d_table = DevBuf(ctx, sizeof(BatchSlot) * max_slots);
+    sv->d_nslots = DevBuf(ctx, sizeof(int));
+    sv->d_ctrl = DevBuf(ctx, sizeof(Ctrl) * max_slots);
+    if (!sv->d_table.p || !sv->d_nslots.p || !sv->d_ctrl.p) return fail(CTENO_ERR_NOMEM, "device allocation failed");
+    HIP_TRY(hipMemsetAsync(sv->d_nslots.p, 0, sizeof(int), sv->stream));
+    HIP_TRY(hipMemsetAsync(sv->d_ctrl.p, 0, sizeof(Ctrl) * max_slots, sv->stream));
+    HIP_TRY(hipHostMalloc((void **)&sv->h_table, sizeof(BatchSlot) * max_slots, hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc((void **)&sv->h_nslots, sizeof(int), hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc((void **)&sv->h_ctrl, sizeof(Ctrl) * max_slots, hipHostMallocDefault));
+    for (int k = max_slots - 1; k >= 0; --k) sv->free_ctrl.push_back(k);
+    // scheme constants (tables, linear weights) shared by every slot
+    DeviceMesh &p = sv->proto;
+    p.r = scheme->degree; p.K = dims_K(p.r); p.S = dims_S(p.r); p.nv = 4; p.physics = CTENO_EULER;
+    p.scheme = scheme->scheme; p.gamma_form = scheme->gamma_form; p.precision = CTENO_MIXED;
+    p.gamma = scheme->gamma; p.lam1p = scheme->lambda1_prime; p.ct = scheme->c_t; p.eps = scheme->eps;
+    make_ref_tables(p.r, p.tab);
+    // capture one batched step
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamSynchronize(sv->stream));
+    HIP_TRY(hipStreamBeginCapture(sv->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = launch_batch_step(sv->proto, sv->d_table.as<BatchSlot>(), sv->d_nslots.as<int>(), max_slots,
+                                     sv->max_blocks, sv->stream);
+    hipError_t e2 = hipStreamEndCapture(sv->stream, &g);
+    if (e != hipSuccess) return fail(CTENO_ERR_DEVICE, std::string("capture: ") + hipGetErrorString(e));
+    HIP_TRY(e2);
+    HIP_TRY(hipGraphInstantiate(&sv->graph, g, nullptr, nullptr, 0));
+    (void)hipGraphDestroy(g);
+    cteno_server *raw = sv.release();
+    raw->builder = std::thread(builder_main, raw);
+    raw->scheduler = std::thread(scheduler_main, raw);
+    *out = raw;
+    return CTENO_OK;
+}
+
+extern "C" cteno_status cteno_server_submit(cteno_server *sv, const cteno_mesh_desc *desc, const double *u0,
+                                            int32_t n_steps, double cfl, uint64_t *ticket) {
+    if (!sv || !desc || !u0 || !ticket) return fail(CTENO_ERR_INVALID, "NULL argument");
+    if (n_steps < 0 || !(cfl > 0)) return fail(CTENO_ERR_INVALID, "bad n_steps or cfl");
+    if (desc->n_cells <= 0 || desc->n_vertices <= 0) return fail(CTENO_ERR_INVALID, "empty mesh");
+    auto rq = std::make_shared<ServerRequest>();
+    rq->t_submit = Clock::now();
+    rq->xy.assign(desc->xy, desc->xy + 2 * (size_t)desc->n_vertices);
+    rq->tri.assign(desc->tri, desc->tri + 3 * (size_t)desc->n_cells);
+    rq->desc = *desc;
+    rq->desc.xy = rq->xy.data();
+    rq->desc.tri = rq->tri.data();
+    rq->u0.assign(u0, u0 + 4 * (size_t)desc->n_cells);
+    rq->n_steps = n_steps;
+    rq->cfl = cfl;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (!sv->sched_error.empty()) return fail(CTENO_ERR_DEVICE, "server stopped: " + sv->sched_error);
+    rq->ticket = sv->next_ticket++;
+    sv->requests[rq->ticket] = rq;
+    sv->to_build.push_back(rq);
+    sv->n_submitted++;
+    sv->cv_build.notify_one();
+    *ticket = rq->ticket;
+    return CTENO_OK;
+}
+
+extern "C" cteno_status cteno_server_poll(cteno_server *sv, uint64_t ticket, int32_t *state, double *u_out,
+                                          int64_t *steps_done, double *latency_s) {
+    if (!sv) return fail(CTENO_ERR_INVALID, "server is NULL");
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto it = sv->requests.find(ticket);
+    if (it == sv->requests.end()) return fail(CTENO_ERR_INVALID, "unknown or released ticket");
+    ServerRequest &rq = *it->second;
+    if (state) *state = rq.state;
+    const bool finished = rq.state == REQ_DONE || rq.state == REQ_FAILED;
+    if (finished && latency_s) *latency_s = std::chrono::duration<double>(rq.t_done - rq.t_submit).count();
+    if (finished && steps_done) *steps_done = rq.steps;
+    if (rq.state == REQ_FAILED) {
+        g_err = rq.err;
+        const cteno_status rc = rq.fail_status == CTENO_OK ? CTENO_ERR_DEVICE : rq.fail_status;
+        if (u_out) sv->requests.erase(it);
+        return rc;
+    }
+    if (rq.state == REQ_DONE && u_out) {
+        std::memcpy(u_out, rq.result.data(), rq.result.size() * sizeof(double));
+        sv->requests.erase(it);
+    }
+    return CTENO_OK;
+}
+
+extern "C" cteno_status cteno_server_drain(cteno_server *sv) {
+    if (!sv) return fail(CTENO_ERR_INVALID, "server is NULL");
+    std::unique_lock<std::mutex> lk(sv->mu);
+    sv->cv_done.wait(lk, [&] { return sv->n_finished >= sv->n_submitted; });
+    if (!sv->sched_error.empty()) return fail(CTENO_ERR_DEVICE, "server stopped: " + sv->sched_error);
+    return CTENO_OK;
+}
+
+extern "C" cteno_status cteno_server_get_stats(cteno_server *sv, cteno_server_stats *st) {
+    if (!sv || !st) return fail(CTENO_ERR_INVALID, "NULL argument");
+    std::lock_guard<std::mutex> lk(sv->mu);
+    st->submitted = sv->n_submitted;
+    st->finished = sv->n_finished;
+    st->active = (int32_t)sv->active.size();
+    st->peak_active = sv->peak_active;
+    st->ticks = sv->ticks;
+    st->cell_stages = sv->cell_stages;
+    st->bytes_in_use = sv->bytes_used;
+    st->peak_bytes = sv->peak_bytes;
+    st->budget_bytes = sv->budget;
+    return CTENO_OK;
+}
+
+extern "C" void cteno_server_destroy(cteno_server *sv) {
+    if (!sv) return;
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->stop = true;
+        sv->to_build.clear();
+        sv->ready.clear();
+    }
+    sv->cv_build.notify_all();
+    sv->cv_sched.notify_all();
+    if (sv->builder.joinable()) sv->builder.join();
+    if (sv->scheduler.joinable()) sv->scheduler.join();
+    (void)hipSetDevice(sv->ctx->device);
+    (void)hipStreamSynchronize(sv->stream);
+    sv->active.clear();
+    if (sv->graph) (void)hipGraphExecDestroy(sv->graph);
+    if (sv->h_table) (void)hipHostFree(sv->h_table);
+    if (sv->h_nslots) (void)hipHostFree(sv->h_nslots);
+    if (sv->h_ctrl) (void)hipHostFree(sv->h_ctrl);
+    sv->d_table.reset();
+    sv->d_nslots.reset();
+    sv->d_ctrl.reset();
+    (void)hipStreamDestroy(sv->stream);
+    delete sv;
 }

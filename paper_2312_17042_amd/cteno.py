@@ -48,6 +48,14 @@ class MeshInfo(C.Structure):
                 ("n_inadmissible", C.c_int32), ("device_bytes", C.c_int64)]
 
 
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("finished", C.c_int64), ("active", C.c_int32), ("peak_active", C.c_int32),
+                ("ticks", C.c_int64), ("cell_stages", C.c_int64), ("bytes_in_use", C.c_int64),
+                ("peak_bytes", C.c_int64), ("budget_bytes", C.c_int64)]
+
+
+REQ_QUEUED, REQ_READY, REQ_RUNNING, REQ_DONE, REQ_FAILED = range(5)
+
 _lib = None
 
 # exported symbols and their argument types (restype is cteno_status unless listed)
@@ -78,8 +86,16 @@ _SIGS = {
                     C.POINTER(C.c_int64)],
     "cteno_count_flips": [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int64)],
     "cteno_util_copy": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t],
+    "cteno_server_create": [C.c_void_p, C.POINTER(Scheme), C.c_size_t, C.c_int32, C.POINTER(C.c_void_p)],
+    "cteno_server_submit": [C.c_void_p, C.POINTER(MeshDesc), C.c_void_p, C.c_int32, C.c_double,
+                            C.POINTER(C.c_uint64)],
+    "cteno_server_poll": [C.c_void_p, C.c_uint64, C.POINTER(C.c_int32), C.c_void_p, C.POINTER(C.c_int64),
+                          C.POINTER(C.c_double)],
+    "cteno_server_drain": [C.c_void_p],
+    "cteno_server_get_stats": [C.c_void_p, C.c_void_p],
+    "cteno_server_destroy": [C.c_void_p],
 }
-_VOID = {"cteno_ctx_destroy", "cteno_mesh_destroy", "cteno_sol_destroy"}
+_VOID = {"cteno_ctx_destroy", "cteno_mesh_destroy", "cteno_sol_destroy", "cteno_server_destroy"}
 
 
 def lib():
@@ -305,3 +321,60 @@ def flux(mesh: Mesh, face_vals, precision=FP64):
     torch.cuda.synchronize()
     _check(lib().cteno_flux(mesh.ctx.h, mesh.h, precision, _dev_ptr(face_vals.contiguous()), _dev_ptr(fo)))
     return fo
+
+
+class Server:
+    """Continuous-batching server of independent 2-D Euler solves (FP32-mixed)."""
+
+    def __init__(self, ctx: Context, scheme: Scheme, budget_bytes: int, max_slots: int = 64):
+        self.ctx = ctx
+        h = C.c_void_p()
+        _check(lib().cteno_server_create(ctx.h, C.byref(scheme), int(budget_bytes), int(max_slots), C.byref(h)))
+        self.h = h
+        self._cells = {}
+        ctx._children.add(self)
+
+    def close(self):
+        if getattr(self, "h", None):
+            if self.ctx.h:
+                lib().cteno_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def submit(self, mesh, u0, n_steps: int, cfl: float = 0.3) -> int:
+        xy = np.ascontiguousarray(mesh.xy, np.float64)
+        tri = np.ascontiguousarray(mesh.tri, np.int32)
+        u0 = np.ascontiguousarray(u0, np.float64).reshape(4, tri.shape[0])
+        d = MeshDesc(xy.shape[0], _np_ptr(xy), tri.shape[0], _np_ptr(tri), (C.c_double * 4)(*mesh.box),
+                     (C.c_int32 * 4)(*mesh.bc))
+        t = C.c_uint64()
+        _check(lib().cteno_server_submit(self.h, C.byref(d), _np_ptr(u0), int(n_steps), float(cfl), C.byref(t)))
+        self._cells[t.value] = tri.shape[0]
+        return t.value
+
+    def poll(self, ticket: int, take: bool = False):
+        """(state, result or None, steps, latency_s).  take=True fetches and releases a finished result."""
+        st = C.c_int32()
+        steps = C.c_int64()
+        lat = C.c_double()
+        out = np.empty((4, self._cells[ticket])) if take else None
+        rc = lib().cteno_server_poll(self.h, int(ticket), C.byref(st), _np_ptr(out) if take else None,
+                                     C.byref(steps), C.byref(lat))
+        if rc != OK:
+            if take:
+                self._cells.pop(ticket, None)
+            raise CtenoError(rc, lib().cteno_last_error().decode())
+        done = st.value == REQ_DONE
+        if take and done:
+            self._cells.pop(ticket, None)
+        return st.value, (out if (take and done) else None), steps.value, lat.value
+
+    def drain(self):
+        _check(lib().cteno_server_drain(self.h))
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        _check(lib().cteno_server_get_stats(self.h, C.byref(s)))
+        return {f: getattr(s, f) for f, _ in ServerStats._fields_}

@@ -348,10 +348,10 @@ def advection_case(n=20, seed=1):
     return m, u0
 
 
-def vortex_case(n=200, seed=2, beta=5.0, center=(5.0, 5.0), L=10.0, gamma=1.4):
+def vortex_case(n=200, seed=2, beta=5.0, center=(5.0, 5.0), L=10.0, gamma=1.4, quad=6):
     """Isentropic vortex on the periodic [0,L]^2 box (n x n squares, 2n^2 cells)."""
     m = split_jitter_mesh(n, n, (0.0, L, 0.0, L), seed=seed)
-    u0 = cell_average(m, isentropic_vortex(0.0, beta, center, (L, L), gamma=gamma))
+    u0 = cell_average(m, isentropic_vortex(0.0, beta, center, (L, L), gamma=gamma), n=quad)
     return m, u0
 
 
@@ -402,11 +402,12 @@ def serving_requests(n_requests=256, rate_hz=10.0, seed=4, lo=2e3, hi=2e5):
     return out
 
 
-def build_request(req: Request, gamma=1.4):
+def build_request(req: Request, gamma=1.4, quad=4):
     """Mesh + initial cell averages for one serving request (mesh seed 4000 + index)."""
     seed = 4000 + req.index
     if req.kind == "vortex":
-        return vortex_case(req.nx, seed=seed, beta=req.params["beta"], center=req.params["center"], gamma=gamma)
+        return vortex_case(req.nx, seed=seed, beta=req.params["beta"], center=req.params["center"], gamma=gamma,
+                           quad=quad)
     p = req.params
     return sod_case(req.nx, req.ny, seed=seed, left=(p["rho_l"], 0.0, 0.0, p["p_l"]),
                     right=(p["rho_r"], 0.0, 0.0, p["p_r"]), gamma=gamma)

@@ -1,0 +1,120 @@
+"""Continuous-batching server on the GPU: each request's result is the same
+alone and in a mix (and the same as a standalone FP32-mixed solve), admission
+is bounded by the HBM budget, and a failing request leaves the others
+untouched."""
+import numpy as np
+import pytest
+
+from paper_2312_17042_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2312_17042_amd import cteno as T  # noqa: E402
+
+SCHEME = dict(physics=T.EULER, scheme=T.CTENOZ, degree=3, lambda1_prime=1e4)
+STEPS = 30
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = T.Context(0)
+    yield c
+    c.close()
+
+
+def _requests():
+    reqs = []
+    reqs.append(W.vortex_case(20, seed=4001, beta=3.0, center=(4.0, 6.0)))
+    reqs.append(W.sod_case(48, 12, seed=4002, left=(0.8, 0.0, 0.0, 0.9), right=(0.3, 0.0, 0.0, 0.2)))
+    reqs.append(W.vortex_case(34, seed=4003, beta=1.5, center=(7.0, 2.0)))
+    reqs.append(W.sod_case(64, 16, seed=4004, left=(0.5, 0.0, 0.0, 0.6), right=(0.9, 0.0, 0.0, 0.4)))
+    reqs.append(W.vortex_case(26, seed=4005, beta=4.5, center=(5.0, 5.0)))
+    reqs.append(W.vortex_case(12, seed=4006, beta=2.0, center=(1.0, 9.0)))
+    return reqs
+
+
+def _standalone(ctx, mesh, u0, steps):
+    m = T.Mesh.from_workload(ctx, mesh, precision=T.MIXED, **SCHEME)
+    s = T.Solution(m, u0)
+    n = s.solve(max_steps=steps, cfl=0.3, precision=T.MIXED, use_graph=False)
+    u, _ = s.download()
+    s.close()
+    m.close()
+    assert n == steps
+    return u
+
+
+def _run(srv, items, steps=STEPS):
+    tickets = [srv.submit(mesh, u0, steps) for mesh, u0 in items]
+    srv.drain()
+    out = []
+    for t in tickets:
+        st, u, n, lat = srv.poll(t, take=True)
+        assert st == T.REQ_DONE and n == steps and lat > 0
+        out.append(u)
+    return out
+
+
+def test_result_same_alone_and_in_mix(ctx):
+    reqs = _requests()
+    srv = T.Server(ctx, T.make_scheme(**SCHEME), budget_bytes=1 << 30, max_slots=16)
+    alone = _run(srv, [reqs[0]])[0]
+    mixed = _run(srv, [reqs[1], reqs[2], reqs[0], reqs[3], reqs[4], reqs[5]])
+    st = srv.stats()
+    srv.close()
+    assert st["peak_active"] >= 2                      # the mix really shared the device
+    assert np.array_equal(alone, mixed[2])
+    ref = _standalone(ctx, *reqs[0], STEPS)
+    rel = np.abs(alone - ref).max() / np.abs(ref).max()
+    assert rel <= 1e-12, rel
+
+
+def test_budget_binds_admission(ctx):
+    reqs = _requests()
+    # room for about two of the larger requests at a time
+    srv = T.Server(ctx, T.make_scheme(**SCHEME), budget_bytes=8 << 20, max_slots=16)
+    outs = _run(srv, reqs)
+    st = srv.stats()
+    srv.close()
+    assert st["finished"] == len(reqs)
+    assert 1 <= st["peak_active"] < len(reqs)
+    assert st["peak_bytes"] <= 8 << 20
+    for (mesh, u0), u in zip(reqs, outs):
+        ref = _standalone(ctx, mesh, u0, STEPS)
+        assert np.abs(u - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_failing_request_is_isolated(ctx):
+    reqs = _requests()[:3]
+    bad_mesh, bad_u0 = W.vortex_case(16, seed=4010)
+    bad_u0 = bad_u0.copy()
+    bad_u0[3, 7] = -1.0            # negative energy: non-physical
+    srv = T.Server(ctx, T.make_scheme(**SCHEME), budget_bytes=1 << 30, max_slots=8)
+    tickets = [srv.submit(m, u, STEPS) for m, u in reqs[:2]]
+    tbad = srv.submit(bad_mesh, bad_u0, STEPS)
+    tickets.append(srv.submit(*reqs[2], STEPS))
+    srv.drain()
+    with pytest.raises(T.CtenoError) as e:
+        srv.poll(tbad, take=True)
+    assert e.value.status == T.ERR_NONPHYSICAL
+    for (mesh, u0), t in zip(reqs, tickets):
+        st, u, n, _ = srv.poll(t, take=True)
+        assert st == T.REQ_DONE
+        assert np.array_equal(u, _standalone(ctx, mesh, u0, STEPS)) or \
+            np.abs(u - _standalone(ctx, mesh, u0, STEPS)).max() <= 1e-12
+    srv.close()
+
+
+def test_oversized_request_is_rejected(ctx):
+    srv = T.Server(ctx, T.make_scheme(**SCHEME), budget_bytes=2 << 20, max_slots=4)
+    mesh, u0 = W.vortex_case(60, seed=4011)           # 7200 cells: more than 2 MiB resident
+    t = srv.submit(mesh, u0, 5)
+    srv.drain()
+    with pytest.raises(T.CtenoError) as e:
+        srv.poll(t, take=True)
+    assert e.value.status == T.ERR_BUSY
+    srv.close()
