@@ -82,6 +82,8 @@ struct HostMesh {
     std::vector<double> area;          // [Npad]
 };
 
+// host threads the calling thread's mesh builds may use (default 16)
+void set_builder_threads(int n);
 // returns CTENO_OK or an error (message in err)
 cteno_status build_host_mesh(const cteno_mesh_desc &d, const cteno_scheme &s, HostMesh &hm, std::string &err);
 

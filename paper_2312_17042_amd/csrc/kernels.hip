@@ -630,71 +630,96 @@ __device__ __forceinline__ void recon_body(const ReconArgs<real, (R + 1) * (R + 
     // force it into scratch memory
     const real lams = st == 2 ? a.lams[2] : (st == 3 ? a.lams[3] : a.lams[4]);
     const real lratio = st == 2 ? a.lam_ratio[2] : (st == 3 ? a.lam_ratio[3] : a.lam_ratio[4]);
-    real out[3][2][NV];
-    uint32_t dword = 0;
+    // The epilogue works on all variables at once, phase by phase, so each
+    // scheme constant (Gram matrix, face basis values) is used once and
+    // dies, instead of staying live across a per-variable loop.
+    // p_1 = (p_opt - sum_s lambda_s p_s) / lambda_1, in place of a_opt
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        // p_1 = (p_opt - sum_s lambda_s p_s) / lambda_1
-        real a1[K];
+    for (int k = 0; k < K; ++k)
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
+        for (int v = 0; v < NV; ++v) {
             real sm = ao[k][v];
             if (k < 2 && st > 1) {
 #pragma unroll
                 for (int q = 0; q < 3; ++q)
                     if ((fl >> q) & 1) sm -= lams * ad[q][k][v];
             }
-            a1[k] = st > 1 ? sm / a.lam1 : sm;
+            ao[k][v] = st > 1 ? sm / a.lam1 : sm;
         }
-        int bits;
-        if (DMODE == 2) {
-            bits = ptr.delta[i * NV + v] & adm;
-        } else if (st == 1) {
-            bits = 1;
-        } else {
-            real si[4];
-            real acc = 0;
+    int bits[NV];
+    if (DMODE == 2) {
 #pragma unroll
-            for (int p = 0; p < K; ++p) {
-                real rowp = 0;
+        for (int v = 0; v < NV; ++v) bits[v] = ptr.delta[i * NV + v] & adm;
+    } else if (st == 1) {
 #pragma unroll
-                for (int q = 0; q < K; ++q) rowp += a.gram[p][q] * a1[q];
-                acc += a1[p] * rowp;
+        for (int v = 0; v < NV; ++v) bits[v] = 1;
+    } else {
+        // smoothness indicators: SI_1 = a1^T G a1, SI_s over the degree-1 block of G
+        real si[NV][4];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) si[v][0] = 0;
+#pragma unroll
+        for (int p = 0; p < K; ++p) {
+            real rowp[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) rowp[v] = 0;
+#pragma unroll
+            for (int q = 0; q < K; ++q) {
+                const real g = a.gram[p][q];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) rowp[v] += g * ao[q][v];
             }
-            si[0] = acc;
 #pragma unroll
-            for (int q = 0; q < 3; ++q) {
+            for (int v = 0; v < NV; ++v) si[v][0] += ao[p][v] * rowp[v];
+        }
+        const real g00 = a.gram[0][0], g01 = a.gram[0][1], g10 = a.gram[1][0], g11 = a.gram[1][1];
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
                 const real x0 = ad[q][0][v], x1 = ad[q][1][v];
-                si[q + 1] = x0 * (a.gram[0][0] * x0 + a.gram[0][1] * x1) + x1 * (a.gram[1][0] * x0 + a.gram[1][1] * x1);
+                si[v][q + 1] = x0 * (g00 * x0 + g01 * x1) + x1 * (g10 * x0 + g11 * x1);
             }
-            bits = teno_bits<real, SCHEME, GFORM>(si, adm, st, a.lam1, lams, lratio, a.ct, a.eps);
-        }
-        dword |= (uint32_t)bits << (8 * v);
-        real fin[K];
-        if (bits & 1) {
 #pragma unroll
-            for (int k = 0; k < K; ++k) fin[k] = a1[k];
-        } else {
+        for (int v = 0; v < NV; ++v)
+            bits[v] = teno_bits<real, SCHEME, GFORM>(si[v], adm, st, a.lam1, lams, lratio, a.ct, a.eps);
+    }
+    uint32_t dword = 0;
+    // final coefficients, in place: p_1, or the mean of the selected
+    // directional polynomials
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        dword |= (uint32_t)bits[v] << (8 * v);
+        if (!(bits[v] & 1)) {
             real s0 = 0, s1 = 0;
             int cnt = 0;
 #pragma unroll
             for (int q = 0; q < 3; ++q)
-                if ((bits >> (q + 1)) & 1) { s0 += ad[q][0][v]; s1 += ad[q][1][v]; ++cnt; }
-            fin[0] = s0 / (real)cnt;
-            fin[1] = s1 / (real)cnt;
+                if ((bits[v] >> (q + 1)) & 1) { s0 += ad[q][0][v]; s1 += ad[q][1][v]; ++cnt; }
+            ao[0][v] = s0 / (real)cnt;
+            ao[1][v] = s1 / (real)cnt;
 #pragma unroll
-            for (int k = 2; k < K; ++k) fin[k] = 0;
+            for (int k = 2; k < K; ++k) ao[k][v] = 0;
         }
-#pragma unroll
-        for (int f = 0; f < 3; ++f)
-#pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                real val = 0;
-#pragma unroll
-                for (int k = 0; k < K; ++k) val += a.basis[f][q][k] * fin[k];
-                out[f][q][v] = (real)(U0[v] + (double)val);
-            }
     }
+    // face Gauss-point values
+    real out[3][2][NV];
+#pragma unroll
+    for (int f = 0; f < 3; ++f)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            real val[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) val[v] = 0;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const real b = a.basis[f][q][k];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) val[v] += b * ao[k][v];
+            }
+#pragma unroll
+            for (int v = 0; v < NV; ++v) out[f][q][v] = (real)(U0[v] + (double)val[v]);
+        }
     if constexpr (NV == 4) {
         // positivity fallback: a cell with a non-physical state (density or
         // pressure <= 0) at any of its Gauss points uses its cell average at

@@ -33,10 +33,12 @@ namespace cteno {
 
 namespace {
 
+thread_local int tl_max_threads = 16;
+
 template <class F>
 void parallel_for(int64_t n, F &&fn) {
     unsigned hw = std::thread::hardware_concurrency();
-    int nt = (int)std::max(1u, std::min(hw, 16u));
+    int nt = (int)std::max(1u, std::min(hw, (unsigned)tl_max_threads));
     if (n < 4096) nt = 1;
     if (nt == 1) {
         for (int64_t i = 0; i < n; ++i) fn(i, 0);
@@ -59,7 +61,7 @@ void parallel_for(int64_t n, F &&fn) {
 
 inline int nthreads_for(int64_t n) {
     unsigned hw = std::thread::hardware_concurrency();
-    int nt = (int)std::max(1u, std::min(hw, 16u));
+    int nt = (int)std::max(1u, std::min(hw, (unsigned)tl_max_threads));
     return n < 4096 ? 1 : nt;
 }
 
@@ -323,6 +325,8 @@ uint64_t spread16(uint32_t x) {
 }
 
 }  // namespace
+
+void set_builder_threads(int n) { tl_max_threads = std::max(1, std::min(n, 16)); }
 
 cteno_status build_host_mesh(const cteno_mesh_desc &d, const cteno_scheme &s, HostMesh &hm, std::string &err) {
     if (d.n_cells <= 0 || d.n_vertices <= 0 || !d.xy || !d.tri) { err = "empty mesh"; return CTENO_ERR_INVALID; }

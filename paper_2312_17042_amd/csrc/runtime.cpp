@@ -858,7 +858,8 @@ struct cteno_server {
     int64_t ticks = 0, cell_stages = 0, n_submitted = 0, n_finished = 0;
     bool stop = false;
     std::string sched_error;
-    std::thread builder, scheduler;
+    std::vector<std::thread> builders;
+    std::thread scheduler;
 };
 
 namespace {
@@ -873,7 +874,8 @@ void slot_footprint(const cteno_server *sv, int64_t N, int64_t &steady, int64_t 
     transient = Np * (E64 * 8 + 6 * 8 + S + 2 * S) + 64;
 }
 
-void builder_main(cteno_server *sv) {
+void builder_main(cteno_server *sv, int threads_each) {
+    set_builder_threads(threads_each);
     for (;;) {
         std::shared_ptr<ServerRequest> rq;
         {
@@ -1147,7 +1149,10 @@ extern "C" cteno_status cteno_server_create(cteno_ctx *ctx, const cteno_scheme *
     HIP_TRY(hipGraphInstantiate(&sv->graph, g, nullptr, nullptr, 0));
     (void)hipGraphDestroy(g);
     cteno_server *raw = sv.release();
-    raw->builder = std::thread(builder_main, raw);
+    // several mesh builders, each with a share of the host threads
+    const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+    const int nb = std::max(1, std::min(4, hw / 2));
+    for (int k = 0; k < nb; ++k) raw->builders.emplace_back(builder_main, raw, std::max(1, std::min(hw, 16) / nb));
     raw->scheduler = std::thread(scheduler_main, raw);
     *out = raw;
     return CTENO_OK;
@@ -1236,7 +1241,8 @@ extern "C" void cteno_server_destroy(cteno_server *sv) {
     }
     sv->cv_build.notify_all();
     sv->cv_sched.notify_all();
-    if (sv->builder.joinable()) sv->builder.join();
+    for (auto &b : sv->builders)
+        if (b.joinable()) b.join();
     if (sv->scheduler.joinable()) sv->scheduler.join();
     (void)hipSetDevice(sv->ctx->device);
     (void)hipStreamSynchronize(sv->stream);
