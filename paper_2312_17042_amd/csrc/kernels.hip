@@ -550,15 +550,26 @@ __device__ __forceinline__ void recon_body(const ReconArgs<real, (R + 1) * (R + 
     int4 slv[SP / 4];
 #pragma unroll
     for (int g = 0; g < SP / 4; ++g) slv[g] = Sv[g * 64];
+    // Rolled loop over the three directional groups with a two-deep load
+    // pipeline: the GV vectors that follow group s (group s + 1, or the head
+    // of the remaining slots) are requested before group s is computed, so a
+    // wave keeps two groups of stream loads in flight.  With no remaining
+    // slots (S = 12) the last iteration requests its own group again.
+    constexpr int NVEC = E / VW;
+    static_assert(S == 12 || 4 * GV <= NVEC, "stream shorter than four groups");
+    V cur[GV];
+#pragma unroll
+    for (int g = 0; g < GV; ++g) cur[g] = Pv[g * 64];
 #pragma unroll 1
     for (int s = 0; s < 3; ++s) {
         int4 sl = slv[0];
 #pragma unroll
         for (int s2 = 1; s2 < 3; ++s2)
             if (s2 == s) sl = slv[s2];
-        V pv[GV];
+        const int gn = (S > 12 || s < 2 ? s + 1 : s) * GV;
+        V nxt[GV];
 #pragma unroll
-        for (int g = 0; g < GV; ++g) pv[g] = Pv[(s * GV + g) * 64];
+        for (int g = 0; g < GV; ++g) nxt[g] = Pv[(gn + g) * 64];
         real adt[2][NV];
 #pragma unroll
         for (int c = 0; c < 2; ++c)
@@ -572,7 +583,7 @@ __device__ __forceinline__ void recon_body(const ReconArgs<real, (R + 1) * (R + 
 #pragma unroll
             for (int q = 0; q < K + 2; ++q) {
                 const int el = t * (K + 2) + q;
-                const real p = comp(pv[el / VW], el % VW);
+                const real p = comp(cur[el / VW], el % VW);
                 if (q < K) {
 #pragma unroll
                     for (int v = 0; v < NV; ++v) ao[q][v] += p * d[v];
@@ -589,37 +600,34 @@ __device__ __forceinline__ void recon_body(const ReconArgs<real, (R + 1) * (R + 
                 for (int c = 0; c < 2; ++c)
 #pragma unroll
                     for (int v = 0; v < NV; ++v) ad[s2][c][v] = adt[c][v];
-        __builtin_amdgcn_sched_barrier(0);   // keep the phases apart: bounded live registers
+#pragma unroll
+        for (int g = 0; g < GV; ++g) cur[g] = nxt[g];
+        __builtin_amdgcn_sched_barrier(0);   // keep the groups apart: bounded live registers
     }
     if constexpr (S > 12) {
-        // remaining slots in two halves (bounded register footprint); a
-        // vector straddling the halves is loaded by both
-        constexpr int T0 = 12 * (K + 2);          // first tail entry (a multiple of VW)
+        // remaining slots (K central entries each): cur holds stream vectors
+        // [3 GV, 4 GV); the rest of the stream follows
+        constexpr int T0 = 12 * (K + 2);
         constexpr int NT = S - 12;
+        constexpr int RV = NVEC - 4 * GV;
+        V rest[RV > 0 ? RV : 1];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            constexpr int HS = (NT + 1) / 2;      // slots per half
-            const int t0 = h * HS, t1 = h == 0 ? HS : NT;
-            const int e0 = T0 + t0 * K, e1 = T0 + t1 * K;      // entries [e0, e1)
-            const int g0 = e0 / VW, g1 = (e1 + VW - 1) / VW;   // vectors [g0, g1)
-            V pv[(HS * K + 2 * VW - 2) / VW + 1];
+        for (int g = 0; g < RV; ++g) rest[g] = Pv[(4 * GV + g) * 64];
 #pragma unroll
-            for (int g = 0; g < g1 - g0; ++g) pv[g] = Pv[(g0 + g) * 64];
+        for (int t = 0; t < NT; ++t) {
+            const int j = 12 + t;
+            const int64_t m = comp(slv[j / 4], j % 4);
+            real d[NV];
+            gather_diff<NV>(ptr.U, m, U0, d);
 #pragma unroll
-            for (int t = t0; t < t1; ++t) {
-                const int j = 12 + t;
-                const int64_t m = comp(slv[j / 4], j % 4);
-                real d[NV];
-                gather_diff<NV>(ptr.U, m, U0, d);
+            for (int q = 0; q < K; ++q) {
+                const int e = T0 + t * K + q;
+                const int gv = e / VW - 3 * GV;     // compile-time after unrolling
+                const real p = gv < GV ? comp(cur[gv < GV ? gv : 0], e % VW)
+                                       : comp(rest[gv < GV ? 0 : gv - GV], e % VW);
 #pragma unroll
-                for (int q = 0; q < K; ++q) {
-                    const int e = T0 + t * K + q;
-                    const real p = comp(pv[e / VW - g0], e % VW);
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) ao[q][v] += p * d[v];
-                }
+                for (int v = 0; v < NV; ++v) ao[q][v] += p * d[v];
             }
-            __builtin_amdgcn_sched_barrier(0);
         }
     }
 
