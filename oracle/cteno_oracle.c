@@ -43,7 +43,8 @@
  *     face's two vertices (face neighbour always assigned to its face),
  *     nearest M_d = 2 K_d of them with the face neighbour first; admissible
  *     when the face is interior and the stencil has >= K_d + 1 cells;
- *     directional degree r_d = 1 for r <= 3;
+ *     directional degree r_d = 1 for r <= 3 and r_d = ceil(r/2) above
+ *     (third-order directional stencils for the fifth-order scheme, Fig. 1);
  *   reference map anchored at the first vertex of the counter-clockwise
  *     normalised triangle; SI multi-indices counted once each;
  *   final polynomial p_1 when delta_1 = 1 (Algorithms 1 and 2);
@@ -850,7 +851,7 @@ or_ctx *or_create(int nvert, const double *xy, int ncell, const int *tri, const 
                   const or_scheme *sch) {
     or_err[0] = 0;
     if (nvert <= 0 || ncell <= 0 || !xy || !tri || !box || !bc || !sch) { set_err("bad arguments", 0); return NULL; }
-    if (sch->degree < 1 || sch->degree > 3) { set_err("degree must be 1..3", sch->degree); return NULL; }
+    if (sch->degree < 1 || sch->degree > OR_MAXR) { set_err("degree must be 1..6", sch->degree); return NULL; }
     or_ctx *c = calloc(1, sizeof(or_ctx));
     c->nvert = nvert; c->N = ncell;
     c->xy = malloc(sizeof(double) * 2 * nvert); memcpy(c->xy, xy, sizeof(double) * 2 * nvert);
@@ -869,18 +870,28 @@ or_ctx *or_create(int nvert, const double *xy, int ncell, const int *tri, const 
     c->lam1p = sch->lambda1_prime; c->ct = sch->c_t; c->eps = sch->eps;
     c->K = (c->r + 1) * (c->r + 2) / 2 - 1;
     c->M = 2 * c->K;
-    c->rd = 1;
+    c->rd = c->r <= 3 ? 1 : (c->r + 1) / 2;
     c->Kd = (c->rd + 1) * (c->rd + 2) / 2 - 1;
     c->Md = 2 * c->Kd;
     c->Nq = (c->r + 2) / 2;
     int k = 1;
     for (int d = 1; d <= c->r; ++d)
         for (int a = d; a >= 0; --a) { c->ex[k][0] = a; c->ex[k][1] = d - a; ++k; }
-    /* Gauss-Legendre points on [0, 1] */
+    /* Gauss-Legendre points on [0, 1] (closed forms of the roots of P_Nq on
+       [-1, 1], mapped; weights 2 / ((1 - x^2) P'_Nq(x)^2), halved) */
     if (c->Nq == 1) { c->gq[0] = 0.5; c->gw[0] = 1.0; }
     else if (c->Nq == 2) {
         double s = 0.5 / sqrt(3.0);
         c->gq[0] = 0.5 - s; c->gq[1] = 0.5 + s; c->gw[0] = c->gw[1] = 0.5;
+    } else if (c->Nq == 3) {
+        double x = sqrt(0.6);
+        c->gq[0] = 0.5 - 0.5 * x; c->gq[1] = 0.5; c->gq[2] = 0.5 + 0.5 * x;
+        c->gw[0] = c->gw[2] = 5.0 / 18.0; c->gw[1] = 8.0 / 18.0;
+    } else {
+        double x1 = sqrt(3.0 / 7.0 - 2.0 / 7.0 * sqrt(1.2)), x2 = sqrt(3.0 / 7.0 + 2.0 / 7.0 * sqrt(1.2));
+        double w1 = (18.0 + sqrt(30.0)) / 36.0, w2 = (18.0 - sqrt(30.0)) / 36.0;
+        c->gq[0] = 0.5 - 0.5 * x2; c->gq[1] = 0.5 - 0.5 * x1; c->gq[2] = 0.5 + 0.5 * x1; c->gq[3] = 0.5 + 0.5 * x2;
+        c->gw[0] = c->gw[3] = 0.5 * w2; c->gw[1] = c->gw[2] = 0.5 * w1;
     }
     /* centroids from the input vertex order */
     c->cx = NULL;
