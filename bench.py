@@ -82,6 +82,53 @@ def run_precision(T, ctx, mesh, sol, u0, prec, steps, warmup):
     return dict(elapsed=el, recon=kr, flux=kf, u=u, t=t, graph_elapsed=elg)
 
 
+def ho_recon_bytes(r, prec):
+    """Algorithmic bytes per cell and launch of the reconstruction at degree
+    r >= 4: the useful pseudo-inverse entries (K x M central, K_d x M_d per
+    directional stencil), M slot indices, the flag byte, the cell's FP64
+    state and its 3 N_q x 4 face-point values."""
+    K = (r + 1) * (r + 2) // 2 - 1
+    rd = (r + 1) // 2
+    Kd = (rd + 1) * (rd + 2) // 2 - 1
+    Md, M, Nq = 2 * Kd, 2 * K, (r + 2) // 2
+    es = 4 if prec == "mixed" else 8
+    return (K * M + 3 * Kd * Md) * es + M * 4 + 1 + 32 + 3 * Nq * 4 * es
+
+
+def orders_bench(T, W, ctx, n=1000, steps=5, warmup=1):
+    """Orders 5 to 7 (r = 4, 5, 6) on the isentropic vortex, n x n squares,
+    CTENOZ lambda1' = 1e4: mixed-precision throughput and the reconstruction's
+    algorithmic bandwidth."""
+    import torch
+    mesh, u0 = W.vortex_case(n, seed=5, quad=3)
+    N = mesh.n_cells
+    out = {"workload": f"isentropic vortex, {n}x{n} split/jittered periodic [0,10]^2 ({N} cells), CTENOZ "
+                       f"lambda1'=1e4, SSP-RK3 CFL 0.3, mixed precision", "cells": N}
+    for r in (4, 5, 6):
+        t0 = time.perf_counter()
+        m = T.Mesh.from_workload(ctx, mesh, physics=T.EULER, scheme=T.CTENOZ, degree=r, lambda1_prime=1e4,
+                                 precision=T.MIXED)
+        t_up = time.perf_counter() - t0
+        sol = T.Solution(m, u0)
+        res = run_precision(T, ctx, m, sol, u0, T.MIXED, steps, warmup)
+        nrec, msrec = res["recon"]
+        nfl, msfl = res["flux"]
+        avg = msrec / max(1, nrec)
+        b = ho_recon_bytes(r, "mixed")
+        gbs = b * N / (avg * 1e-3) / 1e9
+        out[f"r{r}"] = {"order": r + 1, "value": N * 3 * steps / res["elapsed"], "unit": "cell-stage updates/s",
+                        "ms_per_step": 1e3 * res["elapsed"] / steps, "reconstruct_ms": avg,
+                        "flux_rk_ms": msfl / max(1, nfl), "recon_bytes_per_cell": b, "recon_GBs": gbs,
+                        "recon_frac_of_8TBs": gbs / HBM_PEAK_GBS, "upload_precompute_s": t_up,
+                        "device_bytes": int(m.info.device_bytes)}
+        log(f"order {r + 1}: {out[f'r{r}']['value']:.3e} cell-stage/s, recon {avg:.3f} ms ({gbs:.0f} GB/s), "
+            f"flux {msfl / max(1, nfl):.3f} ms, upload {t_up:.1f}s")
+        sol.close()
+        m.close()
+        torch.cuda.synchronize()
+    return out
+
+
 def cpu_baseline(W, target_s=12.0, max_steps=40):
     """The FP64 oracle on a bounded sample of the same workload family: SSP-RK3
     steps on a 320k-cell mesh until about target_s seconds of work."""
@@ -174,6 +221,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=256)
+    ap.add_argument("--no-orders", action="store_true", help="skip the orders 5-7 measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); multi-GPU sharding is a design "
@@ -282,6 +330,8 @@ def main():
     out["copy_calibration"] = {"bytes_read": nbytes, "bytes_written": nbytes, "GBs": 2 * nbytes / el / 1e9,
                                "kernel": "k_copy16"}
     del src, dst
+    if not args.no_orders:
+        out["orders_5_to_7"] = orders_bench(T, W, ctx)
     if not args.no_serving:
         out["serving"] = serving_bench(T, W, ctx, n_requests=args.serving_requests)
     if not args.no_cpu_baseline:

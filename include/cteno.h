@@ -85,10 +85,11 @@ typedef struct {
     int32_t bc[4];         /* kinds of the sides x = x0, x = x1, y = y0, y = y1 */
 } cteno_mesh_desc;
 
-/* Scheme parameters (sec. 2.1-2.6).  degree r in {2, 3}: the central
+/* Scheme parameters (sec. 2.1-2.6).  degree r in 2..6: the central
    polynomial of degree r gives order r+1 and uses M = 2K neighbours,
-   K = (r+1)(r+2)/2 - 1; directional polynomials have degree 1; two
-   Gauss-Legendre points per face.  For the Euler equations a cell whose
+   K = (r+1)(r+2)/2 - 1; directional polynomials have degree r_d = 1 up to
+   r = 3 and ceil(r/2) above (K_d basis functions, M_d = 2 K_d cells);
+   N_q = ceil((r+1)/2) Gauss-Legendre points per face.  For the Euler equations a cell whose
    reconstructed density or pressure is <= 0 at any Gauss point uses its
    cell average at all of them (a positivity fallback the paper does not
    describe; flagged by bit 7 of the selection bytes).
@@ -112,7 +113,8 @@ typedef struct {
 typedef struct {
     int64_t n_cells, n_faces, n_boundary_faces;
     int32_t K, M, slots, nv, nq;
-    int32_t n_inadmissible;     /* interior faces whose directional stencil has < 3 cells */
+    int32_t n_inadmissible;     /* interior faces whose directional stencil has < K_d + 1 cells */
+    int32_t Kd, Md;             /* directional basis size and stencil size (M_d = 2 K_d) */
     int64_t device_bytes;       /* resident device memory of the mesh handle */
 } cteno_mesh_info;
 
@@ -157,7 +159,7 @@ cteno_status cteno_mesh_info_get(const cteno_mesh *mesh, cteno_mesh_info *info);
 cteno_status cteno_mesh_stencils(const cteno_mesh *mesh, int32_t *central, int32_t *directional, int32_t *dir_count);
 /* Pseudo-inverses of selected cells, copied to host: central [n][K][M]
    (columns in the order of cteno_mesh_stencils' central list), directional
-   [n][3][2][M_d] (columns in directional-list order, zero where absent).
+   [n][3][K_d][M_d] (columns in directional-list order, zero where absent).
    which = CTENO_FP64 or CTENO_MIXED (the FP32 copy, widened).  Synchronises. */
 cteno_status cteno_mesh_pinv(cteno_ctx *ctx, const cteno_mesh *mesh, int32_t which, int32_t n, const int32_t *cells,
                              double *central, double *directional);

@@ -16,14 +16,26 @@ namespace cteno {
 // ---------------------------------------------------------------------------
 constexpr int kTile = 64;          // cells per tile of the tiled per-cell arrays (one wave)
 constexpr int kNq = 2;             // Gauss points per face for degree <= 3
-constexpr int kMaxK = 9;
-constexpr int kMaxS = 18;
-constexpr int kDirSlots = 4;       // M_d = 2 K_d with K_d = 2 (degree-1 directional)
-constexpr int kPdEntries = 3 * 2 * kDirSlots;
+constexpr int kMaxR = 6;
+constexpr int kMaxK = 27;          // K at degree 6
+constexpr int kMaxS = 54;          // slots at degree 6
+constexpr int kMaxNq = 4;          // Gauss points per face at degree 6
+constexpr int kDirSlots = 4;       // M_d = 2 K_d with K_d = 2 (degree-1 directional, r <= 3)
 
 inline int dims_K(int r) { return (r + 1) * (r + 2) / 2 - 1; }
 inline int dims_M(int r) { return 2 * dims_K(r); }
-inline int dims_S(int r) { return dims_M(r) > 3 * kDirSlots ? dims_M(r) : 3 * kDirSlots; }
+// directional degree: 1 up to cubic, ceil(r/2) above (third-order directional
+// stencils for the fifth-order scheme)
+inline int dims_rd(int r) { return r <= 3 ? 1 : (r + 1) / 2; }
+inline int dims_Kd(int r) { return dims_K(dims_rd(r)); }
+inline int dims_Md(int r) { return 2 * dims_Kd(r); }
+// slots: the three directional groups of M_d slots first, then the rest of
+// the central stencil
+inline int dims_S(int r) { return dims_M(r) > 3 * dims_Md(r) ? dims_M(r) : 3 * dims_Md(r); }
+inline int dims_Nq(int r) { return (r + 2) / 2; }
+// r >= 4: every slot carries K central and K_d directional entries, padded
+// to a multiple of 4 so each slot is a whole number of 16-byte vectors
+inline int ho_slot_entries(int r) { return (dims_K(r) + dims_Kd(r) + 3) / 4 * 4; }
 
 // tiled index: per-cell array with E entries, 64-cell tiles, entry-major inside a tile
 __host__ __device__ inline size_t tix(int64_t i, int e, int E) {
@@ -45,7 +57,14 @@ inline int round_up(int a, int b) { return (a + b - 1) / b * b; }
 __host__ __device__ constexpr int pinv_offset(int j, int K) {
     return j <= 12 ? j * (K + 2) : 12 * (K + 2) + (j - 12) * K;
 }
-inline int pinv_entries(int r) { return pinv_offset(dims_S(r), dims_K(r)); }
+inline int pinv_entries(int r) {
+    return r <= 3 ? pinv_offset(dims_S(r), dims_K(r)) : dims_S(r) * ho_slot_entries(r);
+}
+// r >= 4: vector-tiled stream with tiles of CT cells (CT = 64 / nv: one lane
+// per cell and variable), VW = 4 (FP32) or 2 (FP64) entries per vector
+__host__ __device__ inline size_t hvix(int64_t i, int e, int E, int VW, int CT) {
+    return ((((size_t)(i / CT) * (E / VW) + e / VW) * CT + (i % CT)) * VW) + (e % VW);
+}
 
 // neighbour code per cell face: bit 31 set = boundary (bits 0..1 = kind),
 // else bits 0..27 neighbour (internal index), 28..29 neighbour's local
@@ -58,7 +77,7 @@ constexpr uint32_t kNbIndexMask = 0x0FFFFFFFu;
 // host mesh builder output (all in internal order unless noted)
 // ---------------------------------------------------------------------------
 struct HostMesh {
-    int N = 0, r = 0, K = 0, M = 0, S = 0, nv = 0;
+    int N = 0, r = 0, K = 0, M = 0, S = 0, nv = 0, Kd = 0, Md = 0, Nq = 0;
     int per_x = 0, per_y = 0;
     double Lx = 0, Ly = 0;
     int64_t n_faces = 0, n_boundary = 0;
@@ -67,7 +86,7 @@ struct HostMesh {
     std::vector<int32_t> iperm;    // user -> internal
     // user-order stencils (for inspection)
     std::vector<int32_t> cen_user;     // [N][M] ascending user ids
-    std::vector<int32_t> dir_user;     // [N][3][4] user ids, -1 padded
+    std::vector<int32_t> dir_user;     // [N][3][Md] user ids, -1 padded
     std::vector<int32_t> dirn_user;    // [N][3]
     // internal-order device inputs
     int SP = 0;                        // slots padded to a multiple of 4
@@ -91,12 +110,12 @@ cteno_status build_host_mesh(const cteno_mesh_desc &d, const cteno_scheme &s, Ho
 // constant tables of the reference triangle (host-computed, FP64)
 // ---------------------------------------------------------------------------
 struct RefTables {
-    int K = 0;
+    int K = 0, Nq = 0;
     int ex[kMaxK][2];               // exponents of psi_k
     double mean[kMaxK];             // mean of psi_k over the reference triangle
     double gram[kMaxK][kMaxK];      // smoothness-indicator Gram matrix
-    double basis[3][kNq][kMaxK];    // phi_k at the face Gauss points
-    double gw[kNq];                 // Gauss weights on [0, 1]
+    double basis[3][kMaxNq][kMaxK]; // phi_k at the face Gauss points
+    double gq[kMaxNq], gw[kMaxNq];  // Gauss points and weights on [0, 1]
 };
 void make_ref_tables(int r, RefTables &t);
 

@@ -10,6 +10,8 @@ struct DeviceMesh {
     int r = 0, K = 0, S = 0, SP = 0, nv = 0, physics = 0;
     int scheme = 0, gamma_form = 0, precision = 0;
     int E64 = 0, E32 = 0;          // pseudo-inverse entries per cell (padded to the vector width)
+    int Kd = 0, Md = 0, Nq = 2;    // directional basis size and members, Gauss points per face
+    int stile = 64;                // cells per stream tile (r >= 4: 64 / nv)
     double gamma = 1.4, ax = 0, ay = 0, lam1p = 1e4, ct = 1e-6, eps = 1e-12;
     double Lx = 0, Ly = 0;
     int32_t *slot = nullptr;       // vector-tiled [SP], VW 4
@@ -20,6 +22,8 @@ struct DeviceMesh {
     double *P64 = nullptr;         // pseudo-inverse stream, vector-tiled [E64], VW 2
     float *P32 = nullptr;          // pseudo-inverse stream, vector-tiled [E32], VW 4
     int32_t *perm = nullptr;       // internal -> user [N]
+    double *htab64 = nullptr;      // r >= 4: Gram matrix [K][K] and face basis [3][Nq][K], FP64
+    float *htab32 = nullptr;       // the same in FP32
     RefTables tab;
     int64_t blocks() const { return (N + 255) / 256; }
 };
@@ -92,8 +96,9 @@ hipError_t launch_count_diff(const DeviceMesh &m, const uint8_t *a, const uint8_
                              hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, size_t n, hipStream_t st);
 hipError_t launch_copy16(void *dst, const void *src, size_t n16, hipStream_t st);
-// dst[a][e] = src[avix(idx[a], e, E, VW)] from exactly one of src64 / src32 / srci
+// dst[a][e] = src[avix(idx[a], e, E, VW)] (ct = 64) or src[hvix(idx[a], e, E, VW, ct)]
+// from exactly one of src64 / src32 / srci
 hipError_t launch_gather_entries(int n, const int32_t *idx, int E, int VW, const double *src64, const float *src32,
-                                 const int32_t *srci, double *dst, hipStream_t st);
+                                 const int32_t *srci, double *dst, hipStream_t st, int ct = 64);
 
 }  // namespace cteno

@@ -59,14 +59,16 @@ __device__ __forceinline__ void load_row(const real *__restrict__ p, real *out) 
 #pragma unroll
             for (int c = 0; c < W; ++c) out[k * W + c] = comp(v, c);
         }
-    } else {
-        static_assert(std::is_same<real, float>::value && n % 2 == 0, "row must be a multiple of 8 bytes");
+    } else if constexpr (std::is_same<real, float>::value && n % 2 == 0) {
 #pragma unroll
         for (int k = 0; k < n / 2; ++k) {
             const float2 v = reinterpret_cast<const float2 *>(p)[k];
             out[2 * k] = v.x;
             out[2 * k + 1] = v.y;
         }
+    } else {
+#pragma unroll
+        for (int k = 0; k < n; ++k) out[k] = p[k];
     }
 }
 template <typename real, int n>
@@ -80,10 +82,12 @@ __device__ __forceinline__ void store_row(real *__restrict__ p, const real *in) 
 #pragma unroll
             for (int k = 0; k < n / 2; ++k) reinterpret_cast<double2 *>(p)[k] = make_double2(in[2 * k], in[2 * k + 1]);
         }
-    } else {
-        static_assert(std::is_same<real, float>::value && n % 2 == 0, "row must be a multiple of 8 bytes");
+    } else if constexpr (std::is_same<real, float>::value && n % 2 == 0) {
 #pragma unroll
         for (int k = 0; k < n / 2; ++k) reinterpret_cast<float2 *>(p)[k] = make_float2(in[2 * k], in[2 * k + 1]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < n; ++k) p[k] = in[k];
     }
 }
 
@@ -337,6 +341,25 @@ static void gauss_legendre4(double x[4], double w[4]) {
     }
 }
 
+// collapsed 4 x 4 Gauss-Legendre rule on the reference triangle (exact to
+// degree 6, the highest monomial degree of the basis)
+static void fill_quad_rule(QuadRule &q) {
+    double x[4], w[4];
+    gauss_legendre4(x, w);
+    int p = 0;
+    for (int u = 0; u < 4; ++u)
+        for (int v = 0; v < 4; ++v) {
+            double su = 0.5 * (x[u] + 1.0), sv = 0.5 * (x[v] + 1.0);
+            q.s[p] = su;
+            q.t[p] = sv * (1.0 - su);
+            q.w[p] = 0.25 * w[u] * w[v] * (1.0 - su);
+            ++p;
+        }
+}
+
+template <int R>
+static hipError_t precompute_ho_r(const DeviceMesh &m, const PrecomputeInputs &in, hipStream_t st);
+
 template <int R>
 static hipError_t precompute_r(const DeviceMesh &m, const PrecomputeInputs &in, hipStream_t st) {
     PreArgs<R> a;
@@ -350,17 +373,7 @@ static hipError_t precompute_r(const DeviceMesh &m, const PrecomputeInputs &in, 
         a.ex[k][1] = m.tab.ex[k][1];
         a.mean[k] = m.tab.mean[k];
     }
-    double x[4], w[4];
-    gauss_legendre4(x, w);
-    int p = 0;
-    for (int u = 0; u < 4; ++u)
-        for (int v = 0; v < 4; ++v) {
-            double su = 0.5 * (x[u] + 1.0), sv = 0.5 * (x[v] + 1.0);
-            a.q.s[p] = su;
-            a.q.t[p] = sv * (1.0 - su);
-            a.q.w[p] = 0.25 * w[u] * w[v] * (1.0 - su);
-            ++p;
-        }
+    fill_quad_rule(a.q);
     const unsigned grid = (unsigned)((m.N + 63) / 64);
     hipLaunchKernelGGL(k_precompute<R>, dim3(grid), dim3(64), 0, st, a);
     return hipGetLastError();
@@ -370,6 +383,9 @@ hipError_t launch_precompute(const DeviceMesh &m, const PrecomputeInputs &in, hi
     switch (m.r) {
         case 2: return precompute_r<2>(m, in, st);
         case 3: return precompute_r<3>(m, in, st);
+        case 4: return precompute_ho_r<4>(m, in, st);
+        case 5: return precompute_ho_r<5>(m, in, st);
+        case 6: return precompute_ho_r<6>(m, in, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -839,10 +855,497 @@ static hipError_t reconstruct_p(const DeviceMesh &m, const double *U, void *FV, 
     return hipErrorInvalidValue;
 }
 
+template <typename real>
+static hipError_t reconstruct_ho_p(const DeviceMesh &m, const double *U, void *FV, uint8_t *delta, int dmode,
+                                   const int *done, hipStream_t st);
+
 hipError_t launch_reconstruct(const DeviceMesh &m, bool fp32, const double *U, void *FV, uint8_t *delta, int dmode,
                               const int *done, hipStream_t st) {
+    if (m.r >= 4)
+        return fp32 ? reconstruct_ho_p<float>(m, U, FV, delta, dmode, done, st)
+                    : reconstruct_ho_p<double>(m, U, FV, delta, dmode, done, st);
     return fp32 ? reconstruct_p<float>(m, U, FV, delta, dmode, done, st)
                 : reconstruct_p<double>(m, U, FV, delta, dmode, done, st);
+}
+
+// ===========================================================================
+// orders 5 to 7 (r = 4..6)
+// ===========================================================================
+// The pseudo-inverse stream of a cell has S = 3 M_d slots (the three
+// directional groups cover the whole central stencil) of EPS entries: K
+// central, K_d directional, zero padding to a multiple of 4.  It is
+// vector-tiled with tiles of CT = 64 / nv cells: the reconstruction runs one
+// lane per (cell, variable), so a wave covers CT cells and its lanes of one
+// cell read the same 16-byte vector.
+
+// sum over the wave; the butterfly adds the same pairs in every lane, so all
+// lanes hold bitwise the same result
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+template <int R>
+struct HoDims {
+    static constexpr int K = (R + 1) * (R + 2) / 2 - 1;
+    static constexpr int RD = (R + 1) / 2;
+    static constexpr int KD = (RD + 1) * (RD + 2) / 2 - 1;
+    static constexpr int MD = 2 * KD;
+    static constexpr int S = 3 * MD;
+    static constexpr int SP = (S + 3) / 4 * 4;
+    static constexpr int EPS = (K + KD + 3) / 4 * 4;
+    static constexpr int E = S * EPS;
+    static constexpr int NQ = (R + 2) / 2;
+    static_assert(S >= 2 * K, "the directional groups must hold the central stencil");
+    static_assert(S <= 64, "one lane per least-squares row");
+};
+
+template <int R>
+struct PreHoArgs {
+    using D = HoDims<R>;
+    int64_t N;
+    const double *verts;
+    const int32_t *slot;
+    const uint8_t *slot_flag;
+    const int8_t *slot_shift;
+    uint8_t *flags;
+    int *rank_fail;
+    double *P64;
+    float *P32;
+    int ct;                  // cells per stream tile
+    double Lx, Ly;
+    int ex[D::K][2];
+    double mean[D::K];
+    QuadRule q;
+};
+
+// One wave per cell, one lane per least-squares row (slot).  Householder QR
+// (sec. 2.1) of the S x K central system and of the three M_d x K_d
+// directional systems; P = R^-1 Q^T diag(|V'_m|), column by column.
+template <int R>
+__global__ __launch_bounds__(256) void k_precompute_ho(const PreHoArgs<R> a) {
+    using D = HoDims<R>;
+    constexpr int K = D::K, KD = D::KD, MD = D::MD, S = D::S, SP = D::SP, EPS = D::EPS, E = D::E;
+    __shared__ double sA[4][K][64];       // central system, column-major, row = lane
+    __shared__ double sD[4][KD][64];      // directional systems (disjoint rows)
+    __shared__ double sH[4][3][K];        // central v0, beta, diag(R)
+    __shared__ double sHd[4][3][3][KD];   // directional v0, beta, diag(R)
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * 4 + wv;
+    if (i >= a.N) return;                 // whole waves; a wave only touches its own LDS
+    double (*cA)[64] = sA[wv];
+    double (*cD)[64] = sD[wv];
+    auto put = [&](int e, double v) {
+        a.P64[hvix(i, e, E, 2, a.ct)] = v;
+        if (a.P32) a.P32[hvix(i, e, E, 4, a.ct)] = (float)v;
+    };
+
+    // reference map of cell i: v0 and J = [v1 - v0, v2 - v0]
+    const double x0 = a.verts[tix(i, 0, 6)], y0 = a.verts[tix(i, 1, 6)];
+    const double ja = a.verts[tix(i, 2, 6)] - x0, jc = a.verts[tix(i, 3, 6)] - y0;
+    const double jb = a.verts[tix(i, 4, 6)] - x0, jd = a.verts[tix(i, 5, 6)] - y0;
+    const double det = ja * jd - jb * jc;
+
+    // row of slot `lane`: A_mk = int_{V'_m} psi_k - |V'_m| mean(psi_k)
+    uint8_t fl = 0;
+    double w = 0.0;
+    double row[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) row[k] = 0.0;
+    if (lane < S) {
+        fl = a.slot_flag[tix(i, lane, S)];
+        if (fl & 1) {
+            const int64_t m = a.slot[avix(i, lane, SP, 4)];
+            const double sx = a.slot_shift[tix(i, 2 * lane, 2 * S)] * a.Lx;
+            const double sy = a.slot_shift[tix(i, 2 * lane + 1, 2 * S)] * a.Ly;
+            double X[3], Y[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const double px = (a.verts[tix(m, 2 * c, 6)] + sx) - x0;
+                const double py = (a.verts[tix(m, 2 * c + 1, 6)] + sy) - y0;
+                X[c] = (jd * px - jb * py) / det;
+                Y[c] = (-jc * px + ja * py) / det;
+            }
+            const double ar = 0.5 * fabs((X[1] - X[0]) * (Y[2] - Y[0]) - (X[2] - X[0]) * (Y[1] - Y[0]));
+            double mom[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) mom[k] = 0.0;
+#pragma unroll 1
+            for (int p = 0; p < 16; ++p) {
+                const double xi = X[0] + a.q.s[p] * (X[1] - X[0]) + a.q.t[p] * (X[2] - X[0]);
+                const double et = Y[0] + a.q.s[p] * (Y[1] - Y[0]) + a.q.t[p] * (Y[2] - Y[0]);
+                double px[R + 1], py[R + 1];
+                px[0] = py[0] = 1.0;
+#pragma unroll
+                for (int e = 1; e <= R; ++e) { px[e] = px[e - 1] * xi; py[e] = py[e - 1] * et; }
+#pragma unroll
+                for (int k = 0; k < K; ++k) mom[k] += a.q.w[p] * (px[a.ex[k][0]] * py[a.ex[k][1]]);
+            }
+#pragma unroll
+            for (int k = 0; k < K; ++k) row[k] = 2.0 * ar * mom[k] - ar * a.mean[k];
+            w = ar;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) cA[k][lane] = row[k];
+#pragma unroll
+    for (int k = 0; k < KD; ++k) cD[k][lane] = (fl & 2) ? row[k] : 0.0;
+    const double wc = w, wd = (fl & 2) ? w : 0.0;
+    __builtin_amdgcn_wave_barrier();
+
+    // central Householder QR; column k's tail (rows > k) keeps the reflector
+    double amax = 0.0;
+#pragma unroll 1
+    for (int k = 0; k < K; ++k) {
+        const double x = lane >= k ? cA[k][lane] : 0.0;
+        const double nrm = sqrt(wave_sum(x * x));
+        const double xk = cA[k][k];
+        const double alpha = xk > 0 ? -nrm : nrm;
+        const double v = lane == k ? xk - alpha : x;
+        const double vv = wave_sum(v * v);
+        const double beta = vv > 0 ? 2.0 / vv : 0.0;
+        if (lane == 0) { sH[wv][0][k] = xk - alpha; sH[wv][1][k] = beta; sH[wv][2][k] = alpha; }
+        amax = fmax(amax, fabs(alpha));
+#pragma unroll 1
+        for (int c = k + 1; c < K; ++c) {
+            const double y = cA[c][lane];
+            const double sm = beta * wave_sum(v * y);
+            cA[c][lane] = y - sm * v;
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    bool rank_ok = amax > 0.0;
+#pragma unroll 1
+    for (int k = 0; k < K; ++k) rank_ok = rank_ok && fabs(sH[wv][2][k]) > 1e-12 * amax;
+    if (!rank_ok && lane == 0) atomicAdd(a.rank_fail, 1);
+
+    // column m of P: apply the reflectors to w_m e_m, then back-substitute;
+    // lane k ends with coefficient k
+#pragma unroll 1
+    for (int m = 0; m < S; ++m) {
+        double b = lane == m ? wc : 0.0;
+#pragma unroll 1
+        for (int k = 0; k < K; ++k) {
+            const double v = lane > k ? cA[k][lane] : (lane == k ? sH[wv][0][k] : 0.0);
+            b -= sH[wv][1][k] * wave_sum(v * b) * v;
+        }
+        double xo = 0.0;
+#pragma unroll 1
+        for (int k = K - 1; k >= 0; --k) {
+            const double xk = __shfl(b, k, 64) / sH[wv][2][k];
+            if (lane == k) xo = xk;
+            if (lane < k) b -= cA[k][lane] * xk;
+        }
+        if (lane < K) put(m * EPS + lane, rank_ok ? xo : 0.0);
+    }
+
+    // directional systems: group s owns rows [s M_d, (s+1) M_d); its members
+    // come first, in directional-list order
+    uint8_t flg = a.flags[i];
+#pragma unroll 1
+    for (int s = 0; s < 3; ++s) {
+        const int base = s * MD;
+        const bool in = lane >= base && lane < base + MD;
+        double dmax = 0.0;
+#pragma unroll 1
+        for (int k = 0; k < KD; ++k) {
+            const int pk = base + k;
+            const double x = (in && lane >= pk) ? cD[k][lane] : 0.0;
+            const double nrm = sqrt(wave_sum(x * x));
+            const double xk = cD[k][pk];
+            const double alpha = xk > 0 ? -nrm : nrm;
+            const double v = lane == pk ? xk - alpha : x;
+            const double vv = wave_sum(v * v);
+            const double beta = vv > 0 ? 2.0 / vv : 0.0;
+            if (lane == 0) { sHd[wv][s][0][k] = xk - alpha; sHd[wv][s][1][k] = beta; sHd[wv][s][2][k] = alpha; }
+            dmax = fmax(dmax, fabs(alpha));
+#pragma unroll 1
+            for (int c = k + 1; c < KD; ++c) {
+                const double y = cD[c][lane];
+                const double sm = beta * wave_sum(v * y);
+                if (in) cD[c][lane] = y - sm * v;
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        bool ok = ((flg >> s) & 1) && dmax > 0.0;
+#pragma unroll 1
+        for (int k = 0; k < KD; ++k) ok = ok && fabs(sHd[wv][s][2][k]) > 1e-12 * dmax;
+        if (!ok) flg &= (uint8_t)~(1u << s);
+#pragma unroll 1
+        for (int t = 0; t < MD; ++t) {
+            const int mrow = base + t;
+            double b = lane == mrow ? wd : 0.0;
+#pragma unroll 1
+            for (int k = 0; k < KD; ++k) {
+                const double v = (in && lane > base + k) ? cD[k][lane] : (lane == base + k ? sHd[wv][s][0][k] : 0.0);
+                b -= sHd[wv][s][1][k] * wave_sum(v * b) * v;
+            }
+            double xo = 0.0;
+#pragma unroll 1
+            for (int k = KD - 1; k >= 0; --k) {
+                const double xk = __shfl(b, base + k, 64) / sHd[wv][s][2][k];
+                if (lane == base + k) xo = xk;
+                if (lane >= base && lane < base + k) b -= cD[k][lane] * xk;
+            }
+            if (lane >= base && lane < base + KD) put(mrow * EPS + K + (lane - base), ok ? xo : 0.0);
+        }
+    }
+    if (lane == 0) a.flags[i] = flg;
+}
+
+template <int R>
+static hipError_t precompute_ho_r(const DeviceMesh &m, const PrecomputeInputs &in, hipStream_t st) {
+    using D = HoDims<R>;
+    if (m.S != D::S || m.E64 != D::E || m.E32 != D::E || m.SP != D::SP) return hipErrorInvalidValue;
+    PreHoArgs<R> a;
+    a.N = m.N;
+    a.verts = in.verts; a.slot = m.slot; a.slot_flag = in.slot_flag; a.slot_shift = in.slot_shift;
+    a.flags = in.flags; a.rank_fail = in.rank_fail;
+    a.P64 = m.P64; a.P32 = m.P32; a.ct = m.stile;
+    a.Lx = m.Lx; a.Ly = m.Ly;
+    for (int k = 0; k < D::K; ++k) {
+        a.ex[k][0] = m.tab.ex[k][0];
+        a.ex[k][1] = m.tab.ex[k][1];
+        a.mean[k] = m.tab.mean[k];
+    }
+    fill_quad_rule(a.q);
+    const unsigned grid = (unsigned)((m.N + 3) / 4);
+    hipLaunchKernelGGL(k_precompute_ho<R>, dim3(grid), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+// scheme constants of the higher-order reconstruction: linear weights, and a
+// device table (Gram matrix [K][K], then face basis [3][N_q][K])
+template <typename real>
+struct ReconHoArgs {
+    int64_t N;
+    const double *U;
+    const int32_t *slot;
+    const uint8_t *flags;
+    const real *P;
+    real *FV;                // AoS [Np][3][N_q][nv]
+    uint8_t *delta;
+    const int *done;
+    const real *tab;
+    real lams[5], lam_ratio[5];
+    real lam1, ct, eps, gamma;
+};
+
+template <typename real, int R, int NV, int SCHEME, int GFORM, int DMODE>
+__global__ __launch_bounds__(256) void k_reconstruct_ho(const ReconHoArgs<real> a) {
+    using D = HoDims<R>;
+    constexpr int K = D::K, KD = D::KD, MD = D::MD, S = D::S, SP = D::SP, EPS = D::EPS, E = D::E, NQ = D::NQ;
+    constexpr int CT = 64 / NV;
+    using V = typename Vec<real>::T;
+    constexpr int VW = Vec<real>::W;
+    constexpr int SV = EPS / VW;          // stream vectors per slot
+    const int64_t i = xcd_block(blockIdx.x, gridDim.x) * (256 / NV) + threadIdx.x / NV;
+    const int v = threadIdx.x % NV;
+    if (i >= a.N) return;                 // all lanes of a cell leave together
+    if (a.done && *a.done) return;
+    const V *__restrict__ Pv = reinterpret_cast<const V *>(a.P) + (size_t)(i / CT) * (E / VW) * CT + (i % CT);
+    const int32_t *__restrict__ Si = a.slot + (size_t)(i >> 6) * (SP / 4) * 256 + (i & 63) * 4;
+    const double U0 = a.U[i * NV + v];
+
+    // a_opt = P_c d and a_s = P_s d, slot by slot; the next slot's stream
+    // vectors and index are requested before the current slot is used
+    real ao[K], ad[3][KD], adt[KD];
+#pragma unroll
+    for (int k = 0; k < K; ++k) ao[k] = 0;
+#pragma unroll
+    for (int k = 0; k < KD; ++k) { adt[k] = 0; ad[0][k] = 0; ad[1][k] = 0; ad[2][k] = 0; }
+    V cur[SV];
+#pragma unroll
+    for (int g = 0; g < SV; ++g) cur[g] = Pv[g * CT];
+    int mcur = Si[0];
+#pragma unroll 1
+    for (int j = 0; j < S; ++j) {
+        const int jn = j + 1 < S ? j + 1 : j;
+        V nxt[SV];
+#pragma unroll
+        for (int g = 0; g < SV; ++g) nxt[g] = Pv[(jn * SV + g) * CT];
+        const int mn = Si[(jn >> 2) * 256 + (jn & 3)];
+        const real d = (real)(a.U[(int64_t)mcur * NV + v] - U0);
+#pragma unroll
+        for (int k = 0; k < K; ++k) ao[k] += comp(cur[k / VW], k % VW) * d;
+#pragma unroll
+        for (int k = 0; k < KD; ++k) adt[k] += comp(cur[(K + k) / VW], (K + k) % VW) * d;
+        if (j % MD == MD - 1) {           // uniform: group j / MD is complete
+            const int s = j / MD;
+#pragma unroll
+            for (int s2 = 0; s2 < 3; ++s2)
+                if (s2 == s)
+#pragma unroll
+                    for (int k = 0; k < KD; ++k) ad[s2][k] = adt[k];
+#pragma unroll
+            for (int k = 0; k < KD; ++k) adt[k] = 0;
+        }
+#pragma unroll
+        for (int g = 0; g < SV; ++g) cur[g] = nxt[g];
+        mcur = mn;
+    }
+
+    const int fl = a.flags[i] & 7;
+    const int adm = 1 | (fl << 1);
+    const int st = 1 + __popc(fl);
+    const real lams = st == 2 ? a.lams[2] : (st == 3 ? a.lams[3] : a.lams[4]);
+    const real lratio = st == 2 ? a.lam_ratio[2] : (st == 3 ? a.lam_ratio[3] : a.lam_ratio[4]);
+    // p_1 = (p_opt - sum_s lambda_s p_s) / lambda_1 (eq. e17), in place
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        real sm = ao[k];
+        if (k < KD && st > 1) {
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+                if ((fl >> q) & 1) sm -= lams * ad[q][k];
+        }
+        ao[k] = st > 1 ? sm / a.lam1 : sm;
+    }
+    int bits;
+    if (DMODE == 2) {
+        bits = a.delta[i * NV + v] & adm;
+    } else if (st == 1) {
+        bits = 1;
+    } else {
+        real si[4];
+        si[0] = 0;
+#pragma unroll
+        for (int p = 0; p < K; ++p) {
+            real rp = 0;
+#pragma unroll
+            for (int q = 0; q < K; ++q) rp += a.tab[p * K + q] * ao[q];
+            si[0] += ao[p] * rp;
+        }
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+            real sv = 0;
+#pragma unroll
+            for (int p = 0; p < KD; ++p) {
+                real rp = 0;
+#pragma unroll
+                for (int q = 0; q < KD; ++q) rp += a.tab[p * K + q] * ad[s][q];
+                sv += ad[s][p] * rp;
+            }
+            si[s + 1] = sv;
+        }
+        bits = teno_bits<real, SCHEME, GFORM>(si, adm, st, a.lam1, lams, lratio, a.ct, a.eps);
+    }
+    // final coefficients: p_1, or the mean of the selected directional polynomials
+    if (!(bits & 1)) {
+        int cnt = 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) ao[k] = 0;
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+            if ((bits >> (q + 1)) & 1) {
+                ++cnt;
+#pragma unroll
+                for (int k = 0; k < KD; ++k) ao[k] += ad[q][k];
+            }
+#pragma unroll
+        for (int k = 0; k < KD; ++k) ao[k] /= (real)cnt;
+    }
+    // face Gauss-point values
+    const real *Bt = a.tab + K * K;
+    real out[3][NQ];
+#pragma unroll
+    for (int f = 0; f < 3; ++f)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            real val = 0;
+#pragma unroll
+            for (int k = 0; k < K; ++k) val += Bt[(f * NQ + q) * K + k] * ao[k];
+            out[f][q] = (real)(U0 + (double)val);
+        }
+    if constexpr (NV == 4) {
+        // positivity fallback (density or pressure <= 0 at a Gauss point):
+        // the four lanes of the cell exchange their values
+        const int l0 = (threadIdx.x & 63) & ~3;
+        bool bad = false;
+#pragma unroll
+        for (int f = 0; f < 3; ++f)
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const real r0 = __shfl(out[f][q], l0, 64), r1 = __shfl(out[f][q], l0 + 1, 64);
+                const real r2 = __shfl(out[f][q], l0 + 2, 64), r3 = __shfl(out[f][q], l0 + 3, 64);
+                const real pr = (a.gamma - 1) * (r3 - (real)0.5 * (r1 * r1 + r2 * r2) / r0);
+                bad |= !(r0 > 0) || !(pr > 0);
+            }
+        if (bad) {
+#pragma unroll
+            for (int f = 0; f < 3; ++f)
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) out[f][q] = (real)U0;
+            bits |= 0x80;
+        }
+    }
+    if (DMODE == 1) a.delta[i * NV + v] = (uint8_t)bits;
+#pragma unroll
+    for (int f = 0; f < 3; ++f)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) a.FV[((i * 3 + f) * NQ + q) * NV + v] = out[f][q];
+}
+
+template <typename real, int R, int NV>
+static hipError_t reconstruct_ho_t(const DeviceMesh &m, const double *U, void *FV, uint8_t *delta, int dmode,
+                                   const int *done, hipStream_t st) {
+    using D = HoDims<R>;
+    ReconHoArgs<real> a;
+    a.N = m.N;
+    a.U = U;
+    a.slot = m.slot;
+    a.flags = m.flags;
+    if constexpr (std::is_same<real, double>::value) { a.P = m.P64; a.tab = m.htab64; }
+    else { a.P = m.P32; a.tab = m.htab32; }
+    if (!a.P || !a.tab || m.stile != 64 / NV || m.E64 != D::E) return hipErrorInvalidValue;
+    a.FV = (real *)FV;
+    a.delta = delta;
+    a.done = done;
+    const double lam1 = 1.0 - 1.0 / m.lam1p;
+    a.lam1 = (real)lam1;
+    a.gamma = (real)m.gamma;
+    a.ct = (real)m.ct;
+    a.eps = (real)m.eps;
+    for (int s = 0; s < 5; ++s) {
+        const double ls = s >= 2 ? (1.0 - lam1) / (s - 1) : 0.0;
+        a.lams[s] = (real)ls;
+        a.lam_ratio[s] = s >= 2 ? (real)(lam1 / ls) : (real)1;
+    }
+    const unsigned grid = (unsigned)((m.N * NV + 255) / 256);
+#define HO_LAUNCH(SCH, GF, DM) \
+    hipLaunchKernelGGL((k_reconstruct_ho<real, R, NV, SCH, GF, DM>), dim3(grid), dim3(256), 0, st, a)
+#define HO_DM(SCH, GF)                        \
+    switch (dmode) {                          \
+        case 0: HO_LAUNCH(SCH, GF, 0); break; \
+        case 1: HO_LAUNCH(SCH, GF, 1); break; \
+        default: HO_LAUNCH(SCH, GF, 2); break; \
+    }
+    if (m.scheme == CTENO_SCHEME_CTENOZ) { HO_DM(CTENO_SCHEME_CTENOZ, CTENO_GAMMA_PAPER); }
+    else if (m.gamma_form == CTENO_GAMMA_LAMBDA) { HO_DM(CTENO_SCHEME_CTENO, CTENO_GAMMA_LAMBDA); }
+    else { HO_DM(CTENO_SCHEME_CTENO, CTENO_GAMMA_PAPER); }
+#undef HO_DM
+#undef HO_LAUNCH
+    return hipGetLastError();
+}
+
+template <typename real>
+static hipError_t reconstruct_ho_p(const DeviceMesh &m, const double *U, void *FV, uint8_t *delta, int dmode,
+                                   const int *done, hipStream_t st) {
+    if (m.nv == 4) {
+        switch (m.r) {
+            case 4: return reconstruct_ho_t<real, 4, 4>(m, U, FV, delta, dmode, done, st);
+            case 5: return reconstruct_ho_t<real, 5, 4>(m, U, FV, delta, dmode, done, st);
+            case 6: return reconstruct_ho_t<real, 6, 4>(m, U, FV, delta, dmode, done, st);
+        }
+    } else {
+        switch (m.r) {
+            case 4: return reconstruct_ho_t<real, 4, 1>(m, U, FV, delta, dmode, done, st);
+            case 5: return reconstruct_ho_t<real, 5, 1>(m, U, FV, delta, dmode, done, st);
+            case 6: return reconstruct_ho_t<real, 6, 1>(m, U, FV, delta, dmode, done, st);
+        }
+    }
+    return hipErrorInvalidValue;
 }
 
 // ===========================================================================
@@ -920,6 +1423,7 @@ struct FluxArgs {
     Ctrl *ctrl;
     double *dt_part;
     real gamma, ax, ay;
+    real gw[4];             // Gauss weights on [0, 1]
     double gamma64;
     int stage;
 };
@@ -988,7 +1492,7 @@ struct FluxPtrs {
 
 // one cell's three faces, residual and (MODE 2) RK stage; returns the cell's
 // CFL bound of the new state when requested, else +inf
-template <typename real, int NV, int PHYS, int MODE>
+template <typename real, int NV, int PHYS, int MODE, int NQ>
 __device__ __forceinline__ double flux_body(const FluxArgs<real> a, const FluxPtrs<real> ptr, int64_t i) {
     double dtc = INFINITY;
     {
@@ -997,35 +1501,35 @@ __device__ __forceinline__ double flux_body(const FluxArgs<real> a, const FluxPt
         for (int v = 0; v < NV; ++v) acc[v] = 0.0;
         double nrm[3][3];
         bool bad = false;
-        real own[3][2][NV];
-        load_row<real, 3 * 2 * NV>(ptr.FV + i * 3 * 2 * NV, &own[0][0][0]);
+        real own[3][NQ][NV];
+        load_row<real, 3 * NQ * NV>(ptr.FV + i * 3 * NQ * NV, &own[0][0][0]);
 #pragma unroll
         for (int f = 0; f < 3; ++f) {
             real nx, ny, len;
             uint32_t code;
             face_record<real>(ptr.fr, i, f, nx, ny, len, code);
             nrm[f][0] = (double)nx; nrm[f][1] = (double)ny; nrm[f][2] = (double)len;
-            real oth[2][NV];
+            real oth[NQ][NV];
             bool owner;
             if (code & kNbBoundary) {
                 owner = true;
                 const bool wall = (code & 3u) == CTENO_WALL;
-                // ghost state at the same Gauss point: oth[1-q] pairs with own[q]
+                // ghost state at the same Gauss point: oth[NQ-1-q] pairs with own[q]
 #pragma unroll
-                for (int q = 0; q < 2; ++q) {
+                for (int q = 0; q < NQ; ++q) {
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) oth[1 - q][v] = own[f][q][v];
+                    for (int v = 0; v < NV; ++v) oth[NQ - 1 - q][v] = own[f][q][v];
                     if (PHYS == CTENO_EULER && wall) {
                         const real mn = own[f][q][1] * nx + own[f][q][2] * ny;
-                        oth[1 - q][1] = own[f][q][1] - 2 * mn * nx;
-                        oth[1 - q][2] = own[f][q][2] - 2 * mn * ny;
+                        oth[NQ - 1 - q][1] = own[f][q][1] - 2 * mn * nx;
+                        oth[NQ - 1 - q][2] = own[f][q][2] - 2 * mn * ny;
                     }
                 }
             } else {
                 owner = (code & kNbOwner) != 0;
                 const int64_t j = code & kNbIndexMask;
                 const int g = (code >> 28) & 3;
-                load_row<real, 2 * NV>(ptr.FV + (j * 3 + g) * 2 * NV, &oth[0][0]);
+                load_row<real, NQ * NV>(ptr.FV + (j * 3 + g) * NQ * NV, &oth[0][0]);
             }
             // both cells of a face evaluate F(owner side, other side; owner normal)
             // at the owner's Gauss points in the owner's order
@@ -1034,12 +1538,12 @@ __device__ __forceinline__ double flux_body(const FluxArgs<real> a, const FluxPt
 #pragma unroll
             for (int v = 0; v < NV; ++v) sumF[v] = 0;
 #pragma unroll
-            for (int q = 0; q < 2; ++q) {
+            for (int q = 0; q < NQ; ++q) {
                 real A[NV], B[NV], F[NV];
 #pragma unroll
                 for (int v = 0; v < NV; ++v) {
                     A[v] = owner ? own[f][q][v] : oth[q][v];
-                    B[v] = owner ? oth[1 - q][v] : own[f][1 - q][v];
+                    B[v] = owner ? oth[NQ - 1 - q][v] : own[f][NQ - 1 - q][v];
                 }
                 if (PHYS == CTENO_EULER) {
                     bad |= !hllc<real>(a.gamma, A, B, fx, fy, F);
@@ -1048,7 +1552,7 @@ __device__ __forceinline__ double flux_body(const FluxArgs<real> a, const FluxPt
                     F[0] = an * (an >= 0 ? A[0] : B[0]);
                 }
 #pragma unroll
-                for (int v = 0; v < NV; ++v) sumF[v] += (real)0.5 * F[v];
+                for (int v = 0; v < NV; ++v) sumF[v] += a.gw[q] * F[v];
             }
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
@@ -1100,14 +1604,14 @@ __device__ __forceinline__ double flux_body(const FluxArgs<real> a, const FluxPt
     return dtc;
 }
 
-template <typename real, int NV, int PHYS, int MODE>
+template <typename real, int NV, int PHYS, int MODE, int NQ>
 __global__ __launch_bounds__(256) void k_flux(const FluxArgs<real> a) {
     const int64_t i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (a.ctrl && a.ctrl->done) return;        // uniform across the grid
     const FluxPtrs<real> ptr{a.FV, a.fr, a.area, a.Un, a.Us, a.Uout, a.dt_ptr, a.flux_out, a.resid, a.ctrl,
                              a.dt_part != nullptr};
     double dtc = INFINITY;
-    if (i < a.N) dtc = flux_body<real, NV, PHYS, MODE>(a, ptr, i);
+    if (i < a.N) dtc = flux_body<real, NV, PHYS, MODE, NQ>(a, ptr, i);
     if (MODE == 2 && a.dt_part) {
         const double bm = block_min(dtc);
         if (threadIdx.x == 0) a.dt_part[blockIdx.x] = bm;
@@ -1131,12 +1635,21 @@ static hipError_t flux_t(const DeviceMesh &m, const FluxLaunch &f, hipStream_t s
     a.gamma = (real)m.gamma; a.ax = (real)m.ax; a.ay = (real)m.ay;
     a.gamma64 = m.gamma;
     a.stage = f.stage;
+    for (int q = 0; q < 4; ++q) a.gw[q] = q < m.tab.Nq ? (real)m.tab.gw[q] : (real)0;
     const unsigned grid = (unsigned)m.blocks();
-    switch (f.mode) {
-        case 0: hipLaunchKernelGGL((k_flux<real, NV, PHYS, 0>), dim3(grid), dim3(256), 0, st, a); break;
-        case 1: hipLaunchKernelGGL((k_flux<real, NV, PHYS, 1>), dim3(grid), dim3(256), 0, st, a); break;
-        default: hipLaunchKernelGGL((k_flux<real, NV, PHYS, 2>), dim3(grid), dim3(256), 0, st, a); break;
+#define FX_LAUNCH(NQ)                                                                                         \
+    switch (f.mode) {                                                                                         \
+        case 0: hipLaunchKernelGGL((k_flux<real, NV, PHYS, 0, NQ>), dim3(grid), dim3(256), 0, st, a); break; \
+        case 1: hipLaunchKernelGGL((k_flux<real, NV, PHYS, 1, NQ>), dim3(grid), dim3(256), 0, st, a); break; \
+        default: hipLaunchKernelGGL((k_flux<real, NV, PHYS, 2, NQ>), dim3(grid), dim3(256), 0, st, a); break; \
     }
+    switch (m.tab.Nq) {
+        case 2: FX_LAUNCH(2); break;
+        case 3: FX_LAUNCH(3); break;
+        case 4: FX_LAUNCH(4); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef FX_LAUNCH
     return hipGetLastError();
 }
 
@@ -1285,7 +1798,7 @@ __global__ __launch_bounds__(256) void k_flux_batch(const FluxArgs<float> a, con
     const FluxPtrs<float> ptr{t.FV, t.fr, t.area, t.U[0], t.U[stage], stage == 2 ? t.U[0] : t.U[stage + 1],
                               &t.ctrl->dt, nullptr, nullptr, t.ctrl, stage == 2};
     double dtc = INFINITY;
-    if (i < t.N) dtc = flux_body<float, 4, CTENO_EULER, 2>(a, ptr, i);
+    if (i < t.N) dtc = flux_body<float, 4, CTENO_EULER, 2, 2>(a, ptr, i);
     if (stage == 2) {
         const double bm = block_min(dtc);
         if (threadIdx.x == 0) t.dt_part[local] = bm;
@@ -1310,6 +1823,8 @@ static hipError_t batch_step_r(const DeviceMesh &proto, const BatchSlot *tab, co
     FluxArgs<float> fa;
     std::memset(&fa, 0, sizeof fa);
     fa.gamma = (float)proto.gamma; fa.ax = (float)proto.ax; fa.ay = (float)proto.ay; fa.gamma64 = proto.gamma;
+    fa.gw[0] = fa.gw[1] = 0.5f;
+    fa.gw[2] = fa.gw[3] = 0.0f;
     hipLaunchKernelGGL(k_control_batch, dim3(max_slots), dim3(1024), 0, st, tab, n_slots);
     for (int stage = 0; stage < 3; ++stage) {
         if (proto.scheme == CTENO_SCHEME_CTENOZ)
@@ -1380,13 +1895,13 @@ hipError_t launch_state_to_user(const DeviceMesh &m, const double *state, double
     return hipGetLastError();
 }
 hipError_t launch_fv_to_user(const DeviceMesh &m, bool fp32, const void *fv, void *user, hipStream_t st) {
-    const int w = 3 * kNq * m.nv;
+    const int w = 3 * m.tab.Nq * m.nv;
     if (fp32) hipLaunchKernelGGL(k_rows_to_user<float>, dim3(grid_for(m.N)), dim3(256), 0, st, m.N, w, m.perm, (const float *)fv, (float *)user);
     else hipLaunchKernelGGL(k_rows_to_user<double>, dim3(grid_for(m.N)), dim3(256), 0, st, m.N, w, m.perm, (const double *)fv, (double *)user);
     return hipGetLastError();
 }
 hipError_t launch_fv_from_user(const DeviceMesh &m, bool fp32, const void *user, void *fv, hipStream_t st) {
-    const int w = 3 * kNq * m.nv;
+    const int w = 3 * m.tab.Nq * m.nv;
     if (fp32) hipLaunchKernelGGL(k_rows_from_user<float>, dim3(grid_for(m.N)), dim3(256), 0, st, m.N, w, m.perm, (const float *)user, (float *)fv);
     else hipLaunchKernelGGL(k_rows_from_user<double>, dim3(grid_for(m.N)), dim3(256), 0, st, m.N, w, m.perm, (const double *)user, (double *)fv);
     return hipGetLastError();
@@ -1441,17 +1956,17 @@ hipError_t launch_copy16(void *dst, const void *src, size_t n16, hipStream_t st)
 }
 
 __global__ void k_gather_entries(int n, const int32_t *idx, int E, int VW, const double *s64, const float *s32,
-                                 const int32_t *si, double *dst) {
+                                 const int32_t *si, double *dst, int ct) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (int64_t)n * E) return;
     const int a = (int)(t / E), e = (int)(t % E);
-    const size_t src = avix(idx[a], e, E, VW);
+    const size_t src = ct == 64 ? avix(idx[a], e, E, VW) : hvix(idx[a], e, E, VW, ct);
     dst[t] = s64 ? s64[src] : (s32 ? (double)s32[src] : (double)si[src]);
 }
 hipError_t launch_gather_entries(int n, const int32_t *idx, int E, int VW, const double *src64, const float *src32,
-                                 const int32_t *srci, double *dst, hipStream_t st) {
+                                 const int32_t *srci, double *dst, hipStream_t st, int ct) {
     hipLaunchKernelGGL(k_gather_entries, dim3(grid_for((int64_t)n * E)), dim3(256), 0, st, n, idx, E, VW, src64,
-                       src32, srci, dst);
+                       src32, srci, dst, ct);
     return hipGetLastError();
 }
 

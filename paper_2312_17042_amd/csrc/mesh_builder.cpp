@@ -2,8 +2,9 @@
 //
 // Builds, from a triangle list: periodic vertex welding, counter-clockwise
 // cells, faces and their owners, the central stencil of M = 2K cells
-// (sec. 2.1) and one compact degree-1 directional stencil per face inside it
-// (sec. 2.3, fig. 1), then lays everything out for the device in 64-cell
+// (sec. 2.1) and one compact directional stencil per face inside it (sec.
+// 2.3, fig. 1; degree 1 up to cubic, ceil(r/2) above, M_d = 2 K_d cells,
+// admissible with at least K_d + 1), then lays everything out for the device in 64-cell
 // tiles, optionally in Morton order.
 //
 // Stencil rule (the paper only names its construction):
@@ -67,7 +68,7 @@ inline int nthreads_for(int64_t n) {
 
 struct Builder {
     const cteno_mesh_desc &d;
-    int N, nvert, r, K, M, S;
+    int N, nvert, r, K, M, S, Kd, Md;
     int per_x, per_y;
     double Lx, Ly;
     std::vector<int32_t> tri;       // CCW-normalised raw vertex ids
@@ -76,7 +77,7 @@ struct Builder {
     std::vector<int32_t> v2c_off, v2c;
     std::vector<int32_t> fnb, fnbf, fbc;   // user order [3N]
     std::vector<int32_t> cen;              // [N][M]
-    std::vector<int32_t> dir;              // [N][3][4]
+    std::vector<int32_t> dir;              // [N][3][Md]
     std::vector<int32_t> dirn;             // [N][3]
     std::string err;
 
@@ -84,6 +85,8 @@ struct Builder {
         K = dims_K(r);
         M = dims_M(r);
         S = dims_S(r);
+        Kd = dims_Kd(r);
+        Md = dims_Md(r);
         per_x = dd.bc[0] == CTENO_PERIODIC;
         per_y = dd.bc[2] == CTENO_PERIODIC;
         Lx = dd.box[1] - dd.box[0];
@@ -225,7 +228,7 @@ struct Builder {
 
     bool stencils() {
         cen.assign((size_t)N * M, -1);
-        dir.assign((size_t)N * 3 * kDirSlots, -1);
+        dir.assign((size_t)N * 3 * Md, -1);
         dirn.assign((size_t)N * 3, 0);
         int nt = nthreads_for(N);
         std::vector<std::vector<int32_t>> stamps(nt);
@@ -302,12 +305,12 @@ struct Builder {
                     cand.push_back({dx * dx + dy * dy, S_[a]});
                 }
                 std::sort(cand.begin(), cand.end());
-                int32_t *out = dir.data() + ((size_t)i * 3 + f) * kDirSlots;
+                int32_t *out = dir.data() + ((size_t)i * 3 + f) * Md;
                 int n = 0;
                 out[n++] = nbf;
-                for (size_t a = 0; a < cand.size() && n < kDirSlots; ++a) out[n++] = cand[a].second;
-                if (n >= 3) dirn[3 * (size_t)i + f] = n;
-                else for (int a = 0; a < kDirSlots; ++a) out[a] = -1;
+                for (size_t a = 0; a < cand.size() && n < Md; ++a) out[n++] = cand[a].second;
+                if (n >= Kd + 1) dirn[3 * (size_t)i + f] = n;
+                else for (int a = 0; a < Md; ++a) out[a] = -1;
             }
         });
         if (bad >= 0) { err = "mesh too small for a stencil at cell " + std::to_string((long long)bad); return false; }
@@ -352,6 +355,7 @@ cteno_status build_host_mesh(const cteno_mesh_desc &d, const cteno_scheme &s, Ho
 
     const int N = b.N, M = b.M, S = b.S, K = b.K;
     hm.N = N; hm.r = s.degree; hm.K = K; hm.M = M; hm.S = S;
+    hm.Kd = b.Kd; hm.Md = b.Md; hm.Nq = dims_Nq(s.degree);
     hm.nv = s.physics == CTENO_EULER ? 4 : 1;
     hm.per_x = b.per_x; hm.per_y = b.per_y; hm.Lx = b.Lx; hm.Ly = b.Ly;
 
@@ -418,7 +422,8 @@ cteno_status build_host_mesh(const cteno_mesh_desc &d, const cteno_scheme &s, Ho
         hm.area[k] = b.area[u];
         // slots: sector groups first, then the remaining central cells, then pads
         const int32_t *cen = b.cen.data() + (size_t)u * M;
-        const int32_t *dr = b.dir.data() + (size_t)u * 3 * kDirSlots;
+        const int Md = b.Md;
+        const int32_t *dr = b.dir.data() + (size_t)u * 3 * Md;
         const int32_t *dn = b.dirn.data() + (size_t)u * 3;
         std::vector<int> used(M, 0);
         std::vector<int32_t> sl(S, -1);
@@ -428,9 +433,9 @@ cteno_status build_host_mesh(const cteno_mesh_desc &d, const cteno_scheme &s, Ho
             if (dn[f] > 0) {
                 adm |= (uint8_t)(1 << f);
                 for (int a = 0; a < dn[f]; ++a) {
-                    sl[f * kDirSlots + a] = dr[f * kDirSlots + a];
-                    fl[f * kDirSlots + a] = 3;
-                    for (int m = 0; m < M; ++m) if (cen[m] == dr[f * kDirSlots + a]) used[m] = 1;
+                    sl[f * Md + a] = dr[f * Md + a];
+                    fl[f * Md + a] = 3;
+                    for (int m = 0; m < M; ++m) if (cen[m] == dr[f * Md + a]) used[m] = 1;
                 }
             } else if (b.fnb[3 * (size_t)u + f] >= 0) {
                 ninad++;
@@ -502,6 +507,39 @@ namespace {
 double fct(int n) { double f = 1; for (int k = 2; k <= n; ++k) f *= k; return f; }
 // integral of xi^a eta^b over the reference triangle
 double ref_int(int a, int b) { return fct(a) * fct(b) / fct(a + b + 2); }
+// n-point Gauss-Legendre rule on [0, 1], points ascending: Newton iteration
+// on P_n from the three-term recurrence, weights 2 / ((1 - z^2) P_n'(z)^2)
+// on [-1, 1], halved
+void gauss_legendre01(int n, double *t, double *w) {
+    const double pi = 3.14159265358979323846;
+    for (int i = 0; i < n; ++i) {
+        double z = std::cos(pi * (i + 0.75) / (n + 0.5)), dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                const double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+            const double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) break;
+        }
+        {   // derivative at the converged root
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                const double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+        }
+        // z runs from near +1 downwards: t = (1 - z) / 2 ascends
+        t[i] = 0.5 * (1.0 - z);
+        w[i] = 1.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
 }  // namespace
 
 void make_ref_tables(int r, RefTables &t) {
@@ -527,12 +565,12 @@ void make_ref_tables(int r, RefTables &t) {
                 }
             t.gram[p][q] = g;
         }
-    // two-point Gauss-Legendre on [0,1]; reference images of the face points
-    double h = 0.5 / std::sqrt(3.0);
-    double tq[kNq] = {0.5 - h, 0.5 + h};
-    t.gw[0] = t.gw[1] = 0.5;
+    // N_q-point Gauss-Legendre on [0,1]; reference images of the face points
+    t.Nq = dims_Nq(r);
+    gauss_legendre01(t.Nq, t.gq, t.gw);
+    const double *tq = t.gq;
     for (int f = 0; f < 3; ++f)
-        for (int q = 0; q < kNq; ++q) {
+        for (int q = 0; q < t.Nq; ++q) {
             double xi, eta;
             if (f == 0) { xi = tq[q]; eta = 0.0; }
             else if (f == 1) { xi = 1.0 - tq[q]; eta = tq[q]; }

@@ -229,7 +229,7 @@ hipError_t h2d(T *dst, const std::vector<T> &src, hipStream_t st) {
 static cteno_status check_scheme(const cteno_scheme &s) {
     if (s.physics != CTENO_ADVECTION && s.physics != CTENO_EULER) return fail(CTENO_ERR_INVALID, "bad physics");
     if (s.scheme != CTENO_SCHEME_CTENO && s.scheme != CTENO_SCHEME_CTENOZ) return fail(CTENO_ERR_INVALID, "bad scheme");
-    if (s.degree < 2 || s.degree > 3) return fail(CTENO_ERR_INVALID, "degree must be 2 or 3");
+    if (s.degree < 2 || s.degree > kMaxR) return fail(CTENO_ERR_INVALID, "degree must be 2..6");
     if (s.precision < 1 || s.precision > 3) return fail(CTENO_ERR_INVALID, "bad precision");
     if (!(s.lambda1_prime > 1.0) || !(s.c_t > 0 && s.c_t < 1) || !(s.eps > 0))
         return fail(CTENO_ERR_INVALID, "bad lambda1_prime, c_t or eps");
@@ -252,6 +252,8 @@ static cteno_status upload_device_mesh(cteno_ctx *ctx, hipStream_t st, HostMesh 
 #define alloc_T(T, n) allocator((T *)nullptr, (n))
     dm.N = hm.N; dm.Np = pad64(hm.N);
     dm.r = hm.r; dm.K = hm.K; dm.S = hm.S; dm.nv = hm.nv;
+    dm.Kd = hm.Kd; dm.Md = hm.Md; dm.Nq = hm.Nq;
+    dm.stile = hm.r >= 4 ? kTile / hm.nv : kTile;
     dm.physics = s.physics; dm.scheme = s.scheme; dm.gamma_form = s.gamma_form; dm.precision = s.precision;
     dm.gamma = s.gamma; dm.ax = s.ax; dm.ay = s.ay; dm.lam1p = s.lambda1_prime; dm.ct = s.c_t; dm.eps = s.eps;
     dm.Lx = hm.Lx; dm.Ly = hm.Ly;
@@ -272,6 +274,23 @@ static cteno_status upload_device_mesh(cteno_ctx *ctx, hipStream_t st, HostMesh 
     if (!dm.slot || !dm.flags || (keep_fr64 && !dm.fr64) || !dm.area || !dm.perm ||
         ((s.precision & CTENO_MIXED) && (!dm.fr32 || !dm.P32)))
         return fail(CTENO_ERR_NOMEM, "device allocation failed");
+    if (hm.r >= 4) {
+        // Gram matrix [K][K] and face basis [3][Nq][K] of the higher-order kernels
+        const int K = hm.K, ntab = K * K + 3 * hm.Nq * K;
+        std::vector<double> t64(ntab);
+        std::vector<float> t32(ntab);
+        for (int p = 0; p < K; ++p)
+            for (int q = 0; q < K; ++q) t64[p * K + q] = dm.tab.gram[p][q];
+        for (int f = 0; f < 3; ++f)
+            for (int q = 0; q < hm.Nq; ++q)
+                for (int k = 0; k < K; ++k) t64[K * K + (f * hm.Nq + q) * K + k] = dm.tab.basis[f][q][k];
+        for (int e = 0; e < ntab; ++e) t32[e] = (float)t64[e];
+        dm.htab64 = alloc_T(double, ntab);
+        dm.htab32 = alloc_T(float, ntab);
+        if (!dm.htab64 || !dm.htab32) return fail(CTENO_ERR_NOMEM, "device allocation failed");
+        HIP_TRY(h2d(dm.htab64, t64, st));
+        HIP_TRY(h2d(dm.htab32, t32, st));
+    }
     // FP64 pseudo-inverses are always computed; kept only when FP64 is resident
     DevBuf p64(ctx, Np * dm.E64 * sizeof(double));
     DevBuf verts(ctx, Np * 6 * sizeof(double)), sflag(ctx, Np * S), sshift(ctx, Np * 2 * S), rfail(ctx, sizeof(int));
@@ -310,7 +329,7 @@ static cteno_status upload_device_mesh(cteno_ctx *ctx, hipStream_t st, HostMesh 
         for (int f = 0; f < 3; ++f)
             if (((hm.flags[k] >> f) & 1) && !((flags[k] >> f) & 1)) {
                 hm.dirn_user[3 * (size_t)u + f] = 0;
-                for (int a = 0; a < kDirSlots; ++a) hm.dir_user[((size_t)u * 3 + f) * kDirSlots + a] = -1;
+                for (int a = 0; a < hm.Md; ++a) hm.dir_user[((size_t)u * 3 + f) * hm.Md + a] = -1;
                 hm.n_inadmissible++;
             }
         hm.flags[k] = flags[k];
@@ -359,7 +378,9 @@ extern "C" cteno_status cteno_mesh_info_get(const cteno_mesh *m, cteno_mesh_info
     info->M = m->host.M;
     info->slots = m->host.S;
     info->nv = m->host.nv;
-    info->nq = kNq;
+    info->nq = m->host.Nq;
+    info->Kd = m->host.Kd;
+    info->Md = m->host.Md;
     info->n_inadmissible = m->host.n_inadmissible;
     info->device_bytes = m->bytes;
     return CTENO_OK;
@@ -390,7 +411,7 @@ extern "C" cteno_status cteno_mesh_pinv(cteno_ctx *ctx, const cteno_mesh *m, int
         idx[a] = hm.iperm[cells[a]];
     }
     // slot tables are not kept on the host; rebuild the column maps from the stencils
-    const int K = hm.K, S = hm.S, M = hm.M;
+    const int K = hm.K, S = hm.S, M = hm.M, Kd = hm.Kd, Md = hm.Md;
     const int E = f32 ? dm.E32 : dm.E64, VW = f32 ? 4 : 2;
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t st = ctx->stream();
@@ -399,7 +420,7 @@ extern "C" cteno_status cteno_mesh_pinv(cteno_ctx *ctx, const cteno_mesh *m, int
     if (!didx.p || !op.p || !dslot.p) return fail(CTENO_ERR_NOMEM, "device allocation failed");
     HIP_TRY(hipMemcpyAsync(didx.p, idx.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, st));
     HIP_TRY(launch_gather_entries(n, didx.as<int32_t>(), E, VW, f32 ? nullptr : dm.P64, f32 ? dm.P32 : nullptr,
-                                  nullptr, op.as<double>(), st));
+                                  nullptr, op.as<double>(), st, dm.stile));
     HIP_TRY(launch_gather_entries(n, didx.as<int32_t>(), dm.SP, 4, nullptr, nullptr, dm.slot, dslot.as<double>(), st));
     std::vector<double> pe((size_t)n * E), slotd((size_t)n * dm.SP);
     HIP_TRY(hipMemcpyAsync(pe.data(), op.p, pe.size() * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -408,10 +429,10 @@ extern "C" cteno_status cteno_mesh_pinv(cteno_ctx *ctx, const cteno_mesh *m, int
     for (int a = 0; a < n; ++a) {
         const int u = cells[a];
         const int32_t *cen = hm.cen_user.data() + (size_t)u * M;
-        const int32_t *dr = hm.dir_user.data() + (size_t)u * 3 * kDirSlots;
+        const int32_t *dr = hm.dir_user.data() + (size_t)u * 3 * Md;
         if (central) std::fill(central + (size_t)a * K * M, central + (size_t)(a + 1) * K * M, 0.0);
         if (directional)
-            std::fill(directional + (size_t)a * 3 * 2 * kDirSlots, directional + (size_t)(a + 1) * 3 * 2 * kDirSlots, 0.0);
+            std::fill(directional + (size_t)a * 3 * Kd * Md, directional + (size_t)(a + 1) * 3 * Kd * Md, 0.0);
         for (int j = 0; j < S; ++j) {
             const int src_k = (int)slotd[(size_t)a * dm.SP + j];
             if (src_k == idx[a]) continue;   // padding slot (the cell itself)
@@ -419,16 +440,17 @@ extern "C" cteno_status cteno_mesh_pinv(cteno_ctx *ctx, const cteno_mesh *m, int
             int cpos = -1;
             for (int q = 0; q < M; ++q) if (cen[q] == src_u) cpos = q;
             if (cpos < 0) return fail(CTENO_ERR_DEVICE, "slot not in stencil");
-            const int off = pinv_offset(j, K);
+            // slot j: K central entries, then (slots of the directional groups) K_d directional ones
+            const int off = hm.r >= 4 ? j * ho_slot_entries(hm.r) : pinv_offset(j, K);
             if (central)
                 for (int k = 0; k < K; ++k) central[((size_t)a * K + k) * M + cpos] = pe[(size_t)a * E + off + k];
-            if (j < 12 && directional) {
-                const int s = j / 4;
+            if (j < 3 * Md && directional) {
+                const int s = j / Md;
                 int dpos = -1;
-                for (int q = 0; q < kDirSlots; ++q) if (dr[s * kDirSlots + q] == src_u) dpos = q;
+                for (int q = 0; q < Md; ++q) if (dr[s * Md + q] == src_u) dpos = q;
                 if (dpos >= 0)
-                    for (int c = 0; c < 2; ++c)
-                        directional[(((size_t)a * 3 + s) * 2 + c) * kDirSlots + dpos] = pe[(size_t)a * E + off + K + c];
+                    for (int c = 0; c < Kd; ++c)
+                        directional[(((size_t)a * 3 + s) * Kd + c) * Md + dpos] = pe[(size_t)a * E + off + K + c];
             }
         }
     }
@@ -438,7 +460,7 @@ extern "C" cteno_status cteno_mesh_pinv(cteno_ctx *ctx, const cteno_mesh *m, int
 extern "C" cteno_status cteno_stencils_host(const cteno_mesh_desc *desc, const cteno_scheme *scheme,
                                             int32_t *central, int32_t *directional, int32_t *dir_count) {
     if (!desc || !scheme) return fail(CTENO_ERR_INVALID, "NULL argument");
-    if (scheme->degree < 2 || scheme->degree > 3) return fail(CTENO_ERR_INVALID, "degree must be 2 or 3");
+    if (scheme->degree < 2 || scheme->degree > kMaxR) return fail(CTENO_ERR_INVALID, "degree must be 2..6");
     HostMesh hm;
     std::string err;
     cteno_scheme s = *scheme;
@@ -479,7 +501,7 @@ struct cteno_sol {
         DevBuf &b = FV[f32 ? 1 : 0];
         if (!b.p) {
             const DeviceMesh &dm = mesh->dm;
-            b = DevBuf(ctx, (size_t)dm.Np * 3 * kNq * dm.nv * (f32 ? sizeof(float) : sizeof(double)));
+            b = DevBuf(ctx, (size_t)dm.Np * 3 * dm.Nq * dm.nv * (f32 ? sizeof(float) : sizeof(double)));
         }
         return b.p;
     }
@@ -603,7 +625,7 @@ extern "C" cteno_status cteno_flux(cteno_ctx *ctx, const cteno_mesh *m, int32_t 
     const DeviceMesh &dm = m->dm;
     hipStream_t st = ctx->stream();
     const size_t es = f32 ? sizeof(float) : sizeof(double);
-    DevBuf fv(ctx, (size_t)dm.Np * 3 * kNq * dm.nv * es), fo(ctx, (size_t)dm.Np * 3 * dm.nv * es);
+    DevBuf fv(ctx, (size_t)dm.Np * 3 * dm.Nq * dm.nv * es), fo(ctx, (size_t)dm.Np * 3 * dm.nv * es);
     if (!fv.p || !fo.p) return fail(CTENO_ERR_NOMEM, "device allocation failed");
     HIP_TRY(launch_fv_from_user(dm, f32, face_vals, fv.p, st));
     FluxLaunch fl;
@@ -1105,6 +1127,7 @@ extern "C" cteno_status cteno_server_create(cteno_ctx *ctx, const cteno_scheme *
     if (!ctx || !scheme || !out) return fail(CTENO_ERR_INVALID, "NULL argument");
     if (cteno_status rc = check_scheme(*scheme)) return rc;
     if (scheme->physics != CTENO_EULER) return fail(CTENO_ERR_INVALID, "serving runs the Euler equations");
+    if (scheme->degree > 3) return fail(CTENO_ERR_INVALID, "serving runs degree 2 or 3");
     if (max_slots < 1 || max_slots > 1024) return fail(CTENO_ERR_INVALID, "max_slots must be 1..1024");
     if (hbm_budget_bytes < (1u << 20)) return fail(CTENO_ERR_INVALID, "budget too small");
     HIP_TRY(hipSetDevice(ctx->device));

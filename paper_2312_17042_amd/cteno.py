@@ -45,7 +45,7 @@ class Scheme(C.Structure):
 class MeshInfo(C.Structure):
     _fields_ = [("n_cells", C.c_int64), ("n_faces", C.c_int64), ("n_boundary_faces", C.c_int64),
                 ("K", C.c_int32), ("M", C.c_int32), ("slots", C.c_int32), ("nv", C.c_int32), ("nq", C.c_int32),
-                ("n_inadmissible", C.c_int32), ("device_bytes", C.c_int64)]
+                ("n_inadmissible", C.c_int32), ("Kd", C.c_int32), ("Md", C.c_int32), ("device_bytes", C.c_int64)]
 
 
 class ServerStats(C.Structure):
@@ -199,6 +199,8 @@ class Mesh:
         self.K = int(info.K)
         self.M = int(info.M)
         self.nq = int(info.nq)
+        self.Kd = int(info.Kd)
+        self.Md = int(info.Md)
 
     @classmethod
     def from_workload(cls, ctx, mesh, **scheme_kw):
@@ -217,7 +219,7 @@ class Mesh:
 
     def stencils(self):
         cen = np.empty((self.N, self.M), np.int32)
-        dr = np.empty((self.N, 3, 4), np.int32)
+        dr = np.empty((self.N, 3, self.Md), np.int32)
         dn = np.empty((self.N, 3), np.int32)
         _check(lib().cteno_mesh_stencils(self.h, _np_ptr(cen), _np_ptr(dr), _np_ptr(dn)))
         return cen, dr, dn
@@ -226,7 +228,7 @@ class Mesh:
         cells = np.ascontiguousarray(cells, np.int32)
         n = cells.shape[0]
         pc = np.empty((n, self.K, self.M))
-        pd = np.empty((n, 3, 2, 4))
+        pd = np.empty((n, 3, self.Kd, self.Md))
         _check(lib().cteno_mesh_pinv(self.ctx.h, self.h, which, n, _np_ptr(cells), _np_ptr(pc), _np_ptr(pd)))
         return pc, pd
 
@@ -237,9 +239,12 @@ def stencils_host(xy, tri, box, bc, scheme: Scheme):
     tri = np.ascontiguousarray(tri, np.int32)
     d = MeshDesc(xy.shape[0], _np_ptr(xy), tri.shape[0], _np_ptr(tri), (C.c_double * 4)(*box), (C.c_int32 * 4)(*bc))
     N = tri.shape[0]
-    K = (scheme.degree + 1) * (scheme.degree + 2) // 2 - 1
+    r = scheme.degree
+    K = (r + 1) * (r + 2) // 2 - 1
+    rd = 1 if r <= 3 else (r + 1) // 2
+    Md = 2 * ((rd + 1) * (rd + 2) // 2 - 1)
     cen = np.empty((N, 2 * K), np.int32)
-    dr = np.empty((N, 3, 4), np.int32)
+    dr = np.empty((N, 3, Md), np.int32)
     dn = np.empty((N, 3), np.int32)
     _check(lib().cteno_stencils_host(C.byref(d), C.byref(scheme), _np_ptr(cen), _np_ptr(dr), _np_ptr(dn)))
     return cen, dr, dn

@@ -47,6 +47,18 @@ CASES = {
                                     gamma_form=O.GAMMA_LAMBDA)),
     "density_r2_ctenoz": (lambda: W.density_wave_case(12, seed=11),
                           dict(physics=O.EULER, scheme=O.CTENOZ, degree=2, lambda1_prime=1e4)),
+    # orders 5 to 7: one lane per (cell, variable), N_q = 3 or 4
+    "density_r4_ctenoz": (lambda: W.density_wave_case(12, seed=11),
+                          dict(physics=O.EULER, scheme=O.CTENOZ, degree=4, lambda1_prime=1e4)),
+    "sod_r4_cteno": (lambda: W.sod_case(48, 12, seed=3),
+                     dict(physics=O.EULER, scheme=O.CTENO, degree=4, lambda1_prime=1e15)),
+    "vortex_r5_ctenoz": (lambda: W.vortex_case(20, seed=6),
+                         dict(physics=O.EULER, scheme=O.CTENOZ, degree=5, lambda1_prime=1e4)),
+    "advection_r6_cteno_lambda": (lambda: W.advection_case(20, seed=1),
+                                  dict(physics=O.ADVECTION, scheme=O.CTENO, degree=6, lambda1_prime=1e15,
+                                       gamma_form=O.GAMMA_LAMBDA)),
+    "vortex_r6_ctenoz": (lambda: W.vortex_case(20, seed=7),
+                         dict(physics=O.EULER, scheme=O.CTENOZ, degree=6, lambda1_prime=1e4)),
 }
 
 
@@ -126,8 +138,15 @@ def test_stencils_and_pinv(ctx, name):
     order = np.argsort(oc[cells], axis=1)
     opc_sorted = np.take_along_axis(opc, order[:, None, :], axis=2)
     for a in range(len(cells)):
-        assert relerr(gpc[a], opc_sorted[a]) < 1e-12, a
-        assert relerr(gpd[a], opd[a]) < 1e-12 if np.abs(opd[a]).max() > 0 else np.abs(gpd[a]).max() == 0
+        # Householder QR is backward stable: the forward error of the
+        # pseudo-inverse grows with the condition number of the system, which
+        # reaches 1e6 for the degree-6 monomial basis
+        tol = max(1e-12, 50 * EPS64 * np.linalg.cond(o.ls_matrix(cells[a])[0]))
+        assert relerr(gpc[a], opc_sorted[a]) < tol, (a, tol)
+        if np.abs(opd[a]).max() > 0:
+            assert relerr(gpd[a], opd[a]) < tol, (a, tol)
+        else:
+            assert np.abs(gpd[a]).max() == 0
     fpc, fpd = m.pinv(cells, T.MIXED)
     assert relerr(fpc, gpc) < 1e-6 and relerr(fpd, gpd) < 1e-6
 
@@ -185,7 +204,8 @@ def test_rk_stages_fp64(ctx, name):
     assert relerr_var(ug, uo, axis_v=0) < 1e-12
 
 
-@pytest.mark.parametrize("name", ["advection_r2_cteno", "vortex_r3_ctenoz", "sod_r3_cteno"])
+@pytest.mark.parametrize("name", ["advection_r2_cteno", "vortex_r3_ctenoz", "sod_r3_cteno", "sod_r4_cteno",
+                                  "vortex_r6_ctenoz"])
 def test_solve_fp64_matches_oracle(ctx, name):
     mesh, u0, o, m = setup_case(ctx, name)
     s = T.Solution(m, u0)
