@@ -225,7 +225,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); multi-GPU sharding is a design "
-              f"note, not part of this build", file=sys.stderr)
+              f"note, not part of this library", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -17,7 +17,7 @@ SRC_PATH = os.path.join(HERE, "cteno_oracle.c")
 
 PERIODIC, WALL, TRANSMISSIVE = 0, 1, 2
 ADVECTION, EULER = 0, 1
-CTENO, CTENOZ = 0, 1
+CTENO, CTENOZ, CWENO, TENO = 0, 1, 2, 3
 GAMMA_PAPER, GAMMA_LAMBDA = 0, 1
 
 
@@ -60,6 +60,7 @@ def lib():
         L.or_smoothness.restype = C.c_double
         L.or_smoothness.argtypes = [P, P, C.c_int, C.c_int]
         L.or_select.argtypes = [P, P, P]
+        L.or_cweno_weights.argtypes = [P, P, P, P]
         L.or_hllc.argtypes = [C.c_double, P, P, C.c_double, C.c_double, P]
         L.or_euler_flux.argtypes = [C.c_double, P, C.c_double, C.c_double, P]
         L.or_reconstruct.argtypes = [P, P, P, P, P, P]
@@ -162,6 +163,13 @@ class Oracle:
         si = np.ascontiguousarray(si, np.float64)
         adm = np.ascontiguousarray(adm, np.int32)
         return lib().or_select(self.h, _p(si), _p(adm))
+
+    def cweno_weights(self, si, adm=(1, 1, 1, 1)):
+        si = np.ascontiguousarray(si, np.float64)
+        adm = np.ascontiguousarray(adm, np.int32)
+        w = np.empty(4)
+        lib().or_cweno_weights(self.h, _p(si), _p(adm), _p(w))
+        return w
 
     def reconstruct(self, U, forced=None, want_coef=False):
         U = np.ascontiguousarray(U, np.float64).reshape(self.nv, self.N)

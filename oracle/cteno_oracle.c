@@ -29,6 +29,11 @@
  *   - CTENO weights (Algorithm 1) and CTENOZ weights (Algorithm 2) with the
  *     cut-off delta_s = [chi_s >= C_T] (eq. e23) and the two-branch final
  *     polynomial (sec. 2.4, 2.5);
+ *   - the comparison schemes of sec. 2.2-2.3: CWENO (nonlinear weights
+ *     lambda_s / (eps + SI_s)^b with b = 4 and the linear weights of eq.
+ *     e18, final polynomial sum_s omega_s p_s with p_1 from eq. e17) and
+ *     TENO (the cut-off of eq. e22-e23 with gamma_s = 1/(SI_s + eps)^6 on
+ *     the central-stencil polynomial itself, then the same two branches);
  *   - HLLC flux with Roe-averaged wave-speed estimates (sec. 2.6);
  *   - third-order explicit Runge-Kutta in time (sec. 2, Shu-Osher SSP form).
  *
@@ -47,7 +52,9 @@
  *     (third-order directional stencils for the fifth-order scheme, Fig. 1);
  *   reference map anchored at the first vertex of the counter-clockwise
  *     normalised triangle; SI multi-indices counted once each;
- *   final polynomial p_1 when delta_1 = 1 (Algorithms 1 and 2);
+ *   final polynomial p_1 when delta_1 = 1 (Algorithms 1 and 2); TENO's p_1
+ *     is the central-stencil least-squares polynomial (p_opt), CTENO's the
+ *     decomposed one of eq. e17;
  *   eps = 1e-12 by default; N_q = ceil((r+1)/2) Gauss-Legendre points.
  */
 #include <math.h>
@@ -67,7 +74,7 @@
 
 enum { OR_PERIODIC = 0, OR_WALL = 1, OR_TRANSMISSIVE = 2 };
 enum { OR_ADVECTION = 0, OR_EULER = 1 };
-enum { OR_CTENO = 0, OR_CTENOZ = 1 };
+enum { OR_CTENO = 0, OR_CTENOZ = 1, OR_CWENO = 2, OR_TENO = 3 };
 enum { OR_GAMMA_PAPER = 0, OR_GAMMA_LAMBDA = 1 };
 
 static char or_err[512];
@@ -594,12 +601,12 @@ static int teno_select(const or_ctx *c, const double *si, const int *adm, double
     double g[4], sum = 0.0;
     int st = 1;
     for (int s = 1; s < 4; ++s) st += adm[s];
-    if (c->scheme == OR_CTENO) {
+    if (c->scheme == OR_CTENO || c->scheme == OR_TENO) {
         for (int s = 0; s < 4; ++s) {
             if (!adm[s]) continue;
             double lam = (s == 0) ? lam1 : lams;
             g[s] = 1.0 / pow6(si[s] + c->eps);
-            if (c->gamma_form == OR_GAMMA_LAMBDA) g[s] = lam / pow6(si[s] + c->eps);
+            if (c->scheme == OR_CTENO && c->gamma_form == OR_GAMMA_LAMBDA) g[s] = lam / pow6(si[s] + c->eps);
         }
     } else {
         double tsum = 0.0;
@@ -615,6 +622,19 @@ static int teno_select(const or_ctx *c, const double *si, const int *adm, double
         if (!(chi < c->ct)) bits |= 1 << s;
     }
     return bits;
+}
+
+/* CWENO nonlinear weights: omega_s proportional to lambda_s / (eps + SI_s)^4
+   over the admissible stencils, normalised to sum 1 */
+static void cweno_weights(const or_ctx *c, const double *si, const int *adm, double lam1, double lams, double *w) {
+    double g[4] = {0, 0, 0, 0}, sum = 0.0;
+    for (int s = 0; s < 4; ++s) {
+        if (!adm[s]) continue;
+        double e = c->eps + si[s], e2 = e * e;
+        g[s] = ((s == 0) ? lam1 : lams) / (e2 * e2);
+        sum += g[s];
+    }
+    for (int s = 0; s < 4; ++s) w[s] = adm[s] ? g[s] / sum : 0.0;
 }
 
 /* evaluate p = U0 + sum a_k (psi_k - mean psi_k) at (xi, eta) */
@@ -652,37 +672,59 @@ static int reconstruct_cell(or_ctx *c, int i, const double *U, const uint8_t *fo
             hh_solve(pc->da[f], n, Kd, pc->dv0[f], pc->db[f], pc->dr[f], b, ad[f]);
         }
         /* p_1 = (p_opt - sum_s lambda_s p_s) / lambda_1 (eq. e17); with no
-           admissible directional stencil the scheme is the linear p_opt */
+           admissible directional stencil the scheme is the linear p_opt.
+           TENO keeps the central-stencil polynomial itself. */
         double a1[OR_MAXK];
         for (int k = 0; k < K; ++k) {
-            if (st == 1) { a1[k] = aopt[k]; continue; }
+            if (st == 1 || c->scheme == OR_TENO) { a1[k] = aopt[k]; continue; }
             double s = aopt[k];
             if (k < Kd)
                 for (int f = 0; f < 3; ++f) if (adm[f + 1]) s -= lams * ad[f][k];
             a1[k] = s / lam1;
         }
         int bits;
-        if (st == 1) {
-            bits = 1;
-        } else {
-            double si[4] = {0, 0, 0, 0};
-            si[0] = smoothness(c, a1, K, c->r);
-            for (int f = 0; f < 3; ++f) if (adm[f + 1]) si[f + 1] = smoothness(c, ad[f], Kd, c->rd);
-            bits = teno_select(c, si, adm, lam1, lams);
-        }
-        if (forced) bits = forced[v] & (1 | (adm[1] << 1) | (adm[2] << 2) | (adm[3] << 3));
-        if (dbits) dbits[v] = (uint8_t)bits;
         double fin[OR_MAXK];
-        if (bits & 1) {
-            for (int k = 0; k < K; ++k) fin[k] = a1[k];
+        if (c->scheme == OR_CWENO) {
+            /* every admissible stencil contributes; the selection byte
+               reports them, and forced selections do not apply */
+            bits = 1 | (adm[1] << 1) | (adm[2] << 2) | (adm[3] << 3);
+            if (st == 1) {
+                for (int k = 0; k < K; ++k) fin[k] = a1[k];
+            } else {
+                double si[4] = {0, 0, 0, 0}, w[4];
+                si[0] = smoothness(c, a1, K, c->r);
+                for (int f = 0; f < 3; ++f) if (adm[f + 1]) si[f + 1] = smoothness(c, ad[f], Kd, c->rd);
+                cweno_weights(c, si, adm, lam1, lams, w);
+                for (int k = 0; k < K; ++k) {
+                    double x = w[0] * a1[k];
+                    if (k < Kd)
+                        for (int f = 0; f < 3; ++f) if (adm[f + 1]) x += w[f + 1] * ad[f][k];
+                    fin[k] = x;
+                }
+            }
         } else {
-            int nd = 0;
-            for (int k = 0; k < K; ++k) fin[k] = 0.0;
-            for (int f = 0; f < 3; ++f)
-                if (bits & (2 << f)) { ++nd; for (int k = 0; k < Kd; ++k) fin[k] += ad[f][k]; }
-            if (nd == 0) return 5;   /* impossible by max chi >= 1/s_t > C_T */
-            for (int k = 0; k < Kd; ++k) fin[k] /= nd;
+            /* TENO-type selection and the two-branch final polynomial */
+            if (st == 1) {
+                bits = 1;
+            } else {
+                double si[4] = {0, 0, 0, 0};
+                si[0] = smoothness(c, a1, K, c->r);
+                for (int f = 0; f < 3; ++f) if (adm[f + 1]) si[f + 1] = smoothness(c, ad[f], Kd, c->rd);
+                bits = teno_select(c, si, adm, lam1, lams);
+            }
+            if (forced) bits = forced[v] & (1 | (adm[1] << 1) | (adm[2] << 2) | (adm[3] << 3));
+            if (bits & 1) {
+                for (int k = 0; k < K; ++k) fin[k] = a1[k];
+            } else {
+                int nd = 0;
+                for (int k = 0; k < K; ++k) fin[k] = 0.0;
+                for (int f = 0; f < 3; ++f)
+                    if (bits & (2 << f)) { ++nd; for (int k = 0; k < Kd; ++k) fin[k] += ad[f][k]; }
+                if (nd == 0) return 5;   /* impossible by max chi >= 1/s_t > C_T */
+                for (int k = 0; k < Kd; ++k) fin[k] /= nd;
+            }
         }
+        if (dbits) dbits[v] = (uint8_t)bits;
         if (coef_out) for (int k = 0; k < K; ++k) coef_out[(size_t)v * K + k] = fin[k];
         const int *t = c->tri + 3 * i;
         for (int f = 0; f < 3; ++f) {
@@ -1014,6 +1056,16 @@ int or_select(or_ctx *c, const double *si, const int *adm) {
     double lam1 = 1.0 - 1.0 / c->lam1p;
     double lams = st > 1 ? (1.0 - lam1) / (st - 1) : 0.0;
     return teno_select(c, si, adm, lam1, lams);
+}
+
+/* CWENO nonlinear weights w[4] for smoothness indicators si[4] and the
+   admissibility mask adm[4] (central first) */
+int or_cweno_weights(or_ctx *c, const double *si, const int *adm, double *w) {
+    int st = 1 + adm[1] + adm[2] + adm[3];
+    double lam1 = st > 1 ? 1.0 - 1.0 / c->lam1p : 1.0;
+    double lams = st > 1 ? (1.0 - lam1) / (st - 1) : 0.0;
+    cweno_weights(c, si, adm, lam1, lams, w);
+    return 0;
 }
 
 int or_hllc(double g, const double *UL, const double *UR, double nx, double ny, double *F) {

@@ -362,6 +362,82 @@ def test_selection_brute_force():
         assert _o(sch, ct=0.5).select([0.2, 0.2, 0.0, 0.0], adm=(1, 1, 0, 0)) == 0b11
 
 
+def test_cweno_weights():
+    """CWENO (sec. 2.2): with equal smoothness indicators the nonlinear
+    weights equal the linear weights of eq. e18, so the reconstruction is
+    p_opt (eq. e16); weights always sum to 1; a rough central stencil gets a
+    vanishing weight."""
+    for lam in (1e4, 1e15):
+        o = _o(O.CWENO, lam=lam)
+        for adm in ((1, 1, 1, 1), (1, 0, 1, 1), (1, 1, 0, 0)):
+            st = sum(adm)
+            lam1 = 1.0 - 1.0 / lam
+            lin = np.array([lam1] + [(1.0 - lam1) / (st - 1) * a for a in adm[1:]])
+            w = o.cweno_weights([0.37, 0.37, 0.37, 0.37], adm)
+            assert np.allclose(w, lin, rtol=1e-12, atol=0)
+            w = o.cweno_weights([2.0, 1e-3, 7.0, 0.2], adm)
+            assert abs(w.sum() - 1.0) < 1e-15 and (w[np.array(adm) == 0] == 0).all()
+    o = _o(O.CWENO, lam=1e4)
+    w = o.cweno_weights([1.0, 1e-4, 1e-4, 1e-4])
+    assert w[0] < 1e-11 and abs(w[1] - 1.0 / 3.0) < 1e-12
+
+
+@pytest.mark.parametrize("degree", [2, 3, 4])
+def test_cweno_reproduces_directional_degree(degree):
+    """All CWENO candidates reproduce a polynomial of the directional degree
+    and the weights sum to 1, so the combination is exact."""
+    rd = 1 if degree <= 3 else (degree + 1) // 2
+    mesh = W.split_jitter_mesh(10, 9, (0.0, 1.0, 0.0, 0.9), seed=5, bc=(2, 2, 2, 2))
+    rng = np.random.default_rng(20 + degree)
+    cf = rng.normal(size=(rd + 1, rd + 1))
+
+    def f(X, Y):
+        v = np.zeros_like(X)
+        for a in range(rd + 1):
+            for b in range(rd + 1 - a):
+                v += cf[a, b] * X ** a * Y ** b
+        return v[None]
+    u = W.cell_average(mesh, f, n=8)
+    o = O.Oracle.from_mesh(mesh, physics=O.ADVECTION, scheme=O.CWENO, degree=degree, lambda1_prime=1e4)
+    fv, dl = o.reconstruct(u)
+    g, _ = np.polynomial.legendre.leggauss(o.Nq)
+    t = 0.5 * (g + 1)
+    err = 0.0
+    for i in range(o.N):
+        p = _ccw(mesh.xy[mesh.tri[i]])
+        for fa in range(3):
+            a, b = p[fa], p[(fa + 1) % 3]
+            for q in range(o.Nq):
+                x = a + t[q] * (b - a)
+                err = max(err, abs(f(np.array([x[0]]), np.array([x[1]]))[0, 0] - fv[i, fa, q, 0]))
+    assert err < 1e-12 * max(1.0, np.abs(u).max())
+
+
+def test_teno_and_cweno_limits():
+    """As lambda1' grows, lambda_1 -> 1 and p_1 of eq. e17 -> p_opt: CTENO
+    becomes TENO (same selections, same values), and on smooth data the CWENO
+    weights go to (1, 0, 0, 0) so CWENO returns p_opt (here: CTENO with the
+    central stencil forced) -- except at cells where a directional fit is
+    nearly flat (SI_s ~ 0 at an extremum), where the central weight collapses:
+    the weakness of CWENO in smooth regions that sec. 2.3 describes."""
+    m, u0 = W.density_wave_case(16, seed=11)
+    res = {}
+    for sch in (O.TENO, O.CTENO, O.CWENO):
+        o = O.Oracle.from_mesh(m, physics=O.EULER, scheme=sch, degree=3, lambda1_prime=1e15)
+        res[sch] = o.reconstruct(u0)
+        if sch == O.CTENO:
+            popt = o.reconstruct(u0, forced=np.ones((o.N, 4), np.uint8))[0]
+    assert np.array_equal(res[O.TENO][1], res[O.CTENO][1])
+    scale = np.abs(res[O.TENO][0]).max()
+    assert np.abs(res[O.TENO][0] - res[O.CTENO][0]).max() < 1e-12 * scale
+    dev = np.abs(popt - res[O.CWENO][0]).max(axis=(1, 2, 3))
+    assert np.median(dev) < 1e-12 * scale
+    assert dev.max() > 1e-6 * scale
+    # at lambda1' = 1e4 the schemes differ: the directional polynomials weigh in
+    o = O.Oracle.from_mesh(m, physics=O.EULER, scheme=O.CWENO, degree=3, lambda1_prime=1e4)
+    assert np.abs(o.reconstruct(u0)[0] - popt).max() > 1e-8 * scale
+
+
 def test_selection_never_empty():
     """delta_1 = 0 implies some directional delta = 1, since max chi >= 1/s_t > C_T."""
     rng = np.random.default_rng(1)
