@@ -40,7 +40,7 @@ FLUX_BYTES = {"mixed": 24 * 4 + 12 + 9 * 4 + 8 + 3 * 32,
 # HBM bytes per cell and launch of the mixed reconstruction kernel measured
 # with the FETCH_SIZE / WRITE_SIZE counters (scaled by the copy-kernel
 # calibration), valid only for the kernel source they were taken on
-MEASURED_TRAFFIC = {"kernels_sha256_prefix": "34a6b442f9baea1b", "recon_mixed_bytes_per_cell": 966.7}
+MEASURED_TRAFFIC = {"kernels_sha256_prefix": "a151f5851dbad6fe", "recon_mixed_bytes_per_cell": 966.7}
 
 
 def kernels_hash():
@@ -127,6 +127,37 @@ def orders_bench(T, W, ctx, n=1000, steps=5, warmup=1):
         m.close()
         torch.cuda.synchronize()
     return out
+
+
+# normalised computational times the paper prints (with respect to CWENO of
+# 5th order) for the single-material triple point problem (Table tab2)
+PAPER_SCHEME_TIMES = {"5th": {"CWENO": 1.000, "TENO": 1.024, "CTENO": 1.043, "CTENOZ": 1.081},
+                      "7th": {"CWENO": 1.538, "TENO": 1.557, "CTENO": 1.571, "CTENOZ": 1.643}}
+
+
+def schemes_bench(T, W, ctx, n=1000, steps=5, warmup=1):
+    """CWENO, TENO, CTENO and CTENOZ at orders 5 and 7 on the same mesh:
+    time per step normalised to CWENO5, beside the paper's ratios."""
+    mesh, u0 = W.vortex_case(n, seed=5, quad=3)
+    N = mesh.n_cells
+    names = [("CWENO", T.CWENO, 1e4), ("TENO", T.TENO, 1e4), ("CTENO", T.CTENO, 1e4), ("CTENOZ", T.CTENOZ, 1e4)]
+    ms = {}
+    for order, r in (("5th", 4), ("7th", 6)):
+        ms[order] = {}
+        for name, sch, lam in names:
+            m = T.Mesh.from_workload(ctx, mesh, physics=T.EULER, scheme=sch, degree=r, lambda1_prime=lam,
+                                     precision=T.MIXED)
+            sol = T.Solution(m, u0)
+            res = run_precision(T, ctx, m, sol, u0, T.MIXED, steps, warmup)
+            ms[order][name] = 1e3 * res["graph_elapsed"] / steps
+            sol.close()
+            m.close()
+    ref = ms["5th"]["CWENO"]
+    norm = {o: {k: v / ref for k, v in d.items()} for o, d in ms.items()}
+    log("schemes (normalised to CWENO5): " + "; ".join(
+        f"{o}: " + ", ".join(f"{k} {v:.3f}" for k, v in d.items()) for o, d in norm.items()))
+    return {"workload": f"isentropic vortex, {n}x{n} ({N} cells), mixed precision, lambda1'=1e4, graph replay",
+            "ms_per_step": ms, "normalised_time": norm, "paper_table_tab2": PAPER_SCHEME_TIMES}
 
 
 def cpu_baseline(W, target_s=12.0, max_steps=40):
@@ -222,6 +253,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=256)
     ap.add_argument("--no-orders", action="store_true", help="skip the orders 5-7 measurement")
+    ap.add_argument("--no-schemes", action="store_true", help="skip the CWENO/TENO/CTENO/CTENOZ cost comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); multi-GPU sharding is a design "
@@ -332,6 +364,8 @@ def main():
     del src, dst
     if not args.no_orders:
         out["orders_5_to_7"] = orders_bench(T, W, ctx)
+    if not args.no_schemes:
+        out["schemes"] = schemes_bench(T, W, ctx)
     if not args.no_serving:
         out["serving"] = serving_bench(T, W, ctx, n_requests=args.serving_requests)
     if not args.no_cpu_baseline:

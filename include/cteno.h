@@ -50,7 +50,9 @@ enum { CTENO_PERIODIC = 0, CTENO_WALL = 1, CTENO_TRANSMISSIVE = 2 };
 /* physics */
 enum { CTENO_ADVECTION = 0, CTENO_EULER = 1 };
 /* weighting scheme: CTENO = Algorithm 1 (sec. 2.4), CTENOZ = Algorithm 2 (sec. 2.5) */
-enum { CTENO_SCHEME_CTENO = 0, CTENO_SCHEME_CTENOZ = 1 };
+/* CTENO: Algorithm 1; CTENOZ: Algorithm 2; CWENO and TENO: the paper's
+   comparison schemes (sec. 2.2-2.3) in the same pipeline */
+enum { CTENO_SCHEME_CTENO = 0, CTENO_SCHEME_CTENOZ = 1, CTENO_SCHEME_CWENO = 2, CTENO_SCHEME_TENO = 3 };
 /* CTENO scale-separation form: PAPER = gamma_s = 1/(SI_s+eps)^6 exactly as in
    Algorithm 1; LAMBDA = gamma_s = lambda_s/(SI_s+eps)^6 (linear weights of
    eq. e18 included) */

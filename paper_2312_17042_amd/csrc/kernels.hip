@@ -512,6 +512,42 @@ __device__ __forceinline__ int teno_bits(const real si[4], int adm, int st, real
     return bits;
 }
 
+// CWENO nonlinear weights (sec. 2.2: the WENO weights with exponent 4 and
+// the linear weights of eq. e18) of the admissible stencils.  FP64 follows
+// the formula; FP32 evaluates w_s = 1 / sum_t (lambda_t / lambda_s)
+// (e_s / e_t)^4, e = SI + eps, which cannot overflow into a NaN.
+template <typename real>
+__device__ __forceinline__ void cweno_weights(const real si[4], int adm, real lams, real lam1, real lratio, real eps,
+                                              real w[4]) {
+    if constexpr (std::is_same<real, double>::value) {
+        double g[4], sum = 0.0;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const double e = si[s] + eps, e2 = e * e;
+            g[s] = ((adm >> s) & 1) ? (s == 0 ? lam1 : lams) / (e2 * e2) : 0.0;
+            sum += g[s];
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) w[s] = g[s] / sum;
+    } else {
+        float e[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) e[s] = si[s] + eps;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            float den = 0.0f;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                if (!((adm >> t) & 1)) continue;
+                const float lr = (s == t) ? 1.0f : (t == 0 ? lratio : (s == 0 ? 1.0f / lratio : 1.0f));
+                const float q = e[s] / e[t], q2 = q * q;
+                den += lr * (q2 * q2);
+            }
+            w[s] = ((adm >> s) & 1) ? 1.0f / den : 0.0f;
+        }
+    }
+}
+
 // per-mesh arrays of one reconstruction (the constants stay in ReconArgs)
 template <typename real>
 struct ReconPtrs {
@@ -668,10 +704,11 @@ __device__ __forceinline__ void recon_body(const ReconArgs<real, (R + 1) * (R + 
                 for (int q = 0; q < 3; ++q)
                     if ((fl >> q) & 1) sm -= lams * ad[q][k][v];
             }
-            ao[k][v] = st > 1 ? sm / a.lam1 : sm;
+            // TENO keeps the central stencil's own polynomial
+            if (SCHEME != CTENO_SCHEME_TENO) ao[k][v] = st > 1 ? sm / a.lam1 : sm;
         }
     int bits[NV];
-    if (DMODE == 2) {
+    if (DMODE == 2 && SCHEME != CTENO_SCHEME_CWENO) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) bits[v] = ptr.delta[i * NV + v] & adm;
     } else if (st == 1) {
@@ -704,9 +741,32 @@ __device__ __forceinline__ void recon_body(const ReconArgs<real, (R + 1) * (R + 
                 const real x0 = ad[q][0][v], x1 = ad[q][1][v];
                 si[v][q + 1] = x0 * (g00 * x0 + g01 * x1) + x1 * (g10 * x0 + g11 * x1);
             }
+        if constexpr (SCHEME == CTENO_SCHEME_CWENO) {
+            // every admissible stencil contributes; final coefficients, in
+            // place: sum_s omega_s p_s
 #pragma unroll
-        for (int v = 0; v < NV; ++v)
-            bits[v] = teno_bits<real, SCHEME, GFORM>(si[v], adm, st, a.lam1, lams, lratio, a.ct, a.eps);
+            for (int v = 0; v < NV; ++v) {
+                bits[v] = adm;
+                real w[4];
+                cweno_weights<real>(si[v], adm, lams, a.lam1, lratio, a.eps, w);
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    real x = w[0] * ao[k][v];
+                    if (k < 2) {
+#pragma unroll
+                        for (int q = 0; q < 3; ++q)
+                            if ((fl >> q) & 1) x += w[q + 1] * ad[q][k][v];
+                    }
+                    ao[k][v] = x;
+                }
+            }
+        } else {
+            constexpr int SEL = SCHEME == CTENO_SCHEME_TENO ? CTENO_SCHEME_CTENO : SCHEME;
+            constexpr int SGF = SCHEME == CTENO_SCHEME_TENO ? CTENO_GAMMA_PAPER : GFORM;
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                bits[v] = teno_bits<real, SEL, SGF>(si[v], adm, st, a.lam1, lams, lratio, a.ct, a.eps);
+        }
     }
     uint32_t dword = 0;
     // final coefficients, in place: p_1, or the mean of the selected
@@ -714,7 +774,7 @@ __device__ __forceinline__ void recon_body(const ReconArgs<real, (R + 1) * (R + 
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
         dword |= (uint32_t)bits[v] << (8 * v);
-        if (!(bits[v] & 1)) {
+        if (SCHEME != CTENO_SCHEME_CWENO && !(bits[v] & 1)) {
             real s0 = 0, s1 = 0;
             int cnt = 0;
 #pragma unroll
@@ -831,6 +891,8 @@ static hipError_t reconstruct_t(const DeviceMesh &m, const double *U, void *FV, 
         default: CT_LAUNCH(SCH, GF, 2); break; \
     }
     if (m.scheme == CTENO_SCHEME_CTENOZ) { CT_DM(CTENO_SCHEME_CTENOZ, CTENO_GAMMA_PAPER); }
+    else if (m.scheme == CTENO_SCHEME_CWENO) { CT_DM(CTENO_SCHEME_CWENO, CTENO_GAMMA_PAPER); }
+    else if (m.scheme == CTENO_SCHEME_TENO) { CT_DM(CTENO_SCHEME_TENO, CTENO_GAMMA_PAPER); }
     else if (m.gamma_form == CTENO_GAMMA_LAMBDA) { CT_DM(CTENO_SCHEME_CTENO, CTENO_GAMMA_LAMBDA); }
     else { CT_DM(CTENO_SCHEME_CTENO, CTENO_GAMMA_PAPER); }
 #undef CT_DM
@@ -1191,19 +1253,22 @@ __global__ __launch_bounds__(256) void k_reconstruct_ho(const ReconHoArgs<real> 
     const int st = 1 + __popc(fl);
     const real lams = st == 2 ? a.lams[2] : (st == 3 ? a.lams[3] : a.lams[4]);
     const real lratio = st == 2 ? a.lam_ratio[2] : (st == 3 ? a.lam_ratio[3] : a.lam_ratio[4]);
-    // p_1 = (p_opt - sum_s lambda_s p_s) / lambda_1 (eq. e17), in place
+    // p_1 = (p_opt - sum_s lambda_s p_s) / lambda_1 (eq. e17), in place;
+    // TENO keeps the central stencil's own polynomial
+    if (SCHEME != CTENO_SCHEME_TENO) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        real sm = ao[k];
-        if (k < KD && st > 1) {
+        for (int k = 0; k < K; ++k) {
+            real sm = ao[k];
+            if (k < KD && st > 1) {
 #pragma unroll
-            for (int q = 0; q < 3; ++q)
-                if ((fl >> q) & 1) sm -= lams * ad[q][k];
+                for (int q = 0; q < 3; ++q)
+                    if ((fl >> q) & 1) sm -= lams * ad[q][k];
+            }
+            ao[k] = st > 1 ? sm / a.lam1 : sm;
         }
-        ao[k] = st > 1 ? sm / a.lam1 : sm;
     }
     int bits;
-    if (DMODE == 2) {
+    if (DMODE == 2 && SCHEME != CTENO_SCHEME_CWENO) {
         bits = a.delta[i * NV + v] & adm;
     } else if (st == 1) {
         bits = 1;
@@ -1229,10 +1294,29 @@ __global__ __launch_bounds__(256) void k_reconstruct_ho(const ReconHoArgs<real> 
             }
             si[s + 1] = sv;
         }
-        bits = teno_bits<real, SCHEME, GFORM>(si, adm, st, a.lam1, lams, lratio, a.ct, a.eps);
+        if constexpr (SCHEME == CTENO_SCHEME_CWENO) {
+            // every admissible stencil contributes: sum_s omega_s p_s, in place
+            bits = adm;
+            real w[4];
+            cweno_weights<real>(si, adm, lams, a.lam1, lratio, a.eps, w);
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                real x = w[0] * ao[k];
+                if (k < KD) {
+#pragma unroll
+                    for (int q = 0; q < 3; ++q)
+                        if ((fl >> q) & 1) x += w[q + 1] * ad[q][k];
+                }
+                ao[k] = x;
+            }
+        } else {
+            constexpr int SEL = SCHEME == CTENO_SCHEME_TENO ? CTENO_SCHEME_CTENO : SCHEME;
+            constexpr int SGF = SCHEME == CTENO_SCHEME_TENO ? CTENO_GAMMA_PAPER : GFORM;
+            bits = teno_bits<real, SEL, SGF>(si, adm, st, a.lam1, lams, lratio, a.ct, a.eps);
+        }
     }
     // final coefficients: p_1, or the mean of the selected directional polynomials
-    if (!(bits & 1)) {
+    if (SCHEME != CTENO_SCHEME_CWENO && !(bits & 1)) {
         int cnt = 0;
 #pragma unroll
         for (int k = 0; k < K; ++k) ao[k] = 0;
@@ -1322,6 +1406,8 @@ static hipError_t reconstruct_ho_t(const DeviceMesh &m, const double *U, void *F
         default: HO_LAUNCH(SCH, GF, 2); break; \
     }
     if (m.scheme == CTENO_SCHEME_CTENOZ) { HO_DM(CTENO_SCHEME_CTENOZ, CTENO_GAMMA_PAPER); }
+    else if (m.scheme == CTENO_SCHEME_CWENO) { HO_DM(CTENO_SCHEME_CWENO, CTENO_GAMMA_PAPER); }
+    else if (m.scheme == CTENO_SCHEME_TENO) { HO_DM(CTENO_SCHEME_TENO, CTENO_GAMMA_PAPER); }
     else if (m.gamma_form == CTENO_GAMMA_LAMBDA) { HO_DM(CTENO_SCHEME_CTENO, CTENO_GAMMA_LAMBDA); }
     else { HO_DM(CTENO_SCHEME_CTENO, CTENO_GAMMA_PAPER); }
 #undef HO_DM
@@ -1829,6 +1915,12 @@ static hipError_t batch_step_r(const DeviceMesh &proto, const BatchSlot *tab, co
     for (int stage = 0; stage < 3; ++stage) {
         if (proto.scheme == CTENO_SCHEME_CTENOZ)
             hipLaunchKernelGGL((k_reconstruct_batch<R, CTENO_SCHEME_CTENOZ, CTENO_GAMMA_PAPER>), dim3(max_blocks),
+                               dim3(256), 0, st, ra, tab, n_slots, stage);
+        else if (proto.scheme == CTENO_SCHEME_CWENO)
+            hipLaunchKernelGGL((k_reconstruct_batch<R, CTENO_SCHEME_CWENO, CTENO_GAMMA_PAPER>), dim3(max_blocks),
+                               dim3(256), 0, st, ra, tab, n_slots, stage);
+        else if (proto.scheme == CTENO_SCHEME_TENO)
+            hipLaunchKernelGGL((k_reconstruct_batch<R, CTENO_SCHEME_TENO, CTENO_GAMMA_PAPER>), dim3(max_blocks),
                                dim3(256), 0, st, ra, tab, n_slots, stage);
         else if (proto.gamma_form == CTENO_GAMMA_LAMBDA)
             hipLaunchKernelGGL((k_reconstruct_batch<R, CTENO_SCHEME_CTENO, CTENO_GAMMA_LAMBDA>), dim3(max_blocks),

@@ -228,7 +228,7 @@ hipError_t h2d(T *dst, const std::vector<T> &src, hipStream_t st) {
 
 static cteno_status check_scheme(const cteno_scheme &s) {
     if (s.physics != CTENO_ADVECTION && s.physics != CTENO_EULER) return fail(CTENO_ERR_INVALID, "bad physics");
-    if (s.scheme != CTENO_SCHEME_CTENO && s.scheme != CTENO_SCHEME_CTENOZ) return fail(CTENO_ERR_INVALID, "bad scheme");
+    if (s.scheme < CTENO_SCHEME_CTENO || s.scheme > CTENO_SCHEME_TENO) return fail(CTENO_ERR_INVALID, "bad scheme");
     if (s.degree < 2 || s.degree > kMaxR) return fail(CTENO_ERR_INVALID, "degree must be 2..6");
     if (s.precision < 1 || s.precision > 3) return fail(CTENO_ERR_INVALID, "bad precision");
     if (!(s.lambda1_prime > 1.0) || !(s.c_t > 0 && s.c_t < 1) || !(s.eps > 0))

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_PKG, "libcteno.so")
 OK, ERR_INVALID, ERR_MESH, ERR_STENCIL, ERR_NOMEM, ERR_DEVICE, ERR_NONPHYSICAL, ERR_BUSY = range(8)
 PERIODIC, WALL, TRANSMISSIVE = 0, 1, 2
 ADVECTION, EULER = 0, 1
-CTENO, CTENOZ = 0, 1
+CTENO, CTENOZ, CWENO, TENO = 0, 1, 2, 3
 GAMMA_PAPER, GAMMA_LAMBDA = 0, 1
 FP64, MIXED, BOTH = 1, 2, 3
 KERNEL_RECONSTRUCT, KERNEL_FLUX, KERNEL_PRECOMPUTE = 0, 1, 2

@@ -59,6 +59,15 @@ CASES = {
                                        gamma_form=O.GAMMA_LAMBDA)),
     "vortex_r6_ctenoz": (lambda: W.vortex_case(20, seed=7),
                          dict(physics=O.EULER, scheme=O.CTENOZ, degree=6, lambda1_prime=1e4)),
+    # the paper's comparison schemes in the same pipeline
+    "vortex_r3_cweno": (lambda: W.vortex_case(24, seed=2),
+                        dict(physics=O.EULER, scheme=O.CWENO, degree=3, lambda1_prime=1e4)),
+    "sod_r3_teno": (lambda: W.sod_case(48, 12, seed=3),
+                    dict(physics=O.EULER, scheme=O.TENO, degree=3, lambda1_prime=1e15)),
+    "sod_r4_cweno": (lambda: W.sod_case(48, 12, seed=3),
+                     dict(physics=O.EULER, scheme=O.CWENO, degree=4, lambda1_prime=1e4)),
+    "density_r4_teno": (lambda: W.density_wave_case(12, seed=11),
+                        dict(physics=O.EULER, scheme=O.TENO, degree=4, lambda1_prime=1e4)),
 }
 
 
@@ -205,7 +214,7 @@ def test_rk_stages_fp64(ctx, name):
 
 
 @pytest.mark.parametrize("name", ["advection_r2_cteno", "vortex_r3_ctenoz", "sod_r3_cteno", "sod_r4_cteno",
-                                  "vortex_r6_ctenoz"])
+                                  "vortex_r6_ctenoz", "sod_r3_teno", "sod_r4_cweno"])
 def test_solve_fp64_matches_oracle(ctx, name):
     mesh, u0, o, m = setup_case(ctx, name)
     s = T.Solution(m, u0)
