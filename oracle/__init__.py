@@ -19,6 +19,7 @@ PERIODIC, WALL, TRANSMISSIVE = 0, 1, 2
 ADVECTION, EULER = 0, 1
 CTENO, CTENOZ, CWENO, TENO = 0, 1, 2, 3
 GAMMA_PAPER, GAMMA_LAMBDA = 0, 1
+CONSERVED, CHARACTERISTIC = 0, 1
 
 
 def build(force: bool = True) -> str:
@@ -34,7 +35,8 @@ def build(force: bool = True) -> str:
 class _Scheme(C.Structure):
     _fields_ = [("physics", C.c_int), ("ax", C.c_double), ("ay", C.c_double), ("gamma", C.c_double),
                 ("scheme", C.c_int), ("degree", C.c_int), ("gamma_form", C.c_int),
-                ("lambda1_prime", C.c_double), ("c_t", C.c_double), ("eps", C.c_double)]
+                ("lambda1_prime", C.c_double), ("c_t", C.c_double), ("eps", C.c_double),
+                ("variables", C.c_int)]
 
 
 _lib = None
@@ -60,6 +62,7 @@ def lib():
         L.or_smoothness.restype = C.c_double
         L.or_smoothness.argtypes = [P, P, C.c_int, C.c_int]
         L.or_select.argtypes = [P, P, P]
+        L.or_char_vectors.argtypes = [C.c_double, P, C.c_double, C.c_double, P, P]
         L.or_cweno_weights.argtypes = [P, P, P, P]
         L.or_hllc.argtypes = [C.c_double, P, P, C.c_double, C.c_double, P]
         L.or_euler_flux.argtypes = [C.c_double, P, C.c_double, C.c_double, P]
@@ -90,13 +93,13 @@ class Oracle:
 
     def __init__(self, xy, tri, box, bc, physics=EULER, scheme=CTENOZ, degree=3,
                  lambda1_prime=1e4, c_t=1e-6, eps=1e-12, gamma=1.4, ax=1.0, ay=1.0,
-                 gamma_form=GAMMA_PAPER):
+                 gamma_form=GAMMA_PAPER, variables=CONSERVED):
         L = lib()
         self._xy = np.ascontiguousarray(xy, dtype=np.float64)
         self._tri = np.ascontiguousarray(tri, dtype=np.int32)
         box = np.ascontiguousarray(box, dtype=np.float64)
         bc = np.ascontiguousarray(bc, dtype=np.int32)
-        s = _Scheme(physics, ax, ay, gamma, scheme, degree, gamma_form, lambda1_prime, c_t, eps)
+        s = _Scheme(physics, ax, ay, gamma, scheme, degree, gamma_form, lambda1_prime, c_t, eps, variables)
         h = L.or_create(self._xy.shape[0], _p(self._xy), self._tri.shape[0], _p(self._tri), _p(box), _p(bc),
                         C.byref(s))
         if not h:
@@ -107,6 +110,9 @@ class Oracle:
         L.or_dims(h, *[C.byref(x) for x in d])
         self.K, self.M, self.Kd, self.Md, self.Nq, self.nv = [x.value for x in d]
         self.physics, self.scheme, self.degree = physics, scheme, degree
+        self.variables = variables
+        # selection bytes: per variable, or per face and characteristic field
+        self.dshape = (3, self.nv) if variables == CHARACTERISTIC else (self.nv,)
 
     @classmethod
     def from_mesh(cls, mesh, **kw):
@@ -159,6 +165,16 @@ class Oracle:
         a = np.ascontiguousarray(a, np.float64)
         return lib().or_smoothness(self.h, _p(a), a.shape[0], r)
 
+    @staticmethod
+    def char_vectors(U, nx, ny, gamma=1.4):
+        """Right eigenvectors R (columns) of the Euler flux Jacobian along
+        (nx, ny) at the conserved state U, and L = R^-1."""
+        U = np.ascontiguousarray(U, np.float64)
+        R = np.empty((4, 4)); Lm = np.empty((4, 4))
+        if lib().or_char_vectors(gamma, _p(U), nx, ny, _p(R), _p(Lm)):
+            raise OracleError("singular eigenvector matrix")
+        return R, Lm
+
     def select(self, si, adm=(1, 1, 1, 1)):
         si = np.ascontiguousarray(si, np.float64)
         adm = np.ascontiguousarray(adm, np.int32)
@@ -174,7 +190,7 @@ class Oracle:
     def reconstruct(self, U, forced=None, want_coef=False):
         U = np.ascontiguousarray(U, np.float64).reshape(self.nv, self.N)
         fv = np.empty((self.N, 3, self.Nq, self.nv))
-        dl = np.empty((self.N, self.nv), np.uint8)
+        dl = np.empty((self.N,) + self.dshape, np.uint8)
         coef = np.empty((self.N, self.nv, self.K)) if want_coef else None
         f = None if forced is None else np.ascontiguousarray(forced, np.uint8)
         self._check(lib().or_reconstruct(self.h, _p(U), _p(f), _p(fv), _p(dl), _p(coef)))
@@ -185,7 +201,7 @@ class Oracle:
         cells = np.ascontiguousarray(cells, np.int32)
         n = cells.shape[0]
         fv = np.empty((n, 3, self.Nq, self.nv))
-        dl = np.empty((n, self.nv), np.uint8)
+        dl = np.empty((n,) + self.dshape, np.uint8)
         self._check(lib().or_reconstruct_cells(self.h, _p(U), n, _p(cells), _p(fv), _p(dl)))
         return fv, dl
 

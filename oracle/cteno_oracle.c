@@ -76,6 +76,7 @@ enum { OR_PERIODIC = 0, OR_WALL = 1, OR_TRANSMISSIVE = 2 };
 enum { OR_ADVECTION = 0, OR_EULER = 1 };
 enum { OR_CTENO = 0, OR_CTENOZ = 1, OR_CWENO = 2, OR_TENO = 3 };
 enum { OR_GAMMA_PAPER = 0, OR_GAMMA_LAMBDA = 1 };
+enum { OR_VARS_CONSERVED = 0, OR_VARS_CHARACTERISTIC = 1 };
 
 static char or_err[512];
 static void set_err(const char *m, long a) { snprintf(or_err, sizeof or_err, "%s (%ld)", m, a); }
@@ -108,7 +109,7 @@ typedef struct {
     double Lx, Ly;
     int physics, nv;
     double ax, ay, gam;
-    int scheme, r, K, M, rd, Kd, Md, Nq, gamma_form;
+    int scheme, r, K, M, rd, Kd, Md, Nq, gamma_form, vars;
     double lam1p, ct, eps;
     int ex[OR_MAXK + 1][2];      /* exponents of psi_k, k = 1..K */
     double gq[OR_MAXNQ], gw[OR_MAXNQ];
@@ -647,94 +648,195 @@ static double poly_eval(const or_ctx *c, double U0, const double *a, int K, doub
     return v;
 }
 
-/* reconstructs cell i: face-point values fv[3][Nq][nv], delta bits per
-   variable; forced (may be NULL) overrides the computed delta bits */
+/* One reconstructed field: a conserved variable, or one characteristic
+   field on one face.  vc[m] are the field's values on the central stencil
+   (central-list order), vd[f][m] on the directional stencils, w0 on the
+   cell.  Least squares (sec. 2.1), p_1 (eq. e17), smoothness indicators,
+   the scheme's selection or weights, and the final coefficients fin[K]
+   (p = w0 + sum_k fin_k phi_k).  forced < 0: compute the selection. */
+static int reconstruct_field(or_ctx *c, or_cell *pc, const int *adm, int st, double lam1, double lams, double w0,
+                             const double *vc, double vd[3][OR_MAXM], int forced, int *bits_out, double *fin) {
+    int M = c->M, K = c->K, Kd = c->Kd;
+    double b[OR_MAXM], aopt[OR_MAXK], ad[3][OR_MAXK];
+    for (int m = 0; m < M; ++m) b[m] = pc->wc[m] * (vc[m] - w0);
+    hh_solve(pc->qa, M, K, pc->qv0, pc->qb, pc->qr, b, aopt);
+    for (int f = 0; f < 3; ++f) {
+        if (!adm[f + 1]) continue;
+        int n = pc->dirn[f];
+        for (int m = 0; m < n; ++m) b[m] = pc->wd[f][m] * (vd[f][m] - w0);
+        hh_solve(pc->da[f], n, Kd, pc->dv0[f], pc->db[f], pc->dr[f], b, ad[f]);
+    }
+    /* p_1 = (p_opt - sum_s lambda_s p_s) / lambda_1 (eq. e17); with no
+       admissible directional stencil the scheme is the linear p_opt.
+       TENO keeps the central-stencil polynomial itself. */
+    double a1[OR_MAXK];
+    for (int k = 0; k < K; ++k) {
+        if (st == 1 || c->scheme == OR_TENO) { a1[k] = aopt[k]; continue; }
+        double sm = aopt[k];
+        if (k < Kd)
+            for (int f = 0; f < 3; ++f) if (adm[f + 1]) sm -= lams * ad[f][k];
+        a1[k] = sm / lam1;
+    }
+    int bits;
+    if (c->scheme == OR_CWENO) {
+        /* every admissible stencil contributes; the selection byte reports
+           them, and forced selections do not apply */
+        bits = 1 | (adm[1] << 1) | (adm[2] << 2) | (adm[3] << 3);
+        if (st == 1) {
+            for (int k = 0; k < K; ++k) fin[k] = a1[k];
+        } else {
+            double si[4] = {0, 0, 0, 0}, w[4];
+            si[0] = smoothness(c, a1, K, c->r);
+            for (int f = 0; f < 3; ++f) if (adm[f + 1]) si[f + 1] = smoothness(c, ad[f], Kd, c->rd);
+            cweno_weights(c, si, adm, lam1, lams, w);
+            for (int k = 0; k < K; ++k) {
+                double x = w[0] * a1[k];
+                if (k < Kd)
+                    for (int f = 0; f < 3; ++f) if (adm[f + 1]) x += w[f + 1] * ad[f][k];
+                fin[k] = x;
+            }
+        }
+    } else {
+        /* TENO-type selection and the two-branch final polynomial */
+        if (st == 1) {
+            bits = 1;
+        } else {
+            double si[4] = {0, 0, 0, 0};
+            si[0] = smoothness(c, a1, K, c->r);
+            for (int f = 0; f < 3; ++f) if (adm[f + 1]) si[f + 1] = smoothness(c, ad[f], Kd, c->rd);
+            bits = teno_select(c, si, adm, lam1, lams);
+        }
+        if (forced >= 0) bits = forced & (1 | (adm[1] << 1) | (adm[2] << 2) | (adm[3] << 3));
+        if (bits & 1) {
+            for (int k = 0; k < K; ++k) fin[k] = a1[k];
+        } else {
+            int nd = 0;
+            for (int k = 0; k < K; ++k) fin[k] = 0.0;
+            for (int f = 0; f < 3; ++f)
+                if (bits & (2 << f)) { ++nd; for (int k = 0; k < Kd; ++k) fin[k] += ad[f][k]; }
+            if (nd == 0) return 5;   /* impossible by max chi >= 1/s_t > C_T */
+            for (int k = 0; k < Kd; ++k) fin[k] /= nd;
+        }
+    }
+    *bits_out = bits;
+    return 0;
+}
+
+/* the physical Gauss points of face f of cell i in reference coordinates */
+static void face_ref_points(const or_ctx *c, int i, int f, double *xi, double *eta) {
+    const int *t = c->tri + 3 * i;
+    int pa = t[f], pb = t[(f + 1) % 3];
+    for (int q = 0; q < c->Nq; ++q) {
+        double x = c->xy[2 * pa] + c->gq[q] * (c->xy[2 * pb] - c->xy[2 * pa]);
+        double y = c->xy[2 * pa + 1] + c->gq[q] * (c->xy[2 * pb + 1] - c->xy[2 * pa + 1]);
+        to_ref(c, i, x, y, xi + q, eta + q);
+    }
+}
+
+/* Right eigenvectors (columns) of the Jacobian of the Euler flux in the
+   direction of the unit normal n at the state U, for the eigenvalues
+   u_n - c, u_n, u_n (shear), u_n + c, and the left eigenvectors L = R^-1
+   obtained by Gauss-Jordan elimination. */
+int or_char_vectors(double g, const double *U, double nx, double ny, double *Rm, double *Lm) {
+    double rho = U[0], u = U[1] / rho, v = U[2] / rho;
+    double p = (g - 1.0) * (U[3] - 0.5 * rho * (u * u + v * v));
+    double cs = sqrt(g * p / rho), H = (U[3] + p) / rho;
+    double un = u * nx + v * ny, ut = -u * ny + v * nx;
+    double R[4][4] = {{1.0, 1.0, 0.0, 1.0},
+                      {u - cs * nx, u, -ny, u + cs * nx},
+                      {v - cs * ny, v, nx, v + cs * ny},
+                      {H - un * cs, 0.5 * (u * u + v * v), ut, H + un * cs}};
+    double A[4][8];
+    for (int r = 0; r < 4; ++r)
+        for (int k = 0; k < 8; ++k) A[r][k] = k < 4 ? R[r][k] : (k - 4 == r ? 1.0 : 0.0);
+    for (int k = 0; k < 4; ++k) {
+        int piv = k;
+        for (int r = k + 1; r < 4; ++r) if (fabs(A[r][k]) > fabs(A[piv][k])) piv = r;
+        if (A[piv][k] == 0.0) return 1;
+        for (int j = 0; j < 8; ++j) { double tmp = A[k][j]; A[k][j] = A[piv][j]; A[piv][j] = tmp; }
+        double d = A[k][k];
+        for (int j = 0; j < 8; ++j) A[k][j] /= d;
+        for (int r = 0; r < 4; ++r) {
+            if (r == k) continue;
+            double f = A[r][k];
+            for (int j = 0; j < 8; ++j) A[r][j] -= f * A[k][j];
+        }
+    }
+    for (int r = 0; r < 4; ++r)
+        for (int k = 0; k < 4; ++k) { Rm[r * 4 + k] = R[r][k]; Lm[r * 4 + k] = A[r][k + 4]; }
+    return 0;
+}
+
+/* reconstructs cell i: face-point values fv[3][Nq][nv] and the selection
+   bits: conserved variables dbits[nv], characteristic variables
+   dbits[3][nv] (per face and field); forced (may be NULL, same layout)
+   overrides the computed selections */
 static int reconstruct_cell(or_ctx *c, int i, const double *U, const uint8_t *forced, double *fv,
                             uint8_t *dbits, double *coef_out) {
     /* forced, fv, dbits, coef_out point at this cell's own entries */
     or_cell *pc = get_cell(c, i);
     if (pc->status) return pc->status;
-    int N = c->N, M = c->M, K = c->K, Kd = c->Kd, nv = c->nv;
+    int N = c->N, M = c->M, K = c->K, nv = c->nv;
     int adm[4] = {1, pc->dirn[0] > 0, pc->dirn[1] > 0, pc->dirn[2] > 0};
     int st = 1 + adm[1] + adm[2] + adm[3];
     double lam1 = 1.0 - 1.0 / c->lam1p;
     double lams = st > 1 ? (1.0 - lam1) / (st - 1) : 0.0;
-    for (int v = 0; v < nv; ++v) {
-        const double *Uv = U + (size_t)v * N;
-        double U0 = Uv[i];
-        double b[OR_MAXM], aopt[OR_MAXK], ad[3][OR_MAXK];
-        for (int m = 0; m < M; ++m) b[m] = pc->wc[m] * (Uv[pc->cen[m]] - U0);
-        hh_solve(pc->qa, M, K, pc->qv0, pc->qb, pc->qr, b, aopt);
+    double vc[OR_MAXM], vd[3][OR_MAXM], fin[OR_MAXK];
+    if (c->vars == OR_VARS_CHARACTERISTIC) {
+        /* per face: fields W = L_f U with the eigenvectors of the flux
+           Jacobian along the face normal at the cell's average state */
+        double U0[OR_MAXNV];
+        for (int v = 0; v < nv; ++v) U0[v] = U[(size_t)v * N + i];
         for (int f = 0; f < 3; ++f) {
-            if (!adm[f + 1]) continue;
-            int n = pc->dirn[f];
-            for (int m = 0; m < n; ++m) b[m] = pc->wd[f][m] * (Uv[pc->dir[f][m]] - U0);
-            hh_solve(pc->da[f], n, Kd, pc->dv0[f], pc->db[f], pc->dr[f], b, ad[f]);
-        }
-        /* p_1 = (p_opt - sum_s lambda_s p_s) / lambda_1 (eq. e17); with no
-           admissible directional stencil the scheme is the linear p_opt.
-           TENO keeps the central-stencil polynomial itself. */
-        double a1[OR_MAXK];
-        for (int k = 0; k < K; ++k) {
-            if (st == 1 || c->scheme == OR_TENO) { a1[k] = aopt[k]; continue; }
-            double s = aopt[k];
-            if (k < Kd)
-                for (int f = 0; f < 3; ++f) if (adm[f + 1]) s -= lams * ad[f][k];
-            a1[k] = s / lam1;
-        }
-        int bits;
-        double fin[OR_MAXK];
-        if (c->scheme == OR_CWENO) {
-            /* every admissible stencil contributes; the selection byte
-               reports them, and forced selections do not apply */
-            bits = 1 | (adm[1] << 1) | (adm[2] << 2) | (adm[3] << 3);
-            if (st == 1) {
-                for (int k = 0; k < K; ++k) fin[k] = a1[k];
-            } else {
-                double si[4] = {0, 0, 0, 0}, w[4];
-                si[0] = smoothness(c, a1, K, c->r);
-                for (int f = 0; f < 3; ++f) if (adm[f + 1]) si[f + 1] = smoothness(c, ad[f], Kd, c->rd);
-                cweno_weights(c, si, adm, lam1, lams, w);
-                for (int k = 0; k < K; ++k) {
-                    double x = w[0] * a1[k];
-                    if (k < Kd)
-                        for (int f = 0; f < 3; ++f) if (adm[f + 1]) x += w[f + 1] * ad[f][k];
-                    fin[k] = x;
+            double Rm[16], Lm[16];
+            if (or_char_vectors(c->gam, U0, c->fnx[3 * i + f], c->fny[3 * i + f], Rm, Lm)) return 6;
+            double xi[OR_MAXNQ], eta[OR_MAXNQ], Wq[OR_MAXNQ][4];
+            face_ref_points(c, i, f, xi, eta);
+            for (int j = 0; j < 4; ++j) {
+                double w0 = 0.0;
+                for (int v = 0; v < 4; ++v) w0 += Lm[j * 4 + v] * U0[v];
+                for (int m = 0; m < M; ++m) {
+                    double x = 0.0;
+                    for (int v = 0; v < 4; ++v) x += Lm[j * 4 + v] * U[(size_t)v * N + pc->cen[m]];
+                    vc[m] = x;
                 }
+                for (int s2 = 0; s2 < 3; ++s2)
+                    for (int m = 0; m < pc->dirn[s2]; ++m) {
+                        double x = 0.0;
+                        for (int v = 0; v < 4; ++v) x += Lm[j * 4 + v] * U[(size_t)v * N + pc->dir[s2][m]];
+                        vd[s2][m] = x;
+                    }
+                int bits;
+                int rc = reconstruct_field(c, pc, adm, st, lam1, lams, w0, vc, vd,
+                                           forced ? forced[f * nv + j] : -1, &bits, fin);
+                if (rc) return rc;
+                if (dbits) dbits[f * nv + j] = (uint8_t)bits;
+                for (int q = 0; q < c->Nq; ++q) Wq[q][j] = poly_eval(c, w0, fin, K, xi[q], eta[q]);
             }
-        } else {
-            /* TENO-type selection and the two-branch final polynomial */
-            if (st == 1) {
-                bits = 1;
-            } else {
-                double si[4] = {0, 0, 0, 0};
-                si[0] = smoothness(c, a1, K, c->r);
-                for (int f = 0; f < 3; ++f) if (adm[f + 1]) si[f + 1] = smoothness(c, ad[f], Kd, c->rd);
-                bits = teno_select(c, si, adm, lam1, lams);
-            }
-            if (forced) bits = forced[v] & (1 | (adm[1] << 1) | (adm[2] << 2) | (adm[3] << 3));
-            if (bits & 1) {
-                for (int k = 0; k < K; ++k) fin[k] = a1[k];
-            } else {
-                int nd = 0;
-                for (int k = 0; k < K; ++k) fin[k] = 0.0;
-                for (int f = 0; f < 3; ++f)
-                    if (bits & (2 << f)) { ++nd; for (int k = 0; k < Kd; ++k) fin[k] += ad[f][k]; }
-                if (nd == 0) return 5;   /* impossible by max chi >= 1/s_t > C_T */
-                for (int k = 0; k < Kd; ++k) fin[k] /= nd;
-            }
+            for (int q = 0; q < c->Nq; ++q)
+                for (int v = 0; v < 4; ++v) {
+                    double x = 0.0;
+                    for (int j = 0; j < 4; ++j) x += Rm[v * 4 + j] * Wq[q][j];
+                    fv[((size_t)f * c->Nq + q) * nv + v] = x;
+                }
         }
-        if (dbits) dbits[v] = (uint8_t)bits;
-        if (coef_out) for (int k = 0; k < K; ++k) coef_out[(size_t)v * K + k] = fin[k];
-        const int *t = c->tri + 3 * i;
-        for (int f = 0; f < 3; ++f) {
-            int pa = t[f], pb = t[(f + 1) % 3];
-            for (int q = 0; q < c->Nq; ++q) {
-                double x = c->xy[2 * pa] + c->gq[q] * (c->xy[2 * pb] - c->xy[2 * pa]);
-                double y = c->xy[2 * pa + 1] + c->gq[q] * (c->xy[2 * pb + 1] - c->xy[2 * pa + 1]);
-                double xi, eta;
-                to_ref(c, i, x, y, &xi, &eta);
-                fv[((size_t)f * c->Nq + q) * nv + v] = poly_eval(c, U0, fin, K, xi, eta);
+    } else {
+        for (int v = 0; v < nv; ++v) {
+            const double *Uv = U + (size_t)v * N;
+            double U0 = Uv[i];
+            for (int m = 0; m < M; ++m) vc[m] = Uv[pc->cen[m]];
+            for (int s2 = 0; s2 < 3; ++s2)
+                for (int m = 0; m < pc->dirn[s2]; ++m) vd[s2][m] = Uv[pc->dir[s2][m]];
+            int bits;
+            int rc = reconstruct_field(c, pc, adm, st, lam1, lams, U0, vc, vd, forced ? forced[v] : -1, &bits, fin);
+            if (rc) return rc;
+            if (dbits) dbits[v] = (uint8_t)bits;
+            if (coef_out) for (int k = 0; k < K; ++k) coef_out[(size_t)v * K + k] = fin[k];
+            for (int f = 0; f < 3; ++f) {
+                double xi[OR_MAXNQ], eta[OR_MAXNQ];
+                face_ref_points(c, i, f, xi, eta);
+                for (int q = 0; q < c->Nq; ++q)
+                    fv[((size_t)f * c->Nq + q) * nv + v] = poly_eval(c, U0, fin, K, xi[q], eta[q]);
             }
         }
     }
@@ -751,7 +853,10 @@ static int reconstruct_cell(or_ctx *c, int i, const double *U, const uint8_t *fo
         if (bad) {
             for (int p = 0; p < 3 * c->Nq; ++p)
                 for (int v = 0; v < nv; ++v) fv[(size_t)p * nv + v] = U[(size_t)v * N + i];
-            if (dbits) for (int v = 0; v < nv; ++v) dbits[v] |= 0x80;
+            if (dbits) {
+                int nb = c->vars == OR_VARS_CHARACTERISTIC ? 3 * nv : nv;
+                for (int k = 0; k < nb; ++k) dbits[k] |= 0x80;
+            }
         }
     }
     return 0;
@@ -877,6 +982,7 @@ typedef struct {
     int physics; double ax, ay, gamma;
     int scheme, degree, gamma_form;
     double lambda1_prime, c_t, eps;
+    int variables;                 /* OR_VARS_CONSERVED | OR_VARS_CHARACTERISTIC */
 } or_scheme;
 
 void or_destroy(or_ctx *c) {
@@ -909,6 +1015,10 @@ or_ctx *or_create(int nvert, const double *xy, int ncell, const int *tri, const 
         for (int k = 0; k < 4; ++k) if (bc[k] == OR_WALL) { set_err("walls need the Euler equations", k); or_destroy(c); return NULL; }
     c->ax = sch->ax; c->ay = sch->ay; c->gam = sch->gamma;
     c->scheme = sch->scheme; c->r = sch->degree; c->gamma_form = sch->gamma_form;
+    c->vars = sch->variables;
+    if (c->vars == OR_VARS_CHARACTERISTIC && c->physics != OR_EULER) {
+        set_err("characteristic variables need the Euler equations", 0); or_destroy(c); return NULL;
+    }
     c->lam1p = sch->lambda1_prime; c->ct = sch->c_t; c->eps = sch->eps;
     c->K = (c->r + 1) * (c->r + 2) / 2 - 1;
     c->M = 2 * c->K;
@@ -1073,7 +1183,8 @@ int or_hllc(double g, const double *UL, const double *UR, double nx, double ny, 
 }
 void or_euler_flux(double g, const double *U, double nx, double ny, double *F) { euler_normal_flux(g, U, nx, ny, F); }
 
-/* reconstruction of all cells: fv[N][3][Nq][nv], delta[N][nv] (may be NULL),
+/* reconstruction of all cells: fv[N][3][Nq][nv], delta[N][nv] (characteristic
+   variables: [N][3][nv]; may be NULL),
    coef[N][nv][K] (may be NULL), forced[N][nv] (may be NULL) */
 int or_reconstruct(or_ctx *c, const double *U, const uint8_t *forced, double *fv, uint8_t *delta, double *coef) {
     int rc = or_prepare(c);
@@ -1081,9 +1192,9 @@ int or_reconstruct(or_ctx *c, const double *U, const uint8_t *forced, double *fv
     int bad = 0;
 #pragma omp parallel for schedule(static) reduction(| : bad)
     for (int i = 0; i < c->N; ++i) {
-        size_t nv = c->nv;
-        bad |= reconstruct_cell(c, i, U, forced ? forced + i * nv : NULL, fv + (size_t)i * 3 * c->Nq * nv,
-                                delta ? delta + i * nv : NULL, coef ? coef + i * nv * c->K : NULL);
+        size_t nv = c->nv, nb = c->vars == OR_VARS_CHARACTERISTIC ? 3 * nv : nv;
+        bad |= reconstruct_cell(c, i, U, forced ? forced + i * nb : NULL, fv + (size_t)i * 3 * c->Nq * nv,
+                                delta ? delta + i * nb : NULL, coef ? coef + i * nv * c->K : NULL);
     }
     if (bad) set_err("reconstruction failure", bad);
     return bad;
@@ -1091,11 +1202,11 @@ int or_reconstruct(or_ctx *c, const double *U, const uint8_t *forced, double *fv
 
 /* reconstruction of selected cells only: fv[n][3][Nq][nv], delta[n][nv] */
 int or_reconstruct_cells(or_ctx *c, const double *U, int n, const int *cells, double *fv, uint8_t *delta) {
-    size_t nv = c->nv, Nq = c->Nq;
+    size_t nv = c->nv, Nq = c->Nq, nb = c->vars == OR_VARS_CHARACTERISTIC ? 3 * nv : nv;
     for (int a = 0; a < n; ++a) {
         int i = cells[a];
         if (i < 0 || i >= c->N) { set_err("cell out of range", i); return 1; }
-        int rc = reconstruct_cell(c, i, U, NULL, fv + (size_t)a * 3 * Nq * nv, delta ? delta + (size_t)a * nv : NULL, NULL);
+        int rc = reconstruct_cell(c, i, U, NULL, fv + (size_t)a * 3 * Nq * nv, delta ? delta + (size_t)a * nb : NULL, NULL);
         if (rc) { set_err("reconstruction failure at cell", i); return rc; }
     }
     return 0;
@@ -1108,7 +1219,7 @@ int or_residual_cells(or_ctx *c, const double *U, int n, const int *cells, doubl
     int nv = c->nv, Nq = c->Nq;
     size_t per = (size_t)3 * Nq * nv;
     double *own = malloc(sizeof(double) * per), *nbf = malloc(sizeof(double) * per);
-    uint8_t dl[OR_MAXNV];
+    uint8_t dl[3 * OR_MAXNV];
     int rc = 0;
     for (int a = 0; a < n && !rc; ++a) {
         int i = cells[a];
@@ -1184,7 +1295,7 @@ int or_residual(or_ctx *c, const double *U, double *R) {
     or_work w;
     w.fv = malloc(sizeof(double) * N * 3 * c->Nq * c->nv);
     w.fo = malloc(sizeof(double) * N * 3 * c->nv);
-    w.delta = malloc(N * c->nv);
+    w.delta = malloc((size_t)N * 3 * c->nv);
     int rc = residual(c, U, R, &w);
     free(w.fv); free(w.fo); free(w.delta);
     return rc;
@@ -1222,7 +1333,7 @@ int or_rk3_step(or_ctx *c, double *U, double dt) {
     or_work w;
     w.fv = malloc(sizeof(double) * (size_t)c->N * 3 * c->Nq * c->nv);
     w.fo = malloc(sizeof(double) * (size_t)c->N * 3 * c->nv);
-    w.delta = malloc((size_t)c->N * c->nv);
+    w.delta = malloc((size_t)c->N * 3 * c->nv);
     int rc = residual(c, U, R, &w);
     if (!rc) {
         for (size_t k = 0; k < n; ++k) U1[k] = U[k] + dt * R[k];
