@@ -160,6 +160,30 @@ def schemes_bench(T, W, ctx, n=1000, steps=5, warmup=1):
             "ms_per_step": ms, "normalised_time": norm, "paper_table_tab2": PAPER_SCHEME_TIMES}
 
 
+def variables_bench(T, W, ctx, n=1000, steps=5, warmup=1):
+    """Reconstruction in characteristic variables (per face, three
+    projections and selections per cell) against conserved variables:
+    mixed-precision step time and reconstruction time at r = 3 and 4."""
+    mesh, u0 = W.vortex_case(n, seed=5, quad=3)
+    out = {"workload": f"isentropic vortex, {n}x{n} ({mesh.n_cells} cells), CTENOZ lambda1'=1e4, mixed precision"}
+    for r in (3, 4):
+        row = {}
+        for name, var in (("conserved", T.CONSERVED), ("characteristic", T.CHARACTERISTIC)):
+            m = T.Mesh.from_workload(ctx, mesh, physics=T.EULER, scheme=T.CTENOZ, degree=r, lambda1_prime=1e4,
+                                     precision=T.MIXED, variables=var)
+            sol = T.Solution(m, u0)
+            res = run_precision(T, ctx, m, sol, u0, T.MIXED, steps, warmup)
+            nrec, msrec = res["recon"]
+            row[name] = {"ms_per_step": 1e3 * res["elapsed"] / steps, "reconstruct_ms": msrec / max(1, nrec)}
+            sol.close()
+            m.close()
+        row["step_ratio"] = row["characteristic"]["ms_per_step"] / row["conserved"]["ms_per_step"]
+        out[f"r{r}"] = row
+        log(f"variables r={r}: conserved {row['conserved']['ms_per_step']:.3f} ms/step, characteristic "
+            f"{row['characteristic']['ms_per_step']:.3f} ms/step (x{row['step_ratio']:.3f})")
+    return out
+
+
 def cpu_baseline(W, target_s=12.0, max_steps=40):
     """The FP64 oracle on a bounded sample of the same workload family: SSP-RK3
     steps on a 320k-cell mesh until about target_s seconds of work."""
@@ -254,6 +278,7 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=256)
     ap.add_argument("--no-orders", action="store_true", help="skip the orders 5-7 measurement")
     ap.add_argument("--no-schemes", action="store_true", help="skip the CWENO/TENO/CTENO/CTENOZ cost comparison")
+    ap.add_argument("--no-variables", action="store_true", help="skip the characteristic-variable cost comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); multi-GPU sharding is a design "
@@ -366,6 +391,8 @@ def main():
         out["orders_5_to_7"] = orders_bench(T, W, ctx)
     if not args.no_schemes:
         out["schemes"] = schemes_bench(T, W, ctx)
+    if not args.no_variables:
+        out["variables"] = variables_bench(T, W, ctx)
     if not args.no_serving:
         out["serving"] = serving_bench(T, W, ctx, n_requests=args.serving_requests)
     if not args.no_cpu_baseline:

@@ -50,6 +50,13 @@ enum { CTENO_PERIODIC = 0, CTENO_WALL = 1, CTENO_TRANSMISSIVE = 2 };
 /* physics */
 enum { CTENO_ADVECTION = 0, CTENO_EULER = 1 };
 /* weighting scheme: CTENO = Algorithm 1 (sec. 2.4), CTENOZ = Algorithm 2 (sec. 2.5) */
+/* Reconstructed variables: conserved variables component-wise, or per face
+   the characteristic fields W = L_f U of the Euler flux Jacobian along the
+   face normal at the cell's average state (sec. 2.2 recommends them for
+   strong shocks; the paper uses them for Sod).  With characteristic
+   variables the selection bytes are per face and field: [n_cells][3][nv]. */
+enum { CTENO_VARS_CONSERVED = 0, CTENO_VARS_CHARACTERISTIC = 1 };
+
 /* CTENO: Algorithm 1; CTENOZ: Algorithm 2; CWENO and TENO: the paper's
    comparison schemes (sec. 2.2-2.3) in the same pipeline */
 enum { CTENO_SCHEME_CTENO = 0, CTENO_SCHEME_CTENOZ = 1, CTENO_SCHEME_CWENO = 2, CTENO_SCHEME_TENO = 3 };
@@ -110,6 +117,7 @@ typedef struct {
     int32_t gamma_form;
     int32_t precision;      /* CTENO_FP64 | CTENO_MIXED | CTENO_BOTH */
     int32_t reorder;        /* 1: Morton-order cells internally for locality; 0: keep order */
+    int32_t variables;      /* CTENO_VARS_CONSERVED | CTENO_VARS_CHARACTERISTIC (Euler only) */
 } cteno_scheme;
 
 typedef struct {
@@ -196,10 +204,11 @@ void cteno_sol_destroy(cteno_sol *sol);
    face_vals: device [n_cells][3][N_q][nv], FP64 (precision CTENO_FP64) or
    FP32 (CTENO_MIXED); point q of face f lies at t_q along the face from
    vertex f to vertex f+1 of the counter-clockwise triangle.
-   delta_out: device [n_cells][nv] or NULL: bit 0 = delta_1 (central),
+   delta_out: device [n_cells][nv] ([n_cells][3][nv] per face and field with
+   characteristic variables) or NULL: bit 0 = delta_1 (central),
    bit 1+f = delta of the directional stencil of face f, bit 7 = positivity
    fallback taken.
-   delta_forced: device [n_cells][nv] or NULL: use these selections instead
+   delta_forced: device, same layout as delta_out, or NULL: use these selections instead
    of computing them (bits of inadmissible stencils are ignored). */
 cteno_status cteno_reconstruct(cteno_ctx *ctx, const cteno_mesh *mesh, const cteno_sol *sol, int32_t precision,
                                void *face_vals, uint8_t *delta_out, const uint8_t *delta_forced);
@@ -233,8 +242,9 @@ cteno_status cteno_rk_stage(cteno_ctx *ctx, const cteno_mesh *mesh, cteno_sol *s
 cteno_status cteno_solve(cteno_ctx *ctx, const cteno_mesh *mesh, cteno_sol *sol, int32_t precision, double t_final,
                          int64_t max_steps, double cfl, int32_t use_graph, int64_t *steps_done);
 
-/* Cells x variables whose TENO selection (delta bits) differs between the
-   FP32 and FP64 reconstructions of the current state.  Needs precision
+/* Selection bytes (cells x variables, or cells x faces x characteristic
+   fields) whose TENO selection (delta bits) differs between the FP32 and
+   FP64 reconstructions of the current state.  Needs precision
    CTENO_BOTH on the mesh.  Synchronises. */
 cteno_status cteno_count_flips(cteno_ctx *ctx, const cteno_mesh *mesh, const cteno_sol *sol, int64_t *flips);
 

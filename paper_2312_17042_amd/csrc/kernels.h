@@ -9,6 +9,7 @@ struct DeviceMesh {
     int64_t N = 0, Np = 0;
     int r = 0, K = 0, S = 0, SP = 0, nv = 0, physics = 0;
     int scheme = 0, gamma_form = 0, precision = 0;
+    int vars = 0;                  // CTENO_VARS_CONSERVED | CTENO_VARS_CHARACTERISTIC
     int E64 = 0, E32 = 0;          // pseudo-inverse entries per cell (padded to the vector width)
     int Kd = 0, Md = 0, Nq = 2;    // directional basis size and members, Gauss points per face
     int stile = 64;                // cells per stream tile (r >= 4: 64 / nv)
@@ -26,6 +27,8 @@ struct DeviceMesh {
     float *htab32 = nullptr;       // the same in FP32
     RefTables tab;
     int64_t blocks() const { return (N + 255) / 256; }
+    // selection bytes per cell: per variable, or per face and characteristic field
+    int delta_bytes() const { return vars == CTENO_VARS_CHARACTERISTIC ? 3 * nv : nv; }
 };
 
 struct PrecomputeInputs {

@@ -91,6 +91,22 @@ __device__ __forceinline__ void store_row(real *__restrict__ p, const real *in) 
     }
 }
 
+// face record of local face f: unit normal, length, neighbour code
+template <typename real>
+__device__ __forceinline__ void face_record(const real *fr, int64_t i, int f, real &nx, real &ny, real &len,
+                                            uint32_t &code) {
+    if constexpr (std::is_same<real, float>::value) {
+        const float4 r = reinterpret_cast<const float4 *>(fr)[(size_t)(i >> 6) * 3 * 64 + f * 64 + (i & 63)];
+        nx = r.x; ny = r.y; len = r.z;
+        code = (uint32_t)__float_as_int(r.w);
+    } else {
+        const double2 *b = reinterpret_cast<const double2 *>(fr) + (size_t)(i >> 6) * 6 * 64 + (i & 63);
+        const double2 r0 = b[(2 * f) * 64], r1 = b[(2 * f + 1) * 64];
+        nx = r0.x; ny = r0.y; len = r1.x;
+        code = (uint32_t)__double_as_longlong(r1.y);
+    }
+}
+
 // Work-groups are dispatched round-robin over the 8 XCDs; remap them so that
 // each XCD (and its L2) works on one contiguous range of cells, which keeps
 // the neighbour gathers of adjacent blocks in the same L2.
@@ -422,8 +438,9 @@ struct ReconArgs {
     const uint8_t *flags;   // [Np]
     const real *P;          // vector-tiled pseudo-inverse stream
     real *FV;               // AoS [Np][3][2][NV]
-    uint8_t *delta;         // AoS [Np][NV]
+    uint8_t *delta;         // AoS [Np][NV] (characteristic variables: [Np][3][NV])
     const int *done;
+    const real *fr;         // face records (characteristic variables)
     real gram[K][K];
     real basis[3][2][K];
     real lam1, ct, eps;
@@ -557,9 +574,96 @@ struct ReconPtrs {
     const real *P;
     real *FV;
     uint8_t *delta;
+    const real *fr;         // face records (characteristic variables only)
 };
 
-template <typename real, int R, int NV, int SCHEME, int GFORM, int DMODE>
+// selection (or CWENO weights) of NV fields and their final coefficients,
+// in place: c1[K][NV] holds the p_1 coefficients on entry and the final
+// polynomial's on exit, cd[3][2][NV] the degree-1 directional ones; forced
+// (DMODE 2) points at the fields' forced selection bytes
+template <typename real, int K, int NV, int SCHEME, int GFORM, int DMODE>
+__device__ __forceinline__ void finish_fields(const ReconArgs<real, K> a, real (&c1)[K][NV], const real (&cd)[3][2][NV],
+                                              int fl, int adm, int st, real lams, real lratio, const uint8_t *forced,
+                                              int (&bits)[NV]) {
+    if (DMODE == 2 && SCHEME != CTENO_SCHEME_CWENO) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) bits[v] = forced[v] & adm;
+    } else if (st == 1) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) bits[v] = 1;
+    } else {
+        // smoothness indicators: SI_1 = a1^T G a1, SI_s over the degree-1 block of G
+        real si[NV][4];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) si[v][0] = 0;
+#pragma unroll
+        for (int p = 0; p < K; ++p) {
+            real rowp[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) rowp[v] = 0;
+#pragma unroll
+            for (int q = 0; q < K; ++q) {
+                const real g = a.gram[p][q];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) rowp[v] += g * c1[q][v];
+            }
+#pragma unroll
+            for (int v = 0; v < NV; ++v) si[v][0] += c1[p][v] * rowp[v];
+        }
+        const real g00 = a.gram[0][0], g01 = a.gram[0][1], g10 = a.gram[1][0], g11 = a.gram[1][1];
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const real x0 = cd[q][0][v], x1 = cd[q][1][v];
+                si[v][q + 1] = x0 * (g00 * x0 + g01 * x1) + x1 * (g10 * x0 + g11 * x1);
+            }
+        if constexpr (SCHEME == CTENO_SCHEME_CWENO) {
+            // every admissible stencil contributes; final coefficients, in
+            // place: sum_s omega_s p_s
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                bits[v] = adm;
+                real w[4];
+                cweno_weights<real>(si[v], adm, lams, a.lam1, lratio, a.eps, w);
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    real x = w[0] * c1[k][v];
+                    if (k < 2) {
+#pragma unroll
+                        for (int q = 0; q < 3; ++q)
+                            if ((fl >> q) & 1) x += w[q + 1] * cd[q][k][v];
+                    }
+                    c1[k][v] = x;
+                }
+            }
+        } else {
+            constexpr int SEL = SCHEME == CTENO_SCHEME_TENO ? CTENO_SCHEME_CTENO : SCHEME;
+            constexpr int SGF = SCHEME == CTENO_SCHEME_TENO ? CTENO_GAMMA_PAPER : GFORM;
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                bits[v] = teno_bits<real, SEL, SGF>(si[v], adm, st, a.lam1, lams, lratio, a.ct, a.eps);
+        }
+    }
+    // final coefficients, in place: p_1, or the mean of the selected
+    // directional polynomials
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        if (SCHEME != CTENO_SCHEME_CWENO && !(bits[v] & 1)) {
+            real s0 = 0, s1 = 0;
+            int cnt = 0;
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+                if ((bits[v] >> (q + 1)) & 1) { s0 += cd[q][0][v]; s1 += cd[q][1][v]; ++cnt; }
+            c1[0][v] = s0 / (real)cnt;
+            c1[1][v] = s1 / (real)cnt;
+#pragma unroll
+            for (int k = 2; k < K; ++k) c1[k][v] = 0;
+        }
+    }
+}
+
+template <typename real, int R, int NV, int SCHEME, int GFORM, int DMODE, int VARS>
 __device__ __forceinline__ void recon_body(const ReconArgs<real, (R + 1) * (R + 2) / 2 - 1> a,
                                            const ReconPtrs<real> ptr, int64_t i) {
     // a and ptr by value: a reference to the kernel-argument struct would make
@@ -707,103 +811,106 @@ __device__ __forceinline__ void recon_body(const ReconArgs<real, (R + 1) * (R + 
             // TENO keeps the central stencil's own polynomial
             if (SCHEME != CTENO_SCHEME_TENO) ao[k][v] = st > 1 ? sm / a.lam1 : sm;
         }
-    int bits[NV];
-    if (DMODE == 2 && SCHEME != CTENO_SCHEME_CWENO) {
+    real out[3][2][NV];
+    constexpr int NB = VARS ? 3 * NV : NV;       // selection bytes per cell
+    uint8_t dbyte[NB];
+    if constexpr (VARS == 0) {
+        int bits[NV];
+        finish_fields<real, K, NV, SCHEME, GFORM, DMODE>(a, ao, ad, fl, adm, st, lams, lratio, ptr.delta + i * NV,
+                                                         bits);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) bits[v] = ptr.delta[i * NV + v] & adm;
-    } else if (st == 1) {
+        for (int v = 0; v < NV; ++v) dbyte[v] = (uint8_t)bits[v];
+        // face Gauss-point values
 #pragma unroll
-        for (int v = 0; v < NV; ++v) bits[v] = 1;
-    } else {
-        // smoothness indicators: SI_1 = a1^T G a1, SI_s over the degree-1 block of G
-        real si[NV][4];
+        for (int f = 0; f < 3; ++f)
 #pragma unroll
-        for (int v = 0; v < NV; ++v) si[v][0] = 0;
+            for (int q = 0; q < 2; ++q) {
+                real val[NV];
 #pragma unroll
-        for (int p = 0; p < K; ++p) {
-            real rowp[NV];
-#pragma unroll
-            for (int v = 0; v < NV; ++v) rowp[v] = 0;
-#pragma unroll
-            for (int q = 0; q < K; ++q) {
-                const real g = a.gram[p][q];
-#pragma unroll
-                for (int v = 0; v < NV; ++v) rowp[v] += g * ao[q][v];
-            }
-#pragma unroll
-            for (int v = 0; v < NV; ++v) si[v][0] += ao[p][v] * rowp[v];
-        }
-        const real g00 = a.gram[0][0], g01 = a.gram[0][1], g10 = a.gram[1][0], g11 = a.gram[1][1];
-#pragma unroll
-        for (int q = 0; q < 3; ++q)
-#pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                const real x0 = ad[q][0][v], x1 = ad[q][1][v];
-                si[v][q + 1] = x0 * (g00 * x0 + g01 * x1) + x1 * (g10 * x0 + g11 * x1);
-            }
-        if constexpr (SCHEME == CTENO_SCHEME_CWENO) {
-            // every admissible stencil contributes; final coefficients, in
-            // place: sum_s omega_s p_s
-#pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                bits[v] = adm;
-                real w[4];
-                cweno_weights<real>(si[v], adm, lams, a.lam1, lratio, a.eps, w);
+                for (int v = 0; v < NV; ++v) val[v] = 0;
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
-                    real x = w[0] * ao[k][v];
-                    if (k < 2) {
+                    const real b = a.basis[f][q][k];
 #pragma unroll
-                        for (int q = 0; q < 3; ++q)
-                            if ((fl >> q) & 1) x += w[q + 1] * ad[q][k][v];
+                    for (int v = 0; v < NV; ++v) val[v] += b * ao[k][v];
+                }
+#pragma unroll
+                for (int v = 0; v < NV; ++v) out[f][q][v] = (real)(U0[v] + (double)val[v]);
+            }
+    } else {
+        // characteristic fields per face: the least-squares coefficients are
+        // linear in the data, so projecting them with L_f equals
+        // reconstructing the projected averages W = L_f U; the face values
+        // are U_0 + R_f (W(x_q) - W_0)
+        static_assert(NV == 4, "characteristic variables need the Euler equations");
+        const real rho = (real)U0[0], uu = (real)(U0[1] / U0[0]), vv = (real)(U0[2] / U0[0]);
+        const real q2 = (real)0.5 * (uu * uu + vv * vv);
+        const real pr = (a.gamma - 1) * ((real)U0[3] - rho * q2);
+        const real cs = sqrt(a.gamma * pr / rho), H = ((real)U0[3] + pr) / rho;
+        const real b1 = (a.gamma - 1) / (cs * cs), b2 = b1 * q2, ic = (real)1 / cs;
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            real nx, ny, len;
+            uint32_t code;
+            face_record<real>(ptr.fr, i, f, nx, ny, len, code);
+            const real un = uu * nx + vv * ny, ut = -uu * ny + vv * nx;
+            const real L[4][4] = {{(real)0.5 * (b2 + un * ic), (real)-0.5 * (b1 * uu + nx * ic),
+                                   (real)-0.5 * (b1 * vv + ny * ic), (real)0.5 * b1},
+                                  {1 - b2, b1 * uu, b1 * vv, -b1},
+                                  {-ut, -ny, nx, 0},
+                                  {(real)0.5 * (b2 - un * ic), (real)-0.5 * (b1 * uu - nx * ic),
+                                   (real)-0.5 * (b1 * vv - ny * ic), (real)0.5 * b1}};
+            const real Rm[4][4] = {{1, 1, 0, 1},
+                                   {uu - cs * nx, uu, -ny, uu + cs * nx},
+                                   {vv - cs * ny, vv, nx, vv + cs * ny},
+                                   {H - un * cs, q2, ut, H + un * cs}};
+            real c1[K][4], cd[3][2][4];
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    real x = 0;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) x += L[j][v] * ao[k][v];
+                    c1[k][j] = x;
+                }
+#pragma unroll
+            for (int s2 = 0; s2 < 3; ++s2)
+#pragma unroll
+                for (int k = 0; k < 2; ++k)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        real x = 0;
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) x += L[j][v] * ad[s2][k][v];
+                        cd[s2][k][j] = x;
                     }
-                    ao[k][v] = x;
+            int bits[4];
+            finish_fields<real, K, 4, SCHEME, GFORM, DMODE>(a, c1, cd, fl, adm, st, lams, lratio,
+                                                            ptr.delta + (i * 3 + f) * 4, bits);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) dbyte[f * 4 + j] = (uint8_t)bits[j];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                real w[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) w[j] = 0;
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const real b = a.basis[f][q][k];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) w[j] += b * c1[k][j];
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    real x = 0;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) x += Rm[v][j] * w[j];
+                    out[f][q][v] = (real)(U0[v] + (double)x);
                 }
             }
-        } else {
-            constexpr int SEL = SCHEME == CTENO_SCHEME_TENO ? CTENO_SCHEME_CTENO : SCHEME;
-            constexpr int SGF = SCHEME == CTENO_SCHEME_TENO ? CTENO_GAMMA_PAPER : GFORM;
-#pragma unroll
-            for (int v = 0; v < NV; ++v)
-                bits[v] = teno_bits<real, SEL, SGF>(si[v], adm, st, a.lam1, lams, lratio, a.ct, a.eps);
         }
     }
-    uint32_t dword = 0;
-    // final coefficients, in place: p_1, or the mean of the selected
-    // directional polynomials
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        dword |= (uint32_t)bits[v] << (8 * v);
-        if (SCHEME != CTENO_SCHEME_CWENO && !(bits[v] & 1)) {
-            real s0 = 0, s1 = 0;
-            int cnt = 0;
-#pragma unroll
-            for (int q = 0; q < 3; ++q)
-                if ((bits[v] >> (q + 1)) & 1) { s0 += ad[q][0][v]; s1 += ad[q][1][v]; ++cnt; }
-            ao[0][v] = s0 / (real)cnt;
-            ao[1][v] = s1 / (real)cnt;
-#pragma unroll
-            for (int k = 2; k < K; ++k) ao[k][v] = 0;
-        }
-    }
-    // face Gauss-point values
-    real out[3][2][NV];
-#pragma unroll
-    for (int f = 0; f < 3; ++f)
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            real val[NV];
-#pragma unroll
-            for (int v = 0; v < NV; ++v) val[v] = 0;
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                const real b = a.basis[f][q][k];
-#pragma unroll
-                for (int v = 0; v < NV; ++v) val[v] += b * ao[k][v];
-            }
-#pragma unroll
-            for (int v = 0; v < NV; ++v) out[f][q][v] = (real)(U0[v] + (double)val[v]);
-        }
     if constexpr (NV == 4) {
         // positivity fallback: a cell with a non-physical state (density or
         // pressure <= 0) at any of its Gauss points uses its cell average at
@@ -825,23 +932,24 @@ __device__ __forceinline__ void recon_body(const ReconArgs<real, (R + 1) * (R + 
                 for (int q = 0; q < 2; ++q)
 #pragma unroll
                     for (int v = 0; v < NV; ++v) out[f][q][v] = (real)U0[v];
-            dword |= 0x80808080u;
+#pragma unroll
+            for (int k = 0; k < NB; ++k) dbyte[k] |= 0x80;
         }
     }
     if (DMODE == 1) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) ptr.delta[i * NV + v] = (uint8_t)(dword >> (8 * v));
+        for (int k = 0; k < NB; ++k) ptr.delta[i * NB + k] = dbyte[k];
     }
     store_row<real, 3 * 2 * NV>(ptr.FV + i * 3 * 2 * NV, &out[0][0][0]);
 }
 
-template <typename real, int R, int NV, int SCHEME, int GFORM, int DMODE>
+template <typename real, int R, int NV, int SCHEME, int GFORM, int DMODE, int VARS>
 __global__ __launch_bounds__(256) void k_reconstruct(const ReconArgs<real, (R + 1) * (R + 2) / 2 - 1> a) {
     const int64_t i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= a.N) return;
     if (a.done && *a.done) return;
-    const ReconPtrs<real> ptr{a.U, a.slot, a.flags, a.P, a.FV, a.delta};
-    recon_body<real, R, NV, SCHEME, GFORM, DMODE>(a, ptr, i);
+    const ReconPtrs<real> ptr{a.U, a.slot, a.flags, a.P, a.FV, a.delta, a.fr};
+    recon_body<real, R, NV, SCHEME, GFORM, DMODE, VARS>(a, ptr, i);
 }
 
 // scheme constants of the reconstruction (tables of the reference triangle,
@@ -866,6 +974,26 @@ static void fill_recon_constants(const DeviceMesh &m, ReconArgs<real, K> &a) {
     }
 }
 
+template <typename real, int R, int NV, int VARS>
+static void reconstruct_launch(const DeviceMesh &m, const ReconArgs<real, (R + 1) * (R + 2) / 2 - 1> &a, int dmode,
+                               unsigned grid, hipStream_t st) {
+#define CT_LAUNCH(SCH, GF, DM) \
+    hipLaunchKernelGGL((k_reconstruct<real, R, NV, SCH, GF, DM, VARS>), dim3(grid), dim3(256), 0, st, a)
+#define CT_DM(SCH, GF)                        \
+    switch (dmode) {                          \
+        case 0: CT_LAUNCH(SCH, GF, 0); break; \
+        case 1: CT_LAUNCH(SCH, GF, 1); break; \
+        default: CT_LAUNCH(SCH, GF, 2); break; \
+    }
+    if (m.scheme == CTENO_SCHEME_CTENOZ) { CT_DM(CTENO_SCHEME_CTENOZ, CTENO_GAMMA_PAPER); }
+    else if (m.scheme == CTENO_SCHEME_CWENO) { CT_DM(CTENO_SCHEME_CWENO, CTENO_GAMMA_PAPER); }
+    else if (m.scheme == CTENO_SCHEME_TENO) { CT_DM(CTENO_SCHEME_TENO, CTENO_GAMMA_PAPER); }
+    else if (m.gamma_form == CTENO_GAMMA_LAMBDA) { CT_DM(CTENO_SCHEME_CTENO, CTENO_GAMMA_LAMBDA); }
+    else { CT_DM(CTENO_SCHEME_CTENO, CTENO_GAMMA_PAPER); }
+#undef CT_DM
+#undef CT_LAUNCH
+}
+
 template <typename real, int R, int NV>
 static hipError_t reconstruct_t(const DeviceMesh &m, const double *U, void *FV, uint8_t *delta, int dmode,
                                 const int *done, hipStream_t st) {
@@ -881,22 +1009,20 @@ static hipError_t reconstruct_t(const DeviceMesh &m, const double *U, void *FV, 
     a.FV = (real *)FV;
     a.delta = delta;
     a.done = done;
+    if constexpr (std::is_same<real, double>::value) a.fr = m.fr64;
+    else a.fr = m.fr32;
     fill_recon_constants<real, K>(m, a);
     const unsigned grid = (unsigned)m.blocks();
-#define CT_LAUNCH(SCH, GF, DM) hipLaunchKernelGGL((k_reconstruct<real, R, NV, SCH, GF, DM>), dim3(grid), dim3(256), 0, st, a)
-#define CT_DM(SCH, GF)              \
-    switch (dmode) {                \
-        case 0: CT_LAUNCH(SCH, GF, 0); break; \
-        case 1: CT_LAUNCH(SCH, GF, 1); break; \
-        default: CT_LAUNCH(SCH, GF, 2); break; \
+    if (m.vars == CTENO_VARS_CHARACTERISTIC) {
+        if constexpr (NV == 4) {
+            if (!a.fr) return hipErrorInvalidValue;
+            reconstruct_launch<real, R, NV, 1>(m, a, dmode, grid, st);
+        } else {
+            return hipErrorInvalidValue;
+        }
+    } else {
+        reconstruct_launch<real, R, NV, 0>(m, a, dmode, grid, st);
     }
-    if (m.scheme == CTENO_SCHEME_CTENOZ) { CT_DM(CTENO_SCHEME_CTENOZ, CTENO_GAMMA_PAPER); }
-    else if (m.scheme == CTENO_SCHEME_CWENO) { CT_DM(CTENO_SCHEME_CWENO, CTENO_GAMMA_PAPER); }
-    else if (m.scheme == CTENO_SCHEME_TENO) { CT_DM(CTENO_SCHEME_TENO, CTENO_GAMMA_PAPER); }
-    else if (m.gamma_form == CTENO_GAMMA_LAMBDA) { CT_DM(CTENO_SCHEME_CTENO, CTENO_GAMMA_LAMBDA); }
-    else { CT_DM(CTENO_SCHEME_CTENO, CTENO_GAMMA_PAPER); }
-#undef CT_DM
-#undef CT_LAUNCH
     return hipGetLastError();
 }
 
@@ -1190,11 +1316,84 @@ struct ReconHoArgs {
     uint8_t *delta;
     const int *done;
     const real *tab;
+    const real *fr;          // face records (characteristic variables)
     real lams[5], lam_ratio[5];
     real lam1, ct, eps, gamma;
 };
 
-template <typename real, int R, int NV, int SCHEME, int GFORM, int DMODE>
+// one lane's field (a conserved variable, or a characteristic field on one
+// face): selection or CWENO weights and the final coefficients, in place in
+// c1[K] (p_1 on entry); cd[3][K_d] the directional coefficients
+template <typename real, int K, int KD, int SCHEME, int GFORM, int DMODE>
+__device__ __forceinline__ int finish_field_ho(const ReconHoArgs<real> a, real (&c1)[K], const real (&cd)[3][KD],
+                                               int fl, int adm, int st, real lams, real lratio, int forced) {
+    int bits;
+    if (DMODE == 2 && SCHEME != CTENO_SCHEME_CWENO) {
+        bits = forced & adm;
+    } else if (st == 1) {
+        bits = 1;
+    } else {
+        real si[4];
+        si[0] = 0;
+#pragma unroll
+        for (int p = 0; p < K; ++p) {
+            real rp = 0;
+#pragma unroll
+            for (int q = 0; q < K; ++q) rp += a.tab[p * K + q] * c1[q];
+            si[0] += c1[p] * rp;
+        }
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+            real sv = 0;
+#pragma unroll
+            for (int p = 0; p < KD; ++p) {
+                real rp = 0;
+#pragma unroll
+                for (int q = 0; q < KD; ++q) rp += a.tab[p * K + q] * cd[s][q];
+                sv += cd[s][p] * rp;
+            }
+            si[s + 1] = sv;
+        }
+        if constexpr (SCHEME == CTENO_SCHEME_CWENO) {
+            // every admissible stencil contributes: sum_s omega_s p_s, in place
+            bits = adm;
+            real w[4];
+            cweno_weights<real>(si, adm, lams, a.lam1, lratio, a.eps, w);
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                real x = w[0] * c1[k];
+                if (k < KD) {
+#pragma unroll
+                    for (int q = 0; q < 3; ++q)
+                        if ((fl >> q) & 1) x += w[q + 1] * cd[q][k];
+                }
+                c1[k] = x;
+            }
+        } else {
+            constexpr int SEL = SCHEME == CTENO_SCHEME_TENO ? CTENO_SCHEME_CTENO : SCHEME;
+            constexpr int SGF = SCHEME == CTENO_SCHEME_TENO ? CTENO_GAMMA_PAPER : GFORM;
+            bits = teno_bits<real, SEL, SGF>(si, adm, st, a.lam1, lams, lratio, a.ct, a.eps);
+        }
+    }
+    // final coefficients: p_1, or the mean of the selected directional polynomials
+    if (SCHEME != CTENO_SCHEME_CWENO && !(bits & 1)) {
+        int cnt = 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) c1[k] = 0;
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+            if ((bits >> (q + 1)) & 1) {
+                ++cnt;
+#pragma unroll
+                for (int k = 0; k < KD; ++k) c1[k] += cd[q][k];
+            }
+#pragma unroll
+        for (int k = 0; k < KD; ++k) c1[k] /= (real)cnt;
+    }
+    return bits;
+}
+
+template <typename real, int R, int NV, int SCHEME, int GFORM, int DMODE, int VARS>
 __global__ __launch_bounds__(256) void k_reconstruct_ho(const ReconHoArgs<real> a) {
     using D = HoDims<R>;
     constexpr int K = D::K, KD = D::KD, MD = D::MD, S = D::S, SP = D::SP, EPS = D::EPS, E = D::E, NQ = D::NQ;
@@ -1267,81 +1466,89 @@ __global__ __launch_bounds__(256) void k_reconstruct_ho(const ReconHoArgs<real> 
             ao[k] = st > 1 ? sm / a.lam1 : sm;
         }
     }
-    int bits;
-    if (DMODE == 2 && SCHEME != CTENO_SCHEME_CWENO) {
-        bits = a.delta[i * NV + v] & adm;
-    } else if (st == 1) {
-        bits = 1;
-    } else {
-        real si[4];
-        si[0] = 0;
-#pragma unroll
-        for (int p = 0; p < K; ++p) {
-            real rp = 0;
-#pragma unroll
-            for (int q = 0; q < K; ++q) rp += a.tab[p * K + q] * ao[q];
-            si[0] += ao[p] * rp;
-        }
-#pragma unroll
-        for (int s = 0; s < 3; ++s) {
-            real sv = 0;
-#pragma unroll
-            for (int p = 0; p < KD; ++p) {
-                real rp = 0;
-#pragma unroll
-                for (int q = 0; q < KD; ++q) rp += a.tab[p * K + q] * ad[s][q];
-                sv += ad[s][p] * rp;
-            }
-            si[s + 1] = sv;
-        }
-        if constexpr (SCHEME == CTENO_SCHEME_CWENO) {
-            // every admissible stencil contributes: sum_s omega_s p_s, in place
-            bits = adm;
-            real w[4];
-            cweno_weights<real>(si, adm, lams, a.lam1, lratio, a.eps, w);
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                real x = w[0] * ao[k];
-                if (k < KD) {
-#pragma unroll
-                    for (int q = 0; q < 3; ++q)
-                        if ((fl >> q) & 1) x += w[q + 1] * ad[q][k];
-                }
-                ao[k] = x;
-            }
-        } else {
-            constexpr int SEL = SCHEME == CTENO_SCHEME_TENO ? CTENO_SCHEME_CTENO : SCHEME;
-            constexpr int SGF = SCHEME == CTENO_SCHEME_TENO ? CTENO_GAMMA_PAPER : GFORM;
-            bits = teno_bits<real, SEL, SGF>(si, adm, st, a.lam1, lams, lratio, a.ct, a.eps);
-        }
-    }
-    // final coefficients: p_1, or the mean of the selected directional polynomials
-    if (SCHEME != CTENO_SCHEME_CWENO && !(bits & 1)) {
-        int cnt = 0;
-#pragma unroll
-        for (int k = 0; k < K; ++k) ao[k] = 0;
-#pragma unroll
-        for (int q = 0; q < 3; ++q)
-            if ((bits >> (q + 1)) & 1) {
-                ++cnt;
-#pragma unroll
-                for (int k = 0; k < KD; ++k) ao[k] += ad[q][k];
-            }
-#pragma unroll
-        for (int k = 0; k < KD; ++k) ao[k] /= (real)cnt;
-    }
-    // face Gauss-point values
     const real *Bt = a.tab + K * K;
     real out[3][NQ];
+    constexpr int NB = VARS ? 3 : 1;              // selection bytes of this lane
+    int dbyte[NB];
+    if constexpr (VARS == 0) {
+        dbyte[0] = finish_field_ho<real, K, KD, SCHEME, GFORM, DMODE>(a, ao, ad, fl, adm, st, lams, lratio,
+                                                                      DMODE == 2 ? a.delta[i * NV + v] : 0);
+        // face Gauss-point values
 #pragma unroll
-    for (int f = 0; f < 3; ++f)
+        for (int f = 0; f < 3; ++f)
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            real val = 0;
+            for (int q = 0; q < NQ; ++q) {
+                real val = 0;
 #pragma unroll
-            for (int k = 0; k < K; ++k) val += Bt[(f * NQ + q) * K + k] * ao[k];
-            out[f][q] = (real)(U0 + (double)val);
+                for (int k = 0; k < K; ++k) val += Bt[(f * NQ + q) * K + k] * ao[k];
+                out[f][q] = (real)(U0 + (double)val);
+            }
+    } else {
+        // characteristic fields per face, lane v reconstructs field v: the
+        // coefficients are projected with row v of L_f using the cell's
+        // other lanes, the face values come back through row v of R_f
+        static_assert(NV == 4, "characteristic variables need the Euler equations");
+        const int l0 = (threadIdx.x & 63) & ~3;
+        const double Ud[4] = {__shfl(U0, l0, 64), __shfl(U0, l0 + 1, 64), __shfl(U0, l0 + 2, 64),
+                              __shfl(U0, l0 + 3, 64)};
+        const real rho = (real)Ud[0], uu = (real)(Ud[1] / Ud[0]), vv = (real)(Ud[2] / Ud[0]);
+        const real q2 = (real)0.5 * (uu * uu + vv * vv);
+        const real pr = (a.gamma - 1) * ((real)Ud[3] - rho * q2);
+        const real cs = sqrt(a.gamma * pr / rho), H = ((real)Ud[3] + pr) / rho;
+        const real b1 = (a.gamma - 1) / (cs * cs), b2 = b1 * q2, ic = (real)1 / cs;
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            real nx, ny, len;
+            uint32_t code;
+            face_record<real>(a.fr, i, f, nx, ny, len, code);
+            const real un = uu * nx + vv * ny, ut = -uu * ny + vv * nx;
+            real Lr[4], Rr[4];      // row v of L_f and of R_f
+            if (v == 0) {
+                Lr[0] = (real)0.5 * (b2 + un * ic); Lr[1] = (real)-0.5 * (b1 * uu + nx * ic);
+                Lr[2] = (real)-0.5 * (b1 * vv + ny * ic); Lr[3] = (real)0.5 * b1;
+                Rr[0] = 1; Rr[1] = 1; Rr[2] = 0; Rr[3] = 1;
+            } else if (v == 1) {
+                Lr[0] = 1 - b2; Lr[1] = b1 * uu; Lr[2] = b1 * vv; Lr[3] = -b1;
+                Rr[0] = uu - cs * nx; Rr[1] = uu; Rr[2] = -ny; Rr[3] = uu + cs * nx;
+            } else if (v == 2) {
+                Lr[0] = -ut; Lr[1] = -ny; Lr[2] = nx; Lr[3] = 0;
+                Rr[0] = vv - cs * ny; Rr[1] = vv; Rr[2] = nx; Rr[3] = vv + cs * ny;
+            } else {
+                Lr[0] = (real)0.5 * (b2 - un * ic); Lr[1] = (real)-0.5 * (b1 * uu - nx * ic);
+                Lr[2] = (real)-0.5 * (b1 * vv - ny * ic); Lr[3] = (real)0.5 * b1;
+                Rr[0] = H - un * cs; Rr[1] = q2; Rr[2] = ut; Rr[3] = H + un * cs;
+            }
+            real c1[K], cd[3][KD];
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                real x = 0;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) x += Lr[u] * __shfl(ao[k], l0 + u, 64);
+                c1[k] = x;
+            }
+#pragma unroll
+            for (int s2 = 0; s2 < 3; ++s2)
+#pragma unroll
+                for (int k = 0; k < KD; ++k) {
+                    real x = 0;
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) x += Lr[u] * __shfl(ad[s2][k], l0 + u, 64);
+                    cd[s2][k] = x;
+                }
+            dbyte[f] = finish_field_ho<real, K, KD, SCHEME, GFORM, DMODE>(
+                a, c1, cd, fl, adm, st, lams, lratio, DMODE == 2 ? a.delta[(i * 3 + f) * NV + v] : 0);
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                real w = 0;
+#pragma unroll
+                for (int k = 0; k < K; ++k) w += Bt[(f * NQ + q) * K + k] * c1[k];
+                real x = 0;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) x += Rr[u] * __shfl(w, l0 + u, 64);
+                out[f][q] = (real)(U0 + (double)x);
+            }
         }
+    }
     if constexpr (NV == 4) {
         // positivity fallback (density or pressure <= 0 at a Gauss point):
         // the four lanes of the cell exchange their values
@@ -1361,10 +1568,17 @@ __global__ __launch_bounds__(256) void k_reconstruct_ho(const ReconHoArgs<real> 
             for (int f = 0; f < 3; ++f)
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) out[f][q] = (real)U0;
-            bits |= 0x80;
+#pragma unroll
+            for (int k = 0; k < NB; ++k) dbyte[k] |= 0x80;
         }
     }
-    if (DMODE == 1) a.delta[i * NV + v] = (uint8_t)bits;
+    if (DMODE == 1) {
+        if constexpr (VARS == 0) a.delta[i * NV + v] = (uint8_t)dbyte[0];
+        else {
+#pragma unroll
+            for (int f = 0; f < 3; ++f) a.delta[(i * 3 + f) * NV + v] = (uint8_t)dbyte[f];
+        }
+    }
 #pragma unroll
     for (int f = 0; f < 3; ++f)
 #pragma unroll
@@ -1383,6 +1597,9 @@ static hipError_t reconstruct_ho_t(const DeviceMesh &m, const double *U, void *F
     if constexpr (std::is_same<real, double>::value) { a.P = m.P64; a.tab = m.htab64; }
     else { a.P = m.P32; a.tab = m.htab32; }
     if (!a.P || !a.tab || m.stile != 64 / NV || m.E64 != D::E) return hipErrorInvalidValue;
+    if constexpr (std::is_same<real, double>::value) a.fr = m.fr64;
+    else a.fr = m.fr32;
+    if (m.vars == CTENO_VARS_CHARACTERISTIC && (NV != 4 || !a.fr)) return hipErrorInvalidValue;
     a.FV = (real *)FV;
     a.delta = delta;
     a.done = done;
@@ -1397,8 +1614,16 @@ static hipError_t reconstruct_ho_t(const DeviceMesh &m, const double *U, void *F
         a.lam_ratio[s] = s >= 2 ? (real)(lam1 / ls) : (real)1;
     }
     const unsigned grid = (unsigned)((m.N * NV + 255) / 256);
-#define HO_LAUNCH(SCH, GF, DM) \
-    hipLaunchKernelGGL((k_reconstruct_ho<real, R, NV, SCH, GF, DM>), dim3(grid), dim3(256), 0, st, a)
+#define HO_LAUNCH(SCH, GF, DM)                                                                               \
+    do {                                                                                                     \
+        if constexpr (NV == 4)                                                                               \
+            if (m.vars == CTENO_VARS_CHARACTERISTIC) {                                                       \
+                hipLaunchKernelGGL((k_reconstruct_ho<real, R, NV, SCH, GF, DM, 1>), dim3(grid), dim3(256), 0, st, \
+                                   a);                                                                       \
+                break;                                                                                       \
+            }                                                                                                \
+        hipLaunchKernelGGL((k_reconstruct_ho<real, R, NV, SCH, GF, DM, 0>), dim3(grid), dim3(256), 0, st, a);   \
+    } while (0)
 #define HO_DM(SCH, GF)                        \
     switch (dmode) {                          \
         case 0: HO_LAUNCH(SCH, GF, 0); break; \
@@ -1513,22 +1738,6 @@ struct FluxArgs {
     double gamma64;
     int stage;
 };
-
-// face record of local face f: unit normal, length, neighbour code
-template <typename real>
-__device__ __forceinline__ void face_record(const real *fr, int64_t i, int f, real &nx, real &ny, real &len,
-                                            uint32_t &code) {
-    if constexpr (std::is_same<real, float>::value) {
-        const float4 r = reinterpret_cast<const float4 *>(fr)[(size_t)(i >> 6) * 3 * 64 + f * 64 + (i & 63)];
-        nx = r.x; ny = r.y; len = r.z;
-        code = (uint32_t)__float_as_int(r.w);
-    } else {
-        const double2 *b = reinterpret_cast<const double2 *>(fr) + (size_t)(i >> 6) * 6 * 64 + (i & 63);
-        const double2 r0 = b[(2 * f) * 64], r1 = b[(2 * f + 1) * 64];
-        nx = r0.x; ny = r0.y; len = r1.x;
-        code = (uint32_t)__double_as_longlong(r1.y);
-    }
-}
 
 template <int NV, int PHYS>
 __device__ __forceinline__ double cell_dt_bound(const double *U, const double nrm[3][3], double area, double gamma,
@@ -1868,8 +2077,8 @@ __global__ __launch_bounds__(256) void k_reconstruct_batch(const ReconArgs<float
     if (t.ctrl->done) return;
     const int64_t i = (b - t.block0) * blockDim.x + threadIdx.x;
     if (i >= t.N) return;
-    const ReconPtrs<float> ptr{t.U[stage], t.slot, t.flags, t.P, t.FV, nullptr};
-    recon_body<float, R, 4, SCHEME, GFORM, 0>(a, ptr, i);
+    const ReconPtrs<float> ptr{t.U[stage], t.slot, t.flags, t.P, t.FV, nullptr, nullptr};
+    recon_body<float, R, 4, SCHEME, GFORM, 0, 0>(a, ptr, i);
 }
 
 __global__ __launch_bounds__(256) void k_flux_batch(const FluxArgs<float> a, const BatchSlot *tab, const int *n_slots) {
@@ -2005,11 +2214,13 @@ hipError_t launch_flux_to_user(const DeviceMesh &m, bool fp32, const void *fo, v
     return hipGetLastError();
 }
 hipError_t launch_delta_to_user(const DeviceMesh &m, const uint8_t *d, uint8_t *user, hipStream_t st) {
-    hipLaunchKernelGGL(k_rows_to_user<uint8_t>, dim3(grid_for(m.N)), dim3(256), 0, st, m.N, m.nv, m.perm, d, user);
+    hipLaunchKernelGGL(k_rows_to_user<uint8_t>, dim3(grid_for(m.N)), dim3(256), 0, st, m.N, m.delta_bytes(), m.perm, d,
+                       user);
     return hipGetLastError();
 }
 hipError_t launch_delta_from_user(const DeviceMesh &m, const uint8_t *user, uint8_t *d, hipStream_t st) {
-    hipLaunchKernelGGL(k_rows_from_user<uint8_t>, dim3(grid_for(m.N)), dim3(256), 0, st, m.N, m.nv, m.perm, user, d);
+    hipLaunchKernelGGL(k_rows_from_user<uint8_t>, dim3(grid_for(m.N)), dim3(256), 0, st, m.N, m.delta_bytes(), m.perm,
+                       user, d);
     return hipGetLastError();
 }
 
@@ -2022,7 +2233,7 @@ __global__ void k_count_diff(int64_t n, const uint8_t *a, const uint8_t *b, unsi
 }
 hipError_t launch_count_diff(const DeviceMesh &m, const uint8_t *a, const uint8_t *b, unsigned long long *count,
                              hipStream_t st) {
-    const int64_t n = m.N * m.nv;
+    const int64_t n = m.N * m.delta_bytes();
     hipLaunchKernelGGL(k_count_diff, dim3(grid_for(n)), dim3(256), 0, st, n, a, b, count);
     return hipGetLastError();
 }

@@ -234,6 +234,10 @@ static cteno_status check_scheme(const cteno_scheme &s) {
     if (!(s.lambda1_prime > 1.0) || !(s.c_t > 0 && s.c_t < 1) || !(s.eps > 0))
         return fail(CTENO_ERR_INVALID, "bad lambda1_prime, c_t or eps");
     if (s.physics == CTENO_EULER && !(s.gamma > 1.0)) return fail(CTENO_ERR_INVALID, "bad gamma");
+    if (s.variables != CTENO_VARS_CONSERVED && s.variables != CTENO_VARS_CHARACTERISTIC)
+        return fail(CTENO_ERR_INVALID, "bad variables");
+    if (s.variables == CTENO_VARS_CHARACTERISTIC && s.physics != CTENO_EULER)
+        return fail(CTENO_ERR_INVALID, "characteristic variables need the Euler equations");
     return CTENO_OK;
 }
 
@@ -255,6 +259,7 @@ static cteno_status upload_device_mesh(cteno_ctx *ctx, hipStream_t st, HostMesh 
     dm.Kd = hm.Kd; dm.Md = hm.Md; dm.Nq = hm.Nq;
     dm.stile = hm.r >= 4 ? kTile / hm.nv : kTile;
     dm.physics = s.physics; dm.scheme = s.scheme; dm.gamma_form = s.gamma_form; dm.precision = s.precision;
+    dm.vars = s.variables;
     dm.gamma = s.gamma; dm.ax = s.ax; dm.ay = s.ay; dm.lam1p = s.lambda1_prime; dm.ct = s.c_t; dm.eps = s.eps;
     dm.Lx = hm.Lx; dm.Ly = hm.Ly;
     make_ref_tables(hm.r, dm.tab);
@@ -600,7 +605,7 @@ extern "C" cteno_status cteno_reconstruct(cteno_ctx *ctx, const cteno_mesh *m, c
     DevBuf dbuf;
     int dmode = 0;
     if (delta_forced || delta_out) {
-        dbuf = DevBuf(ctx, (size_t)dm.Np * dm.nv);
+        dbuf = DevBuf(ctx, (size_t)dm.Np * dm.delta_bytes());
         if (!dbuf.p) return fail(CTENO_ERR_NOMEM, "device allocation failed");
         if (delta_forced) {
             HIP_TRY(launch_delta_from_user(dm, delta_forced, dbuf.as<uint8_t>(), st));
@@ -796,7 +801,8 @@ extern "C" cteno_status cteno_count_flips(cteno_ctx *ctx, const cteno_mesh *m, c
     const DeviceMesh &dm = m->dm;
     hipStream_t st = ctx->stream();
     cteno_sol *s = const_cast<cteno_sol *>(sol);
-    DevBuf d64(ctx, (size_t)dm.Np * dm.nv), d32(ctx, (size_t)dm.Np * dm.nv), cnt(ctx, sizeof(unsigned long long));
+    DevBuf d64(ctx, (size_t)dm.Np * dm.delta_bytes()), d32(ctx, (size_t)dm.Np * dm.delta_bytes()),
+        cnt(ctx, sizeof(unsigned long long));
     void *fv64 = s->fv(false), *fv32 = s->fv(true);
     if (!d64.p || !d32.p || !cnt.p || !fv64 || !fv32) return fail(CTENO_ERR_NOMEM, "device allocation failed");
     HIP_TRY(launch_reconstruct(dm, false, s->U[0].as<double>(), fv64, d64.as<uint8_t>(), 1, nullptr, st));
@@ -1128,6 +1134,7 @@ extern "C" cteno_status cteno_server_create(cteno_ctx *ctx, const cteno_scheme *
     if (cteno_status rc = check_scheme(*scheme)) return rc;
     if (scheme->physics != CTENO_EULER) return fail(CTENO_ERR_INVALID, "serving runs the Euler equations");
     if (scheme->degree > 3) return fail(CTENO_ERR_INVALID, "serving runs degree 2 or 3");
+    if (scheme->variables != CTENO_VARS_CONSERVED) return fail(CTENO_ERR_INVALID, "serving runs conserved variables");
     if (max_slots < 1 || max_slots > 1024) return fail(CTENO_ERR_INVALID, "max_slots must be 1..1024");
     if (hbm_budget_bytes < (1u << 20)) return fail(CTENO_ERR_INVALID, "budget too small");
     HIP_TRY(hipSetDevice(ctx->device));

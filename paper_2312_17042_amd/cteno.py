@@ -20,6 +20,7 @@ OK, ERR_INVALID, ERR_MESH, ERR_STENCIL, ERR_NOMEM, ERR_DEVICE, ERR_NONPHYSICAL, 
 PERIODIC, WALL, TRANSMISSIVE = 0, 1, 2
 ADVECTION, EULER = 0, 1
 CTENO, CTENOZ, CWENO, TENO = 0, 1, 2, 3
+CONSERVED, CHARACTERISTIC = 0, 1
 GAMMA_PAPER, GAMMA_LAMBDA = 0, 1
 FP64, MIXED, BOTH = 1, 2, 3
 KERNEL_RECONSTRUCT, KERNEL_FLUX, KERNEL_PRECOMPUTE = 0, 1, 2
@@ -39,7 +40,8 @@ class MeshDesc(C.Structure):
 class Scheme(C.Structure):
     _fields_ = [("physics", C.c_int32), ("ax", C.c_double), ("ay", C.c_double), ("gamma", C.c_double),
                 ("scheme", C.c_int32), ("degree", C.c_int32), ("lambda1_prime", C.c_double), ("c_t", C.c_double),
-                ("eps", C.c_double), ("gamma_form", C.c_int32), ("precision", C.c_int32), ("reorder", C.c_int32)]
+                ("eps", C.c_double), ("gamma_form", C.c_int32), ("precision", C.c_int32), ("reorder", C.c_int32),
+                ("variables", C.c_int32)]
 
 
 class MeshInfo(C.Structure):
@@ -174,8 +176,9 @@ class Context:
 
 
 def make_scheme(physics=EULER, scheme=CTENOZ, degree=3, lambda1_prime=1e4, c_t=1e-6, eps=1e-12, gamma=1.4,
-                ax=1.0, ay=1.0, gamma_form=GAMMA_PAPER, precision=FP64, reorder=1) -> Scheme:
-    return Scheme(physics, ax, ay, gamma, scheme, degree, lambda1_prime, c_t, eps, gamma_form, precision, reorder)
+                ax=1.0, ay=1.0, gamma_form=GAMMA_PAPER, precision=FP64, reorder=1, variables=0) -> Scheme:
+    return Scheme(physics, ax, ay, gamma, scheme, degree, lambda1_prime, c_t, eps, gamma_form, precision, reorder,
+                  variables)
 
 
 class Mesh:
@@ -286,7 +289,8 @@ class Solution:
         m = self.mesh
         dt = torch.float64 if precision == FP64 else torch.float32
         fv = torch.empty((m.N, 3, m.nq, m.nv), dtype=dt, device=f"cuda:{self.ctx.device}")
-        dl = torch.empty((m.N, m.nv), dtype=torch.uint8, device=fv.device) if want_delta else None
+        dshape = (m.N, 3, m.nv) if m.scheme.variables == CHARACTERISTIC else (m.N, m.nv)
+        dl = torch.empty(dshape, dtype=torch.uint8, device=fv.device) if want_delta else None
         fr = None
         if forced is not None:
             fr = torch.as_tensor(np.ascontiguousarray(forced, np.uint8)).to(fv.device)
