@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcteno_oracle.so")
 SRC_PATH = os.path.join(HERE, "cteno_oracle.c")
 
-PERIODIC, WALL, TRANSMISSIVE = 0, 1, 2
+PERIODIC, WALL, TRANSMISSIVE, INFLOW = 0, 1, 2, 3
 ADVECTION, EULER = 0, 1
 CTENO, CTENOZ, CWENO, TENO = 0, 1, 2, 3
 GAMMA_PAPER, GAMMA_LAMBDA = 0, 1
@@ -39,6 +39,21 @@ class _Scheme(C.Structure):
                 ("variables", C.c_int)]
 
 
+class _Boundary(C.Structure):
+    _fields_ = [("behind", C.c_double * 4), ("ahead", C.c_double * 4), ("line", C.c_double * 3),
+                ("split_kind", C.c_int * 4), ("split_at", C.c_double * 4)]
+
+
+def _boundary(b):
+    """ctypes copy of an object with behind, ahead, line, split_kind and
+    split_at (None: no inflow sides, no switches)."""
+    if b is None:
+        return None
+    pad = lambda v, n: list(v) + [0.0] * (n - len(v))
+    return _Boundary((C.c_double * 4)(*pad(b.behind, 4)), (C.c_double * 4)(*pad(b.ahead, 4)),
+                     (C.c_double * 3)(*b.line), (C.c_int * 4)(*b.split_kind), (C.c_double * 4)(*b.split_at))
+
+
 _lib = None
 
 
@@ -50,7 +65,7 @@ def lib():
         L = C.CDLL(LIB_PATH)
         P = C.c_void_p
         L.or_create.restype = P
-        L.or_create.argtypes = [C.c_int, P, C.c_int, P, P, P, C.POINTER(_Scheme)]
+        L.or_create.argtypes = [C.c_int, P, C.c_int, P, P, P, C.POINTER(_Scheme), C.POINTER(_Boundary)]
         L.or_destroy.argtypes = [P]
         L.or_last_error.restype = C.c_char_p
         L.or_dims.argtypes = [P] + [C.POINTER(C.c_int)] * 6
@@ -68,12 +83,12 @@ def lib():
         L.or_euler_flux.argtypes = [C.c_double, P, C.c_double, C.c_double, P]
         L.or_reconstruct.argtypes = [P, P, P, P, P, P]
         L.or_reconstruct_cells.argtypes = [P, P, C.c_int, P, P, P]
-        L.or_face_fluxes.argtypes = [P, P, P]
-        L.or_residual_cells.argtypes = [P, P, C.c_int, P, P]
-        L.or_residual.argtypes = [P, P, P]
+        L.or_face_fluxes.argtypes = [P, P, C.c_double, P]
+        L.or_residual_cells.argtypes = [P, P, C.c_double, C.c_int, P, P]
+        L.or_residual.argtypes = [P, P, C.c_double, P]
         L.or_dt_bound.restype = C.c_double
         L.or_dt_bound.argtypes = [P, P]
-        L.or_rk3_step.argtypes = [P, P, C.c_double]
+        L.or_rk3_step.argtypes = [P, P, C.c_double, C.c_double]
         L.or_solve.argtypes = [P, P, C.c_double, C.c_double, C.c_int, C.c_double,
                                C.POINTER(C.c_int), C.POINTER(C.c_double)]
         _lib = L
@@ -93,15 +108,16 @@ class Oracle:
 
     def __init__(self, xy, tri, box, bc, physics=EULER, scheme=CTENOZ, degree=3,
                  lambda1_prime=1e4, c_t=1e-6, eps=1e-12, gamma=1.4, ax=1.0, ay=1.0,
-                 gamma_form=GAMMA_PAPER, variables=CONSERVED):
+                 gamma_form=GAMMA_PAPER, variables=CONSERVED, boundary=None):
         L = lib()
         self._xy = np.ascontiguousarray(xy, dtype=np.float64)
         self._tri = np.ascontiguousarray(tri, dtype=np.int32)
         box = np.ascontiguousarray(box, dtype=np.float64)
         bc = np.ascontiguousarray(bc, dtype=np.int32)
         s = _Scheme(physics, ax, ay, gamma, scheme, degree, gamma_form, lambda1_prime, c_t, eps, variables)
+        bnd = _boundary(boundary)
         h = L.or_create(self._xy.shape[0], _p(self._xy), self._tri.shape[0], _p(self._tri), _p(box), _p(bc),
-                        C.byref(s))
+                        C.byref(s), C.byref(bnd) if bnd is not None else None)
         if not h:
             raise OracleError(L.or_last_error().decode())
         self.h = h
@@ -116,6 +132,7 @@ class Oracle:
 
     @classmethod
     def from_mesh(cls, mesh, **kw):
+        kw.setdefault("boundary", getattr(mesh, "boundary", None))
         return cls(mesh.xy, mesh.tri, mesh.box, mesh.bc, **kw)
 
     def __del__(self):
@@ -205,33 +222,34 @@ class Oracle:
         self._check(lib().or_reconstruct_cells(self.h, _p(U), n, _p(cells), _p(fv), _p(dl)))
         return fv, dl
 
-    def residual_cells(self, U, cells):
-        """Residual of selected cells only, R[n][nv] (reconstructs only what it needs)."""
+    def residual_cells(self, U, cells, t=0.0):
+        """Residual of selected cells only at time t (the time of inflow
+        boundary states), R[n][nv] (reconstructs only what it needs)."""
         U = np.ascontiguousarray(U, np.float64).reshape(self.nv, self.N)
         cells = np.ascontiguousarray(cells, np.int32)
         R = np.empty((cells.shape[0], self.nv))
-        self._check(lib().or_residual_cells(self.h, _p(U), cells.shape[0], _p(cells), _p(R)))
+        self._check(lib().or_residual_cells(self.h, _p(U), float(t), cells.shape[0], _p(cells), _p(R)))
         return R
 
-    def face_fluxes(self, fv):
+    def face_fluxes(self, fv, t=0.0):
         fv = np.ascontiguousarray(fv, np.float64)
         fo = np.empty((self.N, 3, self.nv))
-        self._check(lib().or_face_fluxes(self.h, _p(fv), _p(fo)))
+        self._check(lib().or_face_fluxes(self.h, _p(fv), float(t), _p(fo)))
         return fo
 
-    def residual(self, U):
+    def residual(self, U, t=0.0):
         U = np.ascontiguousarray(U, np.float64).reshape(self.nv, self.N)
         R = np.empty((self.nv, self.N))
-        self._check(lib().or_residual(self.h, _p(U), _p(R)))
+        self._check(lib().or_residual(self.h, _p(U), float(t), _p(R)))
         return R
 
     def dt_bound(self, U):
         U = np.ascontiguousarray(U, np.float64).reshape(self.nv, self.N)
         return lib().or_dt_bound(self.h, _p(U))
 
-    def rk3_step(self, U, dt):
+    def rk3_step(self, U, dt, t=0.0):
         U = np.array(U, dtype=np.float64, order="C").reshape(self.nv, self.N)
-        self._check(lib().or_rk3_step(self.h, _p(U), float(dt)))
+        self._check(lib().or_rk3_step(self.h, _p(U), float(t), float(dt)))
         return U
 
     def solve(self, U, t_final, cfl=0.3, t0=0.0, max_steps=1 << 30):

@@ -72,7 +72,7 @@
 #define OR_MAXNQ 4
 #define OR_MAXNV 4
 
-enum { OR_PERIODIC = 0, OR_WALL = 1, OR_TRANSMISSIVE = 2 };
+enum { OR_PERIODIC = 0, OR_WALL = 1, OR_TRANSMISSIVE = 2, OR_INFLOW = 3 };
 enum { OR_ADVECTION = 0, OR_EULER = 1 };
 enum { OR_CTENO = 0, OR_CTENOZ = 1, OR_CWENO = 2, OR_TENO = 3 };
 enum { OR_GAMMA_PAPER = 0, OR_GAMMA_LAMBDA = 1 };
@@ -105,6 +105,12 @@ typedef struct {
     int *canon;        /* canonical vertex id after periodic welding */
     double box[4];
     int bc[4];
+    /* prescribed outside states of inflow faces: bs[0] where
+       x < bline[0] + bline[1] y + bline[2] t, else bs[1]; a side k may switch
+       to kind split_kind[k] (0 = no switch) below split_at[k] */
+    double bs[2][OR_MAXNV], bline[3];
+    int split_kind[4];
+    double split_at[4];
     int per_x, per_y;
     double Lx, Ly;
     int physics, nv;
@@ -285,7 +291,11 @@ static int build_mesh(or_ctx *c) {
             else if (fabs(my - c->box[3]) <= tol) side = 3;
             if (side < 0) { set_err("open edge not on the box boundary", i); free(E); return 0; }
             if (c->bc[side] == OR_PERIODIC) { set_err("unmatched edge on a periodic side", i); free(E); return 0; }
-            c->fnb[3 * i + f] = -1; c->fnbf[3 * i + f] = -1; c->fbc[3 * i + f] = c->bc[side];
+            int kind = c->bc[side];
+            /* coordinate along the side: y on the sides x = const, x on the others */
+            double along = side < 2 ? my : mx;
+            if (c->split_kind[side] != 0 && along < c->split_at[side]) kind = c->split_kind[side];
+            c->fnb[3 * i + f] = -1; c->fnbf[3 * i + f] = -1; c->fbc[3 * i + f] = kind;
         } else {
             set_err("edge shared by more than two cells", E[k].cell); free(E); return 0;
         }
@@ -931,7 +941,17 @@ static int point_flux(const or_ctx *c, const double *UL, const double *UR, doubl
     return hllc(c->gam, UL, UR, nx, ny, F);
 }
 
-static void ghost(const or_ctx *c, int kind, const double *UL, double nx, double ny, double *UR) {
+/* outside state of a boundary face at its Gauss point (px, py) and time t:
+   wall = mirror image of the inside state (normal momentum reversed),
+   transmissive = the inside state, inflow = the prescribed state on the
+   point's side of the moving line */
+static void ghost(const or_ctx *c, int kind, const double *UL, double nx, double ny, double px, double py, double t,
+                  double *UR) {
+    if (kind == OR_INFLOW) {
+        int behind = px < c->bline[0] + c->bline[1] * py + c->bline[2] * t;
+        for (int v = 0; v < c->nv; ++v) UR[v] = c->bs[behind ? 0 : 1][v];
+        return;
+    }
     for (int v = 0; v < c->nv; ++v) UR[v] = UL[v];
     if (kind == OR_WALL && c->physics == OR_EULER) {
         double mn = UL[1] * nx + UL[2] * ny;
@@ -940,9 +960,16 @@ static void ghost(const or_ctx *c, int kind, const double *UL, double nx, double
     }
 }
 
+/* position of Gauss point q of face f of cell i (from vertex f to f+1) */
+static void gauss_point(const or_ctx *c, int i, int f, int q, double *px, double *py) {
+    int a = c->tri[3 * i + f], b = c->tri[3 * i + (f + 1) % 3];
+    *px = c->xy[2 * a] + c->gq[q] * (c->xy[2 * b] - c->xy[2 * a]);
+    *py = c->xy[2 * a + 1] + c->gq[q] * (c->xy[2 * b + 1] - c->xy[2 * a + 1]);
+}
+
 /* outward, quadrature-integrated flux of every cell face: fo[N][3][nv].
    Each interior face is evaluated once, from its lower-numbered cell. */
-static int face_fluxes(or_ctx *c, const double *fv, double *fo) {
+static int face_fluxes(or_ctx *c, const double *fv, double t, double *fo) {
     int N = c->N, nv = c->nv, Nq = c->Nq;
     int err = 0;
 #pragma omp parallel for schedule(static) reduction(| : err)
@@ -960,7 +987,9 @@ static int face_fluxes(or_ctx *c, const double *fv, double *fo) {
                     const double *p = fv + (((size_t)j * 3 + g) * Nq + (Nq - 1 - q)) * nv;
                     for (int v = 0; v < nv; ++v) UR[v] = p[v];
                 } else {
-                    ghost(c, c->fbc[3 * i + f], UL, nx, ny, UR);
+                    double px, py;
+                    gauss_point(c, i, f, q, &px, &py);
+                    ghost(c, c->fbc[3 * i + f], UL, nx, ny, px, py, t, UR);
                 }
                 err |= point_flux(c, UL, UR, nx, ny, F);
                 for (int v = 0; v < nv; ++v) acc[v] += c->gw[q] * F[v];
@@ -995,8 +1024,16 @@ void or_destroy(or_ctx *c) {
     free(c);
 }
 
+/* boundary data of inflow faces (see or_ctx) */
+typedef struct {
+    double behind[4], ahead[4];
+    double line[3];
+    int split_kind[4];
+    double split_at[4];
+} or_boundary;
+
 or_ctx *or_create(int nvert, const double *xy, int ncell, const int *tri, const double *box, const int *bc,
-                  const or_scheme *sch) {
+                  const or_scheme *sch, const or_boundary *bnd) {
     or_err[0] = 0;
     if (nvert <= 0 || ncell <= 0 || !xy || !tri || !box || !bc || !sch) { set_err("bad arguments", 0); return NULL; }
     if (sch->degree < 1 || sch->degree > OR_MAXR) { set_err("degree must be 1..6", sch->degree); return NULL; }
@@ -1008,12 +1045,36 @@ or_ctx *or_create(int nvert, const double *xy, int ncell, const int *tri, const 
     if ((bc[0] == OR_PERIODIC) != (bc[1] == OR_PERIODIC) || (bc[2] == OR_PERIODIC) != (bc[3] == OR_PERIODIC)) {
         set_err("periodic sides must come in pairs", 0); or_destroy(c); return NULL;
     }
+    if (bnd) {
+        for (int v = 0; v < OR_MAXNV; ++v) { c->bs[0][v] = bnd->behind[v]; c->bs[1][v] = bnd->ahead[v]; }
+        for (int k = 0; k < 3; ++k) c->bline[k] = bnd->line[k];
+        for (int k = 0; k < 4; ++k) { c->split_kind[k] = bnd->split_kind[k]; c->split_at[k] = bnd->split_at[k]; }
+    }
+    for (int k = 0; k < 4; ++k) {
+        if (bc[k] < 0 || bc[k] > OR_INFLOW || c->split_kind[k] < 0 || c->split_kind[k] > OR_INFLOW) {
+            set_err("bad boundary kind on side", k); or_destroy(c); return NULL;
+        }
+        if (c->split_kind[k] != 0 && bc[k] == OR_PERIODIC) {
+            set_err("a periodic side cannot switch kind", k); or_destroy(c); return NULL;
+        }
+    }
     c->per_x = bc[0] == OR_PERIODIC; c->per_y = bc[2] == OR_PERIODIC;
     c->Lx = box[1] - box[0]; c->Ly = box[3] - box[2];
     c->physics = sch->physics; c->nv = sch->physics == OR_EULER ? 4 : 1;
     if (sch->physics == OR_ADVECTION)
-        for (int k = 0; k < 4; ++k) if (bc[k] == OR_WALL) { set_err("walls need the Euler equations", k); or_destroy(c); return NULL; }
+        for (int k = 0; k < 4; ++k)
+            if (bc[k] == OR_WALL || c->split_kind[k] == OR_WALL) {
+                set_err("walls need the Euler equations", k); or_destroy(c); return NULL;
+            }
     c->ax = sch->ax; c->ay = sch->ay; c->gam = sch->gamma;
+    int inflow = 0;
+    for (int k = 0; k < 4; ++k) inflow |= bc[k] == OR_INFLOW || c->split_kind[k] == OR_INFLOW;
+    if (inflow && c->physics == OR_EULER)
+        for (int s = 0; s < 2; ++s) {
+            const double *b = c->bs[s];
+            double p = (c->gam - 1.0) * (b[3] - 0.5 * (b[1] * b[1] + b[2] * b[2]) / b[0]);
+            if (!(b[0] > 0.0) || !(p > 0.0)) { set_err("non-physical inflow state", s); or_destroy(c); return NULL; }
+        }
     c->scheme = sch->scheme; c->r = sch->degree; c->gamma_form = sch->gamma_form;
     c->vars = sch->variables;
     if (c->vars == OR_VARS_CHARACTERISTIC && c->physics != OR_EULER) {
@@ -1215,7 +1276,7 @@ int or_reconstruct_cells(or_ctx *c, const double *U, int n, const int *cells, do
 /* residual of selected cells only: each sampled cell and its face
    neighbours are reconstructed, the three face fluxes formed as in
    face_fluxes (owner = lower cell id), R[n][nv] */
-int or_residual_cells(or_ctx *c, const double *U, int n, const int *cells, double *R) {
+int or_residual_cells(or_ctx *c, const double *U, double t, int n, const int *cells, double *R) {
     int nv = c->nv, Nq = c->Nq;
     size_t per = (size_t)3 * Nq * nv;
     double *own = malloc(sizeof(double) * per), *nbf = malloc(sizeof(double) * per);
@@ -1245,7 +1306,9 @@ int or_residual_cells(or_ctx *c, const double *U, int n, const int *cells, doubl
                     const double *p = xfv + ((size_t)xf * Nq + (Nq - 1 - q)) * nv;
                     for (int v = 0; v < nv; ++v) UR[v] = p[v];
                 } else {
-                    ghost(c, c->fbc[3 * i + f], UL, nx, ny, UR);
+                    double px, py;
+                    gauss_point(c, i, f, q, &px, &py);
+                    ghost(c, c->fbc[3 * i + f], UL, nx, ny, px, py, t, UR);
                 }
                 rc |= point_flux(c, UL, UR, nx, ny, F);
                 for (int v = 0; v < nv; ++v) facc[v] += c->gw[q] * F[v];
@@ -1261,8 +1324,8 @@ int or_residual_cells(or_ctx *c, const double *U, int n, const int *cells, doubl
     return rc;
 }
 
-int or_face_fluxes(or_ctx *c, const double *fv, double *fo) {
-    int rc = face_fluxes(c, fv, fo);
+int or_face_fluxes(or_ctx *c, const double *fv, double t, double *fo) {
+    int rc = face_fluxes(c, fv, t, fo);
     if (rc) set_err("non-physical face state", rc);
     return rc;
 }
@@ -1281,22 +1344,22 @@ static void residual_from_fluxes(const or_ctx *c, const double *fo, double *R) {
 
 typedef struct { double *fv, *fo; uint8_t *delta; } or_work;
 
-static int residual(or_ctx *c, const double *U, double *R, or_work *w) {
+static int residual(or_ctx *c, const double *U, double t, double *R, or_work *w) {
     int rc = or_reconstruct(c, U, NULL, w->fv, w->delta, NULL);
     if (rc) return rc;
-    rc = or_face_fluxes(c, w->fv, w->fo);
+    rc = or_face_fluxes(c, w->fv, t, w->fo);
     if (rc) return rc;
     residual_from_fluxes(c, w->fo, R);
     return 0;
 }
 
-int or_residual(or_ctx *c, const double *U, double *R) {
+int or_residual(or_ctx *c, const double *U, double t, double *R) {
     size_t N = c->N;
     or_work w;
     w.fv = malloc(sizeof(double) * N * 3 * c->Nq * c->nv);
     w.fo = malloc(sizeof(double) * N * 3 * c->nv);
     w.delta = malloc((size_t)N * 3 * c->nv);
-    int rc = residual(c, U, R, &w);
+    int rc = residual(c, U, t, R, &w);
     free(w.fv); free(w.fo); free(w.delta);
     return rc;
 }
@@ -1326,22 +1389,23 @@ double or_dt_bound(or_ctx *c, const double *U) {
     return best;
 }
 
-/* one Shu-Osher SSP-RK3 step of size dt, in place on U[nv][N] */
-int or_rk3_step(or_ctx *c, double *U, double dt) {
+/* one Shu-Osher SSP-RK3 step of size dt from time t, in place on U[nv][N];
+   the three residuals are those of the stage times t, t + dt and t + dt/2 */
+int or_rk3_step(or_ctx *c, double *U, double t, double dt) {
     size_t n = (size_t)c->N * c->nv;
     double *U1 = malloc(sizeof(double) * n), *U2 = malloc(sizeof(double) * n), *R = malloc(sizeof(double) * n);
     or_work w;
     w.fv = malloc(sizeof(double) * (size_t)c->N * 3 * c->Nq * c->nv);
     w.fo = malloc(sizeof(double) * (size_t)c->N * 3 * c->nv);
     w.delta = malloc((size_t)c->N * 3 * c->nv);
-    int rc = residual(c, U, R, &w);
+    int rc = residual(c, U, t, R, &w);
     if (!rc) {
         for (size_t k = 0; k < n; ++k) U1[k] = U[k] + dt * R[k];
-        rc = residual(c, U1, R, &w);
+        rc = residual(c, U1, t + dt, R, &w);
     }
     if (!rc) {
         for (size_t k = 0; k < n; ++k) U2[k] = 0.75 * U[k] + 0.25 * (U1[k] + dt * R[k]);
-        rc = residual(c, U2, R, &w);
+        rc = residual(c, U2, t + 0.5 * dt, R, &w);
     }
     if (!rc)
         for (size_t k = 0; k < n; ++k) U[k] = (1.0 / 3.0) * U[k] + (2.0 / 3.0) * (U2[k] + dt * R[k]);
@@ -1360,7 +1424,7 @@ int or_solve(or_ctx *c, double *U, double t0, double t_final, int max_steps, dou
         double dt = cfl * or_dt_bound(c, U);
         double tn = t + dt;
         if (dt >= t_final - t) { dt = t_final - t; tn = t_final; }
-        rc = or_rk3_step(c, U, dt);
+        rc = or_rk3_step(c, U, t, dt);
         if (rc) break;
         t = tn;
         ++n;

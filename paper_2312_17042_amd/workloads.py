@@ -25,8 +25,28 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-PERIODIC, WALL, TRANSMISSIVE = 0, 1, 2
+PERIODIC, WALL, TRANSMISSIVE, INFLOW = 0, 1, 2, 3
 ADVECTION, EULER = 0, 1
+
+
+@dataclass
+class Boundary:
+    """Prescribed outside states of INFLOW faces: `behind` (conserved
+    variables) at points with x < line[0] + line[1] y + line[2] t, `ahead`
+    elsewhere; a side k switches to kind split_kind[k] (0 = no switch) where
+    its coordinate along the side (y on the sides x = const, x on the others)
+    is below split_at[k]."""
+    behind: tuple = (0.0, 0.0, 0.0, 0.0)
+    ahead: tuple = (0.0, 0.0, 0.0, 0.0)
+    line: tuple = (0.0, 0.0, 0.0)
+    split_kind: tuple = (0, 0, 0, 0)
+    split_at: tuple = (0.0, 0.0, 0.0, 0.0)
+
+
+def constant_inflow(state):
+    """One prescribed state on every INFLOW side."""
+    st = tuple(float(v) for v in state)
+    return Boundary(behind=st, ahead=st)
 
 
 @dataclass
@@ -39,6 +59,7 @@ class Mesh:
     ny: int
     seed: int
     meta: dict = field(default_factory=dict)
+    boundary: Boundary | None = None
 
     @property
     def n_cells(self) -> int:
@@ -368,6 +389,82 @@ def density_wave_case(n=20, seed=11, gamma=1.4):
     m = split_jitter_mesh(n, n, (0.0, 1.0, 0.0, 1.0), seed=seed)
     u0 = cell_average(m, density_wave(0.0, gamma))
     return m, u0
+
+
+def shock_density(gamma=1.4):
+    """Shock-density wave interaction (sec. 3.1.2): a Mach 3 shock at x = -4
+    moving into rho = 1 + 0.2 sin(5x), u = 0, p = 1."""
+    def f(X, Y):
+        left = X < -4.0
+        rho = np.where(left, 3.857143, 1.0 + 0.2 * np.sin(5.0 * X))
+        u = np.where(left, 2.629369, 0.0)
+        p = np.where(left, 10.33333, 1.0)
+        return prim_to_cons(rho, u, 0.0 * X, p, gamma)
+    return f
+
+
+SHOCK_DENSITY_POST = (3.857143, 2.629369, 10.33333)   # rho, u, p behind the Mach 3 shock
+
+
+def shock_density_case(nx=200, ny=40, seed=12, gamma=1.4, quad=6, inflow=True):
+    """The shock-density wave on [-5, 5] x [0, 2]: supersonic inflow of the
+    post-shock state at x = -5 (a prescribed-state side; inflow=False makes it
+    transmissive), transmissive outflow at x = 5, walls in y.  nx x ny squares,
+    2 nx ny cells; 200 x 40 gives h = 1/20 as in the paper."""
+    left = INFLOW if inflow else TRANSMISSIVE
+    m = split_jitter_mesh(nx, ny, (-5.0, 5.0, 0.0, 2.0), seed=seed, bc=(left, TRANSMISSIVE, WALL, WALL))
+    rho, u, p = SHOCK_DENSITY_POST
+    m.boundary = constant_inflow(prim_to_cons(rho, u, 0.0, p, gamma))
+    u0 = cell_average(m, shock_density(gamma), n=quad)
+    return m, u0
+
+
+# double Mach reflection (sec. 3.4): states and the incident shock line as the
+# paper gives them (shock foot at x = 0.1667, slope 1.732, Mach 10 into gas at
+# rest with unit sound speed, so the foot moves at 10 / sin 60 = 20 / 1.732),
+# except the post-shock pressure: the Mach 10 jump gives 116.5, the paper
+# prints 116.8333
+DMR_PRE = (1.4, 0.0, 0.0, 1.0)
+DMR_POST = (8.0, 7.145, -4.125, 116.5)
+DMR_LINE = (0.1667, 1.0 / 1.732, 20.0 / 1.732)
+
+
+def dmr(gamma=1.4):
+    """Initial field of the double Mach reflection: post-shock state left of
+    the incident shock line, pre-shock state right of it."""
+    def f(X, Y):
+        behind = X < DMR_LINE[0] + DMR_LINE[1] * Y
+        st = [np.where(behind, b, a) for b, a in zip(DMR_POST, DMR_PRE)]
+        return prim_to_cons(st[0], st[1], st[2], st[3], gamma)
+    return f
+
+
+def dmr_case(nx=240, ny=60, seed=13, gamma=1.4, quad=6):
+    """Double Mach reflection on [0, 4] x [0, 1] to t = 0.2: post-shock
+    inflow at x = 0, transmissive outflow at x = 4, bottom side post-shock
+    inflow for x < 0.1667 and a wall beyond, top side the exact moving
+    incident shock (post-shock state behind the line, pre-shock ahead).
+    nx x ny squares (nx = 4 ny keeps them square); 860 x 215 and 1196 x 299
+    come nearest the paper's 369,604 and 714,138 triangles."""
+    m = split_jitter_mesh(nx, ny, (0.0, 4.0, 0.0, 1.0), seed=seed, bc=(INFLOW, TRANSMISSIVE, WALL, INFLOW))
+    post = tuple(float(v) for v in prim_to_cons(*DMR_POST, gamma))
+    pre = tuple(float(v) for v in prim_to_cons(*DMR_PRE, gamma))
+    m.boundary = Boundary(behind=post, ahead=pre, line=DMR_LINE, split_kind=(0, 0, INFLOW, 0),
+                          split_at=(0.0, 0.0, DMR_LINE[0], 0.0))
+    u0 = cell_average(m, dmr(gamma), n=quad)
+    return m, u0
+
+
+def x_profile(mesh, u, bins):
+    """Area-weighted average of u over x-bins of the box (a 1-D profile of a
+    y-independent flow)."""
+    c = mesh.xy[mesh.tri].mean(1)[:, 0]
+    a = cell_areas(mesh)
+    x0, x1 = mesh.box[0], mesh.box[1]
+    k = np.clip(((c - x0) / (x1 - x0) * bins).astype(np.int64), 0, bins - 1)
+    num = np.bincount(k, weights=u * a, minlength=bins)
+    den = np.bincount(k, weights=a, minlength=bins)
+    return num / np.maximum(den, 1e-300)
 
 
 @dataclass

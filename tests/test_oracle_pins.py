@@ -636,6 +636,190 @@ def test_wall_and_transmissive_conservation():
     assert np.abs(o.residual(U)).max() < 1e-12
 
 
+# ----------------------------------------------------------------------------
+# prescribed-state (inflow) sides
+# ----------------------------------------------------------------------------
+
+def _inflow_expected(o, Ui, state_at):
+    """Residual of a uniform interior state Ui when boundary faces carry the
+    outside states given by state_at(face centre): a closed cell's faces sum
+    F(Ui).n |A| to zero, so only the difference HLLC(Ui, Ub) - F(Ui).n of
+    each prescribed face remains, divided by the area (constant face values
+    make the quadrature exact)."""
+    g = o.geometry()
+    R = np.zeros((4, o.N))
+    for i in range(o.N):
+        for f in range(3):
+            if g["nbr"][i, f] >= 0:
+                continue
+            n = g["normal"][i, f]
+            Ub = state_at(i, f)
+            if Ub is None:
+                continue
+            d = O.hllc(Ui, Ub, n) - O.euler_flux(Ui, n)
+            R[:, i] -= g["length"][i, f] * d / g["area"][i]
+    return R
+
+
+def _face_centres(o, m):
+    """Centre of every boundary face, found by matching the outward normal
+    against the edges of the cell (the oracle may reorder vertices)."""
+    g = o.geometry()
+    out = {}
+    for i in range(o.N):
+        p = m.xy[m.tri[i]]
+        for f in range(3):
+            if g["nbr"][i, f] >= 0:
+                continue
+            n = g["normal"][i, f]
+            for k in range(3):
+                e = p[(k + 1) % 3] - p[k]
+                c = 0.5 * (p[k] + p[(k + 1) % 3])
+                inside = p[(k + 2) % 3] - c
+                if abs(e @ n) < 1e-12 * np.linalg.norm(e) and inside @ n < 0:
+                    out[(i, f)] = (c, p[k], p[(k + 1) % 3])
+    return out
+
+
+def test_inflow_side_closed_form():
+    """A prescribed subsonic state on one side (the others transmissive):
+    the residual of a uniform interior is the HLLC jump of each inflow face."""
+    m = W.split_jitter_mesh(6, 5, (0.0, 1.0, 0.0, 1.0), seed=4, bc=(W.INFLOW, 2, 2, 2))
+    Ub = W.prim_to_cons(1.3, 0.4, -0.2, 1.7)
+    Ui = W.prim_to_cons(1.0, 0.1, 0.05, 1.0)
+    m.boundary = W.constant_inflow(Ub)
+    o = O.Oracle.from_mesh(m, physics=O.EULER, scheme=O.CTENOZ, degree=3)
+    fc = _face_centres(o, m)
+    state = lambda i, f: Ub if abs(fc[(i, f)][0][0]) < 1e-12 else None
+    exp = _inflow_expected(o, Ui, state)
+    U = np.tile(Ui[:, None], (1, o.N))
+    R = o.residual(U)
+    assert np.abs(exp).max() > 0.1
+    assert np.abs(R - exp).max() <= 1e-12 * np.abs(exp).max()
+    # supersonic inflow into a supersonic interior: HLLC takes the Euler flux
+    # of the prescribed (upwind, outside) state
+    Us = W.prim_to_cons(1.0, 3.0, 0.0, 1.0)
+    Uj = W.prim_to_cons(1.05, 2.9, 0.1, 1.1)
+    assert np.allclose(O.hllc(Uj, Us, (-1.0, 0.0)), O.euler_flux(Us, (-1.0, 0.0)), rtol=1e-14, atol=1e-14)
+
+
+def test_inflow_moving_line():
+    """The prescribed state switches across x = l0 + l1 y + l2 t: faces wholly
+    behind the line see `behind`, faces wholly ahead see `ahead`, at the
+    time passed in."""
+    m = W.split_jitter_mesh(6, 8, (0.0, 1.0, 0.0, 1.0), seed=5, bc=(W.INFLOW, 2, 2, 2))
+    A = W.prim_to_cons(1.3, 0.4, -0.2, 1.7)
+    B = W.prim_to_cons(0.8, -0.3, 0.1, 0.6)
+    Ui = W.prim_to_cons(1.0, 0.1, 0.05, 1.0)
+    # on x = 0 the point is behind where 0 < -0.6 + y + 0.4 t, i.e. y > 0.6 - 0.4 t
+    m.boundary = W.Boundary(behind=tuple(A), ahead=tuple(B), line=(-0.6, 1.0, 0.4))
+    o = O.Oracle.from_mesh(m, physics=O.EULER, scheme=O.CTENO, degree=2, lambda1_prime=1e15)
+    fc = _face_centres(o, m)
+    U = np.tile(Ui[:, None], (1, o.N))
+    for t in (0.0, 1.0):
+        ycut = 0.6 - 0.4 * t
+
+        def state(i, f):
+            c, pa, pb = fc[(i, f)]
+            if abs(c[0]) > 1e-12:
+                return None
+            lo, hi = min(pa[1], pb[1]), max(pa[1], pb[1])
+            return A if lo > ycut else B if hi < ycut else "straddle"
+        straddle = [i for (i, f) in fc if isinstance(state(i, f), str)]
+        keep = np.setdiff1d(np.arange(o.N), straddle)
+        exp = _inflow_expected(o, Ui, lambda i, f: None if isinstance(state(i, f), str) else state(i, f))
+        R = o.residual(U, t)
+        assert np.abs(R[:, keep] - exp[:, keep]).max() <= 1e-12 * np.abs(exp).max()
+        # both states are in use at this time
+        assert any(state(i, f) is A for (i, f) in fc) and any(state(i, f) is B for (i, f) in fc)
+
+
+def test_side_switch():
+    """A wall side that switches to a prescribed state below x = 0.4: with
+    the interior at rest the wall part balances (mirror state) and only the
+    prescribed part leaves a residual."""
+    m = W.split_jitter_mesh(10, 4, (0.0, 1.0, 0.0, 0.4), seed=6, bc=(2, 2, W.WALL, 2))
+    Ub = W.prim_to_cons(1.2, 0.0, 0.5, 1.4)
+    Ui = W.prim_to_cons(1.0, 0.0, 0.0, 1.0)
+    m.boundary = W.Boundary(behind=tuple(Ub), ahead=tuple(Ub), split_kind=(0, 0, W.INFLOW, 0),
+                            split_at=(0.0, 0.0, 0.4, 0.0))
+    o = O.Oracle.from_mesh(m, physics=O.EULER, scheme=O.CTENOZ, degree=3)
+    fc = _face_centres(o, m)
+    state = lambda i, f: Ub if abs(fc[(i, f)][0][1]) < 1e-12 and fc[(i, f)][0][0] < 0.4 else None
+    exp = _inflow_expected(o, Ui, state)
+    R = o.residual(np.tile(Ui[:, None], (1, o.N)))
+    assert np.count_nonzero(np.abs(exp).max(0)) == 4
+    assert np.abs(R - exp).max() <= 1e-12 * np.abs(exp).max()
+
+
+def test_rk3_stage_times():
+    """SSP-RK3 in Shu-Osher form evaluates its residuals at t, t + dt and
+    t + dt/2: with the prescribed state switching at t + 0.75 dt only the
+    second stage sees the new state."""
+    m = W.split_jitter_mesh(5, 4, (0.0, 1.0, 0.0, 1.0), seed=7, bc=(W.INFLOW, 2, 2, 2))
+    A = W.prim_to_cons(1.3, 0.4, -0.2, 1.7)
+    B = W.prim_to_cons(0.8, -0.3, 0.1, 0.6)
+    t0, dt = 0.2, 0.01
+    # x = 0 is behind (A) once 0 < l0 + l2 t, i.e. from t0 + 0.75 dt on
+    m.boundary = W.Boundary(behind=tuple(A), ahead=tuple(B), line=(-(t0 + 0.75 * dt), 0.0, 1.0))
+    o = O.Oracle.from_mesh(m, physics=O.EULER, scheme=O.CTENOZ, degree=2)
+    U = np.tile(W.prim_to_cons(1.0, 0.1, 0.05, 1.0)[:, None], (1, o.N))
+    U1 = U + dt * o.residual(U, t0)
+    U2 = 0.75 * U + 0.25 * (U1 + dt * o.residual(U1, t0 + dt))
+    U3 = U / 3.0 + 2.0 / 3.0 * (U2 + dt * o.residual(U2, t0 + 0.5 * dt))
+    assert np.array_equal(o.rk3_step(U, dt, t0), U3)
+    # and the stage at t0 + dt did see the other state
+    assert np.abs(o.residual(U1, t0 + dt) - o.residual(U1, t0)).max() > 1e-3
+
+
+@pytest.mark.parametrize("left", [W.INFLOW, W.TRANSMISSIVE])
+def test_supersonic_inflow_stability(left):
+    """A uniform supersonic stream with 1e-8 noise: a prescribed inflow side
+    keeps the noise at its level, while a transmissive side there takes the
+    inflow from the interior and lets a boundary mode grow."""
+    m = W.split_jitter_mesh(20, 4, (-5.0, -4.5, 0.0, 0.1), seed=12, bc=(left, 2, W.WALL, W.WALL))
+    rho, u, p = W.SHOCK_DENSITY_POST
+    st = W.prim_to_cons(rho, u, 0.0, p)
+    m.boundary = W.constant_inflow(st)
+    o = O.Oracle.from_mesh(m, physics=O.EULER, scheme=O.CTENO, degree=3, lambda1_prime=1e15)
+    U0 = np.tile(st[:, None], (1, o.N))
+    U = U0 * (1 + 1e-8 * np.random.default_rng(1).standard_normal(U0.shape))
+    t = 0.0
+    for _ in range(150):
+        dt = 0.3 * o.dt_bound(U)
+        U = o.rk3_step(U, dt, t)
+        t += dt
+    dev = np.abs(U - U0).max() / np.abs(U0).max()
+    if left == W.INFLOW:
+        assert dev < 1e-7
+    else:
+        assert dev > 1e-5
+
+
+def test_dmr_states_satisfy_rankine_hugoniot():
+    """The double Mach reflection's post-shock state is the Mach 10 jump of
+    the pre-shock state across a shock moving at 10 along its normal
+    (30 degrees below the x axis), to the rounding of the printed values.
+    The paper prints p = 116.8333 behind the shock; that value breaks the
+    momentum balance, the Mach 10 value 116.5 keeps it."""
+    g = 1.4
+    r1, u1, v1, p1 = W.DMR_PRE
+    r2, u2, v2, p2 = W.DMR_POST
+    n = np.array([math.cos(math.pi / 6), -math.sin(math.pi / 6)])   # shock normal, pointing downstream
+    s = 10.0
+    w1 = np.dot([u1, v1], n) - s
+    w2 = np.dot([u2, v2], n) - s
+    assert abs(r1 * w1 - r2 * w2) <= 1e-3 * abs(r1 * w1)
+    assert abs((r1 * w1 * w1 + p1) - (r2 * w2 * w2 + p2)) <= 1e-3 * (r1 * w1 * w1 + p1)
+    h1 = g / (g - 1) * p1 / r1 + 0.5 * w1 * w1
+    h2 = g / (g - 1) * p2 / r2 + 0.5 * w2 * w2
+    assert abs(h1 - h2) <= 1e-3 * h1
+    # tangential velocity is continuous
+    tvec = np.array([n[1], -n[0]])
+    assert abs(np.dot([u2, v2], tvec) - np.dot([u1, v1], tvec)) < 1e-3
+    assert abs((r1 * w1 * w1 + p1) - (r2 * w2 * w2 + 116.8333)) > 1e-3 * (r1 * w1 * w1 + p1)
+
+
 def _orders(errs):
     return [math.log2(errs[k] / errs[k + 1]) for k in range(len(errs) - 1)]
 
