@@ -160,6 +160,50 @@ def schemes_bench(T, W, ctx, n=1000, steps=5, warmup=1):
             "ms_per_step": ms, "normalised_time": norm, "paper_table_tab2": PAPER_SCHEME_TIMES}
 
 
+# the paper's double Mach reflection timings (sec. 3.4): Table tab1's times
+# normalised to CWENO5 on 369,604 triangles, and the wall-clock time of one
+# CTENO5 iteration on 714,138 triangles with 64 MPI processes (AMD EPYC 7542;
+# CTENO7 about 1.5 times that)
+PAPER_DMR_TIMES = {"369604": {"CWENO": 1.000, "TENO": 1.036, "CTENO": 1.033, "CTENOZ": 1.000},
+                   "714138": {"CWENO": 2.798, "TENO": 2.870, "CTENO": 2.795, "CTENOZ": 2.811}}
+PAPER_DMR_CTENO5_S_PER_ITERATION = 1.7
+
+
+def dmr_bench(T, W, ctx, steps=20, warmup=2):
+    """The paper's timing workload: the double Mach reflection on meshes of
+    the paper's two sizes, CWENO / TENO / CTENO / CTENOZ of 5th order
+    (lambda1' = 1e15, conserved variables) from t = 0, FP64 and mixed, time
+    per SSP-RK3 iteration from graph replay; CTENO7 on the larger mesh."""
+    names = [("CWENO", T.CWENO), ("TENO", T.TENO), ("CTENO", T.CTENO), ("CTENOZ", T.CTENOZ)]
+    out = {"workload": "double Mach reflection on [0,4]x[0,1], split/jittered squares, lambda1'=1e15, "
+                       "conserved variables, SSP-RK3 CFL 0.3 from t = 0, graph replay",
+           "ms_per_iteration": {}, "paper_table_tab1": PAPER_DMR_TIMES,
+           "paper_cteno5_s_per_iteration_64_cpu_processes": PAPER_DMR_CTENO5_S_PER_ITERATION}
+    for nx, ny, label in ((860, 215, "369604"), (1196, 299, "714138")):
+        mesh, u0 = W.dmr_case(nx, ny)
+        row = {"cells": mesh.n_cells}
+        runs = [(name, sch, 4) for name, sch in names] + ([("CTENO7", T.CTENO, 6)] if label == "714138" else [])
+        for name, sch, r in runs:
+            m = T.Mesh.from_workload(ctx, mesh, physics=T.EULER, scheme=sch, degree=r, lambda1_prime=1e15,
+                                     precision=T.BOTH)
+            sol = T.Solution(m, u0)
+            row[name] = {}
+            for pname, prec in (("fp64", T.FP64), ("mixed", T.MIXED)):
+                res = run_precision(T, ctx, m, sol, u0, prec, steps, warmup)
+                row[name][pname] = 1e3 * res["graph_elapsed"] / steps
+            sol.close()
+            m.close()
+        out["ms_per_iteration"][label] = row
+        log(f"dmr {label} ({mesh.n_cells} cells): " + ", ".join(
+            f"{k} {v['fp64']:.3f}/{v['mixed']:.3f} ms" for k, v in row.items() if k != "cells"))
+    ref = out["ms_per_iteration"]["369604"]["CWENO"]["fp64"]
+    out["normalised_fp64"] = {lab: {k: v["fp64"] / ref for k, v in row.items() if k != "cells"}
+                              for lab, row in out["ms_per_iteration"].items()}
+    big = out["ms_per_iteration"]["714138"]["CTENO"]
+    out["cteno5_714k_s_per_iteration"] = {"fp64": big["fp64"] / 1e3, "mixed": big["mixed"] / 1e3}
+    return out
+
+
 def variables_bench(T, W, ctx, n=1000, steps=5, warmup=1):
     """Reconstruction in characteristic variables (per face, three
     projections and selections per cell) against conserved variables:
@@ -279,6 +323,7 @@ def main():
     ap.add_argument("--no-orders", action="store_true", help="skip the orders 5-7 measurement")
     ap.add_argument("--no-schemes", action="store_true", help="skip the CWENO/TENO/CTENO/CTENOZ cost comparison")
     ap.add_argument("--no-variables", action="store_true", help="skip the characteristic-variable cost comparison")
+    ap.add_argument("--no-dmr", action="store_true", help="skip the double Mach reflection timings")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); multi-GPU sharding is a design "
@@ -393,6 +438,8 @@ def main():
         out["schemes"] = schemes_bench(T, W, ctx)
     if not args.no_variables:
         out["variables"] = variables_bench(T, W, ctx)
+    if not args.no_dmr:
+        out["dmr"] = dmr_bench(T, W, ctx)
     if not args.no_serving:
         out["serving"] = serving_bench(T, W, ctx, n_requests=args.serving_requests)
     if not args.no_cpu_baseline:

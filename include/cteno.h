@@ -45,8 +45,13 @@ typedef enum {
     CTENO_ERR_BUSY = 7          /* resource budget exhausted; retry later */
 } cteno_status;
 
-/* boundary kinds per box side */
-enum { CTENO_PERIODIC = 0, CTENO_WALL = 1, CTENO_TRANSMISSIVE = 2 };
+/* Boundary kinds per box side.  The outside state of a boundary face at a
+   Gauss point is: WALL, the inside state with its normal momentum reversed;
+   TRANSMISSIVE, the inside state (fit for outflow, not for a supersonic
+   inflow, where it lets a boundary mode grow); INFLOW, a prescribed state
+   (cteno_mesh_desc.behind / ahead).  The paper names its test cases'
+   boundaries only in words (sec. 3); these are the usual ghost states. */
+enum { CTENO_PERIODIC = 0, CTENO_WALL = 1, CTENO_TRANSMISSIVE = 2, CTENO_INFLOW = 3 };
 /* physics */
 enum { CTENO_ADVECTION = 0, CTENO_EULER = 1 };
 /* weighting scheme: CTENO = Algorithm 1 (sec. 2.4), CTENOZ = Algorithm 2 (sec. 2.5) */
@@ -92,6 +97,21 @@ typedef struct {
     const int32_t *tri;    /* host [n_cells][3] */
     double box[4];         /* x0, x1, y0, y1 */
     int32_t bc[4];         /* kinds of the sides x = x0, x = x1, y = y0, y = y1 */
+    /* Prescribed outside states of INFLOW faces (conserved variables; entry 0
+       alone for advection): `behind` at Gauss points (x, y) with
+       x < line[0] + line[1] y + line[2] t at the stage time t, `ahead`
+       elsewhere -- a straight discontinuity moving in x, such as the incident
+       shock of the double Mach reflection (sec. 3.4); a constant inflow sets
+       behind = ahead.  Both must be physical (density, pressure > 0) when a
+       side is INFLOW. */
+    double behind[4], ahead[4];
+    double line[3];
+    /* Optional switch of kind along a side: faces of side k whose midpoint
+       lies below split_at[k] along the side (y on the sides x = const, x on
+       the sides y = const) take kind split_kind[k] instead of bc[k];
+       split_kind[k] = 0 means no switch (periodic sides cannot switch). */
+    int32_t split_kind[4];
+    double split_at[4];
 } cteno_mesh_desc;
 
 /* Scheme parameters (sec. 2.1-2.6).  degree r in 2..6: the central
@@ -215,16 +235,20 @@ cteno_status cteno_reconstruct(cteno_ctx *ctx, const cteno_mesh *mesh, const cte
 /* Face fluxes from face-point values (sec. 2.6, HLLC for Euler, upwind for
    advection), integrated over each face with the Gauss weights:
    face_flux: device [n_cells][3][nv] (FP64 or FP32 by precision), the
-   outward flux of cell i through its face f, times |A_f|. */
+   outward flux of cell i through its face f, times |A_f|.  t is the time of
+   the prescribed states of INFLOW faces. */
 cteno_status cteno_flux(cteno_ctx *ctx, const cteno_mesh *mesh, int32_t precision, const void *face_vals,
-                        void *face_flux);
+                        double t, void *face_flux);
 /* Residual dU/dt = -(1/|V_i|) sum_f outward flux (the semi-discrete form
-   after eq. e1) of the current state: resid device [nv][n_cells] FP64. */
+   after eq. e1) of the current state at the solution's time:
+   resid device [nv][n_cells] FP64. */
 cteno_status cteno_residual(cteno_ctx *ctx, const cteno_mesh *mesh, const cteno_sol *sol, int32_t precision,
                             double *resid);
 /* One SSP-RK3 stage (Shu-Osher form) of size dt on `sol`: stage 0 forms
    U1 = U + dt R(U), stage 1 U2 = 3/4 U + 1/4 (U1 + dt R(U1)), stage 2
-   U <- 1/3 U + 2/3 (U2 + dt R(U2)).  Stages must be issued 0, 1, 2. */
+   U <- 1/3 U + 2/3 (U2 + dt R(U2)).  Stages must be issued 0, 1, 2; the
+   residuals are those of the times t, t + dt and t + dt/2 (t the solution's
+   time, advanced by dt after stage 2). */
 cteno_status cteno_rk_stage(cteno_ctx *ctx, const cteno_mesh *mesh, cteno_sol *sol, int32_t precision, int32_t stage,
                             double dt);
 

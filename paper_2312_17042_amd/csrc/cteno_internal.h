@@ -72,6 +72,8 @@ __host__ __device__ inline size_t hvix(int64_t i, int e, int E, int VW, int CT) 
 constexpr uint32_t kNbBoundary = 0x80000000u;
 constexpr uint32_t kNbOwner = 0x40000000u;
 constexpr uint32_t kNbIndexMask = 0x0FFFFFFFu;
+// boundary faces: kind in bits 0-1; an inflow face's row in the inflow table in bits 2-29
+constexpr uint32_t kNbInflowMask = 0x0FFFFFFFu;
 
 // ---------------------------------------------------------------------------
 // host mesh builder output (all in internal order unless noted)
@@ -99,6 +101,10 @@ struct HostMesh {
     std::vector<double> fr64;          // [12] entries, VW 2; code stored in the low bits of the double
     std::vector<float> fr32;           // [12] entries, VW 4; code stored as the float's bits
     std::vector<double> area;          // [Npad]
+    // inflow faces: first vertex (x, y) and edge vector, rows in internal cell order
+    std::vector<double> bface;         // [n_inflow][4]
+    double bst[2][4] = {};             // prescribed states behind / ahead of the moving line
+    double bline[3] = {};              // x = bline[0] + bline[1] y + bline[2] t
 };
 
 // host threads the calling thread's mesh builds may use (default 16)

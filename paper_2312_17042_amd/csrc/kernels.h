@@ -23,6 +23,10 @@ struct DeviceMesh {
     double *P64 = nullptr;         // pseudo-inverse stream, vector-tiled [E64], VW 2
     float *P32 = nullptr;          // pseudo-inverse stream, vector-tiled [E32], VW 4
     int32_t *perm = nullptr;       // internal -> user [N]
+    double *bface = nullptr;       // [n_inflow][4]: first vertex and edge vector of each inflow face
+    int64_t n_inflow = 0;
+    double bst[2][4] = {};         // inflow states behind / ahead of the moving line
+    double bline[3] = {};          // x = bline[0] + bline[1] y + bline[2] t
     double *htab64 = nullptr;      // r >= 4: Gram matrix [K][K] and face basis [3][Nq][K], FP64
     float *htab32 = nullptr;       // the same in FP32
     RefTables tab;
@@ -56,8 +60,9 @@ struct FluxLaunch {
     double dt_value = 0.0;
     void *flux_out = nullptr;    // AoS [Np][3][nv] of the precision type
     double *resid = nullptr;     // AoS [Np][nv]
-    Ctrl *ctrl = nullptr;        // done / nonphysical (may be null)
+    Ctrl *ctrl = nullptr;        // done / nonphysical (may be null); with dt_ptr also the march time
     double *dt_part = nullptr;   // per-block minima of the CFL bound (stage 2 of a march), or null
+    double t_base = 0.0;         // time of the stage input when the march time is not on the device
 };
 hipError_t launch_flux(const DeviceMesh &m, bool fp32, const FluxLaunch &f, hipStream_t st);
 

@@ -1737,6 +1737,13 @@ struct FluxArgs {
     real gw[4];             // Gauss weights on [0, 1]
     double gamma64;
     int stage;
+    // prescribed-state (inflow) boundary faces
+    const double *bface;    // [n_inflow][4]: first vertex (x, y) and edge vector of each inflow face
+    double bst[2][4];       // outside states behind / ahead of the moving line (conserved variables)
+    double bline[3];        // the line x = bline[0] + bline[1] y + bline[2] t
+    double gq[4];           // Gauss nodes on [0, 1]
+    double t_base;          // time of the stage input when tctrl is null
+    const Ctrl *tctrl;      // time march: the stage input's time is tctrl->t, its step *dt_ptr
 };
 
 template <int NV, int PHYS>
@@ -1808,16 +1815,33 @@ __device__ __forceinline__ double flux_body(const FluxArgs<real> a, const FluxPt
             bool owner;
             if (code & kNbBoundary) {
                 owner = true;
-                const bool wall = (code & 3u) == CTENO_WALL;
-                // ghost state at the same Gauss point: oth[NQ-1-q] pairs with own[q]
+                const uint32_t kind = code & 3u;
+                if (kind == CTENO_INFLOW) {
+                    // prescribed state on the Gauss point's side of the moving line
+                    // at the stage time (t, t + dt, t + dt/2 for the three stages)
+                    const double *e = a.bface + 4 * (int64_t)((code >> 2) & kNbInflowMask);
+                    const double t0 = a.tctrl ? a.tctrl->t : a.t_base;
+                    const double dts = MODE == 2 ? (ptr.dt_ptr ? *ptr.dt_ptr : a.dt_value) : 0.0;
+                    const double ts = t0 + (a.stage == 1 ? dts : a.stage == 2 ? 0.5 * dts : 0.0);
 #pragma unroll
-                for (int q = 0; q < NQ; ++q) {
+                    for (int q = 0; q < NQ; ++q) {
+                        const double px = e[0] + a.gq[q] * e[2], py = e[1] + a.gq[q] * e[3];
+                        const int side = px < a.bline[0] + a.bline[1] * py + a.bline[2] * ts ? 0 : 1;
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) oth[NQ - 1 - q][v] = own[f][q][v];
-                    if (PHYS == CTENO_EULER && wall) {
-                        const real mn = own[f][q][1] * nx + own[f][q][2] * ny;
-                        oth[NQ - 1 - q][1] = own[f][q][1] - 2 * mn * nx;
-                        oth[NQ - 1 - q][2] = own[f][q][2] - 2 * mn * ny;
+                        for (int v = 0; v < NV; ++v) oth[NQ - 1 - q][v] = (real)a.bst[side][v];
+                    }
+                } else {
+                    const bool wall = kind == CTENO_WALL;
+                    // ghost state at the same Gauss point: oth[NQ-1-q] pairs with own[q]
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q) {
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) oth[NQ - 1 - q][v] = own[f][q][v];
+                        if (PHYS == CTENO_EULER && wall) {
+                            const real mn = own[f][q][1] * nx + own[f][q][2] * ny;
+                            oth[NQ - 1 - q][1] = own[f][q][1] - 2 * mn * nx;
+                            oth[NQ - 1 - q][2] = own[f][q][2] - 2 * mn * ny;
+                        }
                     }
                 }
             } else {
@@ -1915,7 +1939,7 @@ __global__ __launch_bounds__(256) void k_flux(const FluxArgs<real> a) {
 
 template <typename real, int NV, int PHYS>
 static hipError_t flux_t(const DeviceMesh &m, const FluxLaunch &f, hipStream_t st) {
-    FluxArgs<real> a;
+    FluxArgs<real> a{};
     a.N = m.N;
     a.FV = (const real *)f.FV;
     if constexpr (std::is_same<real, double>::value) a.fr = m.fr64;
@@ -1929,8 +1953,15 @@ static hipError_t flux_t(const DeviceMesh &m, const FluxLaunch &f, hipStream_t s
     a.dt_part = f.dt_part;
     a.gamma = (real)m.gamma; a.ax = (real)m.ax; a.ay = (real)m.ay;
     a.gamma64 = m.gamma;
-    a.stage = f.stage;
+    a.stage = f.mode == 2 ? f.stage : 0;
     for (int q = 0; q < 4; ++q) a.gw[q] = q < m.tab.Nq ? (real)m.tab.gw[q] : (real)0;
+    a.bface = m.bface;
+    for (int k = 0; k < 2; ++k)
+        for (int v = 0; v < 4; ++v) a.bst[k][v] = m.bst[k][v];
+    for (int k = 0; k < 3; ++k) a.bline[k] = m.bline[k];
+    for (int q = 0; q < 4; ++q) a.gq[q] = q < m.tab.Nq ? m.tab.gq[q] : 0.0;
+    a.t_base = f.t_base;
+    a.tctrl = f.ctrl && f.dt_ptr ? f.ctrl : nullptr;
     const unsigned grid = (unsigned)m.blocks();
 #define FX_LAUNCH(NQ)                                                                                         \
     switch (f.mode) {                                                                                         \
@@ -2115,7 +2146,7 @@ static hipError_t batch_step_r(const DeviceMesh &proto, const BatchSlot *tab, co
     ReconArgs<float, K> ra;
     std::memset(&ra, 0, sizeof ra);
     fill_recon_constants<float, K>(proto, ra);
-    FluxArgs<float> fa;
+    FluxArgs<float> fa{};
     std::memset(&fa, 0, sizeof fa);
     fa.gamma = (float)proto.gamma; fa.ax = (float)proto.ax; fa.ay = (float)proto.ay; fa.gamma64 = proto.gamma;
     fa.gw[0] = fa.gw[1] = 0.5f;

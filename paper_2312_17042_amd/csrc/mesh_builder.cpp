@@ -210,7 +210,9 @@ struct Builder {
                     else if (std::fabs(my - d.box[3]) <= tol) side = 3;
                     if (side < 0) { bad = i; why = 2; return; }
                     if (d.bc[side] == CTENO_PERIODIC) { bad = i; why = 3; return; }
-                    fbc[3 * i + f] = d.bc[side];
+                    const double along = side < 2 ? my : mx;
+                    fbc[3 * i + f] = d.split_kind[side] != 0 && along < d.split_at[side] ? d.split_kind[side]
+                                                                                         : d.bc[side];
                 }
             }
             for (int f = 0; f < 3; ++f)
@@ -334,8 +336,26 @@ void set_builder_threads(int n) { tl_max_threads = std::max(1, std::min(n, 16));
 cteno_status build_host_mesh(const cteno_mesh_desc &d, const cteno_scheme &s, HostMesh &hm, std::string &err) {
     if (d.n_cells <= 0 || d.n_vertices <= 0 || !d.xy || !d.tri) { err = "empty mesh"; return CTENO_ERR_INVALID; }
     if (d.n_cells >= (1 << 28)) { err = "too many cells (limit 2^28)"; return CTENO_ERR_INVALID; }
-    for (int k = 0; k < 4; ++k)
-        if (d.bc[k] < 0 || d.bc[k] > 2) { err = "bad boundary kind"; return CTENO_ERR_INVALID; }
+    bool inflow = false;
+    for (int k = 0; k < 4; ++k) {
+        if (d.bc[k] < 0 || d.bc[k] > CTENO_INFLOW || d.split_kind[k] < 0 || d.split_kind[k] > CTENO_INFLOW) {
+            err = "bad boundary kind";
+            return CTENO_ERR_INVALID;
+        }
+        if (d.split_kind[k] != 0 && d.bc[k] == CTENO_PERIODIC) {
+            err = "a periodic side cannot switch kind";
+            return CTENO_ERR_INVALID;
+        }
+        inflow |= d.bc[k] == CTENO_INFLOW || d.split_kind[k] == CTENO_INFLOW;
+    }
+    if (inflow && s.physics == CTENO_EULER)
+        for (const double *b : {d.behind, d.ahead}) {
+            const double p = (s.gamma - 1.0) * (b[3] - 0.5 * (b[1] * b[1] + b[2] * b[2]) / b[0]);
+            if (!(b[0] > 0.0) || !(p > 0.0)) { err = "non-physical inflow state"; return CTENO_ERR_INVALID; }
+        }
+    for (double v : {d.behind[0], d.behind[1], d.behind[2], d.behind[3], d.ahead[0], d.ahead[1], d.ahead[2],
+                     d.ahead[3], d.line[0], d.line[1], d.line[2]})
+        if (inflow && !std::isfinite(v)) { err = "non-finite inflow data"; return CTENO_ERR_INVALID; }
     if ((d.bc[0] == CTENO_PERIODIC) != (d.bc[1] == CTENO_PERIODIC) ||
         (d.bc[2] == CTENO_PERIODIC) != (d.bc[3] == CTENO_PERIODIC)) {
         err = "periodic sides must come in pairs";
@@ -344,7 +364,10 @@ cteno_status build_host_mesh(const cteno_mesh_desc &d, const cteno_scheme &s, Ho
     if (!(d.box[1] > d.box[0]) || !(d.box[3] > d.box[2])) { err = "bad box"; return CTENO_ERR_INVALID; }
     if (s.physics == CTENO_ADVECTION)
         for (int k = 0; k < 4; ++k)
-            if (d.bc[k] == CTENO_WALL) { err = "walls need the Euler equations"; return CTENO_ERR_INVALID; }
+            if (d.bc[k] == CTENO_WALL || d.split_kind[k] == CTENO_WALL) {
+                err = "walls need the Euler equations";
+                return CTENO_ERR_INVALID;
+            }
 
     Builder b(d, s.degree);
     if (!b.geometry()) { err = b.err; return CTENO_ERR_MESH; }
@@ -403,6 +426,18 @@ cteno_status build_host_mesh(const cteno_mesh_desc &d, const cteno_scheme &s, Ho
         hm.fr32[avix(k, 4 * f + 2, 12, 4)] = (float)len;
         std::memcpy(&hm.fr32[avix(k, 4 * f + 3, 12, 4)], &code, sizeof code);
     };
+
+    // rows of the inflow faces, in internal cell order
+    std::vector<int32_t> inflow_row(3 * (size_t)N, -1);
+    int64_t n_inflow = 0;
+    for (int64_t k = 0; k < N; ++k)
+        for (int f = 0; f < 3; ++f)
+            if (b.fnb[3 * (size_t)hm.perm[k] + f] < 0 && b.fbc[3 * (size_t)hm.perm[k] + f] == CTENO_INFLOW)
+                inflow_row[3 * k + f] = (int32_t)n_inflow++;
+    if (n_inflow > (int64_t)kNbInflowMask) { err = "too many inflow faces"; return CTENO_ERR_INVALID; }
+    hm.bface.assign(4 * (size_t)n_inflow, 0.0);
+    for (int v = 0; v < 4; ++v) { hm.bst[0][v] = d.behind[v]; hm.bst[1][v] = d.ahead[v]; }
+    for (int k = 0; k < 3; ++k) hm.bline[k] = d.line[k];
 
     std::atomic<int64_t> nfaces{0}, nbnd{0};
     std::atomic<int> ninad{0};
@@ -478,6 +513,17 @@ cteno_status build_host_mesh(const cteno_mesh_desc &d, const cteno_scheme &s, Ho
             if (j < 0) {
                 edge_normal(u, f, nx, ny, len);
                 code = kNbBoundary | (uint32_t)b.fbc[3 * (size_t)u + f];
+                const int32_t row = inflow_row[3 * k + f];
+                if (row >= 0) {
+                    const int32_t *tt = b.tri.data() + 3 * (size_t)u;
+                    const int va = tt[f], vb = tt[(f + 1) % 3];
+                    double *e = hm.bface.data() + 4 * (size_t)row;
+                    e[0] = b.X(va);
+                    e[1] = b.Y(va);
+                    e[2] = b.X(vb) - b.X(va);
+                    e[3] = b.Y(vb) - b.Y(va);
+                    code |= (uint32_t)row << 2;
+                }
                 nbnd++;
                 nfaces++;
             } else {

@@ -272,6 +272,15 @@ static cteno_status upload_device_mesh(cteno_ctx *ctx, hipStream_t st, HostMesh 
     dm.fr64 = keep_fr64 ? alloc_T(double, Np * 12) : nullptr;
     dm.area = alloc_T(double, Np);
     dm.perm = alloc_T(int32_t, (size_t)hm.N);
+    dm.n_inflow = (int64_t)(hm.bface.size() / 4);
+    if (dm.n_inflow) {
+        dm.bface = alloc_T(double, hm.bface.size());
+        if (!dm.bface) return fail(CTENO_ERR_NOMEM, "device allocation failed");
+        HIP_TRY(h2d(dm.bface, hm.bface, st));
+    }
+    for (int k = 0; k < 2; ++k)
+        for (int v = 0; v < 4; ++v) dm.bst[k][v] = hm.bst[k][v];
+    for (int k = 0; k < 3; ++k) dm.bline[k] = hm.bline[k];
     if (s.precision & CTENO_MIXED) {
         dm.fr32 = alloc_T(float, Np * 12);
         dm.P32 = alloc_T(float, Np * dm.E32);
@@ -622,7 +631,7 @@ extern "C" cteno_status cteno_reconstruct(cteno_ctx *ctx, const cteno_mesh *m, c
 }
 
 extern "C" cteno_status cteno_flux(cteno_ctx *ctx, const cteno_mesh *m, int32_t precision, const void *face_vals,
-                                   void *face_flux) {
+                                   double t, void *face_flux) {
     if (!ctx || !m || !face_vals || !face_flux) return fail(CTENO_ERR_INVALID, "NULL argument");
     bool f32;
     if (cteno_status rc = check_precision(m, precision, f32)) return rc;
@@ -637,6 +646,7 @@ extern "C" cteno_status cteno_flux(cteno_ctx *ctx, const cteno_mesh *m, int32_t 
     fl.mode = 0;
     fl.FV = fv.p;
     fl.flux_out = fo.p;
+    fl.t_base = t;
     HIP_TRY(timed(ctx, 1, [&] { return launch_flux(dm, f32, fl, st); }));
     HIP_TRY(launch_flux_to_user(dm, f32, fo.p, face_flux, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -661,6 +671,7 @@ extern "C" cteno_status cteno_residual(cteno_ctx *ctx, const cteno_mesh *m, cons
     fl.mode = 1;
     fl.FV = fv;
     fl.resid = r.as<double>();
+    fl.t_base = s->t;
     HIP_TRY(timed(ctx, 1, [&] { return launch_flux(dm, f32, fl, st); }));
     HIP_TRY(launch_state_to_user(dm, r.as<double>(), resid, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -689,6 +700,7 @@ hipError_t issue_stage(cteno_ctx *ctx, cteno_sol *s, bool f32, int stage, const 
     fl.dt_value = dt_value;
     fl.ctrl = ctrl;
     fl.dt_part = dt_part;
+    fl.t_base = s->t;
     return timed(ctx, 1, [&] { return launch_flux(dm, f32, fl, st); });
 }
 }  // namespace
@@ -1193,6 +1205,9 @@ extern "C" cteno_status cteno_server_submit(cteno_server *sv, const cteno_mesh_d
     if (!sv || !desc || !u0 || !ticket) return fail(CTENO_ERR_INVALID, "NULL argument");
     if (n_steps < 0 || !(cfl > 0)) return fail(CTENO_ERR_INVALID, "bad n_steps or cfl");
     if (desc->n_cells <= 0 || desc->n_vertices <= 0) return fail(CTENO_ERR_INVALID, "empty mesh");
+    for (int k = 0; k < 4; ++k)
+        if (desc->bc[k] == CTENO_INFLOW || desc->split_kind[k] != 0)
+            return fail(CTENO_ERR_INVALID, "the server takes periodic, wall and transmissive sides only");
     auto rq = std::make_shared<ServerRequest>();
     rq->t_submit = Clock::now();
     rq->xy.assign(desc->xy, desc->xy + 2 * (size_t)desc->n_vertices);

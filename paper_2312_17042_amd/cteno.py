@@ -17,7 +17,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libcteno.so")
 
 OK, ERR_INVALID, ERR_MESH, ERR_STENCIL, ERR_NOMEM, ERR_DEVICE, ERR_NONPHYSICAL, ERR_BUSY = range(8)
-PERIODIC, WALL, TRANSMISSIVE = 0, 1, 2
+PERIODIC, WALL, TRANSMISSIVE, INFLOW = 0, 1, 2, 3
 ADVECTION, EULER = 0, 1
 CTENO, CTENOZ, CWENO, TENO = 0, 1, 2, 3
 CONSERVED, CHARACTERISTIC = 0, 1
@@ -34,7 +34,26 @@ class CtenoError(RuntimeError):
 
 class MeshDesc(C.Structure):
     _fields_ = [("n_vertices", C.c_int32), ("xy", C.c_void_p), ("n_cells", C.c_int32), ("tri", C.c_void_p),
-                ("box", C.c_double * 4), ("bc", C.c_int32 * 4)]
+                ("box", C.c_double * 4), ("bc", C.c_int32 * 4),
+                ("behind", C.c_double * 4), ("ahead", C.c_double * 4), ("line", C.c_double * 3),
+                ("split_kind", C.c_int32 * 4), ("split_at", C.c_double * 4)]
+
+
+def mesh_desc(xy, tri, box, bc, boundary=None) -> MeshDesc:
+    """Descriptor of contiguous xy (float64) and tri (int32) arrays, which
+    the caller keeps alive.  boundary: an object with behind, ahead, line,
+    split_kind and split_at (prescribed inflow states and side switches), or
+    None."""
+    d = MeshDesc(xy.shape[0], _np_ptr(xy), tri.shape[0], _np_ptr(tri), (C.c_double * 4)(*box),
+                 (C.c_int32 * 4)(*bc))
+    if boundary is not None:
+        pad = lambda v: list(v) + [0.0] * (4 - len(v))
+        d.behind = (C.c_double * 4)(*pad(boundary.behind))
+        d.ahead = (C.c_double * 4)(*pad(boundary.ahead))
+        d.line = (C.c_double * 3)(*boundary.line)
+        d.split_kind = (C.c_int32 * 4)(*boundary.split_kind)
+        d.split_at = (C.c_double * 4)(*boundary.split_at)
+    return d
 
 
 class Scheme(C.Structure):
@@ -81,7 +100,7 @@ _SIGS = {
     "cteno_sol_download": [C.c_void_p, C.c_void_p, C.POINTER(C.c_double)],
     "cteno_sol_destroy": [C.c_void_p],
     "cteno_reconstruct": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p],
-    "cteno_flux": [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p],
+    "cteno_flux": [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_double, C.c_void_p],
     "cteno_residual": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p],
     "cteno_rk_stage": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_double],
     "cteno_solve": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.c_int64, C.c_double, C.c_int32,
@@ -182,12 +201,11 @@ def make_scheme(physics=EULER, scheme=CTENOZ, degree=3, lambda1_prime=1e4, c_t=1
 
 
 class Mesh:
-    def __init__(self, ctx: Context, xy, tri, box, bc, scheme: Scheme):
+    def __init__(self, ctx: Context, xy, tri, box, bc, scheme: Scheme, boundary=None):
         self.ctx = ctx
         self._xy = np.ascontiguousarray(xy, np.float64)
         self._tri = np.ascontiguousarray(tri, np.int32)
-        d = MeshDesc(self._xy.shape[0], _np_ptr(self._xy), self._tri.shape[0], _np_ptr(self._tri),
-                     (C.c_double * 4)(*box), (C.c_int32 * 4)(*bc))
+        d = mesh_desc(self._xy, self._tri, box, bc, boundary)
         h = C.c_void_p()
         _check(lib().cteno_mesh_upload(ctx.h, C.byref(d), C.byref(scheme), C.byref(h)))
         self.h = h
@@ -207,7 +225,8 @@ class Mesh:
 
     @classmethod
     def from_workload(cls, ctx, mesh, **scheme_kw):
-        return cls(ctx, mesh.xy, mesh.tri, mesh.box, mesh.bc, make_scheme(**scheme_kw))
+        return cls(ctx, mesh.xy, mesh.tri, mesh.box, mesh.bc, make_scheme(**scheme_kw),
+                   getattr(mesh, "boundary", None))
 
     def close(self):
         if getattr(self, "h", None):
@@ -236,11 +255,11 @@ class Mesh:
         return pc, pd
 
 
-def stencils_host(xy, tri, box, bc, scheme: Scheme):
+def stencils_host(xy, tri, box, bc, scheme: Scheme, boundary=None):
     """Host-only stencil construction (no GPU needed)."""
     xy = np.ascontiguousarray(xy, np.float64)
     tri = np.ascontiguousarray(tri, np.int32)
-    d = MeshDesc(xy.shape[0], _np_ptr(xy), tri.shape[0], _np_ptr(tri), (C.c_double * 4)(*box), (C.c_int32 * 4)(*bc))
+    d = mesh_desc(xy, tri, box, bc, boundary)
     N = tri.shape[0]
     r = scheme.degree
     K = (r + 1) * (r + 2) // 2 - 1
@@ -323,12 +342,13 @@ class Solution:
         return n.value
 
 
-def flux(mesh: Mesh, face_vals, precision=FP64):
+def flux(mesh: Mesh, face_vals, precision=FP64, t=0.0):
+    """Outward face fluxes times |A_f|; t is the time of prescribed inflow states."""
     import torch
     dt = torch.float64 if precision == FP64 else torch.float32
     fo = torch.empty((mesh.N, 3, mesh.nv), dtype=dt, device=face_vals.device)
     torch.cuda.synchronize()
-    _check(lib().cteno_flux(mesh.ctx.h, mesh.h, precision, _dev_ptr(face_vals.contiguous()), _dev_ptr(fo)))
+    _check(lib().cteno_flux(mesh.ctx.h, mesh.h, precision, _dev_ptr(face_vals.contiguous()), float(t), _dev_ptr(fo)))
     return fo
 
 
@@ -356,8 +376,7 @@ class Server:
         xy = np.ascontiguousarray(mesh.xy, np.float64)
         tri = np.ascontiguousarray(mesh.tri, np.int32)
         u0 = np.ascontiguousarray(u0, np.float64).reshape(4, tri.shape[0])
-        d = MeshDesc(xy.shape[0], _np_ptr(xy), tri.shape[0], _np_ptr(tri), (C.c_double * 4)(*mesh.box),
-                     (C.c_int32 * 4)(*mesh.bc))
+        d = mesh_desc(xy, tri, mesh.box, mesh.bc, getattr(mesh, "boundary", None))
         t = C.c_uint64()
         _check(lib().cteno_server_submit(self.h, C.byref(d), _np_ptr(u0), int(n_steps), float(cfl), C.byref(t)))
         self._cells[t.value] = tri.shape[0]

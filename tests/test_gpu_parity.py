@@ -96,6 +96,16 @@ CASES = {
     "vortex_r5_cweno_char": (lambda: W.vortex_case(20, seed=6),
                              dict(physics=O.EULER, scheme=O.CWENO, degree=5, lambda1_prime=1e4,
                                   variables=O.CHARACTERISTIC)),
+    # prescribed-state sides: the shock-density wave's supersonic inflow and
+    # the double Mach reflection's moving incident shock (top side) and
+    # switched bottom side (inflow, then wall)
+    "shockdensity_r4_cteno": (lambda: W.shock_density_case(40, 8),
+                              dict(physics=O.EULER, scheme=O.CTENO, degree=4, lambda1_prime=1e15)),
+    "dmr_r4_ctenoz": (lambda: W.dmr_case(48, 12),
+                      dict(physics=O.EULER, scheme=O.CTENOZ, degree=4, lambda1_prime=1e15)),
+    "dmr_r3_cteno_char": (lambda: W.dmr_case(48, 12),
+                          dict(physics=O.EULER, scheme=O.CTENO, degree=3, lambda1_prime=1e15,
+                               variables=O.CHARACTERISTIC)),
 }
 
 
@@ -243,7 +253,8 @@ def test_rk_stages_fp64(ctx, name):
 
 @pytest.mark.parametrize("name", ["advection_r2_cteno", "vortex_r3_ctenoz", "sod_r3_cteno", "sod_r4_cteno",
                                   "vortex_r6_ctenoz", "sod_r3_teno", "sod_r4_cweno", "sod_r3_cteno_char",
-                                  "sod_r4_ctenoz_char"])
+                                  "sod_r4_ctenoz_char", "shockdensity_r4_cteno", "dmr_r4_ctenoz",
+                                  "dmr_r3_cteno_char"])
 def test_solve_fp64_matches_oracle(ctx, name):
     mesh, u0, o, m = setup_case(ctx, name)
     s = T.Solution(m, u0)
@@ -257,6 +268,41 @@ def test_solve_fp64_matches_oracle(ctx, name):
     assert steps == so
     assert abs(tg - to) <= 1e-12 * max(1.0, abs(to))
     assert relerr_var(ug, uo, axis_v=0) < 1e-12
+
+
+@pytest.mark.parametrize("name", ["dmr_r4_ctenoz", "dmr_r3_cteno_char"])
+def test_inflow_states_follow_the_time(ctx, name):
+    """The top side's prescribed state moves with the incident shock: every
+    entry point evaluates it at its own time (flux: the time passed in;
+    residual: the solution's; RK stages and marches: t, t + dt, t + dt/2)."""
+    mesh, u0, o, m = setup_case(ctx, name)
+    t0 = 0.05
+    u, _, _ = o.solve(u0, t0, cfl=0.3)
+    ofv, _ = o.reconstruct(u)
+    for t in (t0, 0.12):
+        gfo = T.flux(m, torch.as_tensor(ofv).cuda(), T.FP64, t=t)
+        assert relerr_var(gfo.cpu().numpy(), o.face_fluxes(ofv, t)) < 1e-12
+    # the state on the top side differs between the two times
+    assert np.abs(o.face_fluxes(ofv, t0) - o.face_fluxes(ofv, 0.12)).max() > 1.0
+    s = T.Solution(m, u, t0)
+    assert relerr_var(s.residual(T.FP64).cpu().numpy(), o.residual(u, t0), axis_v=0) < 1e-12
+    dt = 0.3 * o.dt_bound(u)
+    for st in range(3):
+        s.rk_stage(st, dt, T.FP64)
+    ug, tg = s.download()
+    assert abs(tg - (t0 + dt)) < 1e-15
+    assert relerr_var(ug, o.rk3_step(u, dt, t0), axis_v=0) < 1e-12
+    uo, so, to = o.solve(u, 10.0, cfl=0.3, t0=t0, max_steps=10)
+    for graph in (True, False):
+        s.set(u, t0)
+        n = s.solve(t_final=10.0, max_steps=10, cfl=0.3, precision=T.FP64, use_graph=graph)
+        ug, tg = s.download()
+        assert n == so and abs(tg - to) <= 1e-12
+        assert relerr_var(ug, uo, axis_v=0) < 1e-12
+    s.set(u, t0)
+    s.solve(t_final=10.0, max_steps=10, cfl=0.3, precision=T.MIXED)
+    assert relerr_var(s.download()[0], uo, axis_v=0) < 1e-5
+    s.close()
 
 
 def test_graph_replay_equals_direct_launch(ctx):

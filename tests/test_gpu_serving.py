@@ -118,3 +118,14 @@ def test_oversized_request_is_rejected(ctx):
         srv.poll(t, take=True)
     assert e.value.status == T.ERR_BUSY
     srv.close()
+
+
+def test_inflow_sides_are_refused(ctx):
+    """The batched kernels carry no prescribed boundary states: a request
+    with an inflow side is refused at submission."""
+    srv = T.Server(ctx, T.make_scheme(**SCHEME), budget_bytes=1 << 30, max_slots=4)
+    mesh, u0 = W.shock_density_case(40, 8)
+    with pytest.raises(T.CtenoError) as e:
+        srv.submit(mesh, u0, 5)
+    assert e.value.status == T.ERR_INVALID
+    srv.close()

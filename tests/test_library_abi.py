@@ -42,6 +42,27 @@ def test_invalid_arguments_are_reported():
     assert e.value.status == T.ERR_MESH
 
 
+def test_inflow_data_is_checked():
+    """Prescribed-state sides: unphysical states, unknown kinds and switches
+    on periodic sides are refused before anything is built."""
+    sch = T.make_scheme(physics=T.EULER, degree=3)
+    m = W.split_jitter_mesh(8, 4, (0, 1, 0, 0.5), seed=1, bc=(T.INFLOW, 2, 1, 1))
+    good = W.constant_inflow(W.prim_to_cons(1.0, 2.0, 0.0, 1.0))
+    T.stencils_host(m.xy, m.tri, m.box, m.bc, sch, good)
+    for bnd, bc in [(W.constant_inflow((1.0, 0.0, 0.0, -1.0)), m.bc),           # negative energy
+                    (W.Boundary(), m.bc),                                      # zero density
+                    (good, (4, 2, 1, 1)),                                      # unknown kind
+                    (W.Boundary(behind=good.behind, ahead=good.ahead, split_kind=(0, 0, 5, 0)), m.bc)]:
+        with pytest.raises(T.CtenoError) as e:
+            T.stencils_host(m.xy, m.tri, m.box, bc, sch, bnd)
+        assert e.value.status == T.ERR_INVALID
+    per = W.split_jitter_mesh(8, 8, seed=1)
+    sw = W.Boundary(split_kind=(W.WALL, 0, 0, 0), split_at=(0.5, 0, 0, 0))
+    with pytest.raises(T.CtenoError) as e:
+        T.stencils_host(per.xy, per.tri, per.box, per.bc, sch, sw)
+    assert "periodic" in str(e.value)
+
+
 @pytest.mark.parametrize("case", ["adv", "vortex", "sod", "r2", "sod_r4", "r5", "adv_r6"])
 def test_host_stencils_equal_oracle(case):
     if case == "adv":
