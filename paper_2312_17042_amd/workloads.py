@@ -406,15 +406,20 @@ def shock_density(gamma=1.4):
 SHOCK_DENSITY_POST = (3.857143, 2.629369, 10.33333)   # rho, u, p behind the Mach 3 shock
 
 
-def shock_density_case(nx=200, ny=40, seed=12, gamma=1.4, quad=6, inflow=True):
-    """The shock-density wave on [-5, 5] x [0, 2]: supersonic inflow of the
-    post-shock state at x = -5 (a prescribed-state side; inflow=False makes it
-    transmissive), transmissive outflow at x = 5, walls in y.  nx x ny squares,
-    2 nx ny cells; 200 x 40 gives h = 1/20 as in the paper."""
-    left = INFLOW if inflow else TRANSMISSIVE
-    m = split_jitter_mesh(nx, ny, (-5.0, 5.0, 0.0, 2.0), seed=seed, bc=(left, TRANSMISSIVE, WALL, WALL))
+def shock_density_case(nx=200, ny=40, seed=12, gamma=1.4, quad=6, prescribed=True):
+    """The shock-density wave on [-5, 5] x [0, 2], walls in y.  Both open
+    sides take prescribed far-field states: the post-shock state flowing in
+    supersonically at x = -5 and the undisturbed gas at rest at x = 5
+    (rho = 1 + 0.2 sin 25, which the shock does not reach by t = 1.8); the
+    line x = 0 separates the two.  prescribed=False makes both sides
+    transmissive instead.  nx x ny squares, 2 nx ny cells; 200 x 40 gives
+    h = 1/20 as in the paper."""
+    side = INFLOW if prescribed else TRANSMISSIVE
+    m = split_jitter_mesh(nx, ny, (-5.0, 5.0, 0.0, 2.0), seed=seed, bc=(side, side, WALL, WALL))
     rho, u, p = SHOCK_DENSITY_POST
-    m.boundary = constant_inflow(prim_to_cons(rho, u, 0.0, p, gamma))
+    post = tuple(float(v) for v in prim_to_cons(rho, u, 0.0, p, gamma))
+    rest = tuple(float(v) for v in prim_to_cons(1.0 + 0.2 * math.sin(25.0), 0.0, 0.0, 1.0, gamma))
+    m.boundary = Boundary(behind=post, ahead=rest, line=(0.0, 0.0, 0.0))
     u0 = cell_average(m, shock_density(gamma), n=quad)
     return m, u0
 
@@ -440,13 +445,15 @@ def dmr(gamma=1.4):
 
 
 def dmr_case(nx=240, ny=60, seed=13, gamma=1.4, quad=6):
-    """Double Mach reflection on [0, 4] x [0, 1] to t = 0.2: post-shock
-    inflow at x = 0, transmissive outflow at x = 4, bottom side post-shock
-    inflow for x < 0.1667 and a wall beyond, top side the exact moving
-    incident shock (post-shock state behind the line, pre-shock ahead).
-    nx x ny squares (nx = 4 ny keeps them square); 860 x 215 and 1196 x 299
-    come nearest the paper's 369,604 and 714,138 triangles."""
-    m = split_jitter_mesh(nx, ny, (0.0, 4.0, 0.0, 1.0), seed=seed, bc=(INFLOW, TRANSMISSIVE, WALL, INFLOW))
+    """Double Mach reflection on [0, 4] x [0, 1] to t = 0.2: prescribed
+    states on the three open sides from the exact moving incident shock
+    (post-shock state behind the line, pre-shock ahead): post-shock inflow at
+    x = 0, the gas at rest at x = 4 (the line reaches x = 4 only after
+    t = 0.28), the top side across the moving shock; bottom side post-shock
+    for x < 0.1667 and a wall beyond.  nx x ny squares (nx = 4 ny keeps them
+    square); 860 x 215 and 1196 x 299 come nearest the paper's 369,604 and
+    714,138 triangles."""
+    m = split_jitter_mesh(nx, ny, (0.0, 4.0, 0.0, 1.0), seed=seed, bc=(INFLOW, INFLOW, WALL, INFLOW))
     post = tuple(float(v) for v in prim_to_cons(*DMR_POST, gamma))
     pre = tuple(float(v) for v in prim_to_cons(*DMR_PRE, gamma))
     m.boundary = Boundary(behind=post, ahead=pre, line=DMR_LINE, split_kind=(0, 0, INFLOW, 0),

@@ -1,0 +1,137 @@
+"""The paper's shock test cases with prescribed-state sides, run on the GPU
+through the C ABI: the shock-density wave (sec. 3.1.2) and the double Mach
+reflection (sec. 3.4).
+
+Shock-density wave: 200 x 40 split/jittered squares on [-5, 5] x [0, 2]
+(h = 1/20 as in the paper), t = 1.8, 5th order, FP64.  The reference is our
+own CTENOZ5 run of the same one-dimensional flow on a 4000 x 8 channel,
+periodic in y (h = 1/400; the paper uses a 2000-node 1-D WENO5 run),
+compared on 200 x-bins.  The paper's finding (Fig. 5): larger lambda1' resolves the
+post-shock fluctuations better with CTENO, while CTENOZ hardly depends on
+lambda1'.
+
+Double Mach reflection: the incident shock travels undisturbed near the top
+side, so its position there is exact: x = 0.1667 + (y + 20 t)/1.732."""
+import numpy as np
+import pytest
+
+from paper_2312_17042_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2312_17042_amd import cteno as T  # noqa: E402
+
+BINS = 200
+LAMBDAS = (1e3, 1e4, 1e5, 1e15)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = T.Context(0)
+    yield c
+    c.close()
+
+
+def _march(ctx, mesh, u0, t_final, precision=T.FP64, **kw):
+    m = T.Mesh.from_workload(ctx, mesh, precision=precision, physics=T.EULER, **kw)
+    s = T.Solution(m, u0)
+    s.solve(t_final=t_final, cfl=0.3, precision=precision)
+    u, t = s.download()
+    s.close()
+    m.close()
+    assert abs(t - t_final) < 1e-12
+    return u
+
+
+@pytest.fixture(scope="module")
+def sdw_reference(ctx):
+    """CTENOZ5 on a 4000 x 8 channel, periodic in y (the flow is
+    one-dimensional), with the same far-field sides: h = 1/400."""
+    nx = 4000
+    mesh = W.split_jitter_mesh(nx, 8, (-5.0, 5.0, 0.0, 8 * 10.0 / nx), seed=21,
+                               bc=(W.INFLOW, W.INFLOW, W.PERIODIC, W.PERIODIC))
+    mesh.boundary = W.shock_density_case(4, 2)[0].boundary     # the same far-field states
+    u0 = W.cell_average(mesh, W.shock_density(), n=6)
+    ur = _march(ctx, mesh, u0, 1.8, scheme=T.CTENOZ, degree=4, lambda1_prime=1e4)
+    return W.x_profile(mesh, ur[0], BINS)
+
+
+_sdw = {}
+
+
+def _sdw_error(ctx, ref, name, order, lam):
+    """L1 density error against the reference over x in (0.5, 2.3), where
+    the post-shock fluctuations sit at t = 1.8, on the paper's mesh."""
+    key = (name, order, lam)
+    if key not in _sdw:
+        kw = {"CTENOZ": dict(scheme=T.CTENOZ), "CTENO": dict(scheme=T.CTENO, gamma_form=T.GAMMA_LAMBDA),
+              "TENO": dict(scheme=T.TENO), "CWENO": dict(scheme=T.CWENO)}[name]
+        mesh, u0 = W.shock_density_case(200, 40)
+        u = _march(ctx, mesh, u0, 1.8, degree=order - 1, lambda1_prime=lam, **kw)
+        assert np.isfinite(u).all() and u[0].min() > 0
+        x = -5.0 + (np.arange(BINS) + 0.5) * 10.0 / BINS
+        window = (x > 0.5) & (x < 2.3)
+        _sdw[key] = float(np.abs(W.x_profile(mesh, u[0], BINS) - ref)[window].mean())
+    return _sdw[key]
+
+
+@pytest.mark.parametrize("order", [5, 7])
+def test_shock_density_lambda_sensitivity(ctx, sdw_reference, order):
+    """Fig. 5: CTENO resolves the fluctuations better as lambda1' grows
+    (its selection weighs the central stencil by lambda1'; the literal
+    Algorithm 1 ignores lambda1' there), CTENOZ hardly depends on it."""
+    z = [_sdw_error(ctx, sdw_reference, "CTENOZ", order, lam) for lam in LAMBDAS]
+    c = [_sdw_error(ctx, sdw_reference, "CTENO", order, lam) for lam in LAMBDAS]
+    assert max(z) / min(z) < 1.1, z
+    assert min(c[1:]) < 0.9 * c[0], c
+
+
+def test_shock_density_scheme_ranking(ctx, sdw_reference):
+    """Fig. 4: at lambda1' = 1e4 and 5th order CTENO and CTENOZ keep the
+    density-wave amplitude better than CWENO and TENO, CWENO being the most
+    dissipative; CTENOZ improves from 5th to 7th order."""
+    e = {n: _sdw_error(ctx, sdw_reference, n, 5, 1e4) for n in ("CTENOZ", "CTENO", "TENO", "CWENO")}
+    assert max(e["CTENOZ"], e["CTENO"]) < 0.85 * min(e["TENO"], e["CWENO"]), e
+    assert e["CWENO"] > e["TENO"], e
+    assert _sdw_error(ctx, sdw_reference, "CTENOZ", 7, 1e4) < e["CTENOZ"]
+
+
+def _band_profile(mesh, rho, y0, y1, bins):
+    """Area-weighted density over x-bins of the cells whose centroid lies in
+    y0 <= y < y1."""
+    c = mesh.xy[mesh.tri].mean(1)
+    a = W.cell_areas(mesh)
+    sel = (c[:, 1] >= y0) & (c[:, 1] < y1)
+    x0, x1 = mesh.box[0], mesh.box[1]
+    k = np.clip(((c[sel, 0] - x0) / (x1 - x0) * bins).astype(np.int64), 0, bins - 1)
+    num = np.bincount(k, weights=rho[sel] * a[sel], minlength=bins)
+    den = np.bincount(k, weights=a[sel], minlength=bins)
+    return x0 + (np.arange(bins) + 0.5) * (x1 - x0) / bins, num / np.maximum(den, 1e-300)
+
+
+@pytest.mark.parametrize("precision", [T.FP64, T.MIXED])
+def test_dmr_incident_shock_travels_exactly(ctx, precision):
+    """Near the top side the incident Mach 10 shock is undisturbed by the
+    reflection: at t = 0.2 its density midpoint sits at the exact position
+    within two cells, with the post-shock density 8 behind it and 1.4 ahead.
+    This checks the moving prescribed state and the stage times."""
+    ny = 120
+    mesh, u0 = W.dmr_case(4 * ny, ny)
+    u = _march(ctx, mesh, u0, 0.2, precision=precision, scheme=T.CTENOZ, degree=4, lambda1_prime=1e15)
+    assert np.isfinite(u).all() and u[0].min() > 0
+    h = 1.0 / ny
+    y = 0.9
+    x, prof = _band_profile(mesh, u[0], y - h, y + h, 4 * ny)
+    xs = W.DMR_LINE[0] + W.DMR_LINE[1] * y + W.DMR_LINE[2] * 0.2
+    near = (x > xs - 0.4) & (x < xs + 0.4)
+    xn, pn = x[near], prof[near]
+    k = int(np.argmax(pn < 0.5 * (8.0 + 1.4)))          # first bin past the midpoint
+    f = (pn[k - 1] - 4.7) / (pn[k - 1] - pn[k])
+    x_mid = xn[k - 1] + f * (xn[k] - xn[k - 1])
+    assert abs(x_mid - xs) < 2 * h, (x_mid, xs)
+    assert abs(pn[xn < xs - 0.1].mean() - 8.0) < 0.1
+    assert abs(pn[xn > xs + 0.1].mean() - 1.4) < 0.02

@@ -796,6 +796,38 @@ def test_supersonic_inflow_stability(left):
         assert dev > 1e-5
 
 
+@pytest.mark.parametrize("side", [W.INFLOW, W.TRANSMISSIVE])
+def test_open_sides_next_to_gas_at_rest(side):
+    """Gas at rest (the shock-density wave's undisturbed region) with 1e-8
+    noise between two open sides: far-field sides holding the reference
+    state (a Riemann problem against it lets outgoing waves leave) keep the
+    noise at its level; transmissive sides, closed by the one-sided
+    reconstruction where a characteristic enters, let a mode grow."""
+    m = W.split_jitter_mesh(20, 8, (4.0, 5.0, 0.0, 0.4), seed=3, bc=(side, side, W.WALL, W.WALL))
+    c = m.xy[m.tri].mean(1)
+    rho = 1.0 + 0.2 * np.sin(5.0 * c[:, 0])
+    U0 = W.prim_to_cons(rho, 0 * rho, 0 * rho, 1.0 + 0 * rho)
+    m.boundary = W.Boundary(behind=tuple(W.prim_to_cons(1 + 0.2 * math.sin(20.0), 0.0, 0.0, 1.0)),
+                            ahead=tuple(W.prim_to_cons(1 + 0.2 * math.sin(25.0), 0.0, 0.0, 1.0)),
+                            line=(4.5, 0.0, 0.0))
+    U = U0 * (1 + 1e-8 * np.random.default_rng(1).standard_normal(U0.shape))
+    o = O.Oracle.from_mesh(m, physics=O.EULER, scheme=O.CTENOZ, degree=4, lambda1_prime=1e4)
+    t, grew = 0.0, False
+    for _ in range(200):
+        dt = 0.3 * o.dt_bound(U)
+        try:
+            U = o.rk3_step(U, dt, t)
+        except O.OracleError:
+            grew = True
+            break
+        t += dt
+    dev = np.abs(U[2]).max()          # y-momentum: zero in the exact solution
+    if side == W.INFLOW:
+        assert dev < 1e-8
+    else:
+        assert grew or dev > 1e-3
+
+
 def test_dmr_states_satisfy_rankine_hugoniot():
     """The double Mach reflection's post-shock state is the Mach 10 jump of
     the pre-shock state across a shock moving at 10 along its normal
