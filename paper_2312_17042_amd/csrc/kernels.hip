@@ -29,6 +29,7 @@
 #include <cstring>
 #include <cmath>
 #include <type_traits>
+#include <utility>
 
 #include "kernels.h"
 
@@ -1393,6 +1394,131 @@ __device__ __forceinline__ int finish_field_ho(const ReconHoArgs<real> a, real (
     return bits;
 }
 
+// value of x in lane u of each group of four lanes (a quad), by a DPP move
+template <int u>
+__device__ __forceinline__ float quad_bcast(float x) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), u * 0x55, 0xF, 0xF, false));
+}
+template <int u>
+__device__ __forceinline__ double quad_bcast(double x) {
+    const long long b = __builtin_bit_cast(long long, x);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xFFFFFFFFll), u * 0x55, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), u * 0x55, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+// the value that lane `owner` of the quad holds in x[v] for the calling lane's v
+template <typename real, int owner>
+__device__ __forceinline__ real quad_take(const real (&x)[4], int v) {
+    const real x0 = quad_bcast<owner>(x[0]), x1 = quad_bcast<owner>(x[1]);
+    const real x2 = quad_bcast<owner>(x[2]), x3 = quad_bcast<owner>(x[3]);
+    return v == 0 ? x0 : v == 1 ? x1 : v == 2 ? x2 : x3;
+}
+
+// coefficient e of the slot stream is accumulated by lane (e / VW) % 4 of
+// the quad, in its round (e / VW) / 4, component e % VW; these hand
+// coefficients e0, e0 + 1, ... to the variable lanes
+template <typename real, int VW, int GM, int e0, int n, int... k>
+__device__ __forceinline__ void ho_take(const real (&acc)[GM][VW][4], int v, real (&out)[n],
+                                        std::integer_sequence<int, k...>) {
+    ((out[k] = quad_take<real, ((e0 + k) / VW) % 4>(acc[(e0 + k) / VW / 4][(e0 + k) % VW], v)), ...);
+}
+
+template <typename V> __device__ __forceinline__ V vzero();
+template <> __device__ __forceinline__ float4 vzero<float4>() { return make_float4(0.f, 0.f, 0.f, 0.f); }
+template <> __device__ __forceinline__ double2 vzero<double2>() { return make_double2(0.0, 0.0); }
+
+// a_opt = P_c d and a_s = P_s d for the four variables of a cell held by a
+// quad of lanes.  The lanes split each slot's stream instead of each reading
+// all of it: lane q loads the stream vectors q, q + 4, ... and accumulates
+// their coefficients for all four variables (the differences d come from
+// the variable lanes by DPP moves); at the end of each directional group
+// and of the loop the coefficients go to their variable lanes.  Every
+// coefficient sums its slots in slot order, as a lane per variable would.
+template <typename real, int R>
+__device__ __forceinline__ void ho_contract_quad(const ReconHoArgs<real> a, int64_t i, int v, double U0,
+                                                 real (&ao)[HoDims<R>::K], real (&ad)[3][HoDims<R>::KD]) {
+    using D = HoDims<R>;
+    constexpr int K = D::K, KD = D::KD, MD = D::MD, S = D::S, SP = D::SP, EPS = D::EPS, E = D::E;
+    constexpr int CT = 16;
+    using V = typename Vec<real>::T;
+    constexpr int VW = Vec<real>::W;
+    constexpr int SV = EPS / VW;          // stream vectors per slot
+    constexpr int GM = (SV + 3) / 4;      // rounds of four vectors
+    const V *__restrict__ Pv = reinterpret_cast<const V *>(a.P) + (size_t)(i / CT) * (E / VW) * CT + (i % CT);
+    const int32_t *__restrict__ Si = a.slot + (size_t)(i >> 6) * (SP / 4) * 256 + (i & 63) * 4;
+    // the last round may hold fewer than four vectors: the lanes past the end
+    // load the last vector again (same address as a neighbour lane) and drop it
+    const bool tail = 4 * (GM - 1) + v < SV;
+    const int glast = tail ? 4 * (GM - 1) + v : SV - 1;
+    real acc[GM][VW][4];
+#pragma unroll
+    for (int t = 0; t < GM; ++t)
+#pragma unroll
+        for (int c = 0; c < VW; ++c)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc[t][c][u] = 0;
+    // this lane's entries that belong to a directional polynomial
+    bool keep[GM][VW];
+#pragma unroll
+    for (int t = 0; t < GM; ++t)
+#pragma unroll
+        for (int c = 0; c < VW; ++c) {
+            const int e = (4 * t + v) * VW + c;
+            keep[t][c] = !(e >= K && e < K + KD);
+        }
+    V cur[GM], nxt[GM];
+#pragma unroll
+    for (int t = 0; t < GM; ++t) cur[t] = Pv[(t < GM - 1 ? 4 * t + v : glast) * CT];
+    cur[GM - 1] = tail ? cur[GM - 1] : vzero<V>();
+    // neighbour averages one slot ahead, their indices two slots ahead
+    double ucur = a.U[(int64_t)Si[0] * 4 + v];
+    int mnext = Si[1];
+#pragma unroll 1
+    for (int j = 0; j < S; ++j) {
+        const int jn = j + 1 < S ? j + 1 : j;
+        const int jnn = j + 2 < S ? j + 2 : jn;
+#pragma unroll
+        for (int t = 0; t < GM; ++t) nxt[t] = Pv[(jn * SV + (t < GM - 1 ? 4 * t + v : glast)) * CT];
+        nxt[GM - 1] = tail ? nxt[GM - 1] : vzero<V>();
+        const double unxt = a.U[(int64_t)mnext * 4 + v];
+        const int mnn = Si[(jnn >> 2) * 256 + (jnn & 3)];
+        const real dv = (real)(ucur - U0);
+        const real d[4] = {quad_bcast<0>(dv), quad_bcast<1>(dv), quad_bcast<2>(dv), quad_bcast<3>(dv)};
+#pragma unroll
+        for (int t = 0; t < GM; ++t)
+#pragma unroll
+            for (int c = 0; c < VW; ++c)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) acc[t][c][u] += comp(cur[t], c) * d[u];
+        if (j % MD == MD - 1) {           // uniform: group j / MD is complete
+            real x[KD];
+            ho_take<real, VW, GM, K, KD>(acc, v, x, std::make_integer_sequence<int, KD>{});
+            const int s = j / MD;
+            if (s == 0) {
+#pragma unroll
+                for (int k = 0; k < KD; ++k) ad[0][k] = x[k];
+            } else if (s == 1) {
+#pragma unroll
+                for (int k = 0; k < KD; ++k) ad[1][k] = x[k];
+            } else {
+#pragma unroll
+                for (int k = 0; k < KD; ++k) ad[2][k] = x[k];
+            }
+#pragma unroll
+            for (int t = 0; t < GM; ++t)
+#pragma unroll
+                for (int c = 0; c < VW; ++c)
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) acc[t][c][u] = keep[t][c] ? acc[t][c][u] : (real)0;
+        }
+#pragma unroll
+        for (int t = 0; t < GM; ++t) cur[t] = nxt[t];
+        ucur = unxt;
+        mnext = mnn;
+    }
+    ho_take<real, VW, GM, 0, K>(acc, v, ao, std::make_integer_sequence<int, K>{});
+}
+
 template <typename real, int R, int NV, int SCHEME, int GFORM, int DMODE, int VARS>
 __global__ __launch_bounds__(256) void k_reconstruct_ho(const ReconHoArgs<real> a) {
     using D = HoDims<R>;
@@ -1409,9 +1535,14 @@ __global__ __launch_bounds__(256) void k_reconstruct_ho(const ReconHoArgs<real> 
     const int32_t *__restrict__ Si = a.slot + (size_t)(i >> 6) * (SP / 4) * 256 + (i & 63) * 4;
     const double U0 = a.U[i * NV + v];
 
-    // a_opt = P_c d and a_s = P_s d, slot by slot; the next slot's stream
-    // vectors and index are requested before the current slot is used
-    real ao[K], ad[3][KD], adt[KD];
+    real ao[K], ad[3][KD];
+    if constexpr (NV == 4) {
+        ho_contract_quad<real, R>(a, i, v, U0, ao, ad);
+    } else {
+    // a_opt = P_c d and a_s = P_s d, slot by slot (one lane per cell); the
+    // next slot's stream vectors and index are requested before the current
+    // slot is used
+    real adt[KD];
 #pragma unroll
     for (int k = 0; k < K; ++k) ao[k] = 0;
 #pragma unroll
@@ -1445,6 +1576,7 @@ __global__ __launch_bounds__(256) void k_reconstruct_ho(const ReconHoArgs<real> 
 #pragma unroll
         for (int g = 0; g < SV; ++g) cur[g] = nxt[g];
         mcur = mn;
+    }
     }
 
     const int fl = a.flags[i] & 7;
