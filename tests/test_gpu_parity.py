@@ -370,10 +370,13 @@ def test_nonphysical_state_is_reported(ctx):
     assert e.value.status == T.ERR_NONPHYSICAL
 
 
-@pytest.mark.parametrize("which", ["vortex_80k", "sod_1p28M", "vortex_8M"])
+@pytest.mark.parametrize("which", ["vortex_80k", "sod_1p28M", "vortex_8M", "vortex_2M_r4", "vortex_2M_r6",
+                                   "dmr_715k_r4"])
 def test_full_size_sampled_parity(ctx, which):
     """Full configured sizes, one reconstruction and residual in the launch
-    configuration of the time march; the oracle evaluates sampled cells."""
+    configuration of the time march; the oracle evaluates sampled cells.
+    Besides the configured cases: the 2M-cell vortex of the orders 5-7
+    measurement and the double Mach reflection on the larger timing mesh."""
     rng = np.random.default_rng(0)
     if which == "vortex_8M":
         L = large_case(ctx)
@@ -382,6 +385,12 @@ def test_full_size_sampled_parity(ctx, which):
         if which == "vortex_80k":
             mesh, u0 = W.vortex_case(200, seed=2)
             kw = dict(physics=O.EULER, scheme=O.CTENOZ, degree=3, lambda1_prime=1e4)
+        elif which.startswith("vortex_2M"):
+            mesh, u0 = W.vortex_case(1000, seed=5, quad=3)
+            kw = dict(physics=O.EULER, scheme=O.CTENOZ, degree=int(which[-1]), lambda1_prime=1e4)
+        elif which == "dmr_715k_r4":
+            mesh, u0 = W.dmr_case(1196, 299)
+            kw = dict(physics=O.EULER, scheme=O.CTENO, degree=4, lambda1_prime=1e15)
         else:
             mesh, u0 = W.sod_case(1600, 400, seed=3)
             kw = dict(physics=O.EULER, scheme=O.CTENO, degree=3, lambda1_prime=1e15)
@@ -392,10 +401,17 @@ def test_full_size_sampled_parity(ctx, which):
         cx = mesh.xy[mesh.tri].mean(1)[:, 0]
         near = np.where(np.abs(cx - 0.5) < 2.0 / 1600)[0]
         cells = np.unique(np.concatenate([cells, rng.choice(near, 200, replace=False)])).astype(np.int32)
-    if which == "vortex_8M":   # also sample the vortex core, where the selection varies most
+    if which.startswith("vortex_8M") or which.startswith("vortex_2M"):
+        # also sample the vortex core, where the selection varies most
         cx = mesh.xy[mesh.tri].mean(1)
         near = np.where(np.hypot(cx[:, 0] - 5.0, cx[:, 1] - 5.0) < 1.5)[0]
         cells = np.unique(np.concatenate([cells, rng.choice(near, 200, replace=False)])).astype(np.int32)
+    if which == "dmr_715k_r4":  # also sample the incident shock and the prescribed sides
+        c = mesh.xy[mesh.tri].mean(1)
+        shock = np.where(np.abs(c[:, 0] - W.DMR_LINE[0] - W.DMR_LINE[1] * c[:, 1]) < 2.0 / 299)[0]
+        side = np.where((c[:, 0] < 1.0 / 299) | (c[:, 0] > 4.0 - 1.0 / 299) | (c[:, 1] > 1.0 - 1.0 / 299))[0]
+        cells = np.unique(np.concatenate([cells, rng.choice(shock, 200, replace=False),
+                                          rng.choice(side, 100, replace=False)])).astype(np.int32)
     s = T.Solution(m, u0)
     fv, dl = s.reconstruct(T.FP64)
     ofv, odl = o.reconstruct_cells(u0, cells)
