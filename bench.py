@@ -401,7 +401,12 @@ def main():
                      "kernel": "k_reconstruct (FP32)", "bytes_per_cell": RECON_BYTES["mixed"],
                      "avg_launch_ms": avg_ms},
         "kernels": {"reconstruct_ms": avg_ms, "flux_rk_ms": avg_fl,
-                    "flux_rk_GBs": FLUX_BYTES["mixed"] * N / (avg_fl * 1e-3) / 1e9},
+                    "flux_rk_GBs": FLUX_BYTES["mixed"] * N / (avg_fl * 1e-3) / 1e9,
+                    # the stage's two kernels together, algorithmic bytes over their summed time
+                    "recon_plus_flux_GBs": (RECON_BYTES["mixed"] + FLUX_BYTES["mixed"]) * N
+                    / ((avg_ms + avg_fl) * 1e-3) / 1e9,
+                    "recon_plus_flux_frac": (RECON_BYTES["mixed"] + FLUX_BYTES["mixed"]) * N
+                    / ((avg_ms + avg_fl) * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "graph_replay": {"value": N * 3 * args.steps / mx["graph_elapsed"],
                          "ms_per_step": 1e3 * mx["graph_elapsed"] / args.steps,
                          "note": "same steps replayed from a captured HIP graph, no per-kernel events"},
