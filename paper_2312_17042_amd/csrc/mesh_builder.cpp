@@ -427,13 +427,15 @@ cteno_status build_host_mesh(const cteno_mesh_desc &d, const cteno_scheme &s, Ho
         std::memcpy(&hm.fr32[avix(k, 4 * f + 3, 12, 4)], &code, sizeof code);
     };
 
-    // rows of the inflow faces, in internal cell order
-    std::vector<int32_t> inflow_row(3 * (size_t)N, -1);
+    // rows of the inflow faces, in internal cell order (no table without
+    // inflow sides)
+    std::vector<int32_t> inflow_row(inflow ? 3 * (size_t)N : 0, -1);
     int64_t n_inflow = 0;
-    for (int64_t k = 0; k < N; ++k)
-        for (int f = 0; f < 3; ++f)
-            if (b.fnb[3 * (size_t)hm.perm[k] + f] < 0 && b.fbc[3 * (size_t)hm.perm[k] + f] == CTENO_INFLOW)
-                inflow_row[3 * k + f] = (int32_t)n_inflow++;
+    if (inflow)
+        for (int64_t k = 0; k < N; ++k)
+            for (int f = 0; f < 3; ++f)
+                if (b.fnb[3 * (size_t)hm.perm[k] + f] < 0 && b.fbc[3 * (size_t)hm.perm[k] + f] == CTENO_INFLOW)
+                    inflow_row[3 * k + f] = (int32_t)n_inflow++;
     if (n_inflow > (int64_t)kNbInflowMask) { err = "too many inflow faces"; return CTENO_ERR_INVALID; }
     hm.bface.assign(4 * (size_t)n_inflow, 0.0);
     for (int v = 0; v < 4; ++v) { hm.bst[0][v] = d.behind[v]; hm.bst[1][v] = d.ahead[v]; }
@@ -513,7 +515,7 @@ cteno_status build_host_mesh(const cteno_mesh_desc &d, const cteno_scheme &s, Ho
             if (j < 0) {
                 edge_normal(u, f, nx, ny, len);
                 code = kNbBoundary | (uint32_t)b.fbc[3 * (size_t)u + f];
-                const int32_t row = inflow_row[3 * k + f];
+                const int32_t row = inflow ? inflow_row[3 * k + f] : -1;
                 if (row >= 0) {
                     const int32_t *tt = b.tri.data() + 3 * (size_t)u;
                     const int va = tt[f], vb = tt[(f + 1) % 3];
