@@ -392,7 +392,7 @@ def test_full_size_sampled_parity(ctx, which):
             mesh, u0 = W.dmr_case(1196, 299)
             kw = dict(physics=O.EULER, scheme=O.CTENO, degree=4, lambda1_prime=1e15)
         else:
-            mesh, u0 = W.sod_case(1600, 400, seed=3)
+            mesh, u0 = W.sod_case(1600, 400, seed=3, prescribed=True)
             kw = dict(physics=O.EULER, scheme=O.CTENO, degree=3, lambda1_prime=1e15)
         m = T.Mesh.from_workload(ctx, mesh, precision=T.BOTH, **kw)
     o = O.Oracle.from_mesh(mesh, **kw)
