@@ -1473,18 +1473,27 @@ __device__ __forceinline__ void ho_contract_quad(const ReconHoArgs<real> a, int6
 #pragma unroll
     for (int t = 0; t < GM; ++t) cur[t] = Pv[(t < GM - 1 ? 4 * t + v : glast) * CT];
     cur[GM - 1] = tail ? cur[GM - 1] : vzero<V>();
-    // neighbour averages one slot ahead, their indices two slots ahead
-    double ucur = a.U[(int64_t)Si[0] * 4 + v];
-    int mnext = Si[1];
+    // neighbour averages GD slots ahead (a ring), the next index one more:
+    // four in FP32, where the dependent index -> average -> product chain
+    // bounds the order-7 kernel (-11 %); one in FP64, where the ring's
+    // registers would cost a wave per SIMD
+    constexpr int GD = sizeof(real) == 4 ? 4 : 1;
+    auto slot_index = [&](int j) { const int jc = j < S ? j : S - 1; return Si[(jc >> 2) * 256 + (jc & 3)]; };
+    double ring[GD];
+#pragma unroll
+    for (int k = 0; k < GD; ++k) ring[k] = a.U[(int64_t)slot_index(k) * 4 + v];
+    int mnext = slot_index(GD);
 #pragma unroll 1
     for (int j = 0; j < S; ++j) {
         const int jn = j + 1 < S ? j + 1 : j;
-        const int jnn = j + 2 < S ? j + 2 : jn;
 #pragma unroll
         for (int t = 0; t < GM; ++t) nxt[t] = Pv[(jn * SV + (t < GM - 1 ? 4 * t + v : glast)) * CT];
         nxt[GM - 1] = tail ? nxt[GM - 1] : vzero<V>();
-        const double unxt = a.U[(int64_t)mnext * 4 + v];
-        const int mnn = Si[(jnn >> 2) * 256 + (jnn & 3)];
+        const double ucur = ring[0];
+#pragma unroll
+        for (int k = 0; k < GD - 1; ++k) ring[k] = ring[k + 1];
+        ring[GD - 1] = a.U[(int64_t)mnext * 4 + v];
+        mnext = slot_index(j + GD + 1);
         const real dv = (real)(ucur - U0);
         const real d[4] = {quad_bcast<0>(dv), quad_bcast<1>(dv), quad_bcast<2>(dv), quad_bcast<3>(dv)};
 #pragma unroll
@@ -1516,8 +1525,6 @@ __device__ __forceinline__ void ho_contract_quad(const ReconHoArgs<real> a, int6
         }
 #pragma unroll
         for (int t = 0; t < GM; ++t) cur[t] = nxt[t];
-        ucur = unxt;
-        mnext = mnn;
     }
     ho_take<real, VW, GM, 0, K>(acc, v, ao, std::make_integer_sequence<int, K>{});
 }
