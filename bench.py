@@ -135,28 +135,34 @@ PAPER_SCHEME_TIMES = {"5th": {"CWENO": 1.000, "TENO": 1.024, "CTENO": 1.043, "CT
                       "7th": {"CWENO": 1.538, "TENO": 1.557, "CTENO": 1.571, "CTENOZ": 1.643}}
 
 
-def schemes_bench(T, W, ctx, n=1000, steps=5, warmup=1):
-    """CWENO, TENO, CTENO and CTENOZ at orders 5 and 7 on the same mesh:
-    time per step normalised to CWENO5, beside the paper's ratios."""
-    mesh, u0 = W.vortex_case(n, seed=5, quad=3)
+def schemes_bench(T, W, ctx, steps=10, warmup=2):
+    """CWENO, TENO, CTENO and CTENOZ at orders 5 and 7 on Table tab2's own
+    workload, the triple point on 215,000 cells (lambda1' = 1e4, from t = 0):
+    time per step from graph replay, FP64 and mixed, normalised to CWENO5
+    beside the paper's ratios."""
+    mesh, u0 = W.triple_point_case()
     N = mesh.n_cells
-    names = [("CWENO", T.CWENO, 1e4), ("TENO", T.TENO, 1e4), ("CTENO", T.CTENO, 1e4), ("CTENOZ", T.CTENOZ, 1e4)]
-    ms = {}
+    names = [("CWENO", T.CWENO), ("TENO", T.TENO), ("CTENO", T.CTENO), ("CTENOZ", T.CTENOZ)]
+    ms = {"fp64": {}, "mixed": {}}
     for order, r in (("5th", 4), ("7th", 6)):
-        ms[order] = {}
-        for name, sch, lam in names:
-            m = T.Mesh.from_workload(ctx, mesh, physics=T.EULER, scheme=sch, degree=r, lambda1_prime=lam,
-                                     precision=T.MIXED)
+        for p in ms:
+            ms[p][order] = {}
+        for name, sch in names:
+            m = T.Mesh.from_workload(ctx, mesh, physics=T.EULER, scheme=sch, degree=r, lambda1_prime=1e4,
+                                     precision=T.BOTH)
             sol = T.Solution(m, u0)
-            res = run_precision(T, ctx, m, sol, u0, T.MIXED, steps, warmup)
-            ms[order][name] = 1e3 * res["graph_elapsed"] / steps
+            for p, prec in (("fp64", T.FP64), ("mixed", T.MIXED)):
+                res = run_precision(T, ctx, m, sol, u0, prec, steps, warmup)
+                ms[p][order][name] = 1e3 * res["graph_elapsed"] / steps
             sol.close()
             m.close()
-    ref = ms["5th"]["CWENO"]
-    norm = {o: {k: v / ref for k, v in d.items()} for o, d in ms.items()}
-    log("schemes (normalised to CWENO5): " + "; ".join(
-        f"{o}: " + ", ".join(f"{k} {v:.3f}" for k, v in d.items()) for o, d in norm.items()))
-    return {"workload": f"isentropic vortex, {n}x{n} ({N} cells), mixed precision, lambda1'=1e4, graph replay",
+    norm = {p: {o: {k: v / d["5th"]["CWENO"] for k, v in row.items()} for o, row in d.items()}
+            for p, d in ms.items()}
+    for p in norm:
+        log(f"schemes {p} (triple point, normalised to CWENO5): " + "; ".join(
+            f"{o}: " + ", ".join(f"{k} {v:.3f}" for k, v in row.items()) for o, row in norm[p].items()))
+    return {"workload": f"triple point on [0,7]x[0,3], 500x215 split/jittered ({N} cells), walls, "
+                        f"lambda1'=1e4, from t = 0, graph replay",
             "ms_per_step": ms, "normalised_time": norm, "paper_table_tab2": PAPER_SCHEME_TIMES}
 
 

@@ -432,6 +432,28 @@ def shock_density_case(nx=200, ny=40, seed=12, gamma=1.4, quad=6, prescribed=Tru
     return m, u0
 
 
+def triple_point(gamma=1.4):
+    """Single-material triple point (sec. 3.5): (rho, u, v, p) = (1, 0, 0, 1)
+    for x <= 1; (0.125, 0, 0, 0.1) for x > 1, y > 1.5; (1, 0, 0, 0.1) for
+    x > 1, y <= 1.5."""
+    def f(X, Y):
+        left = X <= 1.0
+        top = Y > 1.5
+        rho = np.where(left, 1.0, np.where(top, 0.125, 1.0))
+        p = np.where(left, 1.0, 0.1)
+        return prim_to_cons(rho, 0.0 * X, 0.0 * X, p, gamma)
+    return f
+
+
+def triple_point_case(nx=500, ny=215, seed=14, gamma=1.4, quad=6):
+    """The triple-point problem on [0, 7] x [0, 3], walls on every side, to
+    t = 5.  nx x ny rectangles; 500 x 215 (215,000 cells, h = 0.014) comes
+    nearest the paper's 214,770 triangles with h = 1/67."""
+    m = split_jitter_mesh(nx, ny, (0.0, 7.0, 0.0, 3.0), seed=seed, bc=(WALL, WALL, WALL, WALL))
+    u0 = cell_average(m, triple_point(gamma), n=quad)
+    return m, u0
+
+
 # double Mach reflection (sec. 3.4): states and the incident shock line as the
 # paper gives them (shock foot at x = 0.1667, slope 1.732, Mach 10 into gas at
 # rest with unit sound speed, so the foot moves at 10 / sin 60 = 20 / 1.732),
