@@ -81,6 +81,7 @@ def lib():
         L.or_cweno_weights.argtypes = [P, P, P, P]
         L.or_hllc.argtypes = [C.c_double, P, P, C.c_double, C.c_double, P]
         L.or_euler_flux.argtypes = [C.c_double, P, C.c_double, C.c_double, P]
+        L.or_wall_flux.argtypes = [C.c_double, P, C.c_double, C.c_double, P]
         L.or_reconstruct.argtypes = [P, P, P, P, P, P]
         L.or_reconstruct_cells.argtypes = [P, P, C.c_int, P, P, P]
         L.or_face_fluxes.argtypes = [P, P, C.c_double, P]
@@ -267,6 +268,16 @@ def hllc(UL, UR, n, gamma=1.4):
     F = np.empty(4)
     rc = lib().or_hllc(gamma, _p(UL), _p(UR), float(n[0]), float(n[1]), _p(F))
     if rc:
+        raise OracleError("non-physical state")
+    return F
+
+
+def wall_flux(U, n, gamma=1.4):
+    """HLLC flux through a wall (against the mirror image of U), written out
+    with its zero contact speed."""
+    U = np.ascontiguousarray(U, np.float64)
+    F = np.empty(4)
+    if lib().or_wall_flux(gamma, _p(U), float(n[0]), float(n[1]), _p(F)):
         raise OracleError("non-physical state")
     return F
 

@@ -932,6 +932,35 @@ static int hllc(double g, const double *UL, const double *UR, double nx, double 
     return 0;
 }
 
+/* HLLC against the mirror image of the inside state (a wall).  The two
+   states have opposite normal velocities and equal density, pressure,
+   enthalpy and tangential velocity, so the Roe-averaged normal velocity and
+   the contact speed S_M are zero, S_R = -S_L, and the star flux reduces to
+   the star pressure on the normal: F = (0, p* n_x, p* n_y, 0) with
+   p* = p + rho u_n (u_n - S_L), S_L = min(u_n - c, -c~),
+   c~^2 = (gamma - 1)(H - w^2 / 2).  Written out so that the mass and energy
+   fluxes through a wall are exactly zero, not a rounding residue of the
+   star-region formulas. */
+static int wall_flux(double g, const double *UL, double nx, double ny, double *F) {
+    double r = UL[0];
+    double u = (UL[1] * nx + UL[2] * ny) / r, w = (-UL[1] * ny + UL[2] * nx) / r;
+    double E = UL[3];
+    double p = (g - 1.0) * (E - 0.5 * r * (u * u + w * w));
+    if (!(r > 0) || !(p > 0)) return 6;
+    double c = sqrt(g * p / r);
+    double H = (E + p) / r;
+    double ct = sqrt((g - 1.0) * (H - 0.5 * w * w));
+    double SL = fmin(u - c, -ct);
+    double ps = r * (u - SL) * u + p;
+    F[0] = 0.0;
+    F[1] = ps * nx;
+    F[2] = ps * ny;
+    F[3] = 0.0;
+    return 0;
+}
+
+int or_wall_flux(double g, const double *UL, double nx, double ny, double *F) { return wall_flux(g, UL, nx, ny, F); }
+
 static int point_flux(const or_ctx *c, const double *UL, const double *UR, double nx, double ny, double *F) {
     if (c->physics == OR_ADVECTION) {
         double an = c->ax * nx + c->ay * ny;
@@ -986,6 +1015,10 @@ static int face_fluxes(or_ctx *c, const double *fv, double t, double *fo) {
                     int g = c->fnbf[3 * i + f];
                     const double *p = fv + (((size_t)j * 3 + g) * Nq + (Nq - 1 - q)) * nv;
                     for (int v = 0; v < nv; ++v) UR[v] = p[v];
+                } else if (c->fbc[3 * i + f] == OR_WALL && c->physics == OR_EULER) {
+                    err |= wall_flux(c->gam, UL, nx, ny, F);
+                    for (int v = 0; v < nv; ++v) acc[v] += c->gw[q] * F[v];
+                    continue;
                 } else {
                     double px, py;
                     gauss_point(c, i, f, q, &px, &py);
@@ -1305,6 +1338,10 @@ int or_residual_cells(or_ctx *c, const double *U, double t, int n, const int *ce
                 if (j >= 0) {
                     const double *p = xfv + ((size_t)xf * Nq + (Nq - 1 - q)) * nv;
                     for (int v = 0; v < nv; ++v) UR[v] = p[v];
+                } else if (c->fbc[3 * i + f] == OR_WALL && c->physics == OR_EULER) {
+                    rc |= wall_flux(c->gam, UL, nx, ny, F);
+                    for (int v = 0; v < nv; ++v) facc[v] += c->gw[q] * F[v];
+                    continue;
                 } else {
                     double px, py;
                     gauss_point(c, i, f, q, &px, &py);

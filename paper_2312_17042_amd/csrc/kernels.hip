@@ -1867,6 +1867,31 @@ __device__ __forceinline__ bool hllc(real g, const real *UL, const real *UR, rea
     return ok;
 }
 
+// HLLC through a wall, i.e. against the mirror image of the inside state:
+// the Roe-averaged normal velocity and the contact speed are zero, so the
+// flux is the star pressure on the normal, p* = p + rho u_n (u_n - S_L),
+// with S_L = min(u_n - c, -c~) and c~^2 = (gamma - 1)(H - w^2 / 2).  Written
+// out, the mass and energy fluxes through the wall are exactly zero in
+// either precision (the star-region formulas leave a rounding residue).
+template <typename real>
+__device__ __forceinline__ bool wall_flux(real g, const real *UL, real nx, real ny, real *F) {
+    const real r = UL[0];
+    const real u = (UL[1] * nx + UL[2] * ny) / r, w = (-UL[1] * ny + UL[2] * nx) / r;
+    const real E = UL[3];
+    const real p = (g - 1) * (E - (real)0.5 * r * (u * u + w * w));
+    const bool ok = r > 0 && p > 0;
+    const real c = sqrt(g * p / r);
+    const real H = (E + p) / r;
+    const real ct = sqrt((g - 1) * (H - (real)0.5 * w * w));
+    const real SL = fmin(u - c, -ct);
+    const real ps = r * (u - SL) * u + p;
+    F[0] = 0;
+    F[1] = ps * nx;
+    F[2] = ps * ny;
+    F[3] = 0;
+    return ok;
+}
+
 template <typename real>
 struct FluxArgs {
     int64_t N;
@@ -1961,10 +1986,14 @@ __device__ __forceinline__ double flux_body(const FluxArgs<real> a, const FluxPt
             nrm[f][0] = (double)nx; nrm[f][1] = (double)ny; nrm[f][2] = (double)len;
             real oth[NQ][NV];
             bool owner;
+            bool wallf = false;
             if (code & kNbBoundary) {
                 owner = true;
                 const uint32_t kind = code & 3u;
-                if (kind == CTENO_INFLOW) {
+                wallf = PHYS == CTENO_EULER && kind == CTENO_WALL;
+                if (wallf) {
+                    // the flux comes from wall_flux; no outside state needed
+                } else if (kind == CTENO_INFLOW) {
                     // prescribed state on the Gauss point's side of the moving line
                     // at the stage time (t, t + dt, t + dt/2 for the three stages)
                     const double *e = a.bface + 4 * (int64_t)((code >> 2) & kNbInflowMask);
@@ -1979,18 +2008,12 @@ __device__ __forceinline__ double flux_body(const FluxArgs<real> a, const FluxPt
                         for (int v = 0; v < NV; ++v) oth[NQ - 1 - q][v] = (real)a.bst[side][v];
                     }
                 } else {
-                    const bool wall = kind == CTENO_WALL;
-                    // ghost state at the same Gauss point: oth[NQ-1-q] pairs with own[q]
+                    // transmissive: the inside state at the same Gauss point
+                    // (oth[NQ-1-q] pairs with own[q])
 #pragma unroll
-                    for (int q = 0; q < NQ; ++q) {
+                    for (int q = 0; q < NQ; ++q)
 #pragma unroll
                         for (int v = 0; v < NV; ++v) oth[NQ - 1 - q][v] = own[f][q][v];
-                        if (PHYS == CTENO_EULER && wall) {
-                            const real mn = own[f][q][1] * nx + own[f][q][2] * ny;
-                            oth[NQ - 1 - q][1] = own[f][q][1] - 2 * mn * nx;
-                            oth[NQ - 1 - q][2] = own[f][q][2] - 2 * mn * ny;
-                        }
-                    }
                 }
             } else {
                 owner = (code & kNbOwner) != 0;
@@ -2013,7 +2036,8 @@ __device__ __forceinline__ double flux_body(const FluxArgs<real> a, const FluxPt
                     B[v] = owner ? oth[NQ - 1 - q][v] : own[f][NQ - 1 - q][v];
                 }
                 if (PHYS == CTENO_EULER) {
-                    bad |= !hllc<real>(a.gamma, A, B, fx, fy, F);
+                    if (wallf) bad |= !wall_flux<real>(a.gamma, A, fx, fy, F);
+                    else bad |= !hllc<real>(a.gamma, A, B, fx, fy, F);
                 } else {
                     const real an = a.ax * fx + a.ay * fy;
                     F[0] = an * (an >= 0 ? A[0] : B[0]);

@@ -540,6 +540,27 @@ def test_hllc_identities():
         assert np.allclose(F1, rot(F0), rtol=1e-12, atol=1e-12)
 
 
+def test_wall_flux_is_hllc_against_the_mirror():
+    """The wall flux written out with a zero contact speed equals HLLC
+    against the mirrored state (subsonic and supersonic, towards and away
+    from the wall) up to rounding, and carries exactly no mass or energy."""
+    rng = np.random.default_rng(21)
+    for _ in range(200):
+        rho, p = rng.uniform(0.1, 3.0), rng.uniform(0.1, 3.0)
+        u, v = rng.uniform(-4.0, 4.0, 2)
+        a = rng.uniform(0, 2 * math.pi)
+        n = np.array([math.cos(a), math.sin(a)])
+        U = W.prim_to_cons(rho, u, v, p)
+        mn = U[1] * n[0] + U[2] * n[1]
+        Um = U.copy()
+        Um[1:3] -= 2.0 * mn * n
+        Fw = O.wall_flux(U, n)
+        Fh = O.hllc(U, Um, n)
+        assert Fw[0] == 0.0 and Fw[3] == 0.0
+        scale = abs(Fh[1]) + abs(Fh[2]) + p
+        assert np.abs(Fw - Fh).max() <= 1e-13 * scale
+
+
 def test_hllc_contact_and_supersonic():
     n = np.array([1.0, 0.0])
     # isolated stationary contact: exact pressure flux, no mass flux
