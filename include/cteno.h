@@ -46,7 +46,9 @@ typedef enum {
 } cteno_status;
 
 /* Boundary kinds per box side.  The outside state of a boundary face at a
-   Gauss point is: WALL, the inside state with its normal momentum reversed;
+   Gauss point is: WALL, the inside state with its normal momentum reversed
+   (the HLLC flux against it is evaluated in closed form with its zero
+   contact speed, (0, p* n, 0): no mass or energy crosses a wall);
    TRANSMISSIVE, the inside state (fit for outflow, not for a supersonic
    inflow, where it lets a boundary mode grow); INFLOW, a prescribed state
    (cteno_mesh_desc.behind / ahead).  The paper names its test cases'
