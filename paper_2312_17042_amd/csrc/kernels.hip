@@ -1417,18 +1417,22 @@ __device__ __forceinline__ real quad_take(const real (&x)[4], int v) {
     return v == 0 ? x0 : v == 1 ? x1 : v == 2 ? x2 : x3;
 }
 
-// coefficient e of the slot stream is accumulated by lane (e / VW) % 4 of
-// the quad, in its round (e / VW) / 4, component e % VW; these hand
-// coefficients e0, e0 + 1, ... to the variable lanes
-template <typename real, int VW, int GM, int e0, int n, int... k>
-__device__ __forceinline__ void ho_take(const real (&acc)[GM][VW][4], int v, real (&out)[n],
-                                        std::integer_sequence<int, k...>) {
-    ((out[k] = quad_take<real, ((e0 + k) / VW) % 4>(acc[(e0 + k) / VW / 4][(e0 + k) % VW], v)), ...);
+// Coefficient e of the slot stream is accumulated by lane (e / VW) % 4 of
+// the quad, in its round (e / VW) / 4, component e % VW, for the GF full
+// rounds of four vectors; the four entries past them (the spread tail) by
+// lane e - 4 GF VW.  These hand coefficients e0, e0 + 1, ... to the variable
+// lanes.
+template <typename real, int VW, int GF, int e>
+__device__ __forceinline__ real ho_take1(const real (&acc)[GF][VW][4], const real (&acs)[4], int v) {
+    if constexpr (e < 4 * GF * VW) return quad_take<real, (e / VW) % 4>(acc[e / VW / 4][e % VW], v);
+    else return quad_take<real, e - 4 * GF * VW>(acs, v);
 }
 
-template <typename V> __device__ __forceinline__ V vzero();
-template <> __device__ __forceinline__ float4 vzero<float4>() { return make_float4(0.f, 0.f, 0.f, 0.f); }
-template <> __device__ __forceinline__ double2 vzero<double2>() { return make_double2(0.0, 0.0); }
+template <typename real, int VW, int GF, int e0, int n, int... k>
+__device__ __forceinline__ void ho_take(const real (&acc)[GF][VW][4], const real (&acs)[4], int v, real (&out)[n],
+                                        std::integer_sequence<int, k...>) {
+    ((out[k] = ho_take1<real, VW, GF, e0 + k>(acc, acs, v)), ...);
+}
 
 // a_opt = P_c d and a_s = P_s d for the four variables of a cell held by a
 // quad of lanes.  The lanes split each slot's stream instead of each reading
@@ -1437,6 +1441,9 @@ template <> __device__ __forceinline__ double2 vzero<double2>() { return make_do
 // the variable lanes by DPP moves); at the end of each directional group
 // and of the loop the coefficients go to their variable lanes.  Every
 // coefficient sums its slots in slot order, as a lane per variable would.
+// Where the slot ends in a partial round of four scalars (r = 4 and 6: one
+// float4 or two double2 vectors), lane q reads scalar q of it, so no lane
+// multiplies a vector it does not own.
 template <typename real, int R>
 __device__ __forceinline__ void ho_contract_quad(const ReconHoArgs<real> a, int64_t i, int v, double U0,
                                                  real (&ao)[HoDims<R>::K], real (&ad)[3][HoDims<R>::KD]) {
@@ -1446,33 +1453,39 @@ __device__ __forceinline__ void ho_contract_quad(const ReconHoArgs<real> a, int6
     using V = typename Vec<real>::T;
     constexpr int VW = Vec<real>::W;
     constexpr int SV = EPS / VW;          // stream vectors per slot
-    constexpr int GM = (SV + 3) / 4;      // rounds of four vectors
+    constexpr int GF = SV / 4;            // full rounds of four vectors
+    constexpr bool SPREAD = SV % 4 != 0;  // a tail of four scalars follows
+    static_assert(!SPREAD || (SV % 4) * VW == 4, "a partial round must hold four scalars");
     const V *__restrict__ Pv = reinterpret_cast<const V *>(a.P) + (size_t)(i / CT) * (E / VW) * CT + (i % CT);
+    // this lane's tail scalar of slot j: Pr[j * SV * CT * VW]
+    const real *__restrict__ Pr =
+        reinterpret_cast<const real *>(Pv) + ((4 * GF + v / VW) * CT) * VW + v % VW;
     const int32_t *__restrict__ Si = a.slot + (size_t)(i >> 6) * (SP / 4) * 256 + (i & 63) * 4;
-    // the last round may hold fewer than four vectors: the lanes past the end
-    // load the last vector again (same address as a neighbour lane) and drop it
-    const bool tail = 4 * (GM - 1) + v < SV;
-    const int glast = tail ? 4 * (GM - 1) + v : SV - 1;
-    real acc[GM][VW][4];
+    real acc[GF][VW][4], acs[4];
 #pragma unroll
-    for (int t = 0; t < GM; ++t)
+    for (int t = 0; t < GF; ++t)
 #pragma unroll
         for (int c = 0; c < VW; ++c)
 #pragma unroll
             for (int u = 0; u < 4; ++u) acc[t][c][u] = 0;
-    // this lane's entries that belong to a directional polynomial
-    bool keep[GM][VW];
 #pragma unroll
-    for (int t = 0; t < GM; ++t)
+    for (int u = 0; u < 4; ++u) acs[u] = 0;
+    // this lane's entries that belong to a directional polynomial
+    bool keep[GF][VW];
+#pragma unroll
+    for (int t = 0; t < GF; ++t)
 #pragma unroll
         for (int c = 0; c < VW; ++c) {
             const int e = (4 * t + v) * VW + c;
             keep[t][c] = !(e >= K && e < K + KD);
         }
-    V cur[GM], nxt[GM];
+    const int es = 4 * GF * VW + v;
+    const bool keeps = !(es >= K && es < K + KD);
+    V cur[GF], nxt[GF];
+    real cs = 0, ns = 0;
 #pragma unroll
-    for (int t = 0; t < GM; ++t) cur[t] = Pv[(t < GM - 1 ? 4 * t + v : glast) * CT];
-    cur[GM - 1] = tail ? cur[GM - 1] : vzero<V>();
+    for (int t = 0; t < GF; ++t) cur[t] = Pv[(4 * t + v) * CT];
+    if constexpr (SPREAD) cs = Pr[0];
     // neighbour averages GD slots ahead (a ring), the next index one more:
     // four in FP32, where the dependent index -> average -> product chain
     // bounds the order-7 kernel (-11 %); one in FP64, where the ring's
@@ -1487,8 +1500,8 @@ __device__ __forceinline__ void ho_contract_quad(const ReconHoArgs<real> a, int6
     for (int j = 0; j < S; ++j) {
         const int jn = j + 1 < S ? j + 1 : j;
 #pragma unroll
-        for (int t = 0; t < GM; ++t) nxt[t] = Pv[(jn * SV + (t < GM - 1 ? 4 * t + v : glast)) * CT];
-        nxt[GM - 1] = tail ? nxt[GM - 1] : vzero<V>();
+        for (int t = 0; t < GF; ++t) nxt[t] = Pv[(jn * SV + 4 * t + v) * CT];
+        if constexpr (SPREAD) ns = Pr[(size_t)jn * SV * CT * VW];
         const double ucur = ring[0];
 #pragma unroll
         for (int k = 0; k < GD - 1; ++k) ring[k] = ring[k + 1];
@@ -1497,14 +1510,18 @@ __device__ __forceinline__ void ho_contract_quad(const ReconHoArgs<real> a, int6
         const real dv = (real)(ucur - U0);
         const real d[4] = {quad_bcast<0>(dv), quad_bcast<1>(dv), quad_bcast<2>(dv), quad_bcast<3>(dv)};
 #pragma unroll
-        for (int t = 0; t < GM; ++t)
+        for (int t = 0; t < GF; ++t)
 #pragma unroll
             for (int c = 0; c < VW; ++c)
 #pragma unroll
                 for (int u = 0; u < 4; ++u) acc[t][c][u] += comp(cur[t], c) * d[u];
+        if constexpr (SPREAD) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acs[u] += cs * d[u];
+        }
         if (j % MD == MD - 1) {           // uniform: group j / MD is complete
             real x[KD];
-            ho_take<real, VW, GM, K, KD>(acc, v, x, std::make_integer_sequence<int, KD>{});
+            ho_take<real, VW, GF, K, KD>(acc, acs, v, x, std::make_integer_sequence<int, KD>{});
             const int s = j / MD;
             if (s == 0) {
 #pragma unroll
@@ -1517,16 +1534,19 @@ __device__ __forceinline__ void ho_contract_quad(const ReconHoArgs<real> a, int6
                 for (int k = 0; k < KD; ++k) ad[2][k] = x[k];
             }
 #pragma unroll
-            for (int t = 0; t < GM; ++t)
+            for (int t = 0; t < GF; ++t)
 #pragma unroll
                 for (int c = 0; c < VW; ++c)
 #pragma unroll
                     for (int u = 0; u < 4; ++u) acc[t][c][u] = keep[t][c] ? acc[t][c][u] : (real)0;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acs[u] = keeps ? acs[u] : (real)0;
         }
 #pragma unroll
-        for (int t = 0; t < GM; ++t) cur[t] = nxt[t];
+        for (int t = 0; t < GF; ++t) cur[t] = nxt[t];
+        cs = ns;
     }
-    ho_take<real, VW, GM, 0, K>(acc, v, ao, std::make_integer_sequence<int, K>{});
+    ho_take<real, VW, GF, 0, K>(acc, acs, v, ao, std::make_integer_sequence<int, K>{});
 }
 
 template <typename real, int R, int NV, int SCHEME, int GFORM, int DMODE, int VARS>
