@@ -324,6 +324,26 @@ def test_graph_replay_equals_direct_launch(ctx):
         assert np.array_equal(a.download()[0], b.download()[0])
 
 
+@pytest.mark.parametrize("graph", [False, True])
+def test_degenerate_marches(ctx, graph):
+    """A march with no step budget, or one that starts at or past its final
+    time, takes no step and leaves state and time bitwise unchanged; a march
+    to a final time just ahead takes one step, clipped to land on it."""
+    mesh, u0, o, m = setup_case(ctx, "vortex_r3_ctenoz")
+    t0 = 0.25
+    for prec in (T.FP64, T.MIXED):
+        s = T.Solution(m, u0, t0)
+        for kw in (dict(t_final=10.0, max_steps=0), dict(t_final=t0), dict(t_final=0.1)):
+            assert s.solve(precision=prec, use_graph=graph, **kw) == 0
+            u, t = s.download()
+            assert t == t0 and np.array_equal(u, u0)
+        assert s.solve(t_final=t0 + 1e-9, precision=prec, use_graph=graph) == 1
+        u, t = s.download()
+        assert t == t0 + 1e-9 and not np.array_equal(u, u0)
+        assert np.abs(u - u0).max() <= 1e-6 * np.abs(u0).max()
+        s.close()
+
+
 @pytest.mark.parametrize("prec", [T.FP64, T.MIXED])
 def test_conservation_on_gpu(ctx, prec):
     mesh, u0, o, m = setup_case(ctx, "vortex_r3_ctenoz")

@@ -40,6 +40,9 @@ def test_invalid_arguments_are_reported():
     with pytest.raises(T.CtenoError) as e:
         T.stencils_host(bad.xy, bad.tri, bad.box, bad.bc, T.make_scheme(physics=T.EULER, degree=3))
     assert e.value.status == T.ERR_MESH
+    with pytest.raises(T.CtenoError) as e:                # empty mesh
+        T.stencils_host(m.xy, m.tri[:0], m.box, m.bc, T.make_scheme(physics=T.EULER, degree=3))
+    assert e.value.status == T.ERR_INVALID and "empty" in str(e.value)
 
 
 def test_inflow_data_is_checked():
