@@ -1,5 +1,6 @@
 """CPU-side checks of the C ABI library: it loads, exports every declared
 symbol, and its host stencil builder reproduces the oracle's stencils."""
+import ctypes
 import os
 import re
 
@@ -43,6 +44,15 @@ def test_invalid_arguments_are_reported():
     with pytest.raises(T.CtenoError) as e:                # empty mesh
         T.stencils_host(m.xy, m.tri[:0], m.box, m.bc, T.make_scheme(physics=T.EULER, degree=3))
     assert e.value.status == T.ERR_INVALID and "empty" in str(e.value)
+    # beyond the cell limit (2^28, the inflow row field of a face code): the
+    # descriptor claims that many cells over small arrays; the builder refuses
+    # it before reading them, and the outputs may be NULL
+    d = T.mesh_desc(m.xy, m.tri, m.box, m.bc)
+    d.n_cells = 1 << 28
+    with pytest.raises(T.CtenoError) as e:
+        T._check(T.lib().cteno_stencils_host(ctypes.byref(d), ctypes.byref(T.make_scheme(physics=T.EULER, degree=3)),
+                                             None, None, None))
+    assert e.value.status == T.ERR_INVALID and "2^28" in str(e.value)
 
 
 def test_inflow_data_is_checked():
