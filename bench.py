@@ -43,10 +43,18 @@ FLUX_BYTES = {"mixed": 24 * 4 + 12 + 9 * 4 + 8 + 3 * 32,
 MEASURED_TRAFFIC = {"kernels_sha256_prefix": "19d0de76df99ab6e", "recon_mixed_bytes_per_cell": 966.6}
 
 
+KERNEL_SOURCES = ("kernels_common.h", "k_recon.inl", "k_recon_ho.inl", "k_recon_f32.hip", "k_recon_f64.hip",
+                  "k_recon_ho_f32.hip", "k_recon_ho_f64.hip", "k_precompute.hip", "k_flux.hip")
+
+
 def kernels_hash():
+    """sha256 prefix of the device sources, in a fixed order"""
     import hashlib
-    with open(os.path.join(ROOT, "paper_2312_17042_amd", "csrc", "kernels.hip"), "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2312_17042_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def log(msg):

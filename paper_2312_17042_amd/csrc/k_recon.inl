@@ -1,0 +1,88 @@
+// Reconstruction of degree 2 and 3 (one lane per cell): the kernel and its
+// launch, for one arithmetic type; instantiated per type by k_recon_f32.hip
+// and k_recon_f64.hip.
+#pragma once
+#include "kernels_common.h"
+
+namespace cteno {
+
+template <typename real, int R, int NV, int SCHEME, int GFORM, int DMODE, int VARS>
+__global__ __launch_bounds__(256) void k_reconstruct(const ReconArgs<real, (R + 1) * (R + 2) / 2 - 1> a) {
+    const int64_t i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (i >= a.N) return;
+    if (a.done && *a.done) return;
+    const ReconPtrs<real> ptr{a.U, a.slot, a.flags, a.P, a.FV, a.delta, a.fr};
+    recon_body<real, R, NV, SCHEME, GFORM, DMODE, VARS>(a, ptr, i);
+}
+
+
+template <typename real, int R, int NV, int VARS>
+static void reconstruct_launch(const DeviceMesh &m, const ReconArgs<real, (R + 1) * (R + 2) / 2 - 1> &a, int dmode,
+                               unsigned grid, hipStream_t st) {
+#define CT_LAUNCH(SCH, GF, DM) \
+    hipLaunchKernelGGL((k_reconstruct<real, R, NV, SCH, GF, DM, VARS>), dim3(grid), dim3(256), 0, st, a)
+#define CT_DM(SCH, GF)                        \
+    switch (dmode) {                          \
+        case 0: CT_LAUNCH(SCH, GF, 0); break; \
+        case 1: CT_LAUNCH(SCH, GF, 1); break; \
+        default: CT_LAUNCH(SCH, GF, 2); break; \
+    }
+    if (m.scheme == CTENO_SCHEME_CTENOZ) { CT_DM(CTENO_SCHEME_CTENOZ, CTENO_GAMMA_PAPER); }
+    else if (m.scheme == CTENO_SCHEME_CWENO) { CT_DM(CTENO_SCHEME_CWENO, CTENO_GAMMA_PAPER); }
+    else if (m.scheme == CTENO_SCHEME_TENO) { CT_DM(CTENO_SCHEME_TENO, CTENO_GAMMA_PAPER); }
+    else if (m.gamma_form == CTENO_GAMMA_LAMBDA) { CT_DM(CTENO_SCHEME_CTENO, CTENO_GAMMA_LAMBDA); }
+    else { CT_DM(CTENO_SCHEME_CTENO, CTENO_GAMMA_PAPER); }
+#undef CT_DM
+#undef CT_LAUNCH
+}
+
+template <typename real, int R, int NV>
+static hipError_t reconstruct_t(const DeviceMesh &m, const double *U, void *FV, uint8_t *delta, int dmode,
+                                const int *done, hipStream_t st) {
+    constexpr int K = (R + 1) * (R + 2) / 2 - 1;
+    ReconArgs<real, K> a;
+    a.N = m.N;
+    a.U = U;
+    a.slot = m.slot;
+    a.flags = m.flags;
+    if constexpr (std::is_same<real, double>::value) a.P = m.P64;
+    else a.P = m.P32;
+    if (!a.P) return hipErrorInvalidValue;
+    a.FV = (real *)FV;
+    a.delta = delta;
+    a.done = done;
+    if constexpr (std::is_same<real, double>::value) a.fr = m.fr64;
+    else a.fr = m.fr32;
+    fill_recon_constants<real, K>(m, a);
+    const unsigned grid = (unsigned)m.blocks();
+    if (m.vars == CTENO_VARS_CHARACTERISTIC) {
+        if constexpr (NV == 4) {
+            if (!a.fr) return hipErrorInvalidValue;
+            reconstruct_launch<real, R, NV, 1>(m, a, dmode, grid, st);
+        } else {
+            return hipErrorInvalidValue;
+        }
+    } else {
+        reconstruct_launch<real, R, NV, 0>(m, a, dmode, grid, st);
+    }
+    return hipGetLastError();
+}
+
+template <typename real>
+hipError_t reconstruct_lo(const DeviceMesh &m, const double *U, void *FV, uint8_t *delta, int dmode,
+                                const int *done, hipStream_t st) {
+    if (m.nv == 4) {
+        switch (m.r) {
+            case 2: return reconstruct_t<real, 2, 4>(m, U, FV, delta, dmode, done, st);
+            case 3: return reconstruct_t<real, 3, 4>(m, U, FV, delta, dmode, done, st);
+        }
+    } else {
+        switch (m.r) {
+            case 2: return reconstruct_t<real, 2, 1>(m, U, FV, delta, dmode, done, st);
+            case 3: return reconstruct_t<real, 3, 1>(m, U, FV, delta, dmode, done, st);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace cteno

@@ -1,0 +1,7 @@
+// FP32 (mixed precision) instances of the reconstruction kernels of degree 2 and 3.
+#include "k_recon.inl"
+
+namespace cteno {
+template hipError_t reconstruct_lo<float>(const DeviceMesh &m, const double *U, void *FV, uint8_t *delta, int dmode,
+                                  const int *done, hipStream_t st);
+}  // namespace cteno

@@ -1,0 +1,7 @@
+// FP64 instances of the reconstruction kernels of degree 4 to 6.
+#include "k_recon_ho.inl"
+
+namespace cteno {
+template hipError_t reconstruct_hi<double>(const DeviceMesh &m, const double *U, void *FV, uint8_t *delta, int dmode,
+                                  const int *done, hipStream_t st);
+}  // namespace cteno

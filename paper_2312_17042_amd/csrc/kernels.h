@@ -1,4 +1,33 @@
-// Kernel launchers of the CTENO/CTENOZ library (implemented in kernels.hip).
+// Kernel launchers of the CTENO/CTENOZ library, implemented in k_precompute.hip
+// (pseudo-inverses), k_recon_*.hip (reconstruction, per degree range and
+// arithmetic type) and k_flux.hip (fluxes, RK stages, step control, serving
+// batches, utilities); kernels_common.h holds the shared device code.
+//
+// HIP kernels (gfx950) of the CTENO/CTENOZ finite-volume hot path.
+//
+//   k_precompute   once per mesh, FP64: reference-space moments of every
+//                  stencil cell (sec. 2.1), Householder QR of the M x K
+//                  least-squares matrix and the pseudo-inverse
+//                  P = R^-1 Q^T diag(|V'_m|), for the central stencil and
+//                  the three directional stencils; FP32 copies on request.
+//   k_reconstruct  per cell and stage: gather of neighbour averages, central
+//                  and directional products P d, p_1 (eq. e17), smoothness
+//                  indicators, CTENO (Algorithm 1) / CTENOZ (Algorithm 2)
+//                  selection, final polynomial at the face Gauss points.
+//   k_flux         per cell and stage: HLLC (sec. 2.6) or upwind flux at the
+//                  Gauss points of its three faces, the residual of the
+//                  semi-discrete form after eq. e1, and the SSP-RK3 stage;
+//                  each interior face flux is evaluated identically by both
+//                  of its cells (same operands, same order) so the update is
+//                  conservative to FP64 round-off without atomics.
+//   k_control      per RK step, one thread: time step from the reduced CFL
+//                  bound, clipping to t_final, termination.
+//
+// Memory layout: per-cell static data (stencil slots, pseudo-inverses,
+// face geometry) in 64-cell tiles, entry-major inside a tile, so a wave
+// streams each entry as one contiguous 256/512-byte segment; the state and
+// the face-point values are cell-major (array of structures) so a gather of
+// one neighbour touches one cache line.
 #pragma once
 
 #include "cteno_internal.h"
@@ -44,6 +73,16 @@ struct PrecomputeInputs {
 };
 
 hipError_t launch_precompute(const DeviceMesh &m, const PrecomputeInputs &in, hipStream_t st);
+
+// reconstruction of degree 2-3 (reconstruct_lo) and 4-6 (reconstruct_hi) in
+// arithmetic `real` (float: mixed precision; double: FP64); instantiated in
+// k_recon_f32/f64.hip and k_recon_ho_f32/f64.hip
+template <typename real>
+hipError_t reconstruct_lo(const DeviceMesh &m, const double *U, void *FV, uint8_t *delta, int dmode, const int *done,
+                          hipStream_t st);
+template <typename real>
+hipError_t reconstruct_hi(const DeviceMesh &m, const double *U, void *FV, uint8_t *delta, int dmode, const int *done,
+                          hipStream_t st);
 
 // reconstruction; dmode: 0 none, 1 write delta, 2 forced delta
 hipError_t launch_reconstruct(const DeviceMesh &m, bool fp32, const double *U, void *FV, uint8_t *delta, int dmode,
