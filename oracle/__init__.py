@@ -18,7 +18,7 @@ SRC_PATH = os.path.join(HERE, "cteno_oracle.c")
 PERIODIC, WALL, TRANSMISSIVE, INFLOW = 0, 1, 2, 3
 ADVECTION, EULER = 0, 1
 CTENO, CTENOZ, CWENO, TENO = 0, 1, 2, 3
-GAMMA_PAPER, GAMMA_LAMBDA = 0, 1
+GAMMA_PAPER, GAMMA_LAMBDA, GAMMA_SCALED = 0, 1, 2
 CONSERVED, CHARACTERISTIC = 0, 1
 
 
@@ -36,7 +36,7 @@ class _Scheme(C.Structure):
     _fields_ = [("physics", C.c_int), ("ax", C.c_double), ("ay", C.c_double), ("gamma", C.c_double),
                 ("scheme", C.c_int), ("degree", C.c_int), ("gamma_form", C.c_int),
                 ("lambda1_prime", C.c_double), ("c_t", C.c_double), ("eps", C.c_double),
-                ("variables", C.c_int)]
+                ("variables", C.c_int), ("positivity", C.c_int)]
 
 
 class _Boundary(C.Structure):
@@ -92,6 +92,9 @@ def lib():
         L.or_rk3_step.argtypes = [P, P, C.c_double, C.c_double]
         L.or_solve.argtypes = [P, P, C.c_double, C.c_double, C.c_int, C.c_double,
                                C.POINTER(C.c_int), C.POINTER(C.c_double)]
+        L.or_fallbacks.restype = C.c_longlong
+        L.or_fallbacks.argtypes = [P]
+        L.or_reset_fallbacks.argtypes = [P]
         _lib = L
     return _lib
 
@@ -109,13 +112,14 @@ class Oracle:
 
     def __init__(self, xy, tri, box, bc, physics=EULER, scheme=CTENOZ, degree=3,
                  lambda1_prime=1e4, c_t=1e-6, eps=1e-12, gamma=1.4, ax=1.0, ay=1.0,
-                 gamma_form=GAMMA_PAPER, variables=CONSERVED, boundary=None):
+                 gamma_form=GAMMA_PAPER, variables=CONSERVED, boundary=None, positivity=0):
         L = lib()
         self._xy = np.ascontiguousarray(xy, dtype=np.float64)
         self._tri = np.ascontiguousarray(tri, dtype=np.int32)
         box = np.ascontiguousarray(box, dtype=np.float64)
         bc = np.ascontiguousarray(bc, dtype=np.int32)
-        s = _Scheme(physics, ax, ay, gamma, scheme, degree, gamma_form, lambda1_prime, c_t, eps, variables)
+        s = _Scheme(physics, ax, ay, gamma, scheme, degree, gamma_form, lambda1_prime, c_t, eps, variables,
+                    int(bool(positivity)))
         bnd = _boundary(boundary)
         h = L.or_create(self._xy.shape[0], _p(self._xy), self._tri.shape[0], _p(self._tri), _p(box), _p(bc),
                         C.byref(s), C.byref(bnd) if bnd is not None else None)
@@ -244,6 +248,14 @@ class Oracle:
         self._check(lib().or_residual(self.h, _p(U), float(t), _p(R)))
         return R
 
+    def fallbacks(self, reset=False):
+        """cell reconstructions that took the positivity fallback (positivity=1)
+        since creation or the last reset"""
+        n = int(lib().or_fallbacks(self.h))
+        if reset:
+            lib().or_reset_fallbacks(self.h)
+        return n
+
     def dt_bound(self, U):
         U = np.ascontiguousarray(U, np.float64).reshape(self.nv, self.N)
         return lib().or_dt_bound(self.h, _p(U))
@@ -291,3 +303,10 @@ def euler_flux(U, n, gamma=1.4):
 
 def threads() -> int:
     return int(lib().or_threads())
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of oracle contexts created afterwards (results are
+    bitwise independent of the count)."""
+    lib().or_set_threads.argtypes = [C.c_int]
+    lib().or_set_threads(int(n))

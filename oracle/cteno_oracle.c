@@ -28,13 +28,13 @@
  *   - smoothness indicators SI_s = sum_{q=1..r} int_{V'_0} (D^q p_s)^2 (sec. 2.2);
  *   - CTENO weights (Algorithm 1) and CTENOZ weights (Algorithm 2) with the
  *     cut-off delta_s = [chi_s >= C_T] (eq. e23) and the two-branch final
- *     polynomial (sec. 2.4, 2.5);
- *   - the comparison schemes of sec. 2.2-2.3: CWENO (nonlinear weights
+ *     polynomial (sec. 2.5, 2.6);
+ *   - the comparison schemes of sec. 2.3-2.4: CWENO (nonlinear weights
  *     lambda_s / (eps + SI_s)^b with b = 4 and the linear weights of eq.
  *     e18, final polynomial sum_s omega_s p_s with p_1 from eq. e17) and
  *     TENO (the cut-off of eq. e22-e23 with gamma_s = 1/(SI_s + eps)^6 on
  *     the central-stencil polynomial itself, then the same two branches);
- *   - HLLC flux with Roe-averaged wave-speed estimates (sec. 2.6);
+ *   - HLLC flux with Roe-averaged wave-speed estimates (sec. 2.7);
  *   - third-order explicit Runge-Kutta in time (sec. 2, Shu-Osher SSP form).
  *
  * Readings where the paper is silent or ambiguous (all shared with the GPU
@@ -55,7 +55,16 @@
  *   final polynomial p_1 when delta_1 = 1 (Algorithms 1 and 2); TENO's p_1
  *     is the central-stencil least-squares polynomial (p_opt), CTENO's the
  *     decomposed one of eq. e17;
- *   eps = 1e-12 by default; N_q = ceil((r+1)/2) Gauss-Legendre points.
+ *   eps = 1e-12 by default; N_q = ceil((r+1)/2) Gauss-Legendre points;
+ *   CTENOZ's gamma_s: literally 1 + tau / (SI_s + eps) by default; as an
+ *     option (gamma_form SCALED) 1 + tau / (SI_s + eps)^6, the sixth power
+ *     that Algorithm 1's gamma_s carries, which makes the selection
+ *     independent of the scale of the indicators (the printed form is not:
+ *     tau grows like SI^6, the denominator like SI);
+ *   non-physical face states (density or pressure <= 0) are reported as an
+ *     error, as the paper has no positivity treatment; an optional fallback
+ *     (positivity = 1, not in the paper) replaces all Gauss-point values of
+ *     such a cell by its cell average and flags the cell with bit 7.
  */
 #include <math.h>
 #include <stdint.h>
@@ -75,7 +84,7 @@
 enum { OR_PERIODIC = 0, OR_WALL = 1, OR_TRANSMISSIVE = 2, OR_INFLOW = 3 };
 enum { OR_ADVECTION = 0, OR_EULER = 1 };
 enum { OR_CTENO = 0, OR_CTENOZ = 1, OR_CWENO = 2, OR_TENO = 3 };
-enum { OR_GAMMA_PAPER = 0, OR_GAMMA_LAMBDA = 1 };
+enum { OR_GAMMA_PAPER = 0, OR_GAMMA_LAMBDA = 1, OR_GAMMA_SCALED = 2 };
 enum { OR_VARS_CONSERVED = 0, OR_VARS_CHARACTERISTIC = 1 };
 
 static char or_err[512];
@@ -116,6 +125,8 @@ typedef struct {
     int physics, nv;
     double ax, ay, gam;
     int scheme, r, K, M, rd, Kd, Md, Nq, gamma_form, vars;
+    int positivity;              /* 1: cell-average fallback for non-physical face states */
+    long long n_fallback;        /* cell reconstructions that took the fallback */
     double lam1p, ct, eps;
     int ex[OR_MAXK + 1][2];      /* exponents of psi_k, k = 1..K */
     double gq[OR_MAXNQ], gw[OR_MAXNQ];
@@ -623,7 +634,11 @@ static int teno_select(const or_ctx *c, const double *si, const int *adm, double
         double tsum = 0.0;
         for (int s = 1; s < 4; ++s) if (adm[s]) tsum += fabs(si[s] - si[0]);
         double tau = pow6(tsum / (st - 1));
-        for (int s = 0; s < 4; ++s) if (adm[s]) g[s] = 1.0 + tau / (si[s] + c->eps);
+        for (int s = 0; s < 4; ++s) {
+            if (!adm[s]) continue;
+            if (c->gamma_form == OR_GAMMA_SCALED) g[s] = 1.0 + tau / pow6(si[s] + c->eps);
+            else g[s] = 1.0 + tau / (si[s] + c->eps);
+        }
     }
     for (int s = 0; s < 4; ++s) if (adm[s]) sum += g[s];
     int bits = 0;
@@ -850,10 +865,11 @@ static int reconstruct_cell(or_ctx *c, int i, const double *U, const uint8_t *fo
             }
         }
     }
-    /* positivity fallback (not in the paper): a cell whose reconstructed
-       state is non-physical at any of its Gauss points (density or pressure
-       <= 0) uses its cell average at all of them; flagged with bit 7 */
-    if (c->physics == OR_EULER) {
+    /* optional positivity fallback (not in the paper): a cell whose
+       reconstructed state is non-physical at any of its Gauss points
+       (density or pressure <= 0) uses its cell average at all of them;
+       flagged with bit 7.  Without it the flux reports the state. */
+    if (c->physics == OR_EULER && c->positivity) {
         int bad = 0;
         for (int p = 0; p < 3 * c->Nq; ++p) {
             const double *W = fv + (size_t)p * nv;
@@ -861,6 +877,8 @@ static int reconstruct_cell(or_ctx *c, int i, const double *U, const uint8_t *fo
             if (!(W[0] > 0.0) || !(pr > 0.0)) bad = 1;
         }
         if (bad) {
+#pragma omp atomic
+            c->n_fallback++;
             for (int p = 0; p < 3 * c->Nq; ++p)
                 for (int v = 0; v < nv; ++v) fv[(size_t)p * nv + v] = U[(size_t)v * N + i];
             if (dbits) {
@@ -885,7 +903,7 @@ static void euler_normal_flux(double g, const double *U, double nx, double ny, d
     F[3] = (E + p) * un;
 }
 
-/* HLLC (sec. 2.6) in the face-normal frame: u normal, w tangential velocity */
+/* HLLC (sec. 2.7) in the face-normal frame: u normal, w tangential velocity */
 static int hllc(double g, const double *UL, const double *UR, double nx, double ny, double *F) {
     double rl = UL[0], rr = UR[0];
     double ul = (UL[1] * nx + UL[2] * ny) / rl, wl = (-UL[1] * ny + UL[2] * nx) / rl;
@@ -1045,6 +1063,7 @@ typedef struct {
     int scheme, degree, gamma_form;
     double lambda1_prime, c_t, eps;
     int variables;                 /* OR_VARS_CONSERVED | OR_VARS_CHARACTERISTIC */
+    int positivity;                /* 1: optional cell-average fallback (not in the paper) */
 } or_scheme;
 
 void or_destroy(or_ctx *c) {
@@ -1110,6 +1129,10 @@ or_ctx *or_create(int nvert, const double *xy, int ncell, const int *tri, const 
         }
     c->scheme = sch->scheme; c->r = sch->degree; c->gamma_form = sch->gamma_form;
     c->vars = sch->variables;
+    c->positivity = sch->positivity;
+    if (c->gamma_form == OR_GAMMA_SCALED && c->scheme != OR_CTENOZ) {
+        set_err("the scaled gamma form belongs to CTENOZ", c->gamma_form); or_destroy(c); return NULL;
+    }
     if (c->vars == OR_VARS_CHARACTERISTIC && c->physics != OR_EULER) {
         set_err("characteristic variables need the Euler equations", 0); or_destroy(c); return NULL;
     }
@@ -1152,7 +1175,8 @@ or_ctx *or_create(int nvert, const double *xy, int ncell, const int *tri, const 
     free(cx); free(cy);
     c->cells = calloc((size_t)ncell, sizeof(or_cell *));
 #ifdef _OPENMP
-    c->nthreads = omp_get_max_threads();
+    /* per-thread stamps for as many threads as a later or_set_threads may start */
+    c->nthreads = omp_get_max_threads() > omp_get_num_procs() ? omp_get_max_threads() : omp_get_num_procs();
 #else
     c->nthreads = 1;
 #endif
@@ -1469,6 +1493,21 @@ int or_solve(or_ctx *c, double *U, double t0, double t_final, int max_steps, dou
     *steps = n;
     *t_out = t;
     return rc;
+}
+
+/* number of cell reconstructions that took the positivity fallback since
+   the context was created or the count was reset */
+long long or_fallbacks(const or_ctx *c) { return c->n_fallback; }
+void or_reset_fallbacks(or_ctx *c) { c->n_fallback = 0; }
+
+/* threads of the OpenMP loops of contexts created from now on (timing only:
+   results do not depend on it) */
+void or_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
 }
 
 int or_threads(void) {

@@ -1015,12 +1015,14 @@ def test_sod_converges_without_overshoot(variables):
     """Literal CTENO on the x-split Sod problem (walls in y, transmissive in x)
     converges to the exact Riemann solution: L1 density error falls under
     refinement and the density stays within the initial bounds to 1%, in
-    conserved and in characteristic variables (the paper's choice for Sod)."""
+    conserved and in characteristic variables (the paper's choice for Sod).
+    The 48 x 12 mesh needs the optional positivity fallback (see
+    test_positivity_fallback_is_an_option), so both meshes run with it."""
     errs = []
     for nx, ny in ((24, 6), (48, 12)):
         m, u0 = W.sod_case(nx, ny, seed=3)
         o = O.Oracle.from_mesh(m, physics=O.EULER, scheme=O.CTENO, degree=3, lambda1_prime=1e15,
-                               variables=variables)
+                               variables=variables, positivity=1)
         U, steps, t = o.solve(u0, 0.2, cfl=0.3)
         assert abs(t - 0.2) < 1e-14
         ue = W.cell_average(m, W.sod_exact(0.2), n=6)
@@ -1028,3 +1030,224 @@ def test_sod_converges_without_overshoot(variables):
         errs.append(float((np.abs(U[0] - ue[0]) * ar).sum() / ar.sum()))
         assert U[0].max() <= 1.01 and U[0].min() >= 0.125 * 0.99
     assert errs[1] < 0.75 * errs[0]
+
+
+# ----------------------------------------------------------------------------
+# positivity: reported by default, the fallback only on request
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("variables", [O.CONSERVED, O.CHARACTERISTIC])
+def test_positivity_fallback_is_an_option(variables):
+    """The paper has no positivity treatment.  Without the fallback a Sod
+    step on 48 x 12 raises a non-physical face state: one jittered cell cut
+    by the initial jump (average density 0.20) reconstructs a negative
+    density from its three directional stencils, which all straddle the
+    jump.  With the fallback the same step runs, and exactly that cell takes
+    it in the first stage (bit 7, counted)."""
+    m, u0 = W.sod_case(48, 12, seed=3)
+    kw = dict(physics=O.EULER, scheme=O.CTENO, degree=3, lambda1_prime=1e15, variables=variables)
+    off = O.Oracle.from_mesh(m, **kw)
+    on = O.Oracle.from_mesh(m, positivity=1, **kw)
+    dt = 0.3 * off.dt_bound(u0)
+    with pytest.raises(O.OracleError, match="non-physical"):
+        off.rk3_step(u0, dt)
+    fv_off, d_off = off.reconstruct(u0)
+    fv_on, d_on = on.reconstruct(u0)
+    flagged = np.where((d_on.reshape(m.n_cells, -1) & 0x80).any(1))[0]
+    assert len(flagged) == 1 and on.fallbacks(reset=True) == 1
+    i = flagged[0]
+    assert not (d_off & 0x80).any() and off.fallbacks() == 0
+    g = 0.4
+    p = g * (fv_off[i, ..., 3] - 0.5 * (fv_off[i, ..., 1] ** 2 + fv_off[i, ..., 2] ** 2) / fv_off[i, ..., 0])
+    assert min(fv_off[i, ..., 0].min(), p.min()) <= 0.0
+    assert np.array_equal(fv_on[i], np.broadcast_to(u0[:, i], fv_on[i].shape))
+    others = np.arange(m.n_cells) != i
+    assert np.array_equal(fv_on[others], fv_off[others])
+    U = on.rk3_step(u0, dt)
+    assert np.isfinite(U).all() and on.fallbacks() >= 1
+
+
+def test_positivity_fallback_idle_on_smooth_data():
+    """On the smooth vortex the fallback never fires and changes nothing."""
+    m, u0 = W.vortex_case(12, seed=2)
+    a = O.Oracle.from_mesh(m, physics=O.EULER, scheme=O.CTENOZ, degree=3)
+    b = O.Oracle.from_mesh(m, physics=O.EULER, scheme=O.CTENOZ, degree=3, positivity=1)
+    ua, _, _ = a.solve(u0, 10.0, max_steps=3)
+    ub, _, _ = b.solve(u0, 10.0, max_steps=3)
+    assert np.array_equal(ua, ub) and b.fallbacks() == 0
+
+
+# ----------------------------------------------------------------------------
+# time step: closed forms of the CFL bound
+# ----------------------------------------------------------------------------
+
+def _perimeter_area_extent(m, direction):
+    """Per cell, from its vertices only: perimeter, area (shoelace) and the
+    extent of the triangle across `direction` (max - min of the vertices'
+    coordinate along the perpendicular)."""
+    P = m.xy[m.tri]                                   # [N][3][2]
+    E = np.roll(P, -1, axis=1) - P
+    perim = np.hypot(E[..., 0], E[..., 1]).sum(1)
+    area = 0.5 * np.abs(E[:, 0, 0] * E[:, 1, 1] - E[:, 0, 1] * E[:, 1, 0])
+    e = np.asarray(direction, float) / np.hypot(*direction)
+    q = P[..., 0] * -e[1] + P[..., 1] * e[0]
+    return perim, area, q.max(1) - q.min(1)
+
+
+def test_dt_bound_closed_forms():
+    """The time-step bound min_i 2|V_i| / sum_f |A_f| (|v.n_f| + c) in closed
+    form.  For a convex cell, sum_f |A_f| |e.n_f| = 2 x (extent of the cell
+    across the unit direction e): edges going up and down each cover the
+    extent once.  So with a uniform state of velocity V and sound speed c
+    the bound is min_i 2|V_i| / (c P_i + 2|V| w_i), P the perimeter and w
+    the extent across V; at rest it is the inradius over c, which on an
+    unjittered split grid of squares of side h is h (2 - sqrt 2) / (2 c);
+    for advection with velocity a it is min_i |V_i| / (|a| w_i)."""
+    g = 1.4
+    rho, p = 1.3, 0.7
+    c = math.sqrt(g * p / rho)
+    n = 8
+    flat = W.split_jitter_mesh(n, n, seed=4, jitter=0.0)
+    o = O.Oracle.from_mesh(flat, physics=O.EULER, scheme=O.CTENOZ, degree=2)
+    U = np.tile(np.array(W.prim_to_cons(rho, 0.0, 0.0, p))[:, None], (1, flat.n_cells))
+    h = 1.0 / n
+    assert abs(o.dt_bound(U) - h * (2.0 - math.sqrt(2.0)) / (2.0 * c)) <= 1e-14 * h
+    m = W.split_jitter_mesh(10, 10, seed=6)
+    o = O.Oracle.from_mesh(m, physics=O.EULER, scheme=O.CTENOZ, degree=2)
+    for u, v in ((0.0, 0.0), (0.8, 0.0), (-0.3, 1.7), (2.5, -2.5)):
+        U = np.tile(np.array(W.prim_to_cons(rho, u, v, p))[:, None], (1, m.n_cells))
+        sp = math.hypot(u, v)
+        perim, area, w = _perimeter_area_extent(m, (u, v) if sp > 0 else (1.0, 0.0))
+        expect = (2.0 * area / (c * perim + 2.0 * sp * w)).min()
+        assert abs(o.dt_bound(U) - expect) <= 1e-13 * expect, (u, v)
+    ax, ay = 0.6, -1.1
+    oa = O.Oracle.from_mesh(m, physics=O.ADVECTION, scheme=O.CTENOZ, degree=2, ax=ax, ay=ay)
+    perim, area, w = _perimeter_area_extent(m, (ax, ay))
+    expect = (area / (math.hypot(ax, ay) * w)).min()
+    assert abs(oa.dt_bound(np.ones((1, m.n_cells))) - expect) <= 1e-13 * expect
+
+
+def test_rk3_stability_polynomial():
+    """On a linear problem one SSP-RK3 step multiplies by 1 + z + z^2/2 +
+    z^3/6, z = dt L: with every cell selecting its central stencil the
+    semi-discrete advection operator L is linear, so the step equals
+    U + dt L U + dt^2/2 L^2 U + dt^3/6 L^3 U to round-off.  A cut-off C_T
+    below any attainable chi (>= 1e-72 here) keeps p_1 in every cell.  A
+    wrong stage coefficient or stage input breaks the identity at O(dt^2)."""
+    m, u0 = W.advection_case(12, seed=1)
+    o = O.Oracle.from_mesh(m, physics=O.ADVECTION, scheme=O.CTENO, degree=2, lambda1_prime=1e15, c_t=1e-300)
+    terms = [u0]
+    for _ in range(3):
+        _, dl = o.reconstruct(terms[-1])
+        assert (dl & 1).all(), "central stencil everywhere"
+        terms.append(o.residual(terms[-1]))
+    dt = 0.3 * o.dt_bound(u0)
+    step = o.rk3_step(u0, dt)
+    poly = terms[0] + dt * terms[1] + dt ** 2 / 2 * terms[2] + dt ** 3 / 6 * terms[3]
+    assert np.abs(step - poly).max() <= 1e-13 * np.abs(u0).max()
+    # the second-order truncation differs visibly: the identity is sharp
+    assert np.abs(step - (terms[0] + dt * terms[1] + dt ** 2 / 2 * terms[2])).max() > 1e3 * 1e-13
+
+
+# ----------------------------------------------------------------------------
+# CTENOZ, scaled reading of Algorithm 2's gamma (gamma_form SCALED)
+# ----------------------------------------------------------------------------
+
+def test_scaled_ctenoz_selection():
+    """gamma_s = 1 + tau / (SI_s + eps)^6, tau = (mean_s |SI_s - SI_1|)^6:
+    equal indicators keep every stencil (tau = 0, chi_s = 1/s_t); a rough
+    centre with smooth sectors drops the centre; the bits do not change when
+    all indicators are scaled by the same factor, while the printed form's
+    do (its tau grows like SI^6 against a denominator like SI)."""
+    m = W.split_jitter_mesh(6, 6, seed=1)
+    sc = O.Oracle.from_mesh(m, physics=O.ADVECTION, scheme=O.CTENOZ, gamma_form=O.GAMMA_SCALED)
+    lit = O.Oracle.from_mesh(m, physics=O.ADVECTION, scheme=O.CTENOZ)
+    adm = (1, 1, 1, 1)
+    assert sc.select([0.3, 0.3, 0.3, 0.3], adm) == 0b1111
+    assert sc.select([1.0, 1e-3, 1e-3, 1e-3], adm) == 0b1110
+    assert sc.select([1e-3, 1.0, 1e-3, 1e-3], adm) & 1        # rough sector only: keep the centre
+    assert not sc.select([1e-3, 1.0, 1e-3, 1e-3], adm) & 0b0010
+    rng = np.random.default_rng(5)
+    for _ in range(400):
+        si = 10.0 ** rng.uniform(-6, 1, size=4)
+        b0 = sc.select(si, adm)
+        for k in (-2, 2):
+            assert sc.select(si * 10.0 ** k, adm) == b0
+    # a rough centre next to smooth sectors: the scaled form drops the centre
+    # at every scale; the printed form only at the larger one
+    si = np.array([1.0, 1e-7, 1e-7, 1e-7])
+    for k in (-2, 0, 2):
+        assert sc.select(si * 10.0 ** k, adm) == 0b1110
+    assert lit.select(si, adm) == 0b1110
+    assert lit.select(si * 1e-2, adm) & 1
+    with pytest.raises(O.OracleError):
+        O.Oracle.from_mesh(m, physics=O.ADVECTION, scheme=O.CTENO, gamma_form=O.GAMMA_SCALED)
+
+
+def test_scaled_ctenoz_loses_table2_order_like_cteno():
+    """The scaled reading compares indicators by their ratios, as Algorithm 1
+    does, so in smooth regions it drops the central stencil near extrema of
+    the density wave where a directional indicator is much smaller: it
+    loses the design order there like literal CTENO (Table 1: CTENO4 at
+    lambda1' = 1e4 degrades to 1.79), while the printed CTENOZ keeps the
+    central stencil and its order (Table 2: CTENOZ3 3.00).  So this reading
+    does not reproduce Table 2; the printed one does."""
+    fr = {}
+    for name, kw in (("scaled", dict(scheme=O.CTENOZ, gamma_form=O.GAMMA_SCALED)),
+                     ("printed", dict(scheme=O.CTENOZ)), ("cteno", dict(scheme=O.CTENO))):
+        m, u0 = W.density_wave_case(20, seed=11)
+        o = O.Oracle.from_mesh(m, physics=O.EULER, degree=2, lambda1_prime=1e4, **kw)
+        _, d = o.reconstruct(u0)
+        fr[name] = float((d & 1 == 0).mean())
+    assert fr["printed"] == 0.0 and fr["scaled"] > 0.1 and fr["cteno"] > 0.1
+    orders = {}
+    for name, gf in (("scaled", O.GAMMA_SCALED), ("printed", O.GAMMA_PAPER)):
+        errs = []
+        for n in (10, 20):
+            m, u0 = W.density_wave_case(n, seed=11)
+            o = O.Oracle.from_mesh(m, physics=O.EULER, scheme=O.CTENOZ, degree=2, lambda1_prime=1e4, gamma_form=gf)
+            T = 0.1
+            ns = int(math.ceil(T / (0.3 * o.dt_bound(u0))))
+            U = u0.copy()
+            for _ in range(ns):
+                U = o.rk3_step(U, T / ns)
+            ue = W.cell_average(m, W.density_wave(T))
+            errs.append(math.sqrt(((U[0] - ue[0]) ** 2 * W.cell_areas(m)).sum()))
+        orders[name] = _orders(errs)[0]
+    assert orders["scaled"] < 2.2 and orders["printed"] > 2.6, orders
+
+
+def test_scaled_ctenoz_detects_the_sod_jump():
+    """At the initial Sod jump (96 x 24, characteristic variables, the
+    paper's setup for Sod) the printed CTENOZ keeps the central stencil where
+    the solution jumps and reconstructs non-physical states in 26 cells; the
+    scaled reading, like CTENO, drops it there and stays physical."""
+    m, u0 = W.sod_case(96, 24, seed=3)
+    kw = dict(physics=O.EULER, scheme=O.CTENOZ, degree=3, lambda1_prime=1e4, variables=O.CHARACTERISTIC,
+              positivity=1)
+    lit = O.Oracle.from_mesh(m, **kw)
+    sc = O.Oracle.from_mesh(m, gamma_form=O.GAMMA_SCALED, **kw)
+    lit.reconstruct(u0)
+    _, d = sc.reconstruct(u0)
+    assert lit.fallbacks() >= 20 and sc.fallbacks() == 0
+    cx = m.xy[m.tri].mean(1)[:, 0]
+    near = np.abs(cx - 0.5) < 1.0 / 96
+    assert not (d[near] & 1).all()          # the centre is dropped at the jump
+
+
+@pytest.mark.slow
+def test_scaled_ctenoz_sod_to_t02_without_fallback():
+    """Sod on 96 x 24 in characteristic variables with the scaled reading and
+    no positivity fallback stays physical to t = 0.2 (sec. 3.2: the paper
+    runs CTENOZ on the shock tube), converging towards the exact solution
+    without overshoot above 1 %."""
+    m, u0 = W.sod_case(96, 24, seed=3)
+    o = O.Oracle.from_mesh(m, physics=O.EULER, scheme=O.CTENOZ, degree=3, lambda1_prime=1e4,
+                           variables=O.CHARACTERISTIC, gamma_form=O.GAMMA_SCALED)
+    U, steps, t = o.solve(u0, 0.2, cfl=0.3)
+    assert t == 0.2
+    ue = W.cell_average(m, W.sod_exact(0.2), n=6)
+    ar = W.cell_areas(m)
+    err = float((np.abs(U[0] - ue[0]) * ar).sum() / ar.sum())
+    assert err < 4e-3
+    assert U[0].max() <= 1.01 and U[0].min() >= 0.125 * 0.99
