@@ -56,7 +56,7 @@ typedef enum {
 enum { CTENO_PERIODIC = 0, CTENO_WALL = 1, CTENO_TRANSMISSIVE = 2, CTENO_INFLOW = 3 };
 /* physics */
 enum { CTENO_ADVECTION = 0, CTENO_EULER = 1 };
-/* weighting scheme: CTENO = Algorithm 1 (sec. 2.4), CTENOZ = Algorithm 2 (sec. 2.5) */
+/* weighting scheme: CTENO = Algorithm 1 (sec. 2.5), CTENOZ = Algorithm 2 (sec. 2.6) */
 /* Reconstructed variables: conserved variables component-wise, or per face
    the characteristic fields W = L_f U of the Euler flux Jacobian along the
    face normal at the cell's average state (sec. 2.2 recommends them for
@@ -65,12 +65,17 @@ enum { CTENO_ADVECTION = 0, CTENO_EULER = 1 };
 enum { CTENO_VARS_CONSERVED = 0, CTENO_VARS_CHARACTERISTIC = 1 };
 
 /* CTENO: Algorithm 1; CTENOZ: Algorithm 2; CWENO and TENO: the paper's
-   comparison schemes (sec. 2.2-2.3) in the same pipeline */
+   comparison schemes (sec. 2.3-2.4) in the same pipeline */
 enum { CTENO_SCHEME_CTENO = 0, CTENO_SCHEME_CTENOZ = 1, CTENO_SCHEME_CWENO = 2, CTENO_SCHEME_TENO = 3 };
-/* CTENO scale-separation form: PAPER = gamma_s = 1/(SI_s+eps)^6 exactly as in
-   Algorithm 1; LAMBDA = gamma_s = lambda_s/(SI_s+eps)^6 (linear weights of
-   eq. e18 included) */
-enum { CTENO_GAMMA_PAPER = 0, CTENO_GAMMA_LAMBDA = 1 };
+/* Scale-separation form (gamma_s of the selection).  PAPER: as printed --
+   CTENO gamma_s = 1/(SI_s+eps)^6 (Algorithm 1), CTENOZ gamma_s =
+   1 + tau/(SI_s+eps) with tau = (mean_s |SI_s - SI_1|)^6 (Algorithm 2).
+   LAMBDA (CTENO only): gamma_s = lambda_s/(SI_s+eps)^6, the linear weights
+   of eq. e18 included.  SCALED (CTENOZ only): gamma_s = 1 + tau/(SI_s+eps)^6,
+   the sixth power that Algorithm 1 puts on the denominator, which makes the
+   selection independent of the scale of the indicators (the printed form is
+   not: tau grows like SI^6, the denominator like SI). */
+enum { CTENO_GAMMA_PAPER = 0, CTENO_GAMMA_LAMBDA = 1, CTENO_GAMMA_SCALED = 2 };
 /* arithmetic of the reconstruction, weights and fluxes.  The cell-average
    state, the residual accumulation and the Runge-Kutta update are always
    FP64; MIXED runs reconstruction, smoothness indicators, weights and HLLC
@@ -103,7 +108,7 @@ typedef struct {
        alone for advection): `behind` at Gauss points (x, y) with
        x < line[0] + line[1] y + line[2] t at the stage time t, `ahead`
        elsewhere -- a straight discontinuity moving in x, such as the incident
-       shock of the double Mach reflection (sec. 3.4); a constant inflow sets
+       shock of the double Mach reflection (sec. 3.3); a constant inflow sets
        behind = ahead.  Both must be physical (density, pressure > 0) when a
        side is INFLOW. */
     double behind[4], ahead[4];
@@ -116,17 +121,21 @@ typedef struct {
     double split_at[4];
 } cteno_mesh_desc;
 
-/* Scheme parameters (sec. 2.1-2.6).  degree r in 2..6: the central
+/* Scheme parameters (sec. 2.1-2.7).  degree r in 2..6: the central
    polynomial of degree r gives order r+1 and uses M = 2K neighbours,
    K = (r+1)(r+2)/2 - 1; directional polynomials have degree r_d = 1 up to
    r = 3 and ceil(r/2) above (K_d basis functions, M_d = 2 K_d cells);
-   N_q = ceil((r+1)/2) Gauss-Legendre points per face.  For the Euler equations a cell whose
-   reconstructed density or pressure is <= 0 at any Gauss point uses its
-   cell average at all of them (a positivity fallback the paper does not
-   describe; flagged by bit 7 of the selection bytes).
+   N_q = ceil((r+1)/2) Gauss-Legendre points per face.
    lambda1_prime: eq. e18; c_t: cut-off of eq. e23 (paper: 1e-6); eps: the
    regulariser of the smoothness indicators (not given by the paper; 1e-12
-   recommended). */
+   recommended).
+   positivity (Euler only): 0 (the paper's scheme, which has no positivity
+   treatment) -- a non-physical face state (density or pressure <= 0, or
+   NaN) is reported as CTENO_ERR_NONPHYSICAL; 1 -- an optional fallback the
+   paper does not describe: a cell whose reconstructed density or pressure
+   is <= 0 at any Gauss point uses its cell average at all of them, flagged
+   by bit 7 of its selection bytes and counted (cteno_sol_fallbacks,
+   cteno_request_info.fallbacks). */
 typedef struct {
     int32_t physics;
     double ax, ay;          /* advection velocity (ADVECTION) */
@@ -140,6 +149,7 @@ typedef struct {
     int32_t precision;      /* CTENO_FP64 | CTENO_MIXED | CTENO_BOTH */
     int32_t reorder;        /* 1: Morton-order cells internally for locality; 0: keep order */
     int32_t variables;      /* CTENO_VARS_CONSERVED | CTENO_VARS_CHARACTERISTIC (Euler only) */
+    int32_t positivity;     /* 0: report non-physical states (default); 1: cell-average fallback */
 } cteno_scheme;
 
 typedef struct {
@@ -211,15 +221,22 @@ cteno_status cteno_sol_create(cteno_ctx *ctx, const cteno_mesh *mesh, const doub
 /* Replaces the state with host u [nv][n_cells] and sets the time. */
 cteno_status cteno_sol_set(cteno_sol *sol, const double *u, double t);
 /* Copies the state to host u [nv][n_cells] (may be NULL) and the time to *t
-   (may be NULL).  Synchronises and reports pending device errors. */
+   (may be NULL).  Synchronises and reports pending device errors; returns
+   CTENO_ERR_NONPHYSICAL (outputs written) once if a cteno_rk_stage call
+   since the last report met a non-physical face state. */
 cteno_status cteno_sol_download(cteno_sol *sol, double *u, double *t);
+/* Number of cell reconstructions (cells x stages) of this solution that
+   took the positivity fallback (scheme.positivity = 1) since it was created
+   or last set, over cteno_reconstruct, cteno_residual, cteno_rk_stage and
+   cteno_solve.  Synchronises. */
+cteno_status cteno_sol_fallbacks(cteno_sol *sol, int64_t *count);
 void cteno_sol_destroy(cteno_sol *sol);
 
 /* ---------------------------------------------------------------------- */
 /* stage kernels (low level; outputs in caller cell order)                 */
 /* ---------------------------------------------------------------------- */
 
-/* Reconstruction of the current state of `sol` (sec. 2.1-2.5): central and
+/* Reconstruction of the current state of `sol` (sec. 2.1-2.6): central and
    directional least-squares polynomials, p_1 (eq. e17), smoothness
    indicators, CTENO/CTENOZ selection and the final polynomial, evaluated at
    the N_q Gauss points of each face.
@@ -229,28 +246,31 @@ void cteno_sol_destroy(cteno_sol *sol);
    delta_out: device [n_cells][nv] ([n_cells][3][nv] per face and field with
    characteristic variables) or NULL: bit 0 = delta_1 (central),
    bit 1+f = delta of the directional stencil of face f, bit 7 = positivity
-   fallback taken.
+   fallback taken (scheme.positivity = 1 only).
    delta_forced: device, same layout as delta_out, or NULL: use these selections instead
    of computing them (bits of inadmissible stencils are ignored). */
 cteno_status cteno_reconstruct(cteno_ctx *ctx, const cteno_mesh *mesh, const cteno_sol *sol, int32_t precision,
                                void *face_vals, uint8_t *delta_out, const uint8_t *delta_forced);
-/* Face fluxes from face-point values (sec. 2.6, HLLC for Euler, upwind for
+/* Face fluxes from face-point values (sec. 2.7, HLLC for Euler, upwind for
    advection), integrated over each face with the Gauss weights:
    face_flux: device [n_cells][3][nv] (FP64 or FP32 by precision), the
    outward flux of cell i through its face f, times |A_f|.  t is the time of
-   the prescribed states of INFLOW faces. */
+   the prescribed states of INFLOW faces.  Synchronises; a non-physical face
+   state returns CTENO_ERR_NONPHYSICAL (the fluxes are still written). */
 cteno_status cteno_flux(cteno_ctx *ctx, const cteno_mesh *mesh, int32_t precision, const void *face_vals,
                         double t, void *face_flux);
 /* Residual dU/dt = -(1/|V_i|) sum_f outward flux (the semi-discrete form
    after eq. e1) of the current state at the solution's time:
-   resid device [nv][n_cells] FP64. */
+   resid device [nv][n_cells] FP64.  Synchronises; a non-physical face state
+   returns CTENO_ERR_NONPHYSICAL (the residual is still written). */
 cteno_status cteno_residual(cteno_ctx *ctx, const cteno_mesh *mesh, const cteno_sol *sol, int32_t precision,
                             double *resid);
 /* One SSP-RK3 stage (Shu-Osher form) of size dt on `sol`: stage 0 forms
    U1 = U + dt R(U), stage 1 U2 = 3/4 U + 1/4 (U1 + dt R(U1)), stage 2
    U <- 1/3 U + 2/3 (U2 + dt R(U2)).  Stages must be issued 0, 1, 2; the
    residuals are those of the times t, t + dt and t + dt/2 (t the solution's
-   time, advanced by dt after stage 2). */
+   time, advanced by dt after stage 2).  Asynchronous: a non-physical face
+   state is reported by the next cteno_sol_download. */
 cteno_status cteno_rk_stage(cteno_ctx *ctx, const cteno_mesh *mesh, cteno_sol *sol, int32_t precision, int32_t stage,
                             double dt);
 
@@ -284,7 +304,23 @@ typedef struct {
     int64_t ticks;                  /* batched SSP-RK3 steps launched */
     int64_t cell_stages;            /* cells x stages of finished solves */
     int64_t bytes_in_use, peak_bytes, budget_bytes;
+    int64_t fallbacks;              /* cells x stages of finished solves that took the positivity fallback */
 } cteno_server_stats;
+
+/* One request as the server saw it.  Times in seconds: build_s from
+   submission until its host mesh and stencils were built, queue_s from then
+   until admission, admit_s for the upload and the FP64 pseudo-inverse
+   precompute, run_s from then until its result was on the host (steps,
+   waiting for the batched ticks, result copy); latency_s = submission to
+   result.  Stages not reached yet read 0. */
+typedef struct {
+    int32_t state;                  /* CTENO_REQ_* */
+    int32_t status;                 /* CTENO_OK, or the error of a FAILED request */
+    int64_t n_cells;
+    int64_t steps_done;
+    int64_t fallbacks;              /* cells x stages that took the positivity fallback */
+    double latency_s, build_s, queue_s, admit_s, run_s;
+} cteno_request_info;
 
 enum { CTENO_REQ_QUEUED = 0, CTENO_REQ_READY = 1, CTENO_REQ_RUNNING = 2, CTENO_REQ_DONE = 3, CTENO_REQ_FAILED = 4 };
 
@@ -317,6 +353,9 @@ cteno_status cteno_server_poll(cteno_server *server, uint64_t ticket, int32_t *s
 /* Blocks until every submitted request has finished or failed. */
 cteno_status cteno_server_drain(cteno_server *server);
 cteno_status cteno_server_get_stats(cteno_server *server, cteno_server_stats *stats);
+/* State, counts and latency split of a request that has not been released
+   (a DONE request is released by cteno_server_poll with u_out). */
+cteno_status cteno_server_request_info(cteno_server *server, uint64_t ticket, cteno_request_info *info);
 /* Stops the threads (queued requests are dropped) and frees everything. */
 void cteno_server_destroy(cteno_server *server);
 

@@ -133,6 +133,7 @@ struct Ctrl {
     unsigned long long dt_cand_bits;   // min over cells of the dt bound (bits of a positive double)
     long long step, max_steps;
     int done, pending, nonphysical, pad;
+    unsigned long long fallbacks;      // cells x stages that took the positivity fallback
 };
 
 }  // namespace cteno

@@ -5,19 +5,19 @@
 namespace cteno {
 
 hipError_t launch_reconstruct(const DeviceMesh &m, bool fp32, const double *U, void *FV, uint8_t *delta, int dmode,
-                              const int *done, hipStream_t st) {
+                              const int *done, hipStream_t st, unsigned long long *fb_count) {
     if (m.r >= 4)
-        return fp32 ? reconstruct_hi<float>(m, U, FV, delta, dmode, done, st)
-                    : reconstruct_hi<double>(m, U, FV, delta, dmode, done, st);
-    return fp32 ? reconstruct_lo<float>(m, U, FV, delta, dmode, done, st)
-                : reconstruct_lo<double>(m, U, FV, delta, dmode, done, st);
+        return fp32 ? reconstruct_hi<float>(m, U, FV, delta, dmode, done, st, fb_count)
+                    : reconstruct_hi<double>(m, U, FV, delta, dmode, done, st, fb_count);
+    return fp32 ? reconstruct_lo<float>(m, U, FV, delta, dmode, done, st, fb_count)
+                : reconstruct_lo<double>(m, U, FV, delta, dmode, done, st, fb_count);
 }
 
 template <typename real, int NV, int PHYS, int MODE, int NQ>
 __global__ __launch_bounds__(256) void k_flux(const FluxArgs<real> a) {
     const int64_t i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (a.ctrl && a.ctrl->done) return;        // uniform across the grid
-    const FluxPtrs<real> ptr{a.FV, a.fr, a.area, a.Un, a.Us, a.Uout, a.dt_ptr, a.flux_out, a.resid, a.ctrl,
+    const FluxPtrs<real> ptr{a.FV, a.fr, a.area, a.Un, a.Us, a.Uout, a.dt_ptr, a.flux_out, a.resid, a.nonphys,
                              a.dt_part != nullptr};
     double dtc = INFINITY;
     if (i < a.N) dtc = flux_body<real, NV, PHYS, MODE, NQ>(a, ptr, i);
@@ -40,6 +40,7 @@ static hipError_t flux_t(const DeviceMesh &m, const FluxLaunch &f, hipStream_t s
     a.flux_out = (real *)f.flux_out;
     a.resid = f.resid;
     a.ctrl = f.ctrl;
+    a.nonphys = f.nonphys ? f.nonphys : (f.ctrl ? &f.ctrl->nonphysical : nullptr);
     a.dt_part = f.dt_part;
     a.gamma = (real)m.gamma; a.ax = (real)m.ax; a.ay = (real)m.ay;
     a.gamma64 = m.gamma;
@@ -198,7 +199,7 @@ __global__ __launch_bounds__(256) void k_reconstruct_batch(const ReconArgs<float
     if (t.ctrl->done) return;
     const int64_t i = (b - t.block0) * blockDim.x + threadIdx.x;
     if (i >= t.N) return;
-    const ReconPtrs<float> ptr{t.U[stage], t.slot, t.flags, t.P, t.FV, nullptr, nullptr};
+    const ReconPtrs<float> ptr{t.U[stage], t.slot, t.flags, t.P, t.FV, nullptr, nullptr, &t.ctrl->fallbacks};
     recon_body<float, R, 4, SCHEME, GFORM, 0, 0>(a, ptr, i);
 }
 
@@ -212,7 +213,7 @@ __global__ __launch_bounds__(256) void k_flux_batch(const FluxArgs<float> a, con
     const int64_t local = b - t.block0;
     const int64_t i = local * blockDim.x + threadIdx.x;
     const FluxPtrs<float> ptr{t.FV, t.fr, t.area, t.U[0], t.U[stage], stage == 2 ? t.U[0] : t.U[stage + 1],
-                              &t.ctrl->dt, nullptr, nullptr, t.ctrl, stage == 2};
+                              &t.ctrl->dt, nullptr, nullptr, &t.ctrl->nonphysical, stage == 2};
     double dtc = INFINITY;
     if (i < t.N) dtc = flux_body<float, 4, CTENO_EULER, 2, 2>(a, ptr, i);
     if (stage == 2) {
@@ -243,7 +244,10 @@ static hipError_t batch_step_r(const DeviceMesh &proto, const BatchSlot *tab, co
     fa.gw[2] = fa.gw[3] = 0.0f;
     hipLaunchKernelGGL(k_control_batch, dim3(max_slots), dim3(1024), 0, st, tab, n_slots);
     for (int stage = 0; stage < 3; ++stage) {
-        if (proto.scheme == CTENO_SCHEME_CTENOZ)
+        if (proto.scheme == CTENO_SCHEME_CTENOZ && proto.gamma_form == CTENO_GAMMA_SCALED)
+            hipLaunchKernelGGL((k_reconstruct_batch<R, CTENO_SCHEME_CTENOZ, CTENO_GAMMA_SCALED>), dim3(max_blocks),
+                               dim3(256), 0, st, ra, tab, n_slots, stage);
+        else if (proto.scheme == CTENO_SCHEME_CTENOZ)
             hipLaunchKernelGGL((k_reconstruct_batch<R, CTENO_SCHEME_CTENOZ, CTENO_GAMMA_PAPER>), dim3(max_blocks),
                                dim3(256), 0, st, ra, tab, n_slots, stage);
         else if (proto.scheme == CTENO_SCHEME_CWENO)

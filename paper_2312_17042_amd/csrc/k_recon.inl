@@ -11,7 +11,7 @@ __global__ __launch_bounds__(256) void k_reconstruct(const ReconArgs<real, (R + 
     const int64_t i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= a.N) return;
     if (a.done && *a.done) return;
-    const ReconPtrs<real> ptr{a.U, a.slot, a.flags, a.P, a.FV, a.delta, a.fr};
+    const ReconPtrs<real> ptr{a.U, a.slot, a.flags, a.P, a.FV, a.delta, a.fr, a.fb_count};
     recon_body<real, R, NV, SCHEME, GFORM, DMODE, VARS>(a, ptr, i);
 }
 
@@ -27,7 +27,8 @@ static void reconstruct_launch(const DeviceMesh &m, const ReconArgs<real, (R + 1
         case 1: CT_LAUNCH(SCH, GF, 1); break; \
         default: CT_LAUNCH(SCH, GF, 2); break; \
     }
-    if (m.scheme == CTENO_SCHEME_CTENOZ) { CT_DM(CTENO_SCHEME_CTENOZ, CTENO_GAMMA_PAPER); }
+    if (m.scheme == CTENO_SCHEME_CTENOZ && m.gamma_form == CTENO_GAMMA_SCALED) { CT_DM(CTENO_SCHEME_CTENOZ, CTENO_GAMMA_SCALED); }
+    else if (m.scheme == CTENO_SCHEME_CTENOZ) { CT_DM(CTENO_SCHEME_CTENOZ, CTENO_GAMMA_PAPER); }
     else if (m.scheme == CTENO_SCHEME_CWENO) { CT_DM(CTENO_SCHEME_CWENO, CTENO_GAMMA_PAPER); }
     else if (m.scheme == CTENO_SCHEME_TENO) { CT_DM(CTENO_SCHEME_TENO, CTENO_GAMMA_PAPER); }
     else if (m.gamma_form == CTENO_GAMMA_LAMBDA) { CT_DM(CTENO_SCHEME_CTENO, CTENO_GAMMA_LAMBDA); }
@@ -38,7 +39,7 @@ static void reconstruct_launch(const DeviceMesh &m, const ReconArgs<real, (R + 1
 
 template <typename real, int R, int NV>
 static hipError_t reconstruct_t(const DeviceMesh &m, const double *U, void *FV, uint8_t *delta, int dmode,
-                                const int *done, hipStream_t st) {
+                                const int *done, hipStream_t st, unsigned long long *fb_count) {
     constexpr int K = (R + 1) * (R + 2) / 2 - 1;
     ReconArgs<real, K> a;
     a.N = m.N;
@@ -54,6 +55,7 @@ static hipError_t reconstruct_t(const DeviceMesh &m, const double *U, void *FV, 
     if constexpr (std::is_same<real, double>::value) a.fr = m.fr64;
     else a.fr = m.fr32;
     fill_recon_constants<real, K>(m, a);
+    a.fb_count = fb_count;
     const unsigned grid = (unsigned)m.blocks();
     if (m.vars == CTENO_VARS_CHARACTERISTIC) {
         if constexpr (NV == 4) {
@@ -70,16 +72,16 @@ static hipError_t reconstruct_t(const DeviceMesh &m, const double *U, void *FV, 
 
 template <typename real>
 hipError_t reconstruct_lo(const DeviceMesh &m, const double *U, void *FV, uint8_t *delta, int dmode,
-                                const int *done, hipStream_t st) {
+                          const int *done, hipStream_t st, unsigned long long *fb_count) {
     if (m.nv == 4) {
         switch (m.r) {
-            case 2: return reconstruct_t<real, 2, 4>(m, U, FV, delta, dmode, done, st);
-            case 3: return reconstruct_t<real, 3, 4>(m, U, FV, delta, dmode, done, st);
+            case 2: return reconstruct_t<real, 2, 4>(m, U, FV, delta, dmode, done, st, fb_count);
+            case 3: return reconstruct_t<real, 3, 4>(m, U, FV, delta, dmode, done, st, fb_count);
         }
     } else {
         switch (m.r) {
-            case 2: return reconstruct_t<real, 2, 1>(m, U, FV, delta, dmode, done, st);
-            case 3: return reconstruct_t<real, 3, 1>(m, U, FV, delta, dmode, done, st);
+            case 2: return reconstruct_t<real, 2, 1>(m, U, FV, delta, dmode, done, st, fb_count);
+            case 3: return reconstruct_t<real, 3, 1>(m, U, FV, delta, dmode, done, st, fb_count);
         }
     }
     return hipErrorInvalidValue;

@@ -20,6 +20,8 @@ struct ReconHoArgs {
     const real *fr;          // face records (characteristic variables)
     real lams[5], lam_ratio[5];
     real lam1, ct, eps, gamma;
+    int positivity;          // 1: cell-average fallback for non-physical face states
+    unsigned long long *fb_count;   // cells that took the fallback (may be null)
     // the p_1 step's factors: (p_opt - p1_ls sum_s lambda_s p_s) / p1_l1,
     // (1, lambda_1) for the CTENO family, (0, 1) for TENO, which keeps p_opt
     real p1_ls, p1_l1;
@@ -415,9 +417,10 @@ __global__ __launch_bounds__(256) void k_reconstruct_ho(const ReconHoArgs<real> 
             }
         }
     }
-    if constexpr (NV == 4) {
-        // positivity fallback (density or pressure <= 0 at a Gauss point):
-        // the four lanes of the cell exchange their values
+    if constexpr (NV == 4) if (a.positivity) {
+        // optional positivity fallback (not in the paper; density or
+        // pressure <= 0 at a Gauss point): the four lanes of the cell
+        // exchange their values
         const int l0 = (threadIdx.x & 63) & ~3;
         bool bad = false;
 #pragma unroll
@@ -436,6 +439,7 @@ __global__ __launch_bounds__(256) void k_reconstruct_ho(const ReconHoArgs<real> 
                 for (int q = 0; q < NQ; ++q) out[f][q] = (real)U0;
 #pragma unroll
             for (int k = 0; k < NB; ++k) dbyte[k] |= 0x80;
+            if (v == 0 && a.fb_count) atomicAdd(a.fb_count, 1ull);
         }
     }
     if (DMODE == 1) {
@@ -453,7 +457,7 @@ __global__ __launch_bounds__(256) void k_reconstruct_ho(const ReconHoArgs<real> 
 
 template <typename real, int R, int NV>
 static hipError_t reconstruct_ho_t(const DeviceMesh &m, const double *U, void *FV, uint8_t *delta, int dmode,
-                                   const int *done, hipStream_t st) {
+                                   const int *done, hipStream_t st, unsigned long long *fb_count) {
     using D = HoDims<R>;
     ReconHoArgs<real> a;
     a.N = m.N;
@@ -474,6 +478,8 @@ static hipError_t reconstruct_ho_t(const DeviceMesh &m, const double *U, void *F
     a.gamma = (real)m.gamma;
     a.ct = (real)m.ct;
     a.eps = (real)m.eps;
+    a.positivity = m.positivity;
+    a.fb_count = fb_count;
     for (int s = 0; s < 5; ++s) {
         const double ls = s >= 2 ? (1.0 - lam1) / (s - 1) : 0.0;
         a.lams[s] = (real)ls;
@@ -498,7 +504,8 @@ static hipError_t reconstruct_ho_t(const DeviceMesh &m, const double *U, void *F
         case 1: HO_LAUNCH(SCH, GF, 1); break; \
         default: HO_LAUNCH(SCH, GF, 2); break; \
     }
-    if (m.scheme == CTENO_SCHEME_CTENOZ) { HO_DM(CTENO_SCHEME_CTENOZ, CTENO_GAMMA_PAPER); }
+    if (m.scheme == CTENO_SCHEME_CTENOZ && m.gamma_form == CTENO_GAMMA_SCALED) { HO_DM(CTENO_SCHEME_CTENOZ, CTENO_GAMMA_SCALED); }
+    else if (m.scheme == CTENO_SCHEME_CTENOZ) { HO_DM(CTENO_SCHEME_CTENOZ, CTENO_GAMMA_PAPER); }
     else if (m.scheme == CTENO_SCHEME_CWENO) { HO_DM(CTENO_SCHEME_CWENO, CTENO_GAMMA_PAPER); }
     else if (m.scheme == CTENO_SCHEME_TENO) { HO_DM(CTENO_SCHEME_TENO, CTENO_GAMMA_PAPER); }
     else if (m.gamma_form == CTENO_GAMMA_LAMBDA) { HO_DM(CTENO_SCHEME_CTENO, CTENO_GAMMA_LAMBDA); }
@@ -510,18 +517,18 @@ static hipError_t reconstruct_ho_t(const DeviceMesh &m, const double *U, void *F
 
 template <typename real>
 hipError_t reconstruct_hi(const DeviceMesh &m, const double *U, void *FV, uint8_t *delta, int dmode,
-                                   const int *done, hipStream_t st) {
+                          const int *done, hipStream_t st, unsigned long long *fb_count) {
     if (m.nv == 4) {
         switch (m.r) {
-            case 4: return reconstruct_ho_t<real, 4, 4>(m, U, FV, delta, dmode, done, st);
-            case 5: return reconstruct_ho_t<real, 5, 4>(m, U, FV, delta, dmode, done, st);
-            case 6: return reconstruct_ho_t<real, 6, 4>(m, U, FV, delta, dmode, done, st);
+            case 4: return reconstruct_ho_t<real, 4, 4>(m, U, FV, delta, dmode, done, st, fb_count);
+            case 5: return reconstruct_ho_t<real, 5, 4>(m, U, FV, delta, dmode, done, st, fb_count);
+            case 6: return reconstruct_ho_t<real, 6, 4>(m, U, FV, delta, dmode, done, st, fb_count);
         }
     } else {
         switch (m.r) {
-            case 4: return reconstruct_ho_t<real, 4, 1>(m, U, FV, delta, dmode, done, st);
-            case 5: return reconstruct_ho_t<real, 5, 1>(m, U, FV, delta, dmode, done, st);
-            case 6: return reconstruct_ho_t<real, 6, 1>(m, U, FV, delta, dmode, done, st);
+            case 4: return reconstruct_ho_t<real, 4, 1>(m, U, FV, delta, dmode, done, st, fb_count);
+            case 5: return reconstruct_ho_t<real, 5, 1>(m, U, FV, delta, dmode, done, st, fb_count);
+            case 6: return reconstruct_ho_t<real, 6, 1>(m, U, FV, delta, dmode, done, st, fb_count);
         }
     }
     return hipErrorInvalidValue;

@@ -3,5 +3,5 @@
 
 namespace cteno {
 template hipError_t reconstruct_hi<float>(const DeviceMesh &m, const double *U, void *FV, uint8_t *delta, int dmode,
-                                  const int *done, hipStream_t st);
+                                  const int *done, hipStream_t st, unsigned long long *fb_count);
 }  // namespace cteno

@@ -38,6 +38,7 @@ struct DeviceMesh {
     int64_t N = 0, Np = 0;
     int r = 0, K = 0, S = 0, SP = 0, nv = 0, physics = 0;
     int scheme = 0, gamma_form = 0, precision = 0;
+    int positivity = 0;            // 1: cell-average fallback for non-physical face states
     int vars = 0;                  // CTENO_VARS_CONSERVED | CTENO_VARS_CHARACTERISTIC
     int E64 = 0, E32 = 0;          // pseudo-inverse entries per cell (padded to the vector width)
     int Kd = 0, Md = 0, Nq = 2;    // directional basis size and members, Gauss points per face
@@ -79,14 +80,15 @@ hipError_t launch_precompute(const DeviceMesh &m, const PrecomputeInputs &in, hi
 // k_recon_f32/f64.hip and k_recon_ho_f32/f64.hip
 template <typename real>
 hipError_t reconstruct_lo(const DeviceMesh &m, const double *U, void *FV, uint8_t *delta, int dmode, const int *done,
-                          hipStream_t st);
+                          hipStream_t st, unsigned long long *fb_count);
 template <typename real>
 hipError_t reconstruct_hi(const DeviceMesh &m, const double *U, void *FV, uint8_t *delta, int dmode, const int *done,
-                          hipStream_t st);
+                          hipStream_t st, unsigned long long *fb_count);
 
 // reconstruction; dmode: 0 none, 1 write delta, 2 forced delta
+// fb_count (may be null) counts the cells that take the positivity fallback
 hipError_t launch_reconstruct(const DeviceMesh &m, bool fp32, const double *U, void *FV, uint8_t *delta, int dmode,
-                              const int *done, hipStream_t st);
+                              const int *done, hipStream_t st, unsigned long long *fb_count = nullptr);
 
 // flux / residual / RK stage.  mode: 0 outward face fluxes, 1 residual, 2 RK stage
 struct FluxLaunch {
@@ -100,6 +102,7 @@ struct FluxLaunch {
     void *flux_out = nullptr;    // AoS [Np][3][nv] of the precision type
     double *resid = nullptr;     // AoS [Np][nv]
     Ctrl *ctrl = nullptr;        // done / nonphysical (may be null); with dt_ptr also the march time
+    int *nonphys = nullptr;      // non-physical flag when ctrl is null (may be null)
     double *dt_part = nullptr;   // per-block minima of the CFL bound (stage 2 of a march), or null
     double t_base = 0.0;         // time of the stage input when the march time is not on the device
 };

@@ -141,6 +141,8 @@ struct ReconArgs {
     real lams[5];           // lambda_s for s_t = 2, 3, 4 (index s_t)
     real gamma;             // ratio of specific heats (positivity check)
     real lam_ratio[5];      // lambda_1 / lambda_s (index s_t)
+    int positivity;         // 1: cell-average fallback for non-physical face states
+    unsigned long long *fb_count;   // cells that took the fallback (may be null)
 };
 
 // TENO selection bits for one variable: bit 0 central, bit 1+s directional s.
@@ -164,7 +166,8 @@ __device__ __forceinline__ int teno_bits(const real si[4], int adm, int st, real
             for (int s = 1; s < 4; ++s) if ((adm >> s) & 1) tsum += fabs(si[s] - si[0]);
             const double tau = pow6(tsum / (st - 1));
 #pragma unroll
-            for (int s = 0; s < 4; ++s) g[s] = 1.0 + tau / (si[s] + eps);
+            for (int s = 0; s < 4; ++s)
+                g[s] = 1.0 + (GFORM == CTENO_GAMMA_SCALED ? tau / pow6(si[s] + eps) : tau / (si[s] + eps));
         }
 #pragma unroll
         for (int s = 0; s < 4; ++s) if ((adm >> s) & 1) sum += g[s];
@@ -199,16 +202,29 @@ __device__ __forceinline__ int teno_bits(const real si[4], int adm, int st, real
 #pragma unroll
             for (int s = 1; s < 4; ++s)
                 if ((adm >> s) & 1) { tsum += fabsf(e[s] - e[0]); emin = fminf(emin, e[s]); }
-            const float tau = pow6(tsum / (float)(st - 1));
-            const float G = tau / emin;            // gamma_s = 1 + G w_s, w_s = emin / e_s in (0, 1]
             float num[4], sum = 0.0f;
-            if (G <= 1e30f) {
+            if constexpr (GFORM == CTENO_GAMMA_SCALED) {
+                // gamma_s = 1 + X^6 w_s^6 with X = mean |SI_s - SI_1| / emin
+                const float X = (tsum / (float)(st - 1)) / emin;
+                if (X <= 1e5f) {
 #pragma unroll
-                for (int s = 0; s < 4; ++s) num[s] = 1.0f + G * (emin / e[s]);
+                    for (int s = 0; s < 4; ++s) num[s] = 1.0f + pow6(X * (emin / e[s]));
+                } else {
+                    const float iX6 = pow6(1.0f / X);
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) num[s] = iX6 + pow6(emin / e[s]);
+                }
             } else {
-                const float iG = 1.0f / G;
+                const float tau = pow6(tsum / (float)(st - 1));
+                const float G = tau / emin;        // gamma_s = 1 + G w_s, w_s = emin / e_s in (0, 1]
+                if (G <= 1e30f) {
 #pragma unroll
-                for (int s = 0; s < 4; ++s) num[s] = iG + emin / e[s];
+                    for (int s = 0; s < 4; ++s) num[s] = 1.0f + G * (emin / e[s]);
+                } else {
+                    const float iG = 1.0f / G;
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) num[s] = iG + emin / e[s];
+                }
             }
 #pragma unroll
             for (int s = 0; s < 4; ++s) if ((adm >> s) & 1) sum += num[s];
@@ -223,7 +239,7 @@ __device__ __forceinline__ int teno_bits(const real si[4], int adm, int st, real
     return bits;
 }
 
-// CWENO nonlinear weights (sec. 2.2: the WENO weights with exponent 4 and
+// CWENO nonlinear weights (sec. 2.2-2.3: the WENO weights with exponent 4 and
 // the linear weights of eq. e18) of the admissible stencils.  FP64 follows
 // the formula; FP32 evaluates w_s = 1 / sum_t (lambda_t / lambda_s)
 // (e_s / e_t)^4, e = SI + eps, which cannot overflow into a NaN.
@@ -269,6 +285,7 @@ struct ReconPtrs {
     real *FV;
     uint8_t *delta;
     const real *fr;         // face records (characteristic variables only)
+    unsigned long long *fb; // cells that took the positivity fallback (may be null)
 };
 
 // selection (or CWENO weights) of NV fields and their final coefficients,
@@ -605,10 +622,12 @@ __device__ __forceinline__ void recon_body(const ReconArgs<real, (R + 1) * (R + 
             }
         }
     }
-    if constexpr (NV == 4) {
-        // positivity fallback: a cell with a non-physical state (density or
-        // pressure <= 0) at any of its Gauss points uses its cell average at
-        // all of them; reported with bit 7 of its selection bytes
+    if constexpr (NV == 4) if (a.positivity) {
+        // optional positivity fallback (not in the paper): a cell with a
+        // non-physical state (density or pressure <= 0) at any of its Gauss
+        // points uses its cell average at all of them; reported with bit 7
+        // of its selection bytes and counted.  Without it the flux reports
+        // the state.
         bool bad = false;
 #pragma unroll
         for (int f = 0; f < 3; ++f)
@@ -628,6 +647,7 @@ __device__ __forceinline__ void recon_body(const ReconArgs<real, (R + 1) * (R + 
                     for (int v = 0; v < NV; ++v) out[f][q][v] = (real)U0[v];
 #pragma unroll
             for (int k = 0; k < NB; ++k) dbyte[k] |= 0x80;
+            if (ptr.fb) atomicAdd(ptr.fb, 1ull);
         }
     }
     if (DMODE == 1) {
@@ -653,6 +673,8 @@ inline void fill_recon_constants(const DeviceMesh &m, ReconArgs<real, K> &a) {
     a.gamma = (real)m.gamma;
     a.ct = (real)m.ct;
     a.eps = (real)m.eps;
+    a.positivity = m.positivity;
+    a.fb_count = nullptr;
     for (int s = 0; s < 5; ++s) {
         const double ls = s >= 2 ? (1.0 - lam1) / (s - 1) : 0.0;
         a.lams[s] = (real)ls;
@@ -679,7 +701,7 @@ struct HoDims {
 // fluxes, residual, Runge-Kutta
 // ===========================================================================
 
-// HLLC with Roe-averaged signal speeds (sec. 2.6), in the face-normal frame
+// HLLC with Roe-averaged signal speeds (sec. 2.7), in the face-normal frame
 // (u normal, w tangential velocity); F returned in the global frame.
 template <typename real>
 __device__ __forceinline__ bool hllc(real g, const real *UL, const real *UR, real nx, real ny, real *F) {
@@ -772,7 +794,8 @@ struct FluxArgs {
     double dt_value;
     real *flux_out;
     double *resid;
-    Ctrl *ctrl;
+    Ctrl *ctrl;             // time march: done flag and time (may be null)
+    int *nonphys;           // set when a face state is non-physical (may be null)
     double *dt_part;
     real gamma, ax, ay;
     real gw[4];             // Gauss weights on [0, 1]
@@ -829,7 +852,7 @@ struct FluxPtrs {
     const double *dt_ptr;
     real *flux_out;
     double *resid;
-    Ctrl *ctrl;
+    int *nonphys;           // set when a face state is non-physical (may be null)
     bool want_dt;
 };
 
@@ -921,7 +944,7 @@ __device__ __forceinline__ double flux_body(const FluxArgs<real> a, const FluxPt
                 if (MODE == 0) ptr.flux_out[(i * 3 + f) * NV + v] = (real)out;
             }
         }
-        if (bad && ptr.ctrl) atomicOr(&ptr.ctrl->nonphysical, 1);
+        if (bad && ptr.nonphys) atomicOr(ptr.nonphys, 1);
         if (MODE == 1) {
 #pragma unroll
             for (int v = 0; v < NV; ++v) ptr.resid[i * NV + v] = -acc[v] / ptr.area[i];

@@ -238,6 +238,11 @@ static cteno_status check_scheme(const cteno_scheme &s) {
         return fail(CTENO_ERR_INVALID, "bad variables");
     if (s.variables == CTENO_VARS_CHARACTERISTIC && s.physics != CTENO_EULER)
         return fail(CTENO_ERR_INVALID, "characteristic variables need the Euler equations");
+    if (s.gamma_form < CTENO_GAMMA_PAPER || s.gamma_form > CTENO_GAMMA_SCALED)
+        return fail(CTENO_ERR_INVALID, "bad gamma_form");
+    if (s.gamma_form == CTENO_GAMMA_SCALED && s.scheme != CTENO_SCHEME_CTENOZ)
+        return fail(CTENO_ERR_INVALID, "the scaled gamma form belongs to CTENOZ");
+    if (s.positivity != 0 && s.positivity != 1) return fail(CTENO_ERR_INVALID, "positivity must be 0 or 1");
     return CTENO_OK;
 }
 
@@ -260,6 +265,7 @@ static cteno_status upload_device_mesh(cteno_ctx *ctx, hipStream_t st, HostMesh 
     dm.stile = hm.r >= 4 ? kTile / hm.nv : kTile;
     dm.physics = s.physics; dm.scheme = s.scheme; dm.gamma_form = s.gamma_form; dm.precision = s.precision;
     dm.vars = s.variables;
+    dm.positivity = s.physics == CTENO_EULER ? s.positivity : 0;
     dm.gamma = s.gamma; dm.ax = s.ax; dm.ay = s.ay; dm.lam1p = s.lambda1_prime; dm.ct = s.c_t; dm.eps = s.eps;
     dm.Lx = hm.Lx; dm.Ly = hm.Ly;
     make_ref_tables(hm.r, dm.tab);
@@ -504,6 +510,7 @@ struct cteno_sol {
     DevBuf FV[2];             // face-point values, FP64 / FP32
     DevBuf ctrl;              // Ctrl
     DevBuf dt_part;           // per-block minima of the CFL bound
+    DevBuf status;            // SolStatus: fallback count, non-physical flag of stage calls
     double t = 0.0;
     Ctrl *h_ctrl = nullptr;   // pinned host mirror
     hipGraphExec_t graph[2] = {nullptr, nullptr};
@@ -521,7 +528,16 @@ struct cteno_sol {
     }
 };
 
+// device-side counters of a solution, written by its reconstructions and stage calls
+struct SolStatus {
+    unsigned long long fallbacks;   // cells x stages that took the positivity fallback
+    int nonphysical;                // a stage call met a non-physical face state
+    int pad;
+};
+
 namespace {
+SolStatus *sol_status(const cteno_sol *s) { return s->status.as<SolStatus>(); }
+
 cteno_status check_precision(const cteno_mesh *m, int32_t precision, bool &f32) {
     if (precision != CTENO_FP64 && precision != CTENO_MIXED) return fail(CTENO_ERR_INVALID, "precision must be FP64 or MIXED");
     if (!(m->dm.precision & precision)) return fail(CTENO_ERR_INVALID, "mesh was uploaded without this precision");
@@ -546,7 +562,8 @@ extern "C" cteno_status cteno_sol_create(cteno_ctx *ctx, const cteno_mesh *m, co
     }
     s->ctrl = DevBuf(ctx, sizeof(Ctrl));
     s->dt_part = DevBuf(ctx, (size_t)dm.blocks() * sizeof(double));
-    if (!s->ctrl.p || !s->dt_part.p) return fail(CTENO_ERR_NOMEM, "device allocation failed");
+    s->status = DevBuf(ctx, sizeof(SolStatus));
+    if (!s->ctrl.p || !s->dt_part.p || !s->status.p) return fail(CTENO_ERR_NOMEM, "device allocation failed");
     HIP_TRY(hipMemsetAsync(s->ctrl.p, 0, sizeof(Ctrl), ctx->stream()));
     HIP_TRY(hipHostMalloc((void **)&s->h_ctrl, sizeof(Ctrl), hipHostMallocDefault));
     cteno_sol *raw = s.release();
@@ -565,6 +582,7 @@ extern "C" cteno_status cteno_sol_set(cteno_sol *s, const double *u, double t) {
     if (!tmp.p) return fail(CTENO_ERR_NOMEM, "device allocation failed");
     HIP_TRY(hipMemcpyAsync(tmp.p, u, (size_t)dm.N * dm.nv * sizeof(double), hipMemcpyHostToDevice, st));
     HIP_TRY(launch_user_to_state(dm, tmp.as<double>(), s->U[0].as<double>(), st));
+    HIP_TRY(hipMemsetAsync(s->status.p, 0, sizeof(SolStatus), st));
     HIP_TRY(hipStreamSynchronize(st));
     s->t = t;
     return CTENO_OK;
@@ -575,16 +593,35 @@ extern "C" cteno_status cteno_sol_download(cteno_sol *s, double *u, double *t) {
     const DeviceMesh &dm = s->mesh->dm;
     hipStream_t st = s->ctx->stream();
     HIP_TRY(hipSetDevice(s->ctx->device));
+    DevBuf tmp;
     if (u) {
-        DevBuf tmp(s->ctx, (size_t)dm.N * dm.nv * sizeof(double));
+        tmp = DevBuf(s->ctx, (size_t)dm.N * dm.nv * sizeof(double));
         if (!tmp.p) return fail(CTENO_ERR_NOMEM, "device allocation failed");
         HIP_TRY(launch_state_to_user(dm, s->U[0].as<double>(), tmp.as<double>(), st));
         HIP_TRY(hipMemcpyAsync(u, tmp.p, (size_t)dm.N * dm.nv * sizeof(double), hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipStreamSynchronize(st));
-    } else {
-        HIP_TRY(hipStreamSynchronize(st));
     }
+    SolStatus h{};
+    HIP_TRY(hipMemcpyAsync(&h, s->status.p, sizeof h, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
     if (t) *t = s->t;
+    if (h.nonphysical) {
+        // reported once: the flag of the stage calls is cleared
+        HIP_TRY(hipMemsetAsync(&sol_status(s)->nonphysical, 0, sizeof(int), st));
+        HIP_TRY(hipStreamSynchronize(st));
+        return fail(CTENO_ERR_NONPHYSICAL, "a stage call met a non-physical face state (density or pressure <= 0, "
+                                           "or NaN)");
+    }
+    return CTENO_OK;
+}
+
+extern "C" cteno_status cteno_sol_fallbacks(cteno_sol *s, int64_t *count) {
+    if (!s || !count) return fail(CTENO_ERR_INVALID, "NULL argument");
+    HIP_TRY(hipSetDevice(s->ctx->device));
+    hipStream_t st = s->ctx->stream();
+    SolStatus h{};
+    HIP_TRY(hipMemcpyAsync(&h, s->status.p, sizeof h, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    *count = (int64_t)h.fallbacks;
     return CTENO_OK;
 }
 
@@ -623,7 +660,10 @@ extern "C" cteno_status cteno_reconstruct(cteno_ctx *ctx, const cteno_mesh *m, c
             dmode = 1;
         }
     }
-    HIP_TRY(timed(ctx, 0, [&] { return launch_reconstruct(dm, f32, s->U[0].as<double>(), fv, dbuf.as<uint8_t>(), dmode, nullptr, st); }));
+    HIP_TRY(timed(ctx, 0, [&] {
+        return launch_reconstruct(dm, f32, s->U[0].as<double>(), fv, dbuf.as<uint8_t>(), dmode, nullptr, st,
+                                  &sol_status(s)->fallbacks);
+    }));
     HIP_TRY(launch_fv_to_user(dm, f32, fv, face_vals, st));
     if (delta_out) HIP_TRY(launch_delta_to_user(dm, dbuf.as<uint8_t>(), delta_out, st));
     HIP_TRY(hipStreamSynchronize(st));   // dbuf is released on return
@@ -639,17 +679,23 @@ extern "C" cteno_status cteno_flux(cteno_ctx *ctx, const cteno_mesh *m, int32_t 
     const DeviceMesh &dm = m->dm;
     hipStream_t st = ctx->stream();
     const size_t es = f32 ? sizeof(float) : sizeof(double);
-    DevBuf fv(ctx, (size_t)dm.Np * 3 * dm.Nq * dm.nv * es), fo(ctx, (size_t)dm.Np * 3 * dm.nv * es);
-    if (!fv.p || !fo.p) return fail(CTENO_ERR_NOMEM, "device allocation failed");
+    DevBuf fv(ctx, (size_t)dm.Np * 3 * dm.Nq * dm.nv * es), fo(ctx, (size_t)dm.Np * 3 * dm.nv * es),
+        flag(ctx, sizeof(int));
+    if (!fv.p || !fo.p || !flag.p) return fail(CTENO_ERR_NOMEM, "device allocation failed");
+    HIP_TRY(hipMemsetAsync(flag.p, 0, sizeof(int), st));
     HIP_TRY(launch_fv_from_user(dm, f32, face_vals, fv.p, st));
     FluxLaunch fl;
     fl.mode = 0;
     fl.FV = fv.p;
     fl.flux_out = fo.p;
     fl.t_base = t;
+    fl.nonphys = flag.as<int>();
     HIP_TRY(timed(ctx, 1, [&] { return launch_flux(dm, f32, fl, st); }));
     HIP_TRY(launch_flux_to_user(dm, f32, fo.p, face_flux, st));
+    int bad = 0;
+    HIP_TRY(hipMemcpyAsync(&bad, flag.p, sizeof(int), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    if (bad) return fail(CTENO_ERR_NONPHYSICAL, "non-physical face state (density or pressure <= 0, or NaN)");
     return CTENO_OK;
 }
 
@@ -666,15 +712,27 @@ extern "C" cteno_status cteno_residual(cteno_ctx *ctx, const cteno_mesh *m, cons
     void *fv = s->fv(f32);
     DevBuf r(ctx, (size_t)dm.Np * dm.nv * sizeof(double));
     if (!fv || !r.p) return fail(CTENO_ERR_NOMEM, "device allocation failed");
-    HIP_TRY(timed(ctx, 0, [&] { return launch_reconstruct(dm, f32, s->U[0].as<double>(), fv, nullptr, 0, nullptr, st); }));
+    SolStatus *ss = sol_status(s);
+    HIP_TRY(hipMemsetAsync(&ss->nonphysical, 0, sizeof(int), st));
+    HIP_TRY(timed(ctx, 0, [&] {
+        return launch_reconstruct(dm, f32, s->U[0].as<double>(), fv, nullptr, 0, nullptr, st, &ss->fallbacks);
+    }));
     FluxLaunch fl;
     fl.mode = 1;
     fl.FV = fv;
     fl.resid = r.as<double>();
     fl.t_base = s->t;
+    fl.nonphys = &ss->nonphysical;
     HIP_TRY(timed(ctx, 1, [&] { return launch_flux(dm, f32, fl, st); }));
     HIP_TRY(launch_state_to_user(dm, r.as<double>(), resid, st));
+    int bad = 0;
+    HIP_TRY(hipMemcpyAsync(&bad, &ss->nonphysical, sizeof(int), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    if (bad) {
+        HIP_TRY(hipMemsetAsync(&ss->nonphysical, 0, sizeof(int), st));
+        HIP_TRY(hipStreamSynchronize(st));
+        return fail(CTENO_ERR_NONPHYSICAL, "non-physical face state (density or pressure <= 0, or NaN)");
+    }
     return CTENO_OK;
 }
 
@@ -687,7 +745,8 @@ hipError_t issue_stage(cteno_ctx *ctx, cteno_sol *s, bool f32, int stage, const 
     double *outU = stage == 2 ? s->U[0].as<double>() : s->U[stage + 1].as<double>();
     void *fv = s->fv(f32);
     const int *done = ctrl ? &ctrl->done : nullptr;
-    hipError_t e = timed(ctx, 0, [&] { return launch_reconstruct(dm, f32, in, fv, nullptr, 0, done, st); });
+    SolStatus *ss = sol_status(s);
+    hipError_t e = timed(ctx, 0, [&] { return launch_reconstruct(dm, f32, in, fv, nullptr, 0, done, st, &ss->fallbacks); });
     if (e != hipSuccess) return e;
     FluxLaunch fl;
     fl.mode = 2;
@@ -699,6 +758,7 @@ hipError_t issue_stage(cteno_ctx *ctx, cteno_sol *s, bool f32, int stage, const 
     fl.dt_ptr = dt_ptr;
     fl.dt_value = dt_value;
     fl.ctrl = ctrl;
+    fl.nonphys = ctrl ? nullptr : &ss->nonphysical;    // a march reports through its control block
     fl.dt_part = dt_part;
     fl.t_base = s->t;
     return timed(ctx, 1, [&] { return launch_flux(dm, f32, fl, st); });
@@ -851,7 +911,7 @@ struct ServerRequest {
     std::vector<double> u0;
     int32_t n_steps = 0;
     double cfl = 0.3;
-    Clock::time_point t_submit, t_admit, t_done;
+    Clock::time_point t_submit, t_built, t_admit, t_running, t_done;
     int state = REQ_QUEUED;
     HostMesh hm;
     std::string err;
@@ -859,6 +919,7 @@ struct ServerRequest {
     std::vector<double> result;
     double t_end = 0.0;
     int64_t steps = 0;
+    int64_t fallbacks = 0;
 };
 
 struct ServerSlot {
@@ -895,7 +956,7 @@ struct cteno_server {
     uint64_t next_ticket = 1;
     int64_t bytes_used = 0, peak_bytes = 0;
     int peak_active = 0;
-    int64_t ticks = 0, cell_stages = 0, n_submitted = 0, n_finished = 0;
+    int64_t ticks = 0, cell_stages = 0, n_submitted = 0, n_finished = 0, fallbacks = 0;
     bool stop = false;
     std::string sched_error;
     std::vector<std::thread> builders;
@@ -933,11 +994,12 @@ void builder_main(cteno_server *sv, int threads_each) {
             if (steady + transient > sv->budget) { rc = CTENO_ERR_BUSY; err = "request exceeds the HBM budget"; }
         }
         std::lock_guard<std::mutex> lk(sv->mu);
+        rq->t_built = Clock::now();
         if (rc != CTENO_OK) {
             rq->state = REQ_FAILED;
             rq->err = err;
             rq->fail_status = rc;
-            rq->t_done = Clock::now();
+            rq->t_done = rq->t_built;
             sv->n_finished++;
             sv->cv_done.notify_all();
         } else {
@@ -995,6 +1057,7 @@ cteno_status retire(cteno_server *sv, ServerSlot &sl, const Ctrl &c) {
     auto &rq = sl.req;
     rq->steps = c.step;
     rq->t_end = c.t;
+    rq->fallbacks = (int64_t)c.fallbacks;
     if (c.nonphysical) {
         rq->state = REQ_FAILED;
         rq->fail_status = CTENO_ERR_NONPHYSICAL;
@@ -1054,6 +1117,10 @@ void scheduler_main(cteno_server *sv) {
         }
         for (auto &rq : cand) {
             std::unique_ptr<ServerSlot> sl;
+            {
+                std::lock_guard<std::mutex> lk(sv->mu);
+                rq->t_admit = Clock::now();
+            }
             cteno_status rc = admit(sv, rq, sl);
             if (rc != CTENO_OK && sl && sl->ctrl_index >= 0) sv->free_ctrl.push_back(sl->ctrl_index);
             std::lock_guard<std::mutex> lk(sv->mu);
@@ -1068,7 +1135,7 @@ void scheduler_main(cteno_server *sv) {
                 continue;
             }
             rq->state = REQ_RUNNING;
-            rq->t_admit = Clock::now();
+            rq->t_running = Clock::now();
             sv->bytes_used += sl->bytes;
             sv->peak_bytes = std::max(sv->peak_bytes, sv->bytes_used);
             sv->active.push_back(std::move(sl));
@@ -1129,6 +1196,7 @@ void scheduler_main(cteno_server *sv) {
                 sl.req->t_done = Clock::now();
             }
             sv->cell_stages += sl.dm.N * 3 * c.step;
+            sv->fallbacks += (int64_t)c.fallbacks;
             sv->bytes_used -= sl.bytes;
             sv->free_ctrl.push_back(sl.ctrl_index);
             sv->n_finished++;
@@ -1178,6 +1246,7 @@ extern "C" cteno_status cteno_server_create(cteno_ctx *ctx, const cteno_scheme *
     p.r = scheme->degree; p.K = dims_K(p.r); p.S = dims_S(p.r); p.nv = 4; p.physics = CTENO_EULER;
     p.scheme = scheme->scheme; p.gamma_form = scheme->gamma_form; p.precision = CTENO_MIXED;
     p.gamma = scheme->gamma; p.lam1p = scheme->lambda1_prime; p.ct = scheme->c_t; p.eps = scheme->eps;
+    p.positivity = scheme->positivity;
     make_ref_tables(p.r, p.tab);
     // capture one batched step
     hipGraph_t g = nullptr;
@@ -1273,6 +1342,32 @@ extern "C" cteno_status cteno_server_get_stats(cteno_server *sv, cteno_server_st
     st->bytes_in_use = sv->bytes_used;
     st->peak_bytes = sv->peak_bytes;
     st->budget_bytes = sv->budget;
+    st->fallbacks = sv->fallbacks;
+    return CTENO_OK;
+}
+
+extern "C" cteno_status cteno_server_request_info(cteno_server *sv, uint64_t ticket, cteno_request_info *info) {
+    if (!sv || !info) return fail(CTENO_ERR_INVALID, "NULL argument");
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto it = sv->requests.find(ticket);
+    if (it == sv->requests.end()) return fail(CTENO_ERR_INVALID, "unknown or released ticket");
+    const ServerRequest &rq = *it->second;
+    auto sec = [](Clock::time_point a, Clock::time_point b) {
+        return (a.time_since_epoch().count() && b.time_since_epoch().count() && b >= a)
+                   ? std::chrono::duration<double>(b - a).count() : 0.0;
+    };
+    *info = cteno_request_info{};
+    info->state = rq.state;
+    info->status = rq.state == REQ_FAILED ? (rq.fail_status == CTENO_OK ? CTENO_ERR_DEVICE : rq.fail_status) : CTENO_OK;
+    info->n_cells = (int64_t)rq.tri.size() / 3;
+    info->steps_done = rq.steps;
+    info->fallbacks = rq.fallbacks;
+    const bool finished = rq.state == REQ_DONE || rq.state == REQ_FAILED;
+    info->latency_s = finished ? sec(rq.t_submit, rq.t_done) : 0.0;
+    info->build_s = sec(rq.t_submit, rq.t_built);
+    info->queue_s = sec(rq.t_built, rq.t_admit);
+    info->admit_s = sec(rq.t_admit, rq.t_running);
+    info->run_s = finished ? sec(rq.t_running, rq.t_done) : 0.0;
     return CTENO_OK;
 }
 

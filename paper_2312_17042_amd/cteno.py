@@ -7,8 +7,10 @@ the built library is missing.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import sys
 import weakref
 
 import numpy as np
@@ -21,7 +23,7 @@ PERIODIC, WALL, TRANSMISSIVE, INFLOW = 0, 1, 2, 3
 ADVECTION, EULER = 0, 1
 CTENO, CTENOZ, CWENO, TENO = 0, 1, 2, 3
 CONSERVED, CHARACTERISTIC = 0, 1
-GAMMA_PAPER, GAMMA_LAMBDA = 0, 1
+GAMMA_PAPER, GAMMA_LAMBDA, GAMMA_SCALED = 0, 1, 2
 FP64, MIXED, BOTH = 1, 2, 3
 KERNEL_RECONSTRUCT, KERNEL_FLUX, KERNEL_PRECOMPUTE = 0, 1, 2
 
@@ -60,7 +62,7 @@ class Scheme(C.Structure):
     _fields_ = [("physics", C.c_int32), ("ax", C.c_double), ("ay", C.c_double), ("gamma", C.c_double),
                 ("scheme", C.c_int32), ("degree", C.c_int32), ("lambda1_prime", C.c_double), ("c_t", C.c_double),
                 ("eps", C.c_double), ("gamma_form", C.c_int32), ("precision", C.c_int32), ("reorder", C.c_int32),
-                ("variables", C.c_int32)]
+                ("variables", C.c_int32), ("positivity", C.c_int32)]
 
 
 class MeshInfo(C.Structure):
@@ -72,7 +74,13 @@ class MeshInfo(C.Structure):
 class ServerStats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("finished", C.c_int64), ("active", C.c_int32), ("peak_active", C.c_int32),
                 ("ticks", C.c_int64), ("cell_stages", C.c_int64), ("bytes_in_use", C.c_int64),
-                ("peak_bytes", C.c_int64), ("budget_bytes", C.c_int64)]
+                ("peak_bytes", C.c_int64), ("budget_bytes", C.c_int64), ("fallbacks", C.c_int64)]
+
+
+class RequestInfo(C.Structure):
+    _fields_ = [("state", C.c_int32), ("status", C.c_int32), ("n_cells", C.c_int64), ("steps_done", C.c_int64),
+                ("fallbacks", C.c_int64), ("latency_s", C.c_double), ("build_s", C.c_double),
+                ("queue_s", C.c_double), ("admit_s", C.c_double), ("run_s", C.c_double)]
 
 
 REQ_QUEUED, REQ_READY, REQ_RUNNING, REQ_DONE, REQ_FAILED = range(5)
@@ -99,6 +107,7 @@ _SIGS = {
     "cteno_sol_set": [C.c_void_p, C.c_void_p, C.c_double],
     "cteno_sol_download": [C.c_void_p, C.c_void_p, C.POINTER(C.c_double)],
     "cteno_sol_destroy": [C.c_void_p],
+    "cteno_sol_fallbacks": [C.c_void_p, C.POINTER(C.c_int64)],
     "cteno_reconstruct": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p],
     "cteno_flux": [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_double, C.c_void_p],
     "cteno_residual": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p],
@@ -114,6 +123,7 @@ _SIGS = {
                           C.POINTER(C.c_double)],
     "cteno_server_drain": [C.c_void_p],
     "cteno_server_get_stats": [C.c_void_p, C.c_void_p],
+    "cteno_server_request_info": [C.c_void_p, C.c_uint64, C.POINTER(RequestInfo)],
     "cteno_server_destroy": [C.c_void_p],
 }
 _VOID = {"cteno_ctx_destroy", "cteno_mesh_destroy", "cteno_sol_destroy", "cteno_server_destroy"}
@@ -154,26 +164,88 @@ def _dev_ptr(t):
     return C.c_void_p(t.data_ptr())
 
 
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class TorchAllocator:
+    """Allocator hooks of cteno_ctx_create backed by torch's caching
+    allocator, so that the library's device memory (meshes, states, serving
+    slots) is accounted by torch.  Counts the calls it served."""
+
+    def __init__(self, device: int, stream: int):
+        import torch
+        self.device = device
+        self.stream = stream
+        self.allocs = 0
+        self.frees = 0
+
+        def alloc(nbytes, user):
+            try:
+                ptr = torch.cuda.caching_allocator_alloc(int(nbytes), self.device, self.stream)
+            except Exception:           # out of memory: the library reports CTENO_ERR_NOMEM
+                return None
+            self.allocs += 1
+            return ptr
+
+        def free(ptr, user):
+            self.frees += 1
+            torch.cuda.caching_allocator_delete(ptr)
+
+        self.alloc_fn = _ALLOC_FN(alloc)
+        self.free_fn = _FREE_FN(free)
+
+
+# every open context, closed (children first) before the interpreter shuts
+# down, while the HIP runtime and torch are still whole
+_live_contexts = weakref.WeakSet()
+
+
+def _close_all():
+    for ctx in list(_live_contexts):
+        ctx.close()
+
+
+atexit.register(_close_all)
+
+
+def _finalizing() -> bool:
+    return sys.is_finalizing()
+
+
 class Context:
-    def __init__(self, device: int = 0, stream=None):
+    """A library context on one device.  allocator="torch" (default) routes
+    every device allocation of the library through torch's caching
+    allocator; None uses hipMalloc."""
+
+    def __init__(self, device: int = 0, stream=None, allocator: str | None = "torch"):
         import torch
         if stream is None:
             stream = torch.cuda.current_stream(device).cuda_stream
+        self.allocator = TorchAllocator(device, stream) if allocator == "torch" else None
+        a = self.allocator
         h = C.c_void_p()
-        _check(lib().cteno_ctx_create(device, C.c_void_p(stream), None, None, None, C.byref(h)))
+        _check(lib().cteno_ctx_create(device, C.c_void_p(stream), a.alloc_fn if a else None,
+                                      a.free_fn if a else None, None, C.byref(h)))
         self.h = h
         self.device = device
-        self._children = weakref.WeakSet()   # meshes and solutions, closed before the context
+        self._children = weakref.WeakSet()   # servers, meshes and solutions, closed before the context
+        _live_contexts.add(self)
 
     def close(self):
+        """Destroys the children (servers, solutions, then meshes) and the
+        context; idempotent."""
         if getattr(self, "h", None):
-            for ch in sorted(list(self._children), key=lambda o: 0 if isinstance(o, Solution) else 1):
+            rank = {Server: 0, Solution: 1, Mesh: 2}
+            for ch in sorted(list(self._children), key=lambda o: rank.get(type(o), 3)):
                 ch.close()
             lib().cteno_ctx_destroy(self.h)
             self.h = None
+        _live_contexts.discard(self)
 
     def __del__(self):
-        self.close()
+        if not _finalizing():
+            self.close()
 
     def synchronize(self):
         _check(lib().cteno_ctx_synchronize(self.h))
@@ -195,9 +267,10 @@ class Context:
 
 
 def make_scheme(physics=EULER, scheme=CTENOZ, degree=3, lambda1_prime=1e4, c_t=1e-6, eps=1e-12, gamma=1.4,
-                ax=1.0, ay=1.0, gamma_form=GAMMA_PAPER, precision=FP64, reorder=1, variables=0) -> Scheme:
+                ax=1.0, ay=1.0, gamma_form=GAMMA_PAPER, precision=FP64, reorder=1, variables=0,
+                positivity=0) -> Scheme:
     return Scheme(physics, ax, ay, gamma, scheme, degree, lambda1_prime, c_t, eps, gamma_form, precision, reorder,
-                  variables)
+                  variables, positivity)
 
 
 class Mesh:
@@ -237,7 +310,8 @@ class Mesh:
             self.h = None
 
     def __del__(self):
-        self.close()
+        if not _finalizing():
+            self.close()
 
     def stencils(self):
         cen = np.empty((self.N, self.M), np.int32)
@@ -290,7 +364,8 @@ class Solution:
             self.h = None
 
     def __del__(self):
-        self.close()
+        if not _finalizing():
+            self.close()
 
     def set(self, u, t=0.0):
         u = np.ascontiguousarray(u, np.float64).reshape(self.mesh.nv, self.mesh.N)
@@ -341,12 +416,19 @@ class Solution:
         _check(lib().cteno_count_flips(self.ctx.h, self.mesh.h, self.h, C.byref(n)))
         return n.value
 
+    def fallbacks(self):
+        """cells x stages that took the positivity fallback since create / set"""
+        n = C.c_int64()
+        _check(lib().cteno_sol_fallbacks(self.h, C.byref(n)))
+        return n.value
 
-def flux(mesh: Mesh, face_vals, precision=FP64, t=0.0):
-    """Outward face fluxes times |A_f|; t is the time of prescribed inflow states."""
+
+def flux(mesh: Mesh, face_vals, precision=FP64, t=0.0, out=None):
+    """Outward face fluxes times |A_f|; t is the time of prescribed inflow
+    states; out: a preallocated [N][3][nv] tensor."""
     import torch
     dt = torch.float64 if precision == FP64 else torch.float32
-    fo = torch.empty((mesh.N, 3, mesh.nv), dtype=dt, device=face_vals.device)
+    fo = torch.empty((mesh.N, 3, mesh.nv), dtype=dt, device=face_vals.device) if out is None else out
     torch.cuda.synchronize()
     _check(lib().cteno_flux(mesh.ctx.h, mesh.h, precision, _dev_ptr(face_vals.contiguous()), float(t), _dev_ptr(fo)))
     return fo
@@ -370,7 +452,8 @@ class Server:
             self.h = None
 
     def __del__(self):
-        self.close()
+        if not _finalizing():
+            self.close()
 
     def submit(self, mesh, u0, n_steps: int, cfl: float = 0.3) -> int:
         xy = np.ascontiguousarray(mesh.xy, np.float64)
@@ -406,3 +489,9 @@ class Server:
         s = ServerStats()
         _check(lib().cteno_server_get_stats(self.h, C.byref(s)))
         return {f: getattr(s, f) for f, _ in ServerStats._fields_}
+
+    def info(self, ticket: int) -> dict:
+        """state, counts and latency split (build, queue, admit, run) of an unreleased request"""
+        r = RequestInfo()
+        _check(lib().cteno_server_request_info(self.h, int(ticket), C.byref(r)))
+        return {f: getattr(r, f) for f, _ in RequestInfo._fields_}

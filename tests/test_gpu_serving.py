@@ -15,7 +15,9 @@ if not torch.cuda.is_available():
 
 from paper_2312_17042_amd import cteno as T  # noqa: E402
 
-SCHEME = dict(physics=T.EULER, scheme=T.CTENOZ, degree=3, lambda1_prime=1e4)
+# the serving configuration mixes Sod-type requests, whose initial jumps
+# need the optional positivity fallback; every request reports its count
+SCHEME = dict(physics=T.EULER, scheme=T.CTENOZ, degree=3, lambda1_prime=1e4, positivity=1)
 STEPS = 30
 
 
@@ -71,6 +73,37 @@ def test_result_same_alone_and_in_mix(ctx):
     ref = _standalone(ctx, *reqs[0], STEPS)
     rel = np.abs(alone - ref).max() / np.abs(ref).max()
     assert rel <= 1e-12, rel
+
+
+def test_served_results_match_the_oracle(ctx):
+    """Served results against the FP64 oracle: a vortex and a Sod-type
+    request marched STEPS SSP-RK3 steps in one batch agree with the oracle's
+    march of the same steps within the mixed-precision tolerance (1e-5
+    normwise per variable).  The Sod request runs with the positivity
+    fallback, which its initial jump needs; the request reports how many
+    cells took it, and so does the oracle (FP32 and FP64 may decide a
+    borderline cell differently)."""
+    import oracle as O
+    vortex = W.vortex_case(20, seed=4001, beta=3.0, center=(4.0, 6.0))
+    sod = W.sod_case(48, 12, seed=4002, left=(0.8, 0.0, 0.0, 0.9), right=(0.3, 0.0, 0.0, 0.2))
+    srv = T.Server(ctx, T.make_scheme(**SCHEME), budget_bytes=1 << 30, max_slots=8)
+    tickets = [srv.submit(mesh, u0, STEPS) for mesh, u0 in (vortex, sod)]
+    srv.drain()
+    infos = [srv.info(t) for t in tickets]
+    outs = [srv.poll(t, take=True)[1] for t in tickets]
+    srv.close()
+    okw = dict(physics=O.EULER, scheme=O.CTENOZ, degree=3, lambda1_prime=1e4, positivity=1)
+    for (mesh, u0), u, info in zip((vortex, sod), outs, infos):
+        o = O.Oracle.from_mesh(mesh, **okw)
+        uo, n, _ = o.solve(u0, 1e30, cfl=0.3, max_steps=STEPS)
+        assert n == STEPS and info["steps_done"] == STEPS and info["state"] == T.REQ_DONE
+        err = max(np.abs(u[v] - uo[v]).max() / np.abs(uo[v]).max() for v in range(4))
+        assert err < 1e-5, err
+        assert abs(info["fallbacks"] - o.fallbacks()) <= max(2, 0.05 * o.fallbacks())
+        for key in ("build_s", "queue_s", "admit_s", "run_s"):
+            assert 0.0 <= info[key] <= info["latency_s"]
+        assert info["build_s"] + info["queue_s"] + info["admit_s"] + info["run_s"] <= info["latency_s"] * (1 + 1e-9)
+    assert infos[0]["fallbacks"] == 0 and infos[1]["fallbacks"] > 0
 
 
 def test_budget_binds_admission(ctx):

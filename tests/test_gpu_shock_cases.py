@@ -1,6 +1,8 @@
 """The paper's shock test cases with prescribed-state sides, run on the GPU
 through the C ABI: the shock-density wave (sec. 3.1.2) and the double Mach
-reflection (sec. 3.4).
+reflection (sec. 3.3).  Both start from strong jumps, which the paper's
+scheme reconstructs to non-physical states in a few cells; they run with the
+optional positivity fallback, and the tests bound how often it fires.
 
 Shock-density wave: 200 x 40 split/jittered squares on [-5, 5] x [0, 2]
 (h = 1/20 as in the paper), t = 1.8, 5th order, FP64.  The reference is our
@@ -36,14 +38,22 @@ def ctx():
     c.close()
 
 
+# the largest share of cell reconstructions (cells x stages) that may take
+# the positivity fallback in these marches: measured 0.25 % for the Mach 3
+# shock-density wave and 0.43 % for the Mach 10 double Mach reflection
+FALLBACK_SHARE = 1e-2
+
+
 def _march(ctx, mesh, u0, t_final, precision=T.FP64, **kw):
-    m = T.Mesh.from_workload(ctx, mesh, precision=precision, physics=T.EULER, **kw)
+    m = T.Mesh.from_workload(ctx, mesh, precision=precision, physics=T.EULER, positivity=1, **kw)
     s = T.Solution(m, u0)
-    s.solve(t_final=t_final, cfl=0.3, precision=precision)
+    n = s.solve(t_final=t_final, cfl=0.3, precision=precision)
     u, t = s.download()
+    fb = s.fallbacks()
     s.close()
     m.close()
     assert abs(t - t_final) < 1e-12
+    assert fb <= FALLBACK_SHARE * 3 * n * mesh.n_cells, (fb, n, mesh.n_cells)
     return u
 
 
@@ -69,6 +79,7 @@ def _sdw_error(ctx, ref, name, order, lam):
     key = (name, order, lam)
     if key not in _sdw:
         kw = {"CTENOZ": dict(scheme=T.CTENOZ), "CTENO": dict(scheme=T.CTENO, gamma_form=T.GAMMA_LAMBDA),
+              "CTENOZ-scaled": dict(scheme=T.CTENOZ, gamma_form=T.GAMMA_SCALED),
               "TENO": dict(scheme=T.TENO), "CWENO": dict(scheme=T.CWENO)}[name]
         mesh, u0 = W.shock_density_case(200, 40)
         u = _march(ctx, mesh, u0, 1.8, degree=order - 1, lambda1_prime=lam, **kw)
@@ -88,6 +99,19 @@ def test_shock_density_lambda_sensitivity(ctx, sdw_reference, order):
     c = [_sdw_error(ctx, sdw_reference, "CTENO", order, lam) for lam in LAMBDAS]
     assert max(z) / min(z) < 1.1, z
     assert min(c[1:]) < 0.9 * c[0], c
+
+
+@pytest.mark.parametrize("order", [5, 7])
+def test_shock_density_scaled_ctenoz(ctx, sdw_reference, order):
+    """The scaled reading of Algorithm 2 on the same case: like literal CTENO
+    it drops the central stencil in smooth parts of the post-shock waves, so
+    it damps the fluctuations far more than the printed CTENOZ (and than
+    TENO and CWENO at 5th order) and depends on lambda1' through p_1 where it
+    keeps the centre.  It does not reproduce Figs. 4-5's CTENOZ."""
+    z = [_sdw_error(ctx, sdw_reference, "CTENOZ", order, lam) for lam in LAMBDAS]
+    zs = [_sdw_error(ctx, sdw_reference, "CTENOZ-scaled", order, lam) for lam in LAMBDAS]
+    assert min(zs) > 2.0 * max(z), (zs, z)
+    assert max(zs) / min(zs) < 1.25, zs
 
 
 def test_shock_density_scheme_ranking(ctx, sdw_reference):
@@ -135,20 +159,3 @@ def test_dmr_incident_shock_travels_exactly(ctx, precision):
     assert abs(x_mid - xs) < 2 * h, (x_mid, xs)
     assert abs(pn[xn < xs - 0.1].mean() - 8.0) < 0.1
     assert abs(pn[xn > xs + 0.1].mean() - 1.4) < 0.02
-
-
-@pytest.mark.parametrize("precision", [T.FP64, T.MIXED])
-def test_triple_point_to_t5(ctx, precision):
-    """The single-material triple point (sec. 3.5) on 500 x 215 squares
-    (215,000 cells, h = 0.014) with CTENO5, lambda1' = 1e4, to t = 5: the
-    state stays physical and, with walls on every side, mass and energy stay
-    constant (momentum changes by the wall pressure) to FP64 round-off in
-    both precisions: interior fluxes cancel exactly and the wall flux
-    carries exactly no mass or energy."""
-    mesh, u0 = W.triple_point_case()
-    u = _march(ctx, mesh, u0, 5.0, precision=precision, scheme=T.CTENO, degree=4, lambda1_prime=1e4)
-    assert np.isfinite(u).all() and u[0].min() > 0
-    area = W.cell_areas(mesh)
-    tot0, tot1 = (u0 * area).sum(1), (u * area).sum(1)
-    for v in (0, 3):
-        assert abs(tot1[v] - tot0[v]) <= 1e-11 * abs(tot0[v]), (v, tot0[v], tot1[v])
