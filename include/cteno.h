@@ -259,6 +259,19 @@ cteno_status cteno_reconstruct(cteno_ctx *ctx, const cteno_mesh *mesh, const cte
    state returns CTENO_ERR_NONPHYSICAL (the fluxes are still written). */
 cteno_status cteno_flux(cteno_ctx *ctx, const cteno_mesh *mesh, int32_t precision, const void *face_vals,
                         double t, void *face_flux);
+/* cteno_flux for callers that cannot allocate device memory (code that may
+   not call hipMalloc, such as tight serving loops or a harness that forbids
+   allocation): the same arguments, kernels and results as cteno_flux, with
+   its internal-order staging buffers (face-point values, face fluxes, the
+   non-physical flag) in a fixed 32 MiB array of device memory that the
+   library holds on each device it runs on until the process ends.  It
+   allocates nothing: meshes whose staging exceeds the array
+   (about 116k cells in FP64 at degree 3) are refused with
+   CTENO_ERR_INVALID.  Every call on a device shares that device's array, so
+   calls that overlap on one device (other threads, other streams) race;
+   calls in sequence are safe.  Synchronises. */
+cteno_status cteno_flux_noalloc(cteno_ctx *ctx, const cteno_mesh *mesh, int32_t precision, const void *face_vals,
+                                double t, void *face_flux);
 /* Residual dU/dt = -(1/|V_i|) sum_f outward flux (the semi-discrete form
    after eq. e1) of the current state at the solution's time:
    resid device [nv][n_cells] FP64.  Synchronises; a non-physical face state

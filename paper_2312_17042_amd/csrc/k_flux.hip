@@ -2,6 +2,8 @@
 // kernels, layout conversions and utilities; the reconstruction dispatch.
 #include "kernels_common.h"
 
+#include <mutex>
+
 namespace cteno {
 
 hipError_t launch_reconstruct(const DeviceMesh &m, bool fp32, const double *U, void *FV, uint8_t *delta, int dmode,
@@ -381,6 +383,44 @@ hipError_t launch_copy16(void *dst, const void *src, size_t n16, hipStream_t st)
     if (grid == 0) return hipSuccess;
     hipLaunchKernelGGL(k_copy16, dim3(grid), dim3(256), 0, st, (uint4 *)dst, (const uint4 *)src, n16);
     return hipGetLastError();
+}
+
+// ===========================================================================
+// fixed device scratch of the allocation-free entry point
+// ===========================================================================
+
+// One static buffer per device for callers that cannot allocate device
+// memory (cteno_flux_noalloc): the internal-order face-point values, face
+// fluxes and the non-physical flag of one call.  Host code must use the
+// address that hipGetSymbolAddress returns for the device, never the
+// array's name, which on the host is only a stand-in.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t scratch_init(int device) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device) return hipErrorInvalidDevice;     // the device must be current
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = ptr;
+    return hipSuccess;
+}
+
+void *scratch_device_ptr(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[device];
 }
 
 __global__ void k_gather_entries(int n, const int32_t *idx, int E, int VW, const double *s64, const float *s32,

@@ -145,6 +145,16 @@ hipError_t launch_delta_from_user(const DeviceMesh &m, const uint8_t *user, uint
 hipError_t launch_count_diff(const DeviceMesh &m, const uint8_t *a, const uint8_t *b, unsigned long long *count,
                              hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, size_t n, hipStream_t st);
+
+// Fixed device scratch of the allocation-free entry point (one array per
+// device, held until the process ends).  scratch_init records its device
+// address for `device`, which must be the current device; it is called
+// once per device by cteno_ctx_create.  scratch_device_ptr returns the
+// recorded address, or null before scratch_init succeeded on that device.
+constexpr size_t kScratchBytes = size_t(32) << 20;
+constexpr int kMaxDevices = 64;
+hipError_t scratch_init(int device);
+void *scratch_device_ptr(int device);
 hipError_t launch_copy16(void *dst, const void *src, size_t n16, hipStream_t st);
 // dst[a][e] = src[avix(idx[a], e, E, VW)] (ct = 64) or src[hvix(idx[a], e, E, VW, ct)]
 // from exactly one of src64 / src32 / srci

@@ -143,6 +143,7 @@ extern "C" cteno_status cteno_ctx_create(int device, void *stream, cteno_alloc_f
     HIP_TRY(hipGetDeviceCount(&n));
     if (device < 0 || device >= n) return fail(CTENO_ERR_INVALID, "no such device");
     HIP_TRY(hipSetDevice(device));
+    HIP_TRY(scratch_init(device));       // address of this device's fixed scratch
     auto c = std::make_unique<cteno_ctx>();
     c->device = device;
     c->user_stream = (hipStream_t)stream;
@@ -694,6 +695,45 @@ extern "C" cteno_status cteno_flux(cteno_ctx *ctx, const cteno_mesh *m, int32_t 
     HIP_TRY(launch_flux_to_user(dm, f32, fo.p, face_flux, st));
     int bad = 0;
     HIP_TRY(hipMemcpyAsync(&bad, flag.p, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (bad) return fail(CTENO_ERR_NONPHYSICAL, "non-physical face state (density or pressure <= 0, or NaN)");
+    return CTENO_OK;
+}
+
+extern "C" cteno_status cteno_flux_noalloc(cteno_ctx *ctx, const cteno_mesh *m, int32_t precision,
+                                           const void *face_vals, double t, void *face_flux) {
+    if (!ctx || !m || !face_vals || !face_flux) return fail(CTENO_ERR_INVALID, "NULL argument");
+    bool f32;
+    if (cteno_status rc = check_precision(m, precision, f32)) return rc;
+    const DeviceMesh &dm = m->dm;
+    const size_t es = f32 ? sizeof(float) : sizeof(double);
+    const size_t fv_bytes = (size_t)dm.Np * 3 * dm.Nq * dm.nv * es;
+    const size_t fo_bytes = (size_t)dm.Np * 3 * dm.nv * es;
+    const size_t fo_off = (fv_bytes + 255) / 256 * 256;
+    const size_t flag_off = (fo_off + fo_bytes + 255) / 256 * 256;
+    const size_t need = flag_off + 256;
+    if (need > kScratchBytes)
+        return fail(CTENO_ERR_INVALID, "mesh too large for the fixed scratch: needs " + std::to_string(need) +
+                                           " bytes, holds " + std::to_string(kScratchBytes));
+    HIP_TRY(hipSetDevice(ctx->device));
+    unsigned char *base = (unsigned char *)scratch_device_ptr(ctx->device);
+    if (!base) return fail(CTENO_ERR_DEVICE, "fixed scratch not initialised on this device");
+    void *fv = base, *fo = base + fo_off;
+    unsigned long long *flag = (unsigned long long *)(base + flag_off);
+    hipStream_t st = ctx->stream();
+    // the flag must start at zero; the buffers are fully written before use
+    HIP_TRY(launch_fill_u64(flag, 0ull, 1, st));
+    HIP_TRY(launch_fv_from_user(dm, f32, face_vals, fv, st));
+    FluxLaunch fl;
+    fl.mode = 0;
+    fl.FV = fv;
+    fl.flux_out = fo;
+    fl.t_base = t;
+    fl.nonphys = (int *)flag;
+    HIP_TRY(launch_flux(dm, f32, fl, st));
+    HIP_TRY(launch_flux_to_user(dm, f32, fo, face_flux, st));
+    unsigned long long bad = 0;
+    HIP_TRY(hipMemcpyAsync(&bad, flag, sizeof bad, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     if (bad) return fail(CTENO_ERR_NONPHYSICAL, "non-physical face state (density or pressure <= 0, or NaN)");
     return CTENO_OK;

@@ -110,6 +110,7 @@ _SIGS = {
     "cteno_sol_fallbacks": [C.c_void_p, C.POINTER(C.c_int64)],
     "cteno_reconstruct": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p],
     "cteno_flux": [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_double, C.c_void_p],
+    "cteno_flux_noalloc": [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_double, C.c_void_p],
     "cteno_residual": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p],
     "cteno_rk_stage": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_double],
     "cteno_solve": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.c_int64, C.c_double, C.c_int32,
@@ -423,14 +424,16 @@ class Solution:
         return n.value
 
 
-def flux(mesh: Mesh, face_vals, precision=FP64, t=0.0, out=None):
+def flux(mesh: Mesh, face_vals, precision=FP64, t=0.0, out=None, noalloc=False):
     """Outward face fluxes times |A_f|; t is the time of prescribed inflow
-    states; out: a preallocated [N][3][nv] tensor."""
+    states.  noalloc=True calls cteno_flux_noalloc (staging in the library's
+    fixed device scratch); out: a preallocated [N][3][nv] tensor."""
     import torch
     dt = torch.float64 if precision == FP64 else torch.float32
     fo = torch.empty((mesh.N, 3, mesh.nv), dtype=dt, device=face_vals.device) if out is None else out
     torch.cuda.synchronize()
-    _check(lib().cteno_flux(mesh.ctx.h, mesh.h, precision, _dev_ptr(face_vals.contiguous()), float(t), _dev_ptr(fo)))
+    fn = lib().cteno_flux_noalloc if noalloc else lib().cteno_flux
+    _check(fn(mesh.ctx.h, mesh.h, precision, _dev_ptr(face_vals.contiguous()), float(t), _dev_ptr(fo)))
     return fo
 
 
