@@ -158,6 +158,8 @@ typedef struct {
     int32_t n_inadmissible;     /* interior faces whose directional stencil has < K_d + 1 cells */
     int32_t Kd, Md;             /* directional basis size and stencil size (M_d = 2 K_d) */
     int64_t device_bytes;       /* resident device memory of the mesh handle */
+    int64_t n_cross_cells;      /* cells with a face to another 256-cell block (the fused
+                                   stage's second kernel finishes them); 0 above degree 3 */
 } cteno_mesh_info;
 
 /* ---------------------------------------------------------------------- */
@@ -175,9 +177,21 @@ cteno_status cteno_ctx_set_stream(cteno_ctx *ctx, void *stream);
 /* waits for the stream and reports pending device errors */
 cteno_status cteno_ctx_synchronize(cteno_ctx *ctx);
 const char *cteno_last_error(void);
+/* Stage kernels of degree 2 and 3 in mixed precision for RK stages and
+   marches (cteno_rk_stage, cteno_solve; FP64 stages always run the two
+   kernels): on = 1 (default), one fused kernel per stage reconstructs
+   each block of 256 cells into on-chip memory and evaluates the fluxes of
+   the faces inside the block there, and a second kernel finishes the cells
+   with faces to other blocks; on = 0, a reconstruction kernel writes all
+   face values to device memory and a flux kernel reads them back.  Results
+   agree to FP64 rounding (the fused path sums a cell's faces inside its
+   block first).  Synchronises. */
+cteno_status cteno_ctx_set_fused_stage(cteno_ctx *ctx, int32_t on);
 /* Per-kernel timing with HIP events on the context stream (off by default).
-   kernel: 0 = reconstruction, 1 = flux + residual + RK update, 2 = pseudo-inverse
-   precompute.  Reports launches and summed milliseconds since the last reset. */
+   kernel: 0 = reconstruction (the fused stage kernel when it runs), 1 =
+   flux + residual + RK update (the fused stage's second kernel), 2 =
+   pseudo-inverse precompute.  Reports launches and summed milliseconds
+   since the last reset. */
 cteno_status cteno_ctx_set_timing(cteno_ctx *ctx, int32_t on);
 cteno_status cteno_ctx_kernel_stats(cteno_ctx *ctx, int32_t kernel, int64_t *launches, double *total_ms);
 cteno_status cteno_ctx_reset_stats(cteno_ctx *ctx);

@@ -11,8 +11,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libcteno.so")
-SOURCES = ["k_recon_ho_f64.hip", "k_recon_ho_f32.hip", "k_recon_f64.hip", "k_recon_f32.hip", "k_precompute.hip",
-           "k_flux.hip", "mesh_builder.cpp", "runtime.cpp"]
+SOURCES = ["k_recon_ho_f64.hip", "k_recon_ho_f32.hip", "k_stage_f32.hip", "k_recon_f64.hip",
+           "k_recon_f32.hip", "k_precompute.hip", "k_flux.hip", "mesh_builder.cpp", "runtime.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -38,7 +38,7 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+    with ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 8)) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"]

@@ -31,30 +31,8 @@ __global__ __launch_bounds__(256) void k_flux(const FluxArgs<real> a) {
 
 template <typename real, int NV, int PHYS>
 static hipError_t flux_t(const DeviceMesh &m, const FluxLaunch &f, hipStream_t st) {
-    FluxArgs<real> a{};
-    a.N = m.N;
-    a.FV = (const real *)f.FV;
-    if constexpr (std::is_same<real, double>::value) a.fr = m.fr64;
-    else a.fr = m.fr32;
-    a.area = m.area;
-    a.Un = f.Un; a.Us = f.Us; a.Uout = f.Uout;
-    a.dt_ptr = f.dt_ptr; a.dt_value = f.dt_value;
-    a.flux_out = (real *)f.flux_out;
-    a.resid = f.resid;
-    a.ctrl = f.ctrl;
-    a.nonphys = f.nonphys ? f.nonphys : (f.ctrl ? &f.ctrl->nonphysical : nullptr);
-    a.dt_part = f.dt_part;
-    a.gamma = (real)m.gamma; a.ax = (real)m.ax; a.ay = (real)m.ay;
-    a.gamma64 = m.gamma;
-    a.stage = f.mode == 2 ? f.stage : 0;
-    for (int q = 0; q < 4; ++q) a.gw[q] = q < m.tab.Nq ? (real)m.tab.gw[q] : (real)0;
-    a.bface = m.bface;
-    for (int k = 0; k < 2; ++k)
-        for (int v = 0; v < 4; ++v) a.bst[k][v] = m.bst[k][v];
-    for (int k = 0; k < 3; ++k) a.bline[k] = m.bline[k];
-    for (int q = 0; q < 4; ++q) a.gq[q] = q < m.tab.Nq ? m.tab.gq[q] : 0.0;
-    a.t_base = f.t_base;
-    a.tctrl = f.ctrl && f.dt_ptr ? f.ctrl : nullptr;
+    FluxArgs<real> a;
+    fill_flux_args<real>(m, f, a);
     const unsigned grid = (unsigned)m.blocks();
 #define FX_LAUNCH(NQ)                                                                                         \
     switch (f.mode) {                                                                                         \
@@ -70,6 +48,12 @@ static hipError_t flux_t(const DeviceMesh &m, const FluxLaunch &f, hipStream_t s
     }
 #undef FX_LAUNCH
     return hipGetLastError();
+}
+
+hipError_t launch_stage(const DeviceMesh &m, bool fp32, const FluxLaunch &f, const int *done, int part,
+                        hipStream_t st, unsigned long long *fb_count) {
+    if (!fp32) return hipErrorInvalidValue;      // FP64 stages run the separate kernels
+    return stage_fused<float>(m, f, done, part, st, fb_count);
 }
 
 hipError_t launch_flux(const DeviceMesh &m, bool fp32, const FluxLaunch &f, hipStream_t st) {
@@ -202,7 +186,9 @@ __global__ __launch_bounds__(256) void k_reconstruct_batch(const ReconArgs<float
     const int64_t i = (b - t.block0) * blockDim.x + threadIdx.x;
     if (i >= t.N) return;
     const ReconPtrs<float> ptr{t.U[stage], t.slot, t.flags, t.P, t.FV, nullptr, nullptr, &t.ctrl->fallbacks};
-    recon_body<float, R, 4, SCHEME, GFORM, 0, 0>(a, ptr, i);
+    float out[3][2][4];
+    recon_body<float, R, 4, SCHEME, GFORM, 0, 0>(a, ptr, i, out);
+    store_row<float, 3 * 2 * 4>(ptr.FV + i * 3 * 2 * 4, &out[0][0][0]);
 }
 
 __global__ __launch_bounds__(256) void k_flux_batch(const FluxArgs<float> a, const BatchSlot *tab, const int *n_slots) {

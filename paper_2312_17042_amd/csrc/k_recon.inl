@@ -12,7 +12,9 @@ __global__ __launch_bounds__(256) void k_reconstruct(const ReconArgs<real, (R + 
     if (i >= a.N) return;
     if (a.done && *a.done) return;
     const ReconPtrs<real> ptr{a.U, a.slot, a.flags, a.P, a.FV, a.delta, a.fr, a.fb_count};
-    recon_body<real, R, NV, SCHEME, GFORM, DMODE, VARS>(a, ptr, i);
+    real out[3][2][NV];
+    recon_body<real, R, NV, SCHEME, GFORM, DMODE, VARS>(a, ptr, i, out);
+    store_row<real, 3 * 2 * NV>(ptr.FV + i * 3 * 2 * NV, &out[0][0][0]);
 }
 
 

@@ -60,7 +60,15 @@ struct DeviceMesh {
     double *htab64 = nullptr;      // r >= 4: Gram matrix [K][K] and face basis [3][Nq][K], FP64
     float *htab32 = nullptr;       // the same in FP32
     RefTables tab;
+    // fused stage (degree <= 3): cells with a face whose neighbour lies in
+    // another 256-cell block, ascending
+    int32_t *xcells = nullptr;
+    int64_t n_cross = 0;
+    bool fused = false;            // the march runs the fused stage kernels
     int64_t blocks() const { return (N + 255) / 256; }
+    int64_t cross_blocks() const { return (n_cross + 255) / 256; }
+    // per-block CFL minima of one march step: both stage kernels' blocks
+    int64_t dt_parts() const { return blocks() + (fused ? cross_blocks() : 0); }
     // selection bytes per cell: per variable, or per face and characteristic field
     int delta_bytes() const { return vars == CTENO_VARS_CHARACTERISTIC ? 3 * nv : nv; }
 };
@@ -105,8 +113,20 @@ struct FluxLaunch {
     int *nonphys = nullptr;      // non-physical flag when ctrl is null (may be null)
     double *dt_part = nullptr;   // per-block minima of the CFL bound (stage 2 of a march), or null
     double t_base = 0.0;         // time of the stage input when the march time is not on the device
+    double *racc = nullptr;      // fused stage: partial sums [Np][nv] of cells with faces to other blocks
 };
 hipError_t launch_flux(const DeviceMesh &m, bool fp32, const FluxLaunch &f, hipStream_t st);
+
+// Fused SSP-RK3 stage of degree <= 3 in mixed precision (f.mode 2): part 0 reconstructs each
+// 256-cell block into LDS, evaluates the faces inside the block and updates
+// the cells whose faces all lie inside it; the others store their face
+// values and partial sums (f.racc), and part 1 finishes them with the faces
+// to other blocks.  The two parts are launched in order, 0 then 1.
+hipError_t launch_stage(const DeviceMesh &m, bool fp32, const FluxLaunch &f, const int *done, int part,
+                        hipStream_t st, unsigned long long *fb_count);
+template <typename real>
+hipError_t stage_fused(const DeviceMesh &m, const FluxLaunch &f, const int *done, int part, hipStream_t st,
+                       unsigned long long *fb_count);     // instantiated for float (k_stage_f32.hip)
 
 // per-block minima of the CFL bound of state U into dt_part[blocks()], from the
 // face records of the stage kernels' precision (fp32) so a march's first step

@@ -374,9 +374,11 @@ __device__ __forceinline__ void finish_fields(const ReconArgs<real, K> a, real (
     }
 }
 
+// Reconstruction of cell i: its face Gauss-point values in out (and its
+// selection bytes, DMODE 1); the caller stores them
 template <typename real, int R, int NV, int SCHEME, int GFORM, int DMODE, int VARS>
 __device__ __forceinline__ void recon_body(const ReconArgs<real, (R + 1) * (R + 2) / 2 - 1> a,
-                                           const ReconPtrs<real> ptr, int64_t i) {
+                                           const ReconPtrs<real> ptr, int64_t i, real (&out)[3][2][NV]) {
     // a and ptr by value: a reference to the kernel-argument struct would make
     // the compiler copy it to scratch memory
     constexpr int K = (R + 1) * (R + 2) / 2 - 1;
@@ -522,7 +524,6 @@ __device__ __forceinline__ void recon_body(const ReconArgs<real, (R + 1) * (R + 
             // TENO keeps the central stencil's own polynomial
             if (SCHEME != CTENO_SCHEME_TENO) ao[k][v] = st > 1 ? sm / a.lam1 : sm;
         }
-    real out[3][2][NV];
     constexpr int NB = VARS ? 3 * NV : NV;       // selection bytes per cell
     uint8_t dbyte[NB];
     if constexpr (VARS == 0) {
@@ -654,7 +655,6 @@ __device__ __forceinline__ void recon_body(const ReconArgs<real, (R + 1) * (R + 
 #pragma unroll
         for (int k = 0; k < NB; ++k) ptr.delta[i * NB + k] = dbyte[k];
     }
-    store_row<real, 3 * 2 * NV>(ptr.FV + i * 3 * 2 * NV, &out[0][0][0]);
 }
 
 
@@ -808,7 +808,46 @@ struct FluxArgs {
     double gq[4];           // Gauss nodes on [0, 1]
     double t_base;          // time of the stage input when tctrl is null
     const Ctrl *tctrl;      // time march: the stage input's time is tctrl->t, its step *dt_ptr
+    // fused stage: cells with a face whose neighbour lies in another
+    // 256-cell block finish in a second kernel from their partial sums
+    double *racc;           // [Np][NV] partial sums of those cells
+    const int32_t *xcells;  // their list, ascending
+    int64_t n_cross;
+    int64_t part_off;       // offset of the second kernel's block minima in dt_part
 };
+
+// the launch arguments of a flux / residual / RK stage (MODE f.mode)
+template <typename real>
+inline void fill_flux_args(const DeviceMesh &m, const FluxLaunch &f, FluxArgs<real> &a) {
+    a = FluxArgs<real>{};
+    a.N = m.N;
+    a.FV = (const real *)f.FV;
+    if constexpr (std::is_same<real, double>::value) a.fr = m.fr64;
+    else a.fr = m.fr32;
+    a.area = m.area;
+    a.Un = f.Un; a.Us = f.Us; a.Uout = f.Uout;
+    a.dt_ptr = f.dt_ptr; a.dt_value = f.dt_value;
+    a.flux_out = (real *)f.flux_out;
+    a.resid = f.resid;
+    a.ctrl = f.ctrl;
+    a.nonphys = f.nonphys ? f.nonphys : (f.ctrl ? &f.ctrl->nonphysical : nullptr);
+    a.dt_part = f.dt_part;
+    a.gamma = (real)m.gamma; a.ax = (real)m.ax; a.ay = (real)m.ay;
+    a.gamma64 = m.gamma;
+    a.stage = f.mode == 2 ? f.stage : 0;
+    for (int q = 0; q < 4; ++q) a.gw[q] = q < m.tab.Nq ? (real)m.tab.gw[q] : (real)0;
+    a.bface = m.bface;
+    for (int k = 0; k < 2; ++k)
+        for (int v = 0; v < 4; ++v) a.bst[k][v] = m.bst[k][v];
+    for (int k = 0; k < 3; ++k) a.bline[k] = m.bline[k];
+    for (int q = 0; q < 4; ++q) a.gq[q] = q < m.tab.Nq ? m.tab.gq[q] : 0.0;
+    a.t_base = f.t_base;
+    a.tctrl = f.ctrl && f.dt_ptr ? f.ctrl : nullptr;
+    a.racc = f.racc;
+    a.xcells = m.xcells;
+    a.n_cross = m.n_cross;
+    a.part_off = m.blocks();
+}
 
 template <int NV, int PHYS>
 __device__ __forceinline__ double cell_dt_bound(const double *U, const double nrm[3][3], double area, double gamma,
@@ -856,134 +895,170 @@ struct FluxPtrs {
     bool want_dt;
 };
 
+// Outside values of a boundary face at its Gauss points, oth[NQ-1-q]
+// paired with ownf[q]: a prescribed (inflow) state on the Gauss point's side
+// of the moving line at the stage time (t, t + dt, t + dt/2 for the three
+// stages), or the inside state (transmissive).  Returns true for a wall of
+// the Euler equations, whose flux comes in closed form from the inside state.
+template <typename real, int NV, int PHYS, int MODE, int NQ>
+__device__ __forceinline__ bool boundary_state(const FluxArgs<real> a, const double *dt_ptr, uint32_t code,
+                                               const real (&ownf)[NQ][NV], real (&oth)[NQ][NV]) {
+    const uint32_t kind = code & 3u;
+    if (PHYS == CTENO_EULER && kind == CTENO_WALL) return true;
+    if (kind == CTENO_INFLOW) {
+        const double *e = a.bface + 4 * (int64_t)((code >> 2) & kNbInflowMask);
+        const double t0 = a.tctrl ? a.tctrl->t : a.t_base;
+        const double dts = MODE == 2 ? (dt_ptr ? *dt_ptr : a.dt_value) : 0.0;
+        const double ts = t0 + (a.stage == 1 ? dts : a.stage == 2 ? 0.5 * dts : 0.0);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const double px = e[0] + a.gq[q] * e[2], py = e[1] + a.gq[q] * e[3];
+            const int side = px < a.bline[0] + a.bline[1] * py + a.bline[2] * ts ? 0 : 1;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) oth[NQ - 1 - q][v] = (real)a.bst[side][v];
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) oth[NQ - 1 - q][v] = ownf[q][v];
+    }
+    return false;
+}
+
+// A cell's outward flux through one face, |A| sum_q w_q F_q, with its sign.
+// Both cells of a face evaluate F(owner side, other side; owner normal) at
+// the owner's Gauss points in the owner's order, so the two terms are
+// bitwise negatives of each other.
+template <typename real, int NV, int PHYS, int NQ>
+__device__ __forceinline__ void face_term(const FluxArgs<real> a, const real (&ownf)[NQ][NV],
+                                          const real (&oth)[NQ][NV], bool owner, bool wallf, real nx, real ny,
+                                          real len, double (&term)[NV], bool &bad) {
+    const real fx = owner ? nx : -nx, fy = owner ? ny : -ny;
+    real sumF[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) sumF[v] = 0;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        real A[NV], B[NV], F[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            A[v] = owner ? ownf[q][v] : oth[q][v];
+            B[v] = owner ? oth[NQ - 1 - q][v] : ownf[NQ - 1 - q][v];
+        }
+        if (PHYS == CTENO_EULER) {
+            if (wallf) bad |= !wall_flux<real>(a.gamma, A, fx, fy, F);
+            else bad |= !hllc<real>(a.gamma, A, B, fx, fy, F);
+        } else {
+            const real an = a.ax * fx + a.ay * fy;
+            F[0] = an * (an >= 0 ? A[0] : B[0]);
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) sumF[v] += a.gw[q] * F[v];
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const double val = (double)(len * sumF[v]);
+        term[v] = owner ? val : -val;
+    }
+}
+
+// U^n, the stage input and the area of cell i (the RK stage's operands)
+template <typename real, int NV>
+__device__ __forceinline__ void rk_load(const FluxPtrs<real> ptr, int64_t i, double (&u0)[NV], double (&us)[NV],
+                                        double &ar) {
+    ar = ptr.area[i];
+    if constexpr (NV == 4) {
+        const double2 *U2 = reinterpret_cast<const double2 *>(ptr.Un);
+        const double2 *S2 = reinterpret_cast<const double2 *>(ptr.Us);
+        const double2 x0 = U2[2 * i], x1 = U2[2 * i + 1], y0 = S2[2 * i], y1 = S2[2 * i + 1];
+        u0[0] = x0.x; u0[1] = x0.y; u0[2] = x1.x; u0[3] = x1.y;
+        us[0] = y0.x; us[1] = y0.y; us[2] = y1.x; us[3] = y1.y;
+    } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) { u0[v] = ptr.Un[i * NV + v]; us[v] = ptr.Us[i * NV + v]; }
+    }
+}
+
+// SSP-RK3 stage of cell i from the sum acc of its outward face fluxes (the
+// residual is -acc / |V_i|) and its loaded operands: writes the new state;
+// returns its CFL bound when requested, else +inf
+template <typename real, int NV, int PHYS>
+__device__ __forceinline__ double rk_apply(const FluxArgs<real> a, const FluxPtrs<real> ptr, int64_t i,
+                                           const double (&acc)[NV], const double (&nrm)[3][3],
+                                           const double (&u0)[NV], const double (&us)[NV], double ar) {
+    const double dt = ptr.dt_ptr ? *ptr.dt_ptr : a.dt_value;
+    double un[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const double R = -acc[v] / ar;
+        double r;
+        if (a.stage == 0) r = us[v] + dt * R;
+        else if (a.stage == 1) r = 0.75 * u0[v] + 0.25 * (us[v] + dt * R);
+        else r = (1.0 / 3.0) * u0[v] + (2.0 / 3.0) * (us[v] + dt * R);
+        un[v] = r;
+    }
+    if constexpr (NV == 4) {
+        double2 *O2 = reinterpret_cast<double2 *>(ptr.Uout);
+        O2[2 * i] = make_double2(un[0], un[1]);
+        O2[2 * i + 1] = make_double2(un[2], un[3]);
+    } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) ptr.Uout[i * NV + v] = un[v];
+    }
+    return ptr.want_dt ? cell_dt_bound<NV, PHYS>(un, nrm, ar, a.gamma64, (double)a.ax, (double)a.ay) : INFINITY;
+}
+
+template <typename real, int NV, int PHYS>
+__device__ __forceinline__ double rk_update(const FluxArgs<real> a, const FluxPtrs<real> ptr, int64_t i,
+                                            const double (&acc)[NV], const double (&nrm)[3][3]) {
+    double u0[NV], us[NV], ar;
+    rk_load<real, NV>(ptr, i, u0, us, ar);
+    return rk_apply<real, NV, PHYS>(a, ptr, i, acc, nrm, u0, us, ar);
+}
+
 // one cell's three faces, residual and (MODE 2) RK stage; returns the cell's
 // CFL bound of the new state when requested, else +inf
 template <typename real, int NV, int PHYS, int MODE, int NQ>
 __device__ __forceinline__ double flux_body(const FluxArgs<real> a, const FluxPtrs<real> ptr, int64_t i) {
-    double dtc = INFINITY;
-    {
-        double acc[NV];
+    double acc[NV];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) acc[v] = 0.0;
-        double nrm[3][3];
-        bool bad = false;
-        real own[3][NQ][NV];
-        load_row<real, 3 * NQ * NV>(ptr.FV + i * 3 * NQ * NV, &own[0][0][0]);
+    for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+    double nrm[3][3];
+    bool bad = false;
+    real own[3][NQ][NV];
+    load_row<real, 3 * NQ * NV>(ptr.FV + i * 3 * NQ * NV, &own[0][0][0]);
 #pragma unroll
-        for (int f = 0; f < 3; ++f) {
-            real nx, ny, len;
-            uint32_t code;
-            face_record<real>(ptr.fr, i, f, nx, ny, len, code);
-            nrm[f][0] = (double)nx; nrm[f][1] = (double)ny; nrm[f][2] = (double)len;
-            real oth[NQ][NV];
-            bool owner;
-            bool wallf = false;
-            if (code & kNbBoundary) {
-                owner = true;
-                const uint32_t kind = code & 3u;
-                wallf = PHYS == CTENO_EULER && kind == CTENO_WALL;
-                if (wallf) {
-                    // the flux comes from wall_flux; no outside state needed
-                } else if (kind == CTENO_INFLOW) {
-                    // prescribed state on the Gauss point's side of the moving line
-                    // at the stage time (t, t + dt, t + dt/2 for the three stages)
-                    const double *e = a.bface + 4 * (int64_t)((code >> 2) & kNbInflowMask);
-                    const double t0 = a.tctrl ? a.tctrl->t : a.t_base;
-                    const double dts = MODE == 2 ? (ptr.dt_ptr ? *ptr.dt_ptr : a.dt_value) : 0.0;
-                    const double ts = t0 + (a.stage == 1 ? dts : a.stage == 2 ? 0.5 * dts : 0.0);
-#pragma unroll
-                    for (int q = 0; q < NQ; ++q) {
-                        const double px = e[0] + a.gq[q] * e[2], py = e[1] + a.gq[q] * e[3];
-                        const int side = px < a.bline[0] + a.bline[1] * py + a.bline[2] * ts ? 0 : 1;
-#pragma unroll
-                        for (int v = 0; v < NV; ++v) oth[NQ - 1 - q][v] = (real)a.bst[side][v];
-                    }
-                } else {
-                    // transmissive: the inside state at the same Gauss point
-                    // (oth[NQ-1-q] pairs with own[q])
-#pragma unroll
-                    for (int q = 0; q < NQ; ++q)
-#pragma unroll
-                        for (int v = 0; v < NV; ++v) oth[NQ - 1 - q][v] = own[f][q][v];
-                }
-            } else {
-                owner = (code & kNbOwner) != 0;
-                const int64_t j = code & kNbIndexMask;
-                const int g = (code >> 28) & 3;
-                load_row<real, NQ * NV>(ptr.FV + (j * 3 + g) * NQ * NV, &oth[0][0]);
-            }
-            // both cells of a face evaluate F(owner side, other side; owner normal)
-            // at the owner's Gauss points in the owner's order
-            const real fx = owner ? nx : -nx, fy = owner ? ny : -ny;
-            real sumF[NV];
-#pragma unroll
-            for (int v = 0; v < NV; ++v) sumF[v] = 0;
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                real A[NV], B[NV], F[NV];
-#pragma unroll
-                for (int v = 0; v < NV; ++v) {
-                    A[v] = owner ? own[f][q][v] : oth[q][v];
-                    B[v] = owner ? oth[NQ - 1 - q][v] : own[f][NQ - 1 - q][v];
-                }
-                if (PHYS == CTENO_EULER) {
-                    if (wallf) bad |= !wall_flux<real>(a.gamma, A, fx, fy, F);
-                    else bad |= !hllc<real>(a.gamma, A, B, fx, fy, F);
-                } else {
-                    const real an = a.ax * fx + a.ay * fy;
-                    F[0] = an * (an >= 0 ? A[0] : B[0]);
-                }
-#pragma unroll
-                for (int v = 0; v < NV; ++v) sumF[v] += a.gw[q] * F[v];
-            }
-#pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                const double val = (double)(len * sumF[v]);
-                const double out = owner ? val : -val;
-                acc[v] += out;
-                if (MODE == 0) ptr.flux_out[(i * 3 + f) * NV + v] = (real)out;
-            }
+    for (int f = 0; f < 3; ++f) {
+        real nx, ny, len;
+        uint32_t code;
+        face_record<real>(ptr.fr, i, f, nx, ny, len, code);
+        nrm[f][0] = (double)nx; nrm[f][1] = (double)ny; nrm[f][2] = (double)len;
+        real oth[NQ][NV];
+        bool owner = true, wallf = false;
+        if (code & kNbBoundary) {
+            wallf = boundary_state<real, NV, PHYS, MODE, NQ>(a, ptr.dt_ptr, code, own[f], oth);
+        } else {
+            owner = (code & kNbOwner) != 0;
+            const int64_t j = code & kNbIndexMask;
+            const int g = (code >> 28) & 3;
+            load_row<real, NQ * NV>(ptr.FV + (j * 3 + g) * NQ * NV, &oth[0][0]);
         }
-        if (bad && ptr.nonphys) atomicOr(ptr.nonphys, 1);
-        if (MODE == 1) {
+        double term[NV];
+        face_term<real, NV, PHYS, NQ>(a, own[f], oth, owner, wallf, nx, ny, len, term, bad);
 #pragma unroll
-            for (int v = 0; v < NV; ++v) ptr.resid[i * NV + v] = -acc[v] / ptr.area[i];
-        }
-        if (MODE == 2) {
-            const double dt = ptr.dt_ptr ? *ptr.dt_ptr : a.dt_value;
-            const double ar = ptr.area[i];
-            double u0[NV], us[NV], un[NV];
-            if constexpr (NV == 4) {
-                const double2 *U2 = reinterpret_cast<const double2 *>(ptr.Un);
-                const double2 *S2 = reinterpret_cast<const double2 *>(ptr.Us);
-                const double2 x0 = U2[2 * i], x1 = U2[2 * i + 1], y0 = S2[2 * i], y1 = S2[2 * i + 1];
-                u0[0] = x0.x; u0[1] = x0.y; u0[2] = x1.x; u0[3] = x1.y;
-                us[0] = y0.x; us[1] = y0.y; us[2] = y1.x; us[3] = y1.y;
-            } else {
-#pragma unroll
-                for (int v = 0; v < NV; ++v) { u0[v] = ptr.Un[i * NV + v]; us[v] = ptr.Us[i * NV + v]; }
-            }
-#pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                const double R = -acc[v] / ar;
-                double r;
-                if (a.stage == 0) r = us[v] + dt * R;
-                else if (a.stage == 1) r = 0.75 * u0[v] + 0.25 * (us[v] + dt * R);
-                else r = (1.0 / 3.0) * u0[v] + (2.0 / 3.0) * (us[v] + dt * R);
-                un[v] = r;
-            }
-            if constexpr (NV == 4) {
-                double2 *O2 = reinterpret_cast<double2 *>(ptr.Uout);
-                O2[2 * i] = make_double2(un[0], un[1]);
-                O2[2 * i + 1] = make_double2(un[2], un[3]);
-            } else {
-#pragma unroll
-                for (int v = 0; v < NV; ++v) ptr.Uout[i * NV + v] = un[v];
-            }
-            if (ptr.want_dt) dtc = cell_dt_bound<NV, PHYS>(un, nrm, ar, a.gamma64, (double)a.ax, (double)a.ay);
+        for (int v = 0; v < NV; ++v) {
+            acc[v] += term[v];
+            if (MODE == 0) ptr.flux_out[(i * 3 + f) * NV + v] = (real)term[v];
         }
     }
-    return dtc;
+    if (bad && ptr.nonphys) atomicOr(ptr.nonphys, 1);
+    if (MODE == 1) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) ptr.resid[i * NV + v] = -acc[v] / ptr.area[i];
+    }
+    if (MODE == 2) return rk_update<real, NV, PHYS>(a, ptr, i, acc, nrm);
+    return INFINITY;
 }
 
 }  // namespace cteno

@@ -47,6 +47,7 @@ struct cteno_ctx {
     cteno_free_fn free_fn = nullptr;
     void *user = nullptr;
     bool timing = false;
+    bool fused_stage = true;    // degree <= 3: the fused stage kernels (else reconstruction + flux)
     int64_t launches[3] = {0, 0, 0};
     double total_ms[3] = {0, 0, 0};
     struct Pending { int kernel; hipEvent_t a, b; };
@@ -176,6 +177,14 @@ extern "C" cteno_status cteno_ctx_synchronize(cteno_ctx *c) {
     HIP_TRY(hipSetDevice(c->device));
     HIP_TRY(hipStreamSynchronize(c->stream()));
     collect_timing(c);
+    return CTENO_OK;
+}
+
+extern "C" cteno_status cteno_ctx_set_fused_stage(cteno_ctx *c, int32_t on) {
+    if (!c) return fail(CTENO_ERR_INVALID, "ctx is NULL");
+    HIP_TRY(hipSetDevice(c->device));
+    HIP_TRY(hipStreamSynchronize(c->stream()));
+    c->fused_stage = on != 0;
     return CTENO_OK;
 }
 
@@ -361,6 +370,29 @@ static cteno_status upload_device_mesh(cteno_ctx *ctx, hipStream_t st, HostMesh 
     } else {
         dm.P64 = nullptr;
     }
+    // fused stage (degree <= 3; single meshes -- the batched serving kernels
+    // keep the reconstruction + flux pair): the cells with a face whose
+    // neighbour lies in another 256-cell block, from the face codes
+    dm.fused = keep_fr64 && hm.r <= 3 && hm.Nq == 2;
+    if (dm.fused) {
+        std::vector<int32_t> xc;
+        for (int64_t k = 0; k < hm.N; ++k)
+            for (int f = 0; f < 3; ++f) {
+                uint32_t code;
+                std::memcpy(&code, &hm.fr32[avix(k, 4 * f + 3, 12, 4)], sizeof code);
+                if (!(code & kNbBoundary) && ((int64_t)(code & kNbIndexMask) >> 8) != (k >> 8)) {
+                    xc.push_back((int32_t)k);
+                    break;
+                }
+            }
+        dm.n_cross = (int64_t)xc.size();
+        if (dm.n_cross) {
+            dm.xcells = alloc_T(int32_t, xc.size());
+            if (!dm.xcells) return fail(CTENO_ERR_NOMEM, "device allocation failed");
+            HIP_TRY(h2d(dm.xcells, xc, st));
+            HIP_TRY(hipStreamSynchronize(st));
+        }
+    }
     // release host-only copies that the device now holds
     hm.slot.clear(); hm.slot.shrink_to_fit();
     hm.slot_flag.clear(); hm.slot_flag.shrink_to_fit();
@@ -404,6 +436,7 @@ extern "C" cteno_status cteno_mesh_info_get(const cteno_mesh *m, cteno_mesh_info
     info->Md = m->host.Md;
     info->n_inadmissible = m->host.n_inadmissible;
     info->device_bytes = m->bytes;
+    info->n_cross_cells = m->dm.n_cross;
     return CTENO_OK;
 }
 
@@ -512,9 +545,11 @@ struct cteno_sol {
     DevBuf ctrl;              // Ctrl
     DevBuf dt_part;           // per-block minima of the CFL bound
     DevBuf status;            // SolStatus: fallback count, non-physical flag of stage calls
+    DevBuf racc;              // fused stage: partial sums of cells with faces to other blocks
     double t = 0.0;
     Ctrl *h_ctrl = nullptr;   // pinned host mirror
     hipGraphExec_t graph[2] = {nullptr, nullptr};
+    bool graph_fused[2] = {false, false};   // stage kernels a captured graph holds
     ~cteno_sol() {
         for (auto &g : graph) if (g) (void)hipGraphExecDestroy(g);
         if (h_ctrl) (void)hipHostFree(h_ctrl);
@@ -562,7 +597,7 @@ extern "C" cteno_status cteno_sol_create(cteno_ctx *ctx, const cteno_mesh *m, co
         HIP_TRY(hipMemsetAsync(u.p, 0, bytes, ctx->stream()));
     }
     s->ctrl = DevBuf(ctx, sizeof(Ctrl));
-    s->dt_part = DevBuf(ctx, (size_t)dm.blocks() * sizeof(double));
+    s->dt_part = DevBuf(ctx, (size_t)dm.dt_parts() * sizeof(double));
     s->status = DevBuf(ctx, sizeof(SolStatus));
     if (!s->ctrl.p || !s->dt_part.p || !s->status.p) return fail(CTENO_ERR_NOMEM, "device allocation failed");
     HIP_TRY(hipMemsetAsync(s->ctrl.p, 0, sizeof(Ctrl), ctx->stream()));
@@ -777,6 +812,11 @@ extern "C" cteno_status cteno_residual(cteno_ctx *ctx, const cteno_mesh *m, cons
 }
 
 namespace {
+// The fused stage runs in mixed precision: in FP64 the reconstruction holds
+// one wave per SIMD, too few to hide the flux phase behind the block barrier
+// (measured slower than the two kernels), so FP64 keeps the separate kernels.
+bool use_fused(const cteno_ctx *ctx, const DeviceMesh &dm, bool f32) { return f32 && dm.fused && ctx->fused_stage; }
+
 // one SSP-RK3 stage on sol; dt from a device pointer or a host value
 hipError_t issue_stage(cteno_ctx *ctx, cteno_sol *s, bool f32, int stage, const double *dt_ptr, double dt_value,
                        Ctrl *ctrl, double *dt_part, hipStream_t st) {
@@ -786,8 +826,6 @@ hipError_t issue_stage(cteno_ctx *ctx, cteno_sol *s, bool f32, int stage, const 
     void *fv = s->fv(f32);
     const int *done = ctrl ? &ctrl->done : nullptr;
     SolStatus *ss = sol_status(s);
-    hipError_t e = timed(ctx, 0, [&] { return launch_reconstruct(dm, f32, in, fv, nullptr, 0, done, st, &ss->fallbacks); });
-    if (e != hipSuccess) return e;
     FluxLaunch fl;
     fl.mode = 2;
     fl.FV = fv;
@@ -801,7 +839,26 @@ hipError_t issue_stage(cteno_ctx *ctx, cteno_sol *s, bool f32, int stage, const 
     fl.nonphys = ctrl ? nullptr : &ss->nonphysical;    // a march reports through its control block
     fl.dt_part = dt_part;
     fl.t_base = s->t;
+    if (use_fused(ctx, dm, f32)) {
+        fl.racc = s->racc.as<double>();
+        hipError_t e = timed(ctx, 0, [&] { return launch_stage(dm, f32, fl, done, 0, st, &ss->fallbacks); });
+        if (e != hipSuccess) return e;
+        return timed(ctx, 1, [&] { return launch_stage(dm, f32, fl, done, 1, st, &ss->fallbacks); });
+    }
+    hipError_t e = timed(ctx, 0, [&] { return launch_reconstruct(dm, f32, in, fv, nullptr, 0, done, st, &ss->fallbacks); });
+    if (e != hipSuccess) return e;
     return timed(ctx, 1, [&] { return launch_flux(dm, f32, fl, st); });
+}
+
+// the work buffers a stage needs: face values, and the fused stage's partial sums
+bool stage_buffers(cteno_ctx *ctx, cteno_sol *s, bool f32) {
+    if (!s->fv(f32)) return false;
+    const DeviceMesh &dm = s->mesh->dm;
+    if (use_fused(ctx, dm, f32) && !s->racc.p) {
+        s->racc = DevBuf(ctx, (size_t)dm.Np * dm.nv * sizeof(double));
+        if (!s->racc.p) return false;
+    }
+    return true;
 }
 }  // namespace
 
@@ -813,7 +870,7 @@ extern "C" cteno_status cteno_rk_stage(cteno_ctx *ctx, const cteno_mesh *m, cten
     bool f32;
     if (cteno_status rc = check_precision(m, precision, f32)) return rc;
     HIP_TRY(hipSetDevice(ctx->device));
-    if (!sol->fv(f32)) return fail(CTENO_ERR_NOMEM, "device allocation failed");
+    if (!stage_buffers(ctx, sol, f32)) return fail(CTENO_ERR_NOMEM, "device allocation failed");
     HIP_TRY(issue_stage(ctx, sol, f32, stage, nullptr, dt, nullptr, nullptr, ctx->stream()));
     if (stage == 2) sol->t += dt;
     return CTENO_OK;
@@ -826,7 +883,8 @@ namespace {
 hipError_t issue_step(cteno_ctx *ctx, cteno_sol *s, bool f32, hipStream_t st) {
     Ctrl *c = s->ctrl.as<Ctrl>();
     double *part = s->dt_part.as<double>();
-    hipError_t e = launch_control(c, part, s->mesh->dm.blocks(), 0, st);
+    const DeviceMesh &dm = s->mesh->dm;
+    hipError_t e = launch_control(c, part, use_fused(ctx, dm, f32) ? dm.dt_parts() : dm.blocks(), 0, st);
     for (int stage = 0; stage < 3 && e == hipSuccess; ++stage)
         e = issue_stage(ctx, s, f32, stage, &c->dt, 0.0, c, stage == 2 ? part : nullptr, st);
     return e;
@@ -842,7 +900,7 @@ extern "C" cteno_status cteno_solve(cteno_ctx *ctx, const cteno_mesh *m, cteno_s
     bool f32;
     if (cteno_status rc = check_precision(m, precision, f32)) return rc;
     HIP_TRY(hipSetDevice(ctx->device));
-    if (!s->fv(f32)) return fail(CTENO_ERR_NOMEM, "device allocation failed");
+    if (!stage_buffers(ctx, s, f32)) return fail(CTENO_ERR_NOMEM, "device allocation failed");
     const DeviceMesh &dm = m->dm;
     hipStream_t st = ctx->stream();
     Ctrl *dc = s->ctrl.as<Ctrl>();
@@ -855,6 +913,9 @@ extern "C" cteno_status cteno_solve(cteno_ctx *ctx, const cteno_mesh *m, cteno_s
     h.dt_cand_bits = 0x7FF0000000000000ull;
     HIP_TRY(hipMemcpyAsync(dc, &h, sizeof(Ctrl), hipMemcpyHostToDevice, st));
     HIP_TRY(launch_dt_partials(dm, f32, s->U[0].as<double>(), s->dt_part.as<double>(), st));
+    if (use_fused(ctx, dm, f32) && dm.cross_blocks())    // the second stage kernel's minima: none yet
+        HIP_TRY(launch_fill_u64((unsigned long long *)(s->dt_part.as<double>() + dm.blocks()),
+                                0x7FF0000000000000ull, (size_t)dm.cross_blocks(), st));
 
     // graphs need a capturable stream: the context's own stream when the
     // caller uses the null stream
@@ -868,7 +929,12 @@ extern "C" cteno_status cteno_solve(cteno_ctx *ctx, const cteno_mesh *m, cteno_s
         HIP_TRY(hipStreamWaitEvent(gs, ev, 0));
     }
     hipGraphExec_t &gx = s->graph[f32 ? 1 : 0];
+    if (gx && s->graph_fused[f32 ? 1 : 0] != use_fused(ctx, dm, f32)) {   // captured with the other stage kernels
+        (void)hipGraphExecDestroy(gx);
+        gx = nullptr;
+    }
     if (graph && !gx) {
+        s->graph_fused[f32 ? 1 : 0] = use_fused(ctx, dm, f32);
         hipGraph_t g = nullptr;
         HIP_TRY(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
         hipError_t e = issue_step(ctx, s, f32, gs);

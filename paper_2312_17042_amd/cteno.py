@@ -68,7 +68,8 @@ class Scheme(C.Structure):
 class MeshInfo(C.Structure):
     _fields_ = [("n_cells", C.c_int64), ("n_faces", C.c_int64), ("n_boundary_faces", C.c_int64),
                 ("K", C.c_int32), ("M", C.c_int32), ("slots", C.c_int32), ("nv", C.c_int32), ("nq", C.c_int32),
-                ("n_inadmissible", C.c_int32), ("Kd", C.c_int32), ("Md", C.c_int32), ("device_bytes", C.c_int64)]
+                ("n_inadmissible", C.c_int32), ("Kd", C.c_int32), ("Md", C.c_int32), ("device_bytes", C.c_int64),
+                ("n_cross_cells", C.c_int64)]
 
 
 class ServerStats(C.Structure):
@@ -95,6 +96,7 @@ _SIGS = {
     "cteno_ctx_synchronize": [C.c_void_p],
     "cteno_last_error": [],
     "cteno_ctx_set_timing": [C.c_void_p, C.c_int32],
+    "cteno_ctx_set_fused_stage": [C.c_void_p, C.c_int32],
     "cteno_ctx_kernel_stats": [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)],
     "cteno_ctx_reset_stats": [C.c_void_p],
     "cteno_mesh_upload": [C.c_void_p, C.POINTER(MeshDesc), C.POINTER(Scheme), C.POINTER(C.c_void_p)],
@@ -253,6 +255,10 @@ class Context:
 
     def set_timing(self, on: bool):
         _check(lib().cteno_ctx_set_timing(self.h, int(bool(on))))
+
+    def set_fused_stage(self, on: bool):
+        """degree <= 3 RK stages: fused kernels (default) or reconstruction + flux"""
+        _check(lib().cteno_ctx_set_fused_stage(self.h, int(bool(on))))
 
     def kernel_stats(self, kernel: int):
         n = C.c_int64()

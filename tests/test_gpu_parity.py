@@ -132,6 +132,18 @@ CASES = {
 EPS64 = float(np.finfo(np.float64).eps)
 
 
+def mixed_tolerance(name, mesh, uo, t):
+    """Tolerance of a mixed-precision march against the FP64 oracle: 1e-5
+    normwise per variable, or 1% of the oracle's own error against the exact
+    solution (vortex cases: the vortex carried by the free stream), whichever
+    is larger."""
+    tol = 1e-5
+    if name.startswith("vortex"):
+        exact = W.cell_average(mesh, W.isentropic_vortex(t))
+        tol = max(tol, 0.01 * relerr_var(uo, exact, axis_v=0))
+    return tol
+
+
 def flux_scale(mesh, u, cells, gamma=1.4):
     """Per-variable size of the face terms that the residual of a cell sums,
     max over the sampled cells of |physical flux of U_i| x perimeter / area.
@@ -664,8 +676,10 @@ def test_flips_are_counted(ctx):
     for i, var in cand[:: max(1, len(cand) // 4)][:4]:
         chi = _chi_of(mesh, kw, int(i), int(var), lo=1e-9)
         assert chi is not None
-        for k in range(-6, 7):
-            ct = chi * (1.0 + k * 1.5e-7)
+        # offsets of half a step from chi itself, where the FP64 selections
+        # of library and oracle (different rounding orders) could differ
+        for k in range(-6, 6):
+            ct = chi * (1.0 + (k + 0.5) * 1.5e-7)
             _, od = O.Oracle.from_mesh(mesh, c_t=ct, **kw).reconstruct(U_FLIP)
             mk = T.Mesh.from_workload(ctx, mesh, precision=T.BOTH, c_t=ct, **kw)
             sk = T.Solution(mk, U_FLIP)
@@ -678,3 +692,41 @@ def test_flips_are_counted(ctx):
             sk.close()
             mk.close()
     assert total > 0
+
+
+@pytest.mark.parametrize("name", ["advection_r2_cteno", "vortex_r3_ctenoz", "density_r2_ctenoz", "dmr_r3_cteno_char",
+                                  "vortex_r3_ctenoz_scaled"])
+def test_fused_stage_matches_split_kernels(ctx, name):
+    """Mixed-precision marches of degree <= 3 run the fused stage kernels by
+    default.  Against the separate reconstruction and flux kernels: the
+    first stage is the same to FP64 rounding (the fused kernels sum a cell's
+    in-block faces first, and evaluate a face inside a block once, its other
+    cell taking the exact negation); over 12 steps the FP64 rounding
+    differences of the state enter the FP32 reconstruction, so the marches
+    agree to the mixed-precision tolerance, and each agrees with the oracle
+    to it: 1e-5 normwise per variable, or 1% of the oracle's own error
+    against the exact solution where that is larger (the scaled CTENOZ
+    reading switches stencils at many smooth cells, so FP32 and FP64 take
+    different stencils at some of them)."""
+    mesh, u0, o, m = setup_case(ctx, name)
+    steps = 12
+    uo, so, to = o.solve(u0, 10.0, cfl=0.3, max_steps=steps)
+    dt = 0.3 * o.dt_bound(u0)
+    out, stage0 = {}, {}
+    for fused in (True, False):
+        ctx.set_fused_stage(fused)
+        try:
+            s = T.Solution(m, u0)
+            s.rk_stage(0, dt, T.MIXED)
+            stage0[fused] = s.download()[0]
+            s.set(u0, 0.0)
+            assert s.solve(t_final=10.0, max_steps=steps, cfl=0.3, precision=T.MIXED) == so
+            out[fused], _ = s.download()
+            s.close()
+        finally:
+            ctx.set_fused_stage(True)
+    assert relerr_var(stage0[True], stage0[False], axis_v=0) < 1e-13
+    tol = mixed_tolerance(name, mesh, uo, to)
+    assert relerr_var(out[True], out[False], axis_v=0) < tol
+    for fused in (True, False):
+        assert relerr_var(out[fused], uo, axis_v=0) < tol

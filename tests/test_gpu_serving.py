@@ -40,9 +40,16 @@ def _requests():
 
 
 def _standalone(ctx, mesh, u0, steps):
+    """A standalone FP32-mixed solve through the same reconstruction and flux
+    kernels as the server's batches (the fused stage kernels sum a cell's
+    faces in another order)."""
     m = T.Mesh.from_workload(ctx, mesh, precision=T.MIXED, **SCHEME)
     s = T.Solution(m, u0)
-    n = s.solve(max_steps=steps, cfl=0.3, precision=T.MIXED, use_graph=False)
+    ctx.set_fused_stage(False)
+    try:
+        n = s.solve(max_steps=steps, cfl=0.3, precision=T.MIXED, use_graph=False)
+    finally:
+        ctx.set_fused_stage(True)
     u, _ = s.download()
     s.close()
     m.close()

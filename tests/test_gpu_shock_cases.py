@@ -105,13 +105,20 @@ def test_shock_density_lambda_sensitivity(ctx, sdw_reference, order):
 def test_shock_density_scaled_ctenoz(ctx, sdw_reference, order):
     """The scaled reading of Algorithm 2 on the same case: like literal CTENO
     it drops the central stencil in smooth parts of the post-shock waves, so
-    it damps the fluctuations far more than the printed CTENOZ (and than
-    TENO and CWENO at 5th order) and depends on lambda1' through p_1 where it
-    keeps the centre.  It does not reproduce Figs. 4-5's CTENOZ."""
+    it damps the fluctuations more than the printed CTENOZ at 5th order
+    (0.151 against 0.129) and about four times more at 7th order (0.36-0.41
+    against 0.089), where it also depends on lambda1' (through p_1 where it
+    keeps the centre).  It does not reproduce Figs. 4-5's CTENOZ, which
+    improves from 5th to 7th order."""
     z = [_sdw_error(ctx, sdw_reference, "CTENOZ", order, lam) for lam in LAMBDAS]
     zs = [_sdw_error(ctx, sdw_reference, "CTENOZ-scaled", order, lam) for lam in LAMBDAS]
-    assert min(zs) > 2.0 * max(z), (zs, z)
-    assert max(zs) / min(zs) < 1.25, zs
+    assert min(zs) > max(z), (zs, z)
+    if order == 7:
+        # selections near the cut-off decide where the fluctuations are damped,
+        # so the error varies with lambda1' and with rounding (0.35-0.45)
+        assert min(zs) > 2.0 * max(z), (zs, z)
+    else:
+        assert max(zs) / min(zs) < 1.1, zs
 
 
 def test_shock_density_scheme_ranking(ctx, sdw_reference):
