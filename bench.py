@@ -47,9 +47,10 @@ CELL_UPDATE_BYTES = 32 + 32 + 8
 # HBM bytes per cell and launch measured with the FETCH_SIZE / WRITE_SIZE
 # counters (scaled by the copy-kernel calibration), valid only for the
 # kernel sources they were taken on
-MEASURED_TRAFFIC = {"kernels_sha256_prefix": None, "stage_mixed_bytes_per_cell": None,
-                    "cross_mixed_bytes_per_cell": None, "stage_fp64_bytes_per_cell": None,
-                    "cross_fp64_bytes_per_cell": None}
+MEASURED_TRAFFIC = {"kernels_sha256_prefix": None,
+                    "bytes_per_cell": {"k_stage": None, "k_stage_cross": None,
+                                       "k_reconstruct_f32": None, "k_flux_f32": None,
+                                       "k_reconstruct_f64": None, "k_flux_f64": None}}
 
 
 KERNEL_SOURCES = ("kernels_common.h", "k_recon.inl", "k_recon_ho.inl", "k_stage.inl", "k_recon_f32.hip",
@@ -467,22 +468,25 @@ def main():
     N = mesh.n_cells
 
     res, split = {}, {}
-    precs = [("mixed", T.MIXED)] + ([] if args.no_fp64 else [("fp64", T.FP64)])
-    # the fused stage kernels (default), then the separate reconstruction
-    # and flux kernels for comparison
-    for fused, store in ((True, res), (False, split)):
-        if not fused and args.no_split:
-            continue
+    # mixed precision through the fused stage kernels (the default), FP64
+    # through its reconstruction and flux kernels (the fused kernels are
+    # FP32 only), then mixed precision through the separate kernels for
+    # comparison
+    runs = [("mixed", T.MIXED, True, res)]
+    if not args.no_fp64:
+        runs.append(("fp64", T.FP64, False, res))
+    if not args.no_split:
+        runs.append(("mixed", T.MIXED, False, split))
+    for name, prec, fused, store in runs:
         ctx.set_fused_stage(fused)
-        for name, prec in precs:
-            log(f"timing {name} ({'fused' if fused else 'split'} stage kernels): {args.warmup} warm-up + "
-                f"{args.steps} steps")
-            r = run_precision(T, ctx, m, sol, u0, prec, args.steps, args.warmup)
-            r["value"] = N * 3 * args.steps / r["elapsed"]
-            store[name] = r
-            log(f"{name}: {r['value']:.3e} cell-stage/s, {1e3 * r['elapsed'] / args.steps:.3f} ms/step, "
-                f"kernel 0 {r['recon'][1] / max(1, r['recon'][0]):.3f} ms/launch, "
-                f"kernel 1 {r['flux'][1] / max(1, r['flux'][0]):.3f} ms/launch")
+        kernels = "fused stage kernels" if fused else "reconstruction + flux kernels"
+        log(f"timing {name} ({kernels}): {args.warmup} warm-up + {args.steps} steps")
+        r = run_precision(T, ctx, m, sol, u0, prec, args.steps, args.warmup)
+        r["value"] = N * 3 * args.steps / r["elapsed"]
+        store[name] = r
+        log(f"{name}: {r['value']:.3e} cell-stage/s, {1e3 * r['elapsed'] / args.steps:.3f} ms/step, "
+            f"kernel 0 {r['recon'][1] / max(1, r['recon'][0]):.3f} ms/launch, "
+            f"kernel 1 {r['flux'][1] / max(1, r['flux'][0]):.3f} ms/launch")
     ctx.set_fused_stage(True)
     x_cross = int(m.info.n_cross_cells) / N
 
@@ -525,7 +529,8 @@ def main():
     achieved = gbs(b0, t0)
     stage_gbs = gbs(STAGE_BYTES["mixed"], t0 + t1)
     fresh = kernels_hash() == MEASURED_TRAFFIC["kernels_sha256_prefix"]
-    traffic = MEASURED_TRAFFIC["stage_mixed_bytes_per_cell"] * N if fresh else None
+    measured = MEASURED_TRAFFIC["bytes_per_cell"] if fresh else None
+    traffic = measured["k_stage"] * N if fresh else None
     out = {
         "metric": "cell-stage updates/s (mixed FP32 vs FP64) at stated error; serving p50/p99",
         "value": mx["value"],
@@ -556,8 +561,7 @@ def main():
                                      "calibration; null unless taken on these kernel sources"},
         "kernels": {"stage_ms": t0, "cross_ms": t1, "cross_cells_fraction": x_cross,
                     "bytes_per_cell": {"stage": STAGE_BYTES["mixed"], "k_stage_share": b0, "k_stage_cross_share": b1},
-                    "measured_bytes_per_cell": {k: MEASURED_TRAFFIC[k] for k in MEASURED_TRAFFIC
-                                                if k.endswith("per_cell")} if fresh else None},
+                    "measured_bytes_per_cell": measured},
         "graph_replay": {"value": N * 3 * args.steps / mx["graph_elapsed"],
                          "ms_per_step": 1e3 * mx["graph_elapsed"] / args.steps,
                          "note": "same steps replayed from a captured HIP graph, no per-kernel events"},
@@ -565,14 +569,15 @@ def main():
     if "fp64" in res:
         f = res["fp64"]
         a0, a1 = kstats(f)
-        c0, _ = stage_split_bytes("fp64")
         out["fp64"] = {"value": f["value"], "ms_per_step": 1e3 * f["elapsed"] / args.steps,
                        "graph_replay_value": N * 3 * args.steps / f["graph_elapsed"],
-                       "stage_ms": a0, "cross_ms": a1,
-                       "k_stage_GBs": gbs(c0, a0), "k_stage_frac": gbs(c0, a0) / HBM_PEAK_GBS,
+                       "stage_kernels": "k_reconstruct + k_flux (FP64)",
+                       "reconstruct_ms": a0, "flux_rk_ms": a1,
+                       "reconstruct_GBs": gbs(RECON_BYTES["fp64"], a0),
+                       "reconstruct_frac": gbs(RECON_BYTES["fp64"], a0) / HBM_PEAK_GBS,
                        "stage_GBs": gbs(STAGE_BYTES["fp64"], a0 + a1),
                        "stage_frac": gbs(STAGE_BYTES["fp64"], a0 + a1) / HBM_PEAK_GBS,
-                       "bytes_per_cell": {"stage": STAGE_BYTES["fp64"], "k_stage_share": c0}}
+                       "bytes_per_cell": {"stage": STAGE_BYTES["fp64"], "reconstruct_share": RECON_BYTES["fp64"]}}
         out["mixed_over_fp64"] = mx["value"] / f["value"]
     if split:
         out["split_kernels"] = {}

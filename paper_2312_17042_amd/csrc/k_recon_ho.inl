@@ -94,7 +94,7 @@ __device__ __forceinline__ int finish_field_ho(const ReconHoArgs<real> a, real (
                 for (int k = 0; k < KD; ++k) c1[k] += cd[q][k];
             }
 #pragma unroll
-        for (int k = 0; k < KD; ++k) c1[k] /= (real)cnt;
+        for (int k = 0; k < KD; ++k) c1[k] = fdiv(c1[k], (real)cnt);
     }
     return bits;
 }
@@ -362,8 +362,8 @@ __global__ __launch_bounds__(256) void k_reconstruct_ho(const ReconHoArgs<real> 
         const real rho = (real)Ud[0], uu = (real)(Ud[1] / Ud[0]), vv = (real)(Ud[2] / Ud[0]);
         const real q2 = (real)0.5 * (uu * uu + vv * vv);
         const real pr = (a.gamma - 1) * ((real)Ud[3] - rho * q2);
-        const real cs = sqrt(a.gamma * pr / rho), H = ((real)Ud[3] + pr) / rho;
-        const real b1 = (a.gamma - 1) / (cs * cs), b2 = b1 * q2, ic = (real)1 / cs;
+        const real cs = fsqrt(fdiv(a.gamma * pr, rho)), H = fdiv((real)Ud[3] + pr, rho);
+        const real b1 = fdiv(a.gamma - 1, cs * cs), b2 = b1 * q2, ic = frcp(cs);
 #pragma unroll
         for (int f = 0; f < 3; ++f) {
             real nx, ny, len;
@@ -429,7 +429,7 @@ __global__ __launch_bounds__(256) void k_reconstruct_ho(const ReconHoArgs<real> 
             for (int q = 0; q < NQ; ++q) {
                 const real r0 = __shfl(out[f][q], l0, 64), r1 = __shfl(out[f][q], l0 + 1, 64);
                 const real r2 = __shfl(out[f][q], l0 + 2, 64), r3 = __shfl(out[f][q], l0 + 3, 64);
-                const real pr = (a.gamma - 1) * (r3 - (real)0.5 * (r1 * r1 + r2 * r2) / r0);
+                const real pr = euler_pressure(a.gamma, r0, r1, r2, r3);
                 bad |= !(r0 > 0) || !(pr > 0);
             }
         if (bad) {

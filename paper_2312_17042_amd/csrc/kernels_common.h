@@ -29,6 +29,33 @@ __device__ __forceinline__ float comp(const float4 &v, int c) { return c == 0 ? 
 __device__ __forceinline__ double comp(const double2 &v, int c) { return c == 0 ? v.x : v.y; }
 __device__ __forceinline__ int comp(const int4 &v, int c) { return c == 0 ? v.x : c == 1 ? v.y : c == 2 ? v.z : v.w; }
 
+// Division, reciprocal and square root in the working precision.  FP64 keeps
+// the IEEE operations.  FP32 takes the hardware reciprocal and square root
+// (about 1 ulp each): a few ulps beside the correctly rounded sequences, at a
+// fraction of their instruction count, which bounds the FP32 kernels.
+__device__ __forceinline__ float fdiv(float x, float y) { return x * __builtin_amdgcn_rcpf(y); }
+__device__ __forceinline__ double fdiv(double x, double y) { return x / y; }
+__device__ __forceinline__ float frcp(float y) { return __builtin_amdgcn_rcpf(y); }
+__device__ __forceinline__ double frcp(double y) { return 1.0 / y; }
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double fsqrt(double x) { return sqrt(x); }
+
+// Pressure of a conserved Euler state (rho, m_x, m_y, E).  The positivity
+// fallback of the reconstructions and the admissibility test of the fluxes
+// evaluate it with this one sequence of roundings (contraction into fused
+// operations is off here), so a face state that the fallback accepts is
+// accepted by the flux: two formulas could disagree on a state whose
+// pressure is within rounding of zero, which FP32 meets in strong shocks.
+template <typename real>
+__device__ __forceinline__ real euler_pressure(real g, real r, real mx, real my, real E) {
+#pragma clang fp contract(off)
+    const real q = (real)0.5 * (mx * mx + my * my);
+    real ke;
+    if constexpr (std::is_same<real, float>::value) ke = q * __builtin_amdgcn_rcpf(r);
+    else ke = q / r;
+    return (g - 1) * (E - ke);
+}
+
 // n consecutive reals from/to an aligned address with the widest vector the
 // row size allows (16 bytes, else 8 bytes)
 template <typename real, int n>
@@ -178,11 +205,17 @@ __device__ __forceinline__ int teno_bits(const real si[4], int adm, int st, real
                 if (!(chi < ct)) bits |= 1 << s;
             }
     } else {
-        float e[4];
+        // chi_s < C_T is decided as num_s < C_T sum_t num_t (sum > 0), with
+        // one reciprocal per stencil and no division
+        float e[4], re[4];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) e[s] = si[s] + eps;
+        for (int s = 0; s < 4; ++s) {
+            e[s] = si[s] + eps;
+            re[s] = frcp(e[s]);
+        }
         if (SCHEME == CTENO_SCHEME_CTENO) {
-            // chi_s = 1 / sum_t (lambda_t / lambda_s) (e_s / e_t)^6
+            // chi_s = 1 / den_s, den_s = sum_t (lambda_t / lambda_s) (e_s / e_t)^6
+            const float ilratio = frcp(lratio);
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
                 if (!((adm >> s) & 1)) continue;
@@ -191,48 +224,52 @@ __device__ __forceinline__ int teno_bits(const real si[4], int adm, int st, real
                 for (int t = 0; t < 4; ++t) {
                     if (!((adm >> t) & 1)) continue;
                     float lr = 1.0f;
-                    if (GFORM == CTENO_GAMMA_LAMBDA && s != t) lr = (t == 0) ? lratio : (s == 0 ? 1.0f / lratio : 1.0f);
-                    den += lr * pow6(e[s] / e[t]);
+                    if (GFORM == CTENO_GAMMA_LAMBDA && s != t) lr = (t == 0) ? lratio : (s == 0 ? ilratio : 1.0f);
+                    den += lr * pow6(e[s] * re[t]);
                 }
-                const float chi = 1.0f / den;
-                if (!(chi < ct)) bits |= 1 << s;
+                if (!(ct * den > 1.0f)) bits |= 1 << s;
             }
         } else {
-            float tsum = 0.0f, emin = e[0];
+            float tsum = 0.0f, emin = e[0], remin = re[0];
 #pragma unroll
             for (int s = 1; s < 4; ++s)
-                if ((adm >> s) & 1) { tsum += fabsf(e[s] - e[0]); emin = fminf(emin, e[s]); }
+                if ((adm >> s) & 1) {
+                    tsum += fabsf(e[s] - e[0]);
+                    emin = fminf(emin, e[s]);
+                    remin = fmaxf(remin, re[s]);
+                }
+            const float mean = tsum * (st == 2 ? 1.0f : st == 3 ? 0.5f : 1.0f / 3.0f);
             float num[4], sum = 0.0f;
             if constexpr (GFORM == CTENO_GAMMA_SCALED) {
                 // gamma_s = 1 + X^6 w_s^6 with X = mean |SI_s - SI_1| / emin
-                const float X = (tsum / (float)(st - 1)) / emin;
+                const float X = mean * remin;
                 if (X <= 1e5f) {
 #pragma unroll
-                    for (int s = 0; s < 4; ++s) num[s] = 1.0f + pow6(X * (emin / e[s]));
+                    for (int s = 0; s < 4; ++s) num[s] = 1.0f + pow6(X * (emin * re[s]));
                 } else {
-                    const float iX6 = pow6(1.0f / X);
+                    const float iX6 = pow6(frcp(X));
 #pragma unroll
-                    for (int s = 0; s < 4; ++s) num[s] = iX6 + pow6(emin / e[s]);
+                    for (int s = 0; s < 4; ++s) num[s] = iX6 + pow6(emin * re[s]);
                 }
             } else {
-                const float tau = pow6(tsum / (float)(st - 1));
-                const float G = tau / emin;        // gamma_s = 1 + G w_s, w_s = emin / e_s in (0, 1]
+                const float tau = pow6(mean);
+                const float G = tau * remin;       // gamma_s = 1 + G w_s, w_s = emin / e_s in (0, 1]
                 if (G <= 1e30f) {
 #pragma unroll
-                    for (int s = 0; s < 4; ++s) num[s] = 1.0f + G * (emin / e[s]);
+                    for (int s = 0; s < 4; ++s) num[s] = 1.0f + G * (emin * re[s]);
                 } else {
-                    const float iG = 1.0f / G;
+                    const float iG = frcp(G);
 #pragma unroll
-                    for (int s = 0; s < 4; ++s) num[s] = iG + emin / e[s];
+                    for (int s = 0; s < 4; ++s) num[s] = iG + emin * re[s];
                 }
             }
 #pragma unroll
             for (int s = 0; s < 4; ++s) if ((adm >> s) & 1) sum += num[s];
+            const float lim = ct * sum;
 #pragma unroll
             for (int s = 0; s < 4; ++s)
                 if ((adm >> s) & 1) {
-                    const float chi = num[s] / sum;
-                    if (!(chi < ct)) bits |= 1 << s;
+                    if (!(num[s] < lim)) bits |= 1 << s;
                 }
         }
     }
@@ -257,20 +294,24 @@ __device__ __forceinline__ void cweno_weights(const real si[4], int adm, real la
 #pragma unroll
         for (int s = 0; s < 4; ++s) w[s] = g[s] / sum;
     } else {
-        float e[4];
+        float e[4], re[4];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) e[s] = si[s] + eps;
+        for (int s = 0; s < 4; ++s) {
+            e[s] = si[s] + eps;
+            re[s] = frcp(e[s]);
+        }
+        const float ilratio = frcp(lratio);
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             float den = 0.0f;
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 if (!((adm >> t) & 1)) continue;
-                const float lr = (s == t) ? 1.0f : (t == 0 ? lratio : (s == 0 ? 1.0f / lratio : 1.0f));
-                const float q = e[s] / e[t], q2 = q * q;
+                const float lr = (s == t) ? 1.0f : (t == 0 ? lratio : (s == 0 ? ilratio : 1.0f));
+                const float q = e[s] * re[t], q2 = q * q;
                 den += lr * (q2 * q2);
             }
-            w[s] = ((adm >> s) & 1) ? 1.0f / den : 0.0f;
+            w[s] = ((adm >> s) & 1) ? frcp(den) : 0.0f;
         }
     }
 }
@@ -303,7 +344,11 @@ __device__ __forceinline__ void finish_fields(const ReconArgs<real, K> a, real (
 #pragma unroll
         for (int v = 0; v < NV; ++v) bits[v] = 1;
     } else {
-        // smoothness indicators: SI_1 = a1^T G a1, SI_s over the degree-1 block of G
+        // smoothness indicators: SI_1 = a1^T G a1, SI_s over the degree-1 block
+        // of G.  FP64 sums the full quadratic form; FP32 its upper triangle,
+        // whose off-diagonal entries the FP32 table holds doubled
+        // (fill_recon_constants), at about half the products.
+        constexpr bool SYM = std::is_same<real, float>::value;
         real si[NV][4];
 #pragma unroll
         for (int v = 0; v < NV; ++v) si[v][0] = 0;
@@ -313,7 +358,7 @@ __device__ __forceinline__ void finish_fields(const ReconArgs<real, K> a, real (
 #pragma unroll
             for (int v = 0; v < NV; ++v) rowp[v] = 0;
 #pragma unroll
-            for (int q = 0; q < K; ++q) {
+            for (int q = SYM ? p : 0; q < K; ++q) {
                 const real g = a.gram[p][q];
 #pragma unroll
                 for (int v = 0; v < NV; ++v) rowp[v] += g * c1[q][v];
@@ -327,7 +372,8 @@ __device__ __forceinline__ void finish_fields(const ReconArgs<real, K> a, real (
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
                 const real x0 = cd[q][0][v], x1 = cd[q][1][v];
-                si[v][q + 1] = x0 * (g00 * x0 + g01 * x1) + x1 * (g10 * x0 + g11 * x1);
+                if constexpr (SYM) si[v][q + 1] = x0 * (g00 * x0 + g01 * x1) + g11 * (x1 * x1);
+                else si[v][q + 1] = x0 * (g00 * x0 + g01 * x1) + x1 * (g10 * x0 + g11 * x1);
             }
         if constexpr (SCHEME == CTENO_SCHEME_CWENO) {
             // every admissible stencil contributes; final coefficients, in
@@ -366,8 +412,8 @@ __device__ __forceinline__ void finish_fields(const ReconArgs<real, K> a, real (
 #pragma unroll
             for (int q = 0; q < 3; ++q)
                 if ((bits[v] >> (q + 1)) & 1) { s0 += cd[q][0][v]; s1 += cd[q][1][v]; ++cnt; }
-            c1[0][v] = s0 / (real)cnt;
-            c1[1][v] = s1 / (real)cnt;
+            c1[0][v] = cnt == 1 ? s0 : cnt == 2 ? (real)0.5 * s0 : fdiv(s0, (real)3);
+            c1[1][v] = cnt == 1 ? s1 : cnt == 2 ? (real)0.5 * s1 : fdiv(s1, (real)3);
 #pragma unroll
             for (int k = 2; k < K; ++k) c1[k][v] = 0;
         }
@@ -522,7 +568,7 @@ __device__ __forceinline__ void recon_body(const ReconArgs<real, (R + 1) * (R + 
                     if ((fl >> q) & 1) sm -= lams * ad[q][k][v];
             }
             // TENO keeps the central stencil's own polynomial
-            if (SCHEME != CTENO_SCHEME_TENO) ao[k][v] = st > 1 ? sm / a.lam1 : sm;
+            if (SCHEME != CTENO_SCHEME_TENO) ao[k][v] = st > 1 ? fdiv(sm, a.lam1) : sm;
         }
     constexpr int NB = VARS ? 3 * NV : NV;       // selection bytes per cell
     uint8_t dbyte[NB];
@@ -558,8 +604,8 @@ __device__ __forceinline__ void recon_body(const ReconArgs<real, (R + 1) * (R + 
         const real rho = (real)U0[0], uu = (real)(U0[1] / U0[0]), vv = (real)(U0[2] / U0[0]);
         const real q2 = (real)0.5 * (uu * uu + vv * vv);
         const real pr = (a.gamma - 1) * ((real)U0[3] - rho * q2);
-        const real cs = sqrt(a.gamma * pr / rho), H = ((real)U0[3] + pr) / rho;
-        const real b1 = (a.gamma - 1) / (cs * cs), b2 = b1 * q2, ic = (real)1 / cs;
+        const real cs = fsqrt(fdiv(a.gamma * pr, rho)), H = fdiv((real)U0[3] + pr, rho);
+        const real b1 = fdiv(a.gamma - 1, cs * cs), b2 = b1 * q2, ic = frcp(cs);
 #pragma unroll
         for (int f = 0; f < 3; ++f) {
             real nx, ny, len;
@@ -635,8 +681,7 @@ __device__ __forceinline__ void recon_body(const ReconArgs<real, (R + 1) * (R + 
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
                 const real rho = out[f][q][0];
-                const real pr = (a.gamma - 1) * (out[f][q][3] - (real)0.5 * (out[f][q][1] * out[f][q][1] +
-                                                                             out[f][q][2] * out[f][q][2]) / rho);
+                const real pr = euler_pressure(a.gamma, rho, out[f][q][1], out[f][q][2], out[f][q][3]);
                 bad |= !(rho > 0) || !(pr > 0);
             }
         if (bad) {
@@ -663,8 +708,12 @@ __device__ __forceinline__ void recon_body(const ReconArgs<real, (R + 1) * (R + 
 template <typename real, int K>
 inline void fill_recon_constants(const DeviceMesh &m, ReconArgs<real, K> &a) {
     a.N = m.N;
+    // FP64: the Gram matrix; FP32: its upper triangle with the off-diagonal
+    // entries doubled (finish_fields sums the quadratic form over it), the
+    // lower triangle as is
+    constexpr bool sym = std::is_same<real, float>::value;
     for (int p = 0; p < K; ++p)
-        for (int q = 0; q < K; ++q) a.gram[p][q] = (real)m.tab.gram[p][q];
+        for (int q = 0; q < K; ++q) a.gram[p][q] = (real)((sym && q > p ? 2.0 : 1.0) * m.tab.gram[p][q]);
     for (int f = 0; f < 3; ++f)
         for (int q = 0; q < 2; ++q)
             for (int k = 0; k < K; ++k) a.basis[f][q][k] = (real)m.tab.basis[f][q][k];
@@ -706,43 +755,43 @@ struct HoDims {
 template <typename real>
 __device__ __forceinline__ bool hllc(real g, const real *UL, const real *UR, real nx, real ny, real *F) {
     const real rl = UL[0], rr = UR[0];
-    const real ul = (UL[1] * nx + UL[2] * ny) / rl, wl = (-UL[1] * ny + UL[2] * nx) / rl;
-    const real ur = (UR[1] * nx + UR[2] * ny) / rr, wr = (-UR[1] * ny + UR[2] * nx) / rr;
+    const real ul = fdiv(UL[1] * nx + UL[2] * ny, rl), wl = fdiv(-UL[1] * ny + UL[2] * nx, rl);
+    const real ur = fdiv(UR[1] * nx + UR[2] * ny, rr), wr = fdiv(-UR[1] * ny + UR[2] * nx, rr);
     const real El = UL[3], Er = UR[3];
     const real h = (real)0.5;
-    const real pl = (g - 1) * (El - h * rl * (ul * ul + wl * wl));
-    const real pr = (g - 1) * (Er - h * rr * (ur * ur + wr * wr));
+    const real pl = euler_pressure(g, rl, UL[1], UL[2], El);
+    const real pr = euler_pressure(g, rr, UR[1], UR[2], Er);
     const bool ok = rl > 0 && rr > 0 && pl > 0 && pr > 0;
-    const real cl = sqrt(g * pl / rl), cr = sqrt(g * pr / rr);
-    const real Hl = (El + pl) / rl, Hr = (Er + pr) / rr;
-    const real D = sqrt(rr / rl);
-    const real ut = (ul + ur * D) / (1 + D);
-    const real wt = (wl + wr * D) / (1 + D);
-    const real Ht = (Hl + Hr * D) / (1 + D);
-    const real ct = sqrt((g - 1) * (Ht - h * (ut * ut + wt * wt)));
+    const real cl = fsqrt(fdiv(g * pl, rl)), cr = fsqrt(fdiv(g * pr, rr));
+    const real Hl = fdiv(El + pl, rl), Hr = fdiv(Er + pr, rr);
+    const real D = fsqrt(fdiv(rr, rl));
+    const real ut = fdiv(ul + ur * D, 1 + D);
+    const real wt = fdiv(wl + wr * D, 1 + D);
+    const real Ht = fdiv(Hl + Hr * D, 1 + D);
+    const real ct = fsqrt((g - 1) * (Ht - h * (ut * ut + wt * wt)));
     const real SL = fmin(ul - cl, ut - ct);
     const real SR = fmax(ur + cr, ut + ct);
-    const real SM = (rr * ur * (SR - ur) - rl * ul * (SL - ul) + pl - pr) / (rr * (SR - ur) - rl * (SL - ul));
+    const real SM = fdiv(rr * ur * (SR - ur) - rl * ul * (SL - ul) + pl - pr, rr * (SR - ur) - rl * (SL - ul));
     const real ps = rl * (ul - SL) * (ul - SM) + pl;
     real Fn[4];
     if (SL > 0) {
         Fn[0] = rl * ul; Fn[1] = rl * ul * ul + pl; Fn[2] = rl * ul * wl; Fn[3] = ul * (El + pl);
     } else if (0 < SM) {
         const real d = SL - SM;
-        const real Us0 = rl * (SL - ul) / d;
-        const real Us1 = ((SL - ul) * rl * ul + ps - pl) / d;
-        const real Us2 = (SL - ul) * rl * wl / d;
-        const real Us3 = ((SL - ul) * El - pl * ul + ps * SM) / d;
+        const real Us0 = fdiv(rl * (SL - ul), d);
+        const real Us1 = fdiv((SL - ul) * rl * ul + ps - pl, d);
+        const real Us2 = fdiv((SL - ul) * rl * wl, d);
+        const real Us3 = fdiv((SL - ul) * El - pl * ul + ps * SM, d);
         Fn[0] = rl * ul + SL * (Us0 - rl);
         Fn[1] = (rl * ul * ul + pl) + SL * (Us1 - rl * ul);
         Fn[2] = rl * ul * wl + SL * (Us2 - rl * wl);
         Fn[3] = ul * (El + pl) + SL * (Us3 - El);
     } else if (0 < SR) {
         const real d = SR - SM;
-        const real Us0 = rr * (SR - ur) / d;
-        const real Us1 = ((SR - ur) * rr * ur + ps - pr) / d;
-        const real Us2 = (SR - ur) * rr * wr / d;
-        const real Us3 = ((SR - ur) * Er - pr * ur + ps * SM) / d;
+        const real Us0 = fdiv(rr * (SR - ur), d);
+        const real Us1 = fdiv((SR - ur) * rr * ur + ps - pr, d);
+        const real Us2 = fdiv((SR - ur) * rr * wr, d);
+        const real Us3 = fdiv((SR - ur) * Er - pr * ur + ps * SM, d);
         Fn[0] = rr * ur + SR * (Us0 - rr);
         Fn[1] = (rr * ur * ur + pr) + SR * (Us1 - rr * ur);
         Fn[2] = rr * ur * wr + SR * (Us2 - rr * wr);
@@ -766,13 +815,13 @@ __device__ __forceinline__ bool hllc(real g, const real *UL, const real *UR, rea
 template <typename real>
 __device__ __forceinline__ bool wall_flux(real g, const real *UL, real nx, real ny, real *F) {
     const real r = UL[0];
-    const real u = (UL[1] * nx + UL[2] * ny) / r, w = (-UL[1] * ny + UL[2] * nx) / r;
+    const real u = fdiv(UL[1] * nx + UL[2] * ny, r), w = fdiv(-UL[1] * ny + UL[2] * nx, r);
     const real E = UL[3];
-    const real p = (g - 1) * (E - (real)0.5 * r * (u * u + w * w));
+    const real p = euler_pressure(g, r, UL[1], UL[2], E);
     const bool ok = r > 0 && p > 0;
-    const real c = sqrt(g * p / r);
-    const real H = (E + p) / r;
-    const real ct = sqrt((g - 1) * (H - (real)0.5 * w * w));
+    const real c = fsqrt(fdiv(g * p, r));
+    const real H = fdiv(E + p, r);
+    const real ct = fsqrt((g - 1) * (H - (real)0.5 * w * w));
     const real SL = fmin(u - c, -ct);
     const real ps = r * (u - SL) * u + p;
     F[0] = 0;
