@@ -6,8 +6,12 @@
 
 namespace cteno {
 
+// The FP64 march in conserved variables is held to two waves per SIMD (its
+// directional coefficients wait in LDS); the other instances take the
+// registers they need
 template <typename real, int R, int NV, int SCHEME, int GFORM, int DMODE, int VARS>
-__global__ __launch_bounds__(256) void k_reconstruct(const ReconArgs<real, (R + 1) * (R + 2) / 2 - 1> a) {
+__global__ __launch_bounds__(256, (std::is_same<real, double>::value && VARS == 0 && DMODE != 2) ? 2 : 1)
+void k_reconstruct(const ReconArgs<real, (R + 1) * (R + 2) / 2 - 1> a) {
     const int64_t i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= a.N) return;
     if (a.done && *a.done) return;

@@ -322,7 +322,7 @@ __global__ __launch_bounds__(256) void k_reconstruct_ho(const ReconHoArgs<real> 
     // because without the step the compiler's schedule needs a third more
     // registers (110 instead of 81 VGPRs at r = 4, 187 instead of 145 at r = 6)
     {
-        const real ls = lams * a.p1_ls;
+        const real ls = lams * a.p1_ls, il1 = frcp(a.p1_l1);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             real sm = ao[k];
@@ -331,7 +331,7 @@ __global__ __launch_bounds__(256) void k_reconstruct_ho(const ReconHoArgs<real> 
                 for (int q = 0; q < 3; ++q)
                     if ((fl >> q) & 1) sm -= ls * ad[q][k];
             }
-            ao[k] = st > 1 ? sm / a.p1_l1 : sm;
+            ao[k] = st > 1 ? sm * il1 : sm;
         }
     }
     const real *Bt = a.tab + K * K;

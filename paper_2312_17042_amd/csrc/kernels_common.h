@@ -30,9 +30,10 @@ __device__ __forceinline__ double comp(const double2 &v, int c) { return c == 0 
 __device__ __forceinline__ int comp(const int4 &v, int c) { return c == 0 ? v.x : c == 1 ? v.y : c == 2 ? v.z : v.w; }
 
 // Division, reciprocal and square root in the working precision.  FP64 keeps
-// the IEEE operations.  FP32 takes the hardware reciprocal and square root
-// (about 1 ulp each): a few ulps beside the correctly rounded sequences, at a
-// fraction of their instruction count, which bounds the FP32 kernels.
+// the IEEE operations (the fluxes multiply by an IEEE reciprocal where
+// several quotients share a denominator: one more rounding).  FP32 takes the
+// hardware reciprocal and square root (about 1 ulp each): a few ulps beside
+// the correctly rounded sequences, at a fraction of their instruction count.
 __device__ __forceinline__ float fdiv(float x, float y) { return x * __builtin_amdgcn_rcpf(y); }
 __device__ __forceinline__ double fdiv(double x, double y) { return x / y; }
 __device__ __forceinline__ float frcp(float y) { return __builtin_amdgcn_rcpf(y); }
@@ -333,8 +334,8 @@ struct ReconPtrs {
 // in place: c1[K][NV] holds the p_1 coefficients on entry and the final
 // polynomial's on exit, cd[3][2][NV] the degree-1 directional ones; forced
 // (DMODE 2) points at the fields' forced selection bytes
-template <typename real, int K, int NV, int SCHEME, int GFORM, int DMODE>
-__device__ __forceinline__ void finish_fields(const ReconArgs<real, K> a, real (&c1)[K][NV], const real (&cd)[3][2][NV],
+template <typename real, int K, int NV, int SCHEME, int GFORM, int DMODE, typename CD>
+__device__ __forceinline__ void finish_fields(const ReconArgs<real, K> a, real (&c1)[K][NV], const CD cd,
                                               int fl, int adm, int st, real lams, real lratio, const uint8_t *forced,
                                               int (&bits)[NV]) {
     if (DMODE == 2 && SCHEME != CTENO_SCHEME_CWENO) {
@@ -371,7 +372,7 @@ __device__ __forceinline__ void finish_fields(const ReconArgs<real, K> a, real (
         for (int q = 0; q < 3; ++q)
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                const real x0 = cd[q][0][v], x1 = cd[q][1][v];
+                const real x0 = cd(q, 0, v), x1 = cd(q, 1, v);
                 if constexpr (SYM) si[v][q + 1] = x0 * (g00 * x0 + g01 * x1) + g11 * (x1 * x1);
                 else si[v][q + 1] = x0 * (g00 * x0 + g01 * x1) + x1 * (g10 * x0 + g11 * x1);
             }
@@ -389,7 +390,7 @@ __device__ __forceinline__ void finish_fields(const ReconArgs<real, K> a, real (
                     if (k < 2) {
 #pragma unroll
                         for (int q = 0; q < 3; ++q)
-                            if ((fl >> q) & 1) x += w[q + 1] * cd[q][k][v];
+                            if ((fl >> q) & 1) x += w[q + 1] * cd(q, k, v);
                     }
                     c1[k][v] = x;
                 }
@@ -411,13 +412,36 @@ __device__ __forceinline__ void finish_fields(const ReconArgs<real, K> a, real (
             int cnt = 0;
 #pragma unroll
             for (int q = 0; q < 3; ++q)
-                if ((bits[v] >> (q + 1)) & 1) { s0 += cd[q][0][v]; s1 += cd[q][1][v]; ++cnt; }
+                if ((bits[v] >> (q + 1)) & 1) { s0 += cd(q, 0, v); s1 += cd(q, 1, v); ++cnt; }
             c1[0][v] = cnt == 1 ? s0 : cnt == 2 ? (real)0.5 * s0 : fdiv(s0, (real)3);
             c1[1][v] = cnt == 1 ? s1 : cnt == 2 ? (real)0.5 * s1 : fdiv(s1, (real)3);
 #pragma unroll
             for (int k = 2; k < K; ++k) c1[k][v] = 0;
         }
     }
+}
+
+// the degree-1 directional coefficients cd(q, c, v) of a cell: in registers,
+// or parked in LDS (FP64 reconstruction, 256 lanes per block)
+template <typename real, int NV>
+struct CdRegs {
+    const real (&a)[3][2][NV];
+    __device__ __forceinline__ real operator()(int q, int c, int v) const { return a[q][c][v]; }
+};
+template <int NV>
+struct CdLds {
+    const double *p;
+    __device__ __forceinline__ double operator()(int q, int c, int v) const {
+        return p[((q * 2 + c) * NV + v) * 256 + threadIdx.x];
+    }
+};
+
+// block-shared parking space of the FP64 reconstruction's directional
+// coefficients, [3][2][NV] x 256 lanes
+template <int NV>
+__device__ __forceinline__ double *ad_lds() {
+    __shared__ double lad[3 * 2 * NV * 256];
+    return lad;
 }
 
 // Reconstruction of cell i: its face Gauss-point values in out (and its
@@ -444,6 +468,11 @@ __device__ __forceinline__ void recon_body(const ReconArgs<real, (R + 1) * (R + 
     for (int v = 0; v < NV; ++v) U0[v] = ptr.U[i * NV + v];
 
     real ao[K][NV], ad[3][2][NV];
+    // FP64: the directional coefficients wait in LDS until the epilogue
+    // (registers for two waves per SIMD); 256 lanes per block
+    constexpr bool AD_LDS = std::is_same<real, double>::value;
+    double *lad = nullptr;
+    if constexpr (AD_LDS) lad = ad_lds<NV>();
 #pragma unroll
     for (int k = 0; k < K; ++k)
 #pragma unroll
@@ -465,87 +494,172 @@ __device__ __forceinline__ void recon_body(const ReconArgs<real, (R + 1) * (R + 
     int4 slv[SP / 4];
 #pragma unroll
     for (int g = 0; g < SP / 4; ++g) slv[g] = Sv[g * 64];
-    // Rolled loop over the three directional groups with a two-deep load
-    // pipeline: the GV vectors that follow group s (group s + 1, or the head
-    // of the remaining slots) are requested before group s is computed, so a
-    // wave keeps two groups of stream loads in flight.  With no remaining
-    // slots (S = 12) the last iteration requests its own group again.
     constexpr int NVEC = E / VW;
-    static_assert(S == 12 || 4 * GV <= NVEC, "stream shorter than four groups");
-    V cur[GV];
-#pragma unroll
-    for (int g = 0; g < GV; ++g) cur[g] = Pv[g * 64];
+    if constexpr (AD_LDS) {
+        // FP64: half a group of stream vectors in flight per wave, loaded at
+        // the top of its part, and the directional coefficients parked in
+        // LDS, so that two waves fit on a SIMD
 #pragma unroll 1
-    for (int s = 0; s < 3; ++s) {
-        int4 sl = slv[0];
+        for (int s = 0; s < 3; ++s) {
+            int4 sl = slv[0];
 #pragma unroll
-        for (int s2 = 1; s2 < 3; ++s2)
-            if (s2 == s) sl = slv[s2];
-        const int gn = (S > 12 || s < 2 ? s + 1 : s) * GV;
-        V nxt[GV];
+            for (int s2 = 1; s2 < 3; ++s2)
+                if (s2 == s) sl = slv[s2];
+            real adt[2][NV];
 #pragma unroll
-        for (int g = 0; g < GV; ++g) nxt[g] = Pv[(gn + g) * 64];
-        real adt[2][NV];
+            for (int c = 0; c < 2; ++c)
 #pragma unroll
-        for (int c = 0; c < 2; ++c)
+                for (int v = 0; v < NV; ++v) adt[c][v] = 0;
+            // the group in two halves of two slots (whole vectors)
+            constexpr int PARTS = (GE / 2) % VW == 0 ? 2 : 1;
+            constexpr int PVEC = GV / PARTS, PT = 4 / PARTS;
 #pragma unroll
-            for (int v = 0; v < NV; ++v) adt[c][v] = 0;
+            for (int h = 0; h < PARTS; ++h) {
+                V cur[PVEC];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int64_t m = comp(sl, t);
-            real d[NV];
-            gather_diff<NV>(ptr.U, m, U0, d);
+                for (int g = 0; g < PVEC; ++g) cur[g] = Pv[(s * GV + h * PVEC + g) * 64];
 #pragma unroll
-            for (int q = 0; q < K + 2; ++q) {
-                const int el = t * (K + 2) + q;
-                const real p = comp(cur[el / VW], el % VW);
-                if (q < K) {
+                for (int t = h * PT; t < (h + 1) * PT; ++t) {
+                    const int64_t m = comp(sl, t);
+                    real d[NV];
+                    gather_diff<NV>(ptr.U, m, U0, d);
+#pragma unroll
+                    for (int q = 0; q < K + 2; ++q) {
+                        const int el = t * (K + 2) + q - h * PVEC * VW;
+                        const real p = comp(cur[el / VW], el % VW);
+                        if (q < K) {
+#pragma unroll
+                            for (int v = 0; v < NV; ++v) ao[q][v] += p * d[v];
+                        } else {
+#pragma unroll
+                            for (int v = 0; v < NV; ++v) adt[q - K][v] += p * d[v];
+                        }
+                    }
+                }
+                if (PARTS > 1) __builtin_amdgcn_sched_barrier(0);
+            }
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                for (int v = 0; v < NV; ++v) lad[((s * 2 + c) * NV + v) * 256 + threadIdx.x] = adt[c][v];
+            __builtin_amdgcn_sched_barrier(0);   // keep the groups apart: bounded live registers
+        }
+        if constexpr (S > 12) {
+            // remaining slots (K central entries each), from stream vector 3 GV
+            // on, in parts of at most three slots
+            constexpr int T0 = 12 * (K + 2);
+            constexpr int NT = S - 12;
+#pragma unroll
+            for (int t0 = 0; t0 < NT; t0 += 3) {
+                constexpr int PV = (3 * K + 2 * VW - 2) / VW;     // vectors that three slots can touch
+                const int v0 = (T0 + t0 * K) / VW;
+                V buf[PV];
+#pragma unroll
+                for (int g = 0; g < PV; ++g)
+                    if (v0 + g < NVEC) buf[g] = Pv[(v0 + g) * 64];
+#pragma unroll
+                for (int t = t0; t < t0 + 3 && t < NT; ++t) {
+                    const int j = 12 + t;
+                    const int64_t m = comp(slv[j / 4], j % 4);
+                    real d[NV];
+                    gather_diff<NV>(ptr.U, m, U0, d);
+#pragma unroll
+                    for (int q = 0; q < K; ++q) {
+                        const int e = T0 + t * K + q;
+                        const real p = comp(buf[e / VW - v0], e % VW);
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) ao[q][v] += p * d[v];
+                    }
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+    } else {
+        // Rolled loop over the three directional groups with a two-deep load
+        // pipeline: the GV vectors that follow group s (group s + 1, or the head
+        // of the remaining slots) are requested before group s is computed, so a
+        // wave keeps two groups of stream loads in flight.  With no remaining
+        // slots (S = 12) the last iteration requests its own group again.
+        static_assert(S == 12 || 4 * GV <= NVEC, "stream shorter than four groups");
+        V cur[GV];
+#pragma unroll
+        for (int g = 0; g < GV; ++g) cur[g] = Pv[g * 64];
+#pragma unroll 1
+        for (int s = 0; s < 3; ++s) {
+            int4 sl = slv[0];
+#pragma unroll
+            for (int s2 = 1; s2 < 3; ++s2)
+                if (s2 == s) sl = slv[s2];
+            const int gn = (S > 12 || s < 2 ? s + 1 : s) * GV;
+            V nxt[GV];
+#pragma unroll
+            for (int g = 0; g < GV; ++g) nxt[g] = Pv[(gn + g) * 64];
+            real adt[2][NV];
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                for (int v = 0; v < NV; ++v) adt[c][v] = 0;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int64_t m = comp(sl, t);
+                real d[NV];
+                gather_diff<NV>(ptr.U, m, U0, d);
+#pragma unroll
+                for (int q = 0; q < K + 2; ++q) {
+                    const int el = t * (K + 2) + q;
+                    const real p = comp(cur[el / VW], el % VW);
+                    if (q < K) {
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) ao[q][v] += p * d[v];
+                    } else {
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) adt[q - K][v] += p * d[v];
+                    }
+                }
+            }
+#pragma unroll
+            for (int s2 = 0; s2 < 3; ++s2)
+                if (s2 == s)
+#pragma unroll
+                    for (int c = 0; c < 2; ++c)
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) ad[s2][c][v] = adt[c][v];
+#pragma unroll
+            for (int g = 0; g < GV; ++g) cur[g] = nxt[g];
+            __builtin_amdgcn_sched_barrier(0);   // keep the groups apart: bounded live registers
+        }
+        if constexpr (S > 12) {
+            // remaining slots (K central entries each): cur holds stream vectors
+            // [3 GV, 4 GV); the rest of the stream follows
+            constexpr int T0 = 12 * (K + 2);
+            constexpr int NT = S - 12;
+            constexpr int RV = NVEC - 4 * GV;
+            V rest[RV > 0 ? RV : 1];
+#pragma unroll
+            for (int g = 0; g < RV; ++g) rest[g] = Pv[(4 * GV + g) * 64];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const int j = 12 + t;
+                const int64_t m = comp(slv[j / 4], j % 4);
+                real d[NV];
+                gather_diff<NV>(ptr.U, m, U0, d);
+#pragma unroll
+                for (int q = 0; q < K; ++q) {
+                    const int e = T0 + t * K + q;
+                    const int gv = e / VW - 3 * GV;     // compile-time after unrolling
+                    const real p = gv < GV ? comp(cur[gv < GV ? gv : 0], e % VW)
+                                           : comp(rest[gv < GV ? 0 : gv - GV], e % VW);
 #pragma unroll
                     for (int v = 0; v < NV; ++v) ao[q][v] += p * d[v];
-                } else {
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) adt[q - K][v] += p * d[v];
                 }
             }
         }
-#pragma unroll
-        for (int s2 = 0; s2 < 3; ++s2)
-            if (s2 == s)
-#pragma unroll
-                for (int c = 0; c < 2; ++c)
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) ad[s2][c][v] = adt[c][v];
-#pragma unroll
-        for (int g = 0; g < GV; ++g) cur[g] = nxt[g];
-        __builtin_amdgcn_sched_barrier(0);   // keep the groups apart: bounded live registers
     }
-    if constexpr (S > 12) {
-        // remaining slots (K central entries each): cur holds stream vectors
-        // [3 GV, 4 GV); the rest of the stream follows
-        constexpr int T0 = 12 * (K + 2);
-        constexpr int NT = S - 12;
-        constexpr int RV = NVEC - 4 * GV;
-        V rest[RV > 0 ? RV : 1];
-#pragma unroll
-        for (int g = 0; g < RV; ++g) rest[g] = Pv[(4 * GV + g) * 64];
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            const int j = 12 + t;
-            const int64_t m = comp(slv[j / 4], j % 4);
-            real d[NV];
-            gather_diff<NV>(ptr.U, m, U0, d);
-#pragma unroll
-            for (int q = 0; q < K; ++q) {
-                const int e = T0 + t * K + q;
-                const int gv = e / VW - 3 * GV;     // compile-time after unrolling
-                const real p = gv < GV ? comp(cur[gv < GV ? gv : 0], e % VW)
-                                       : comp(rest[gv < GV ? 0 : gv - GV], e % VW);
-#pragma unroll
-                for (int v = 0; v < NV; ++v) ao[q][v] += p * d[v];
-            }
-        }
-    }
-
+    // the directional coefficients, wherever they wait
+    auto adv = [&](int q, int c, int v) -> real {
+        if constexpr (AD_LDS) return lad[((q * 2 + c) * NV + v) * 256 + threadIdx.x];
+        else return ad[q][c][v];
+    };
     const int fl = ptr.flags[i] & 7;
     const int adm = 1 | (fl << 1);
     const int st = 1 + __popc(fl);
@@ -556,7 +670,9 @@ __device__ __forceinline__ void recon_body(const ReconArgs<real, (R + 1) * (R + 
     // The epilogue works on all variables at once, phase by phase, so each
     // scheme constant (Gram matrix, face basis values) is used once and
     // dies, instead of staying live across a per-variable loop.
-    // p_1 = (p_opt - sum_s lambda_s p_s) / lambda_1, in place of a_opt
+    // p_1 = (p_opt - sum_s lambda_s p_s) / lambda_1, in place of a_opt, with
+    // one reciprocal of lambda_1
+    const real ilam1 = frcp(a.lam1);
 #pragma unroll
     for (int k = 0; k < K; ++k)
 #pragma unroll
@@ -565,17 +681,21 @@ __device__ __forceinline__ void recon_body(const ReconArgs<real, (R + 1) * (R + 
             if (k < 2 && st > 1) {
 #pragma unroll
                 for (int q = 0; q < 3; ++q)
-                    if ((fl >> q) & 1) sm -= lams * ad[q][k][v];
+                    if ((fl >> q) & 1) sm -= lams * adv(q, k, v);
             }
             // TENO keeps the central stencil's own polynomial
-            if (SCHEME != CTENO_SCHEME_TENO) ao[k][v] = st > 1 ? fdiv(sm, a.lam1) : sm;
+            if (SCHEME != CTENO_SCHEME_TENO) ao[k][v] = st > 1 ? sm * ilam1 : sm;
         }
     constexpr int NB = VARS ? 3 * NV : NV;       // selection bytes per cell
     uint8_t dbyte[NB];
     if constexpr (VARS == 0) {
         int bits[NV];
-        finish_fields<real, K, NV, SCHEME, GFORM, DMODE>(a, ao, ad, fl, adm, st, lams, lratio, ptr.delta + i * NV,
-                                                         bits);
+        if constexpr (AD_LDS)
+            finish_fields<real, K, NV, SCHEME, GFORM, DMODE>(a, ao, CdLds<NV>{lad}, fl, adm, st, lams, lratio,
+                                                             ptr.delta + i * NV, bits);
+        else
+            finish_fields<real, K, NV, SCHEME, GFORM, DMODE>(a, ao, CdRegs<real, NV>{ad}, fl, adm, st, lams, lratio,
+                                                             ptr.delta + i * NV, bits);
 #pragma unroll
         for (int v = 0; v < NV; ++v) dbyte[v] = (uint8_t)bits[v];
         // face Gauss-point values
@@ -640,11 +760,11 @@ __device__ __forceinline__ void recon_body(const ReconArgs<real, (R + 1) * (R + 
                     for (int j = 0; j < 4; ++j) {
                         real x = 0;
 #pragma unroll
-                        for (int v = 0; v < 4; ++v) x += L[j][v] * ad[s2][k][v];
+                        for (int v = 0; v < 4; ++v) x += L[j][v] * adv(s2, k, v);
                         cd[s2][k][j] = x;
                     }
             int bits[4];
-            finish_fields<real, K, 4, SCHEME, GFORM, DMODE>(a, c1, cd, fl, adm, st, lams, lratio,
+            finish_fields<real, K, 4, SCHEME, GFORM, DMODE>(a, c1, CdRegs<real, 4>{cd}, fl, adm, st, lams, lratio,
                                                             ptr.delta + (i * 3 + f) * 4, bits);
 #pragma unroll
             for (int j = 0; j < 4; ++j) dbyte[f * 4 + j] = (uint8_t)bits[j];
@@ -754,20 +874,23 @@ struct HoDims {
 // (u normal, w tangential velocity); F returned in the global frame.
 template <typename real>
 __device__ __forceinline__ bool hllc(real g, const real *UL, const real *UR, real nx, real ny, real *F) {
+    // one reciprocal per denominator, shared by the quotients over it
     const real rl = UL[0], rr = UR[0];
-    const real ul = fdiv(UL[1] * nx + UL[2] * ny, rl), wl = fdiv(-UL[1] * ny + UL[2] * nx, rl);
-    const real ur = fdiv(UR[1] * nx + UR[2] * ny, rr), wr = fdiv(-UR[1] * ny + UR[2] * nx, rr);
+    const real irl = frcp(rl), irr = frcp(rr);
+    const real ul = (UL[1] * nx + UL[2] * ny) * irl, wl = (-UL[1] * ny + UL[2] * nx) * irl;
+    const real ur = (UR[1] * nx + UR[2] * ny) * irr, wr = (-UR[1] * ny + UR[2] * nx) * irr;
     const real El = UL[3], Er = UR[3];
     const real h = (real)0.5;
     const real pl = euler_pressure(g, rl, UL[1], UL[2], El);
     const real pr = euler_pressure(g, rr, UR[1], UR[2], Er);
     const bool ok = rl > 0 && rr > 0 && pl > 0 && pr > 0;
-    const real cl = fsqrt(fdiv(g * pl, rl)), cr = fsqrt(fdiv(g * pr, rr));
-    const real Hl = fdiv(El + pl, rl), Hr = fdiv(Er + pr, rr);
-    const real D = fsqrt(fdiv(rr, rl));
-    const real ut = fdiv(ul + ur * D, 1 + D);
-    const real wt = fdiv(wl + wr * D, 1 + D);
-    const real Ht = fdiv(Hl + Hr * D, 1 + D);
+    const real cl = fsqrt((g * pl) * irl), cr = fsqrt((g * pr) * irr);
+    const real Hl = (El + pl) * irl, Hr = (Er + pr) * irr;
+    const real D = fsqrt(rr * irl);
+    const real iD = frcp(1 + D);
+    const real ut = (ul + ur * D) * iD;
+    const real wt = (wl + wr * D) * iD;
+    const real Ht = (Hl + Hr * D) * iD;
     const real ct = fsqrt((g - 1) * (Ht - h * (ut * ut + wt * wt)));
     const real SL = fmin(ul - cl, ut - ct);
     const real SR = fmax(ur + cr, ut + ct);
@@ -777,21 +900,21 @@ __device__ __forceinline__ bool hllc(real g, const real *UL, const real *UR, rea
     if (SL > 0) {
         Fn[0] = rl * ul; Fn[1] = rl * ul * ul + pl; Fn[2] = rl * ul * wl; Fn[3] = ul * (El + pl);
     } else if (0 < SM) {
-        const real d = SL - SM;
-        const real Us0 = fdiv(rl * (SL - ul), d);
-        const real Us1 = fdiv((SL - ul) * rl * ul + ps - pl, d);
-        const real Us2 = fdiv((SL - ul) * rl * wl, d);
-        const real Us3 = fdiv((SL - ul) * El - pl * ul + ps * SM, d);
+        const real id = frcp(SL - SM);
+        const real Us0 = (rl * (SL - ul)) * id;
+        const real Us1 = ((SL - ul) * rl * ul + ps - pl) * id;
+        const real Us2 = ((SL - ul) * rl * wl) * id;
+        const real Us3 = ((SL - ul) * El - pl * ul + ps * SM) * id;
         Fn[0] = rl * ul + SL * (Us0 - rl);
         Fn[1] = (rl * ul * ul + pl) + SL * (Us1 - rl * ul);
         Fn[2] = rl * ul * wl + SL * (Us2 - rl * wl);
         Fn[3] = ul * (El + pl) + SL * (Us3 - El);
     } else if (0 < SR) {
-        const real d = SR - SM;
-        const real Us0 = fdiv(rr * (SR - ur), d);
-        const real Us1 = fdiv((SR - ur) * rr * ur + ps - pr, d);
-        const real Us2 = fdiv((SR - ur) * rr * wr, d);
-        const real Us3 = fdiv((SR - ur) * Er - pr * ur + ps * SM, d);
+        const real id = frcp(SR - SM);
+        const real Us0 = (rr * (SR - ur)) * id;
+        const real Us1 = ((SR - ur) * rr * ur + ps - pr) * id;
+        const real Us2 = ((SR - ur) * rr * wr) * id;
+        const real Us3 = ((SR - ur) * Er - pr * ur + ps * SM) * id;
         Fn[0] = rr * ur + SR * (Us0 - rr);
         Fn[1] = (rr * ur * ur + pr) + SR * (Us1 - rr * ur);
         Fn[2] = rr * ur * wr + SR * (Us2 - rr * wr);
@@ -815,12 +938,13 @@ __device__ __forceinline__ bool hllc(real g, const real *UL, const real *UR, rea
 template <typename real>
 __device__ __forceinline__ bool wall_flux(real g, const real *UL, real nx, real ny, real *F) {
     const real r = UL[0];
-    const real u = fdiv(UL[1] * nx + UL[2] * ny, r), w = fdiv(-UL[1] * ny + UL[2] * nx, r);
+    const real ir = frcp(r);
+    const real u = (UL[1] * nx + UL[2] * ny) * ir, w = (-UL[1] * ny + UL[2] * nx) * ir;
     const real E = UL[3];
     const real p = euler_pressure(g, r, UL[1], UL[2], E);
     const bool ok = r > 0 && p > 0;
-    const real c = fsqrt(fdiv(g * p, r));
-    const real H = fdiv(E + p, r);
+    const real c = fsqrt((g * p) * ir);
+    const real H = (E + p) * ir;
     const real ct = fsqrt((g - 1) * (H - (real)0.5 * w * w));
     const real SL = fmin(u - c, -ct);
     const real ps = r * (u - SL) * u + p;
