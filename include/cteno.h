@@ -328,17 +328,18 @@ cteno_status cteno_count_flips(cteno_ctx *ctx, const cteno_mesh *mesh, const cte
 typedef struct {
     int64_t submitted, finished;
     int32_t active, peak_active;    /* solves resident on the device now / at most */
-    int64_t ticks;                  /* batched SSP-RK3 steps launched */
+    int64_t ticks;                  /* batched SSP-RK3 steps launched (4 per tick) */
     int64_t cell_stages;            /* cells x stages of finished solves */
     int64_t bytes_in_use, peak_bytes, budget_bytes;
     int64_t fallbacks;              /* cells x stages of finished solves that took the positivity fallback */
 } cteno_server_stats;
 
 /* One request as the server saw it.  Times in seconds: build_s from
-   submission until its host mesh and stencils were built, queue_s from then
-   until admission, admit_s for the upload and the FP64 pseudo-inverse
-   precompute, run_s from then until its result was on the host (steps,
-   waiting for the batched ticks, result copy); latency_s = submission to
+   submission until its host mesh and stencils were built; queue_s the time
+   spent waiting, for device memory before the upload and for a batch slot
+   after it; admit_s for the upload and the FP64 pseudo-inverse precompute;
+   run_s from joining a batch until its result was on the host (steps,
+   the batched ticks of the others, result copy); latency_s = submission to
    result.  Stages not reached yet read 0. */
 typedef struct {
     int32_t state;                  /* CTENO_REQ_* */
@@ -352,16 +353,18 @@ typedef struct {
 enum { CTENO_REQ_QUEUED = 0, CTENO_REQ_READY = 1, CTENO_REQ_RUNNING = 2, CTENO_REQ_DONE = 3, CTENO_REQ_FAILED = 4 };
 
 /* Starts a server for independent 2-D Euler solves with one scheme (FP32
-   reconstruction / weights / HLLC, FP64 state; degree 2 or 3).  A host
-   thread builds each request's mesh and stencils; a scheduler thread admits
-   built requests in arrival order while at most max_slots are resident and
-   their device footprint (pseudo-inverses, geometry, state, face values,
-   plus the transient FP64 precompute of a newcomer) fits in
-   hbm_budget_bytes, runs one batched SSP-RK3 step of every resident solve per
-   tick (one launch per kernel for all of them, replayed from a HIP graph;
-   each solve keeps its own CFL time step), and returns finished solves'
-   memory so waiting requests join between ticks.  Work is issued on a
-   stream owned by the server. */
+   reconstruction / weights / HLLC, FP64 state; degree 2 or 3).  Builder
+   threads take requests in arrival order, build each one's mesh and
+   stencils on the host, wait until its device footprint (pseudo-inverses,
+   geometry, state, face values, plus the transient FP64 precompute) fits in
+   hbm_budget_bytes beside the resident solves, and upload it and run its
+   precompute on a stream of their own, overlapping the batched steps.  A
+   scheduler thread puts resident requests into batch slots (at most
+   max_slots) and runs ticks of four batched SSP-RK3 steps of every slot
+   (one launch per kernel for all of them, replayed from a HIP graph whose
+   grid covers the active cells; each solve keeps its own CFL time step and
+   stops at its own step count), retiring finished solves between ticks and
+   returning their memory.  Work is issued on streams owned by the server. */
 cteno_status cteno_server_create(cteno_ctx *ctx, const cteno_scheme *scheme, size_t hbm_budget_bytes,
                                  int32_t max_slots, cteno_server **out);
 /* Queues a solve of n_steps SSP-RK3 steps at the given CFL number from the

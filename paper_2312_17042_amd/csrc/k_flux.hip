@@ -169,10 +169,15 @@ hipError_t launch_control(Ctrl *ctrl, const double *part, int64_t n_part, int co
 // ===========================================================================
 
 // slot of global block b: slots hold consecutive block ranges in table order
+// (binary search for the first range that ends past b)
 __device__ __forceinline__ int find_slot(const BatchSlot *tab, int n, int64_t b) {
-    for (int k = 0; k < n; ++k)
-        if (b < tab[k].block0 + tab[k].nblocks) return b >= tab[k].block0 ? k : -1;
-    return -1;
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (tab[mid].block0 + tab[mid].nblocks > b) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo < n && b >= tab[lo].block0 ? lo : -1;
 }
 
 template <int R, int SCHEME, int GFORM>

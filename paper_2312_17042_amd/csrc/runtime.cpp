@@ -1017,7 +1017,9 @@ struct ServerRequest {
     std::vector<double> u0;
     int32_t n_steps = 0;
     double cfl = 0.3;
-    Clock::time_point t_submit, t_built, t_admit, t_running, t_done;
+    // submitted, host mesh built, upload started (memory reserved), resident
+    // on the device, in a batch slot, finished
+    Clock::time_point t_submit, t_built, t_admit, t_ready, t_running, t_done;
     int state = REQ_QUEUED;
     HostMesh hm;
     std::string err;
@@ -1038,6 +1040,11 @@ struct ServerSlot {
 };
 }  // namespace
 
+// SSP-RK3 steps per tick: one graph launch and one host round trip cover
+// this many batched steps (a solve that finishes within a tick idles through
+// the rest of it)
+constexpr int kStepsPerTick = 4;
+
 struct cteno_server {
     cteno_ctx *ctx = nullptr;
     cteno_scheme scheme{};
@@ -1051,11 +1058,13 @@ struct cteno_server {
     BatchSlot *h_table = nullptr;
     int *h_nslots = nullptr;
     Ctrl *h_ctrl = nullptr;
-    hipGraphExec_t graph = nullptr;
+    // one captured tick per grid size (powers of two up to max_blocks)
+    std::map<int64_t, hipGraphExec_t> graphs;
     // host side
     std::mutex mu;
-    std::condition_variable cv_build, cv_sched, cv_done;
-    std::deque<std::shared_ptr<ServerRequest>> to_build, ready;
+    std::condition_variable cv_build, cv_upload, cv_sched, cv_done, cv_budget;
+    std::deque<std::shared_ptr<ServerRequest>> to_build, built;
+    std::deque<std::unique_ptr<ServerSlot>> prepared;   // resident on the device, waiting for a slot
     std::map<uint64_t, std::shared_ptr<ServerRequest>> requests;
     std::vector<std::unique_ptr<ServerSlot>> active;
     std::vector<int> free_ctrl;
@@ -1065,7 +1074,8 @@ struct cteno_server {
     int64_t ticks = 0, cell_stages = 0, n_submitted = 0, n_finished = 0, fallbacks = 0;
     bool stop = false;
     std::string sched_error;
-    std::vector<std::thread> builders;
+    std::vector<std::thread> builders, uploaders;
+    std::vector<hipStream_t> upload_streams;
     std::thread scheduler;
 };
 
@@ -1081,6 +1091,54 @@ void slot_footprint(const cteno_server *sv, int64_t N, int64_t &steady, int64_t 
     transient = Np * (E64 * 8 + 6 * 8 + S + 2 * S) + 64;
 }
 
+// a request's device state on a builder's stream: mesh arrays and FP64
+// precompute, state buffers, the initial state in internal order and its
+// time-step partials; synchronises that stream
+cteno_status prepare_slot(cteno_server *sv, const std::shared_ptr<ServerRequest> &rq, std::unique_ptr<ServerSlot> &sl,
+                          hipStream_t st) {
+    sl = std::make_unique<ServerSlot>();
+    sl->req = rq;
+    cteno_scheme s = sv->scheme;
+    s.precision = CTENO_MIXED;
+    int64_t bytes = 0;
+    cteno_status rc = upload_device_mesh(sv->ctx, st, rq->hm, s, sl->dm, sl->bufs, bytes, false);
+    if (rc != CTENO_OK) return rc;
+    const DeviceMesh &dm = sl->dm;
+    const size_t sb = (size_t)dm.Np * dm.nv * sizeof(double);
+    for (auto &u : sl->U) {
+        u = DevBuf(sv->ctx, sb);
+        if (!u.p) return fail(CTENO_ERR_NOMEM, "device allocation failed");
+        HIP_TRY(hipMemsetAsync(u.p, 0, sb, st));
+    }
+    sl->FV = DevBuf(sv->ctx, (size_t)dm.Np * 3 * kNq * dm.nv * sizeof(float));
+    sl->dt_part = DevBuf(sv->ctx, (size_t)dm.blocks() * sizeof(double));
+    if (!sl->FV.p || !sl->dt_part.p) return fail(CTENO_ERR_NOMEM, "device allocation failed");
+    bytes += (int64_t)(3 * sb + sl->FV.bytes + sl->dt_part.bytes);
+    // initial state: caller order -> internal order
+    DevBuf tmp(sv->ctx, (size_t)dm.N * dm.nv * sizeof(double));
+    if (!tmp.p) return fail(CTENO_ERR_NOMEM, "device allocation failed");
+    HIP_TRY(hipMemcpyAsync(tmp.p, rq->u0.data(), (size_t)dm.N * dm.nv * sizeof(double), hipMemcpyHostToDevice, st));
+    HIP_TRY(launch_user_to_state(dm, tmp.as<double>(), sl->U[0].as<double>(), st));
+    HIP_TRY(launch_dt_partials(dm, true, sl->U[0].as<double>(), sl->dt_part.as<double>(), st));
+    HIP_TRY(hipStreamSynchronize(st));     // tmp and the host u0 are released after this
+    rq->u0.clear();
+    rq->u0.shrink_to_fit();
+    sl->bytes = bytes;
+    return CTENO_OK;
+}
+
+void fail_request(cteno_server *sv, ServerRequest &rq, cteno_status rc, const std::string &err) {
+    rq.state = REQ_FAILED;
+    rq.fail_status = rc;
+    rq.err = err;
+    rq.t_done = Clock::now();
+    rq.hm = HostMesh();
+    sv->n_finished++;
+    sv->cv_done.notify_all();
+}
+
+// A builder thread takes queued requests in arrival order and builds each
+// one's host mesh and stencils.
 void builder_main(cteno_server *sv, int threads_each) {
     set_builder_threads(threads_each);
     for (;;) {
@@ -1094,93 +1152,78 @@ void builder_main(cteno_server *sv, int threads_each) {
         }
         std::string err;
         cteno_status rc = build_host_mesh(rq->desc, sv->scheme, rq->hm, err);
-        int64_t steady = 0, transient = 0;
         if (rc == CTENO_OK) {
+            int64_t steady = 0, transient = 0;
             slot_footprint(sv, rq->hm.N, steady, transient);
             if (steady + transient > sv->budget) { rc = CTENO_ERR_BUSY; err = "request exceeds the HBM budget"; }
         }
         std::lock_guard<std::mutex> lk(sv->mu);
         rq->t_built = Clock::now();
-        if (rc != CTENO_OK) {
-            rq->state = REQ_FAILED;
-            rq->err = err;
-            rq->fail_status = rc;
-            rq->t_done = rq->t_built;
-            sv->n_finished++;
-            sv->cv_done.notify_all();
-        } else {
-            rq->state = REQ_READY;
-            sv->ready.push_back(rq);
-            sv->cv_sched.notify_all();
-        }
+        if (rc != CTENO_OK) { fail_request(sv, *rq, rc, err); continue; }
+        rq->state = REQ_READY;
+        sv->built.push_back(rq);
+        sv->cv_upload.notify_one();
     }
 }
 
-cteno_status admit(cteno_server *sv, const std::shared_ptr<ServerRequest> &rq, std::unique_ptr<ServerSlot> &sl) {
-    sl = std::make_unique<ServerSlot>();
-    sl->req = rq;
-    cteno_scheme s = sv->scheme;
-    s.precision = CTENO_MIXED;
-    int64_t bytes = 0;
-    cteno_status rc = upload_device_mesh(sv->ctx, sv->stream, rq->hm, s, sl->dm, sl->bufs, bytes, false);
-    if (rc != CTENO_OK) return rc;
-    const DeviceMesh &dm = sl->dm;
-    const size_t sb = (size_t)dm.Np * dm.nv * sizeof(double);
-    for (auto &u : sl->U) {
-        u = DevBuf(sv->ctx, sb);
-        if (!u.p) return fail(CTENO_ERR_NOMEM, "device allocation failed");
-        HIP_TRY(hipMemsetAsync(u.p, 0, sb, sv->stream));
+// An upload thread takes built requests in the order they were built, waits
+// until the device budget holds the request's steady plus transient
+// footprint beside the resident solves, uploads it and runs its FP64
+// precompute on its own stream (overlapping the batched ticks), and hands the
+// resident solve to the scheduler.
+void uploader_main(cteno_server *sv, int index) {
+    const bool dev_ok = hipSetDevice(sv->ctx->device) == hipSuccess;
+    const hipStream_t st = sv->upload_streams[index];
+    for (;;) {
+        std::shared_ptr<ServerRequest> rq;
+        int64_t reserve = 0;
+        {
+            std::unique_lock<std::mutex> lk(sv->mu);
+            sv->cv_upload.wait(lk, [&] { return sv->stop || !sv->built.empty(); });
+            if (sv->stop) return;
+            rq = sv->built.front();
+            sv->built.pop_front();
+            if (!dev_ok) { fail_request(sv, *rq, CTENO_ERR_DEVICE, "hipSetDevice failed"); continue; }
+            int64_t steady = 0, transient = 0;
+            slot_footprint(sv, rq->hm.N, steady, transient);
+            reserve = steady + transient;
+            sv->cv_budget.wait(lk, [&] { return sv->stop || sv->bytes_used + reserve <= sv->budget; });
+            if (sv->stop) return;
+            sv->bytes_used += reserve;
+            sv->peak_bytes = std::max(sv->peak_bytes, sv->bytes_used);
+            rq->t_admit = Clock::now();
+        }
+        std::unique_ptr<ServerSlot> sl;
+        const cteno_status rc = prepare_slot(sv, rq, sl, st);
+        const std::string perr = g_err;
+        std::lock_guard<std::mutex> lk(sv->mu);
+        if (rc != CTENO_OK) {
+            sv->bytes_used -= reserve;
+            sl.reset();
+            fail_request(sv, *rq, rc, perr);
+            sv->cv_budget.notify_all();
+            continue;
+        }
+        // the transient precompute buffers are gone: keep what stays resident
+        sv->bytes_used += sl->bytes - reserve;
+        sv->peak_bytes = std::max(sv->peak_bytes, sv->bytes_used);
+        rq->t_ready = Clock::now();
+        sv->prepared.push_back(std::move(sl));
+        sv->cv_budget.notify_all();
+        sv->cv_sched.notify_all();
     }
-    sl->FV = DevBuf(sv->ctx, (size_t)dm.Np * 3 * kNq * dm.nv * sizeof(float));
-    sl->dt_part = DevBuf(sv->ctx, (size_t)dm.blocks() * sizeof(double));
-    if (!sl->FV.p || !sl->dt_part.p) return fail(CTENO_ERR_NOMEM, "device allocation failed");
-    bytes += (int64_t)(3 * sb + sl->FV.bytes + sl->dt_part.bytes);
-    // initial state: caller order -> internal order
+}
+
+// the result of a finished slot in caller order, into `result` (the
+// caller publishes it under the server lock)
+cteno_status retire(cteno_server *sv, ServerSlot &sl, std::vector<double> &result) {
+    const DeviceMesh &dm = sl.dm;
     DevBuf tmp(sv->ctx, (size_t)dm.N * dm.nv * sizeof(double));
     if (!tmp.p) return fail(CTENO_ERR_NOMEM, "device allocation failed");
-    HIP_TRY(hipMemcpyAsync(tmp.p, rq->u0.data(), (size_t)dm.N * dm.nv * sizeof(double), hipMemcpyHostToDevice,
-                           sv->stream));
-    HIP_TRY(launch_user_to_state(dm, tmp.as<double>(), sl->U[0].as<double>(), sv->stream));
-    HIP_TRY(launch_dt_partials(dm, true, sl->U[0].as<double>(), sl->dt_part.as<double>(), sv->stream));
-    // control block
-    sl->ctrl_index = sv->free_ctrl.back();
-    sv->free_ctrl.pop_back();
-    Ctrl c{};
-    c.t = 0.0;
-    c.t_final = INFINITY;
-    c.cfl = rq->cfl;
-    c.max_steps = rq->n_steps;
-    Ctrl *dc = sv->d_ctrl.as<Ctrl>() + sl->ctrl_index;
-    HIP_TRY(hipMemcpyAsync(dc, &c, sizeof(Ctrl), hipMemcpyHostToDevice, sv->stream));
-    HIP_TRY(hipStreamSynchronize(sv->stream));     // host buffers (u0, c) are released after this
-    rq->u0.clear();
-    rq->u0.shrink_to_fit();
-    sl->bytes = bytes;
-    return CTENO_OK;
-}
-
-cteno_status retire(cteno_server *sv, ServerSlot &sl, const Ctrl &c) {
-    auto &rq = sl.req;
-    rq->steps = c.step;
-    rq->t_end = c.t;
-    rq->fallbacks = (int64_t)c.fallbacks;
-    if (c.nonphysical) {
-        rq->state = REQ_FAILED;
-        rq->fail_status = CTENO_ERR_NONPHYSICAL;
-        rq->err = "non-physical state (density or pressure <= 0, or NaN)";
-    } else {
-        const DeviceMesh &dm = sl.dm;
-        DevBuf tmp(sv->ctx, (size_t)dm.N * dm.nv * sizeof(double));
-        if (!tmp.p) return fail(CTENO_ERR_NOMEM, "device allocation failed");
-        rq->result.resize((size_t)dm.N * dm.nv);
-        HIP_TRY(launch_state_to_user(dm, sl.U[0].as<double>(), tmp.as<double>(), sv->stream));
-        HIP_TRY(hipMemcpyAsync(rq->result.data(), tmp.p, rq->result.size() * sizeof(double), hipMemcpyDeviceToHost,
-                               sv->stream));
-        HIP_TRY(hipStreamSynchronize(sv->stream));
-        rq->state = REQ_DONE;
-    }
-    rq->hm = HostMesh();
-    rq->t_done = Clock::now();
+    result.resize((size_t)dm.N * dm.nv);
+    HIP_TRY(launch_state_to_user(dm, sl.U[0].as<double>(), tmp.as<double>(), sv->stream));
+    HIP_TRY(hipMemcpyAsync(result.data(), tmp.p, result.size() * sizeof(double), hipMemcpyDeviceToHost, sv->stream));
+    HIP_TRY(hipStreamSynchronize(sv->stream));
     return CTENO_OK;
 }
 
@@ -1195,58 +1238,69 @@ void scheduler_fail(cteno_server *sv, const std::string &m) {
             kv.second->t_done = Clock::now();
             sv->n_finished++;
         }
-    sv->ready.clear();
     sv->to_build.clear();
+    sv->built.clear();
+    sv->stop = true;
+    sv->cv_build.notify_all();
+    sv->cv_upload.notify_all();
+    sv->cv_budget.notify_all();
     sv->cv_done.notify_all();
+}
+
+// the captured tick for a grid of `blocks` blocks (captured on first use)
+hipGraphExec_t tick_graph(cteno_server *sv, int64_t blocks) {
+    auto it = sv->graphs.find(blocks);
+    if (it != sv->graphs.end()) return it->second;
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(sv->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return nullptr;
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < kStepsPerTick && e == hipSuccess; ++k)
+        e = launch_batch_step(sv->proto, sv->d_table.as<BatchSlot>(), sv->d_nslots.as<int>(), sv->max_slots, blocks,
+                              sv->stream);
+    hipError_t e2 = hipStreamEndCapture(sv->stream, &g);
+    hipGraphExec_t x = nullptr;
+    if (e == hipSuccess && e2 == hipSuccess && hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess) x = nullptr;
+    if (g) (void)hipGraphDestroy(g);
+    if (x) sv->graphs[blocks] = x;
+    return x;
 }
 
 void scheduler_main(cteno_server *sv) {
     if (hipSetDevice(sv->ctx->device) != hipSuccess) { scheduler_fail(sv, "hipSetDevice failed"); return; }
     bool dirty = true;
+    int64_t grid = 0;
     for (;;) {
-        // admissions: ready requests, in arrival order, while slots and memory allow
-        std::deque<std::shared_ptr<ServerRequest>> cand;
+        // admissions: resident solves, in the order their uploads finished,
+        // while slots are free (no device work: the builders did it)
         {
             std::unique_lock<std::mutex> lk(sv->mu);
             if (sv->active.empty())
-                sv->cv_sched.wait(lk, [&] { return sv->stop || !sv->ready.empty(); });
-            if (sv->stop && sv->active.empty() && sv->ready.empty()) return;
-            while (!sv->ready.empty() && (int)(sv->active.size() + cand.size()) < sv->max_slots) {
-                int64_t steady, transient;
-                slot_footprint(sv, sv->ready.front()->hm.N, steady, transient);
-                int64_t pending = 0;
-                for (auto &c : cand) { int64_t a, b; slot_footprint(sv, c->hm.N, a, b); pending += a; }
-                if (sv->bytes_used + pending + steady + transient > sv->budget) break;
-                cand.push_back(sv->ready.front());
-                sv->ready.pop_front();
+                sv->cv_sched.wait(lk, [&] { return sv->stop || !sv->prepared.empty(); });
+            if (sv->stop && sv->active.empty()) return;
+            while (!sv->stop && !sv->prepared.empty() && (int)sv->active.size() < sv->max_slots) {
+                std::unique_ptr<ServerSlot> sl = std::move(sv->prepared.front());
+                sv->prepared.pop_front();
+                sl->ctrl_index = sv->free_ctrl.back();
+                sv->free_ctrl.pop_back();
+                Ctrl &c = sv->h_ctrl[sl->ctrl_index];
+                c = Ctrl{};
+                c.t = 0.0;
+                c.t_final = INFINITY;
+                c.cfl = sl->req->cfl;
+                c.max_steps = sl->req->n_steps;
+                // stream-ordered before the next tick and before this entry's read-back
+                if (hipMemcpyAsync(sv->d_ctrl.as<Ctrl>() + sl->ctrl_index, &c, sizeof(Ctrl), hipMemcpyHostToDevice,
+                                   sv->stream) != hipSuccess) {
+                    lk.unlock();
+                    scheduler_fail(sv, "control upload failed");
+                    return;
+                }
+                sl->req->state = REQ_RUNNING;
+                sl->req->t_running = Clock::now();
+                sv->active.push_back(std::move(sl));
+                sv->peak_active = std::max(sv->peak_active, (int)sv->active.size());
+                dirty = true;
             }
-        }
-        for (auto &rq : cand) {
-            std::unique_ptr<ServerSlot> sl;
-            {
-                std::lock_guard<std::mutex> lk(sv->mu);
-                rq->t_admit = Clock::now();
-            }
-            cteno_status rc = admit(sv, rq, sl);
-            if (rc != CTENO_OK && sl && sl->ctrl_index >= 0) sv->free_ctrl.push_back(sl->ctrl_index);
-            std::lock_guard<std::mutex> lk(sv->mu);
-            if (rc != CTENO_OK) {
-                rq->state = REQ_FAILED;
-                rq->fail_status = rc;
-                rq->err = g_err;
-                rq->t_done = Clock::now();
-                rq->hm = HostMesh();
-                sv->n_finished++;
-                sv->cv_done.notify_all();
-                continue;
-            }
-            rq->state = REQ_RUNNING;
-            rq->t_running = Clock::now();
-            sv->bytes_used += sl->bytes;
-            sv->peak_bytes = std::max(sv->peak_bytes, sv->bytes_used);
-            sv->active.push_back(std::move(sl));
-            sv->peak_active = std::max(sv->peak_active, (int)sv->active.size());
-            dirty = true;
         }
         if (sv->active.empty()) continue;
         if (dirty) {
@@ -1270,6 +1324,10 @@ void scheduler_main(cteno_server *sv) {
             }
             *sv->h_nslots = (int)sv->active.size();
             if (b0 > sv->max_blocks) { scheduler_fail(sv, "block budget exceeded"); return; }
+            // the smallest power-of-two grid that covers the active blocks
+            grid = 64;
+            while (grid < b0) grid *= 2;
+            grid = std::min(grid, sv->max_blocks);
             if (hipMemcpyAsync(sv->d_table.p, sv->h_table, sizeof(BatchSlot) * sv->active.size(),
                                hipMemcpyHostToDevice, sv->stream) != hipSuccess ||
                 hipMemcpyAsync(sv->d_nslots.p, sv->h_nslots, sizeof(int), hipMemcpyHostToDevice, sv->stream) !=
@@ -1279,9 +1337,11 @@ void scheduler_main(cteno_server *sv) {
             }
             dirty = false;
         }
-        // one SSP-RK3 step of every active solve
-        if (hipGraphLaunch(sv->graph, sv->stream) != hipSuccess) { scheduler_fail(sv, "graph launch failed"); return; }
-        sv->ticks++;
+        // kStepsPerTick SSP-RK3 steps of every active solve
+        hipGraphExec_t gx = tick_graph(sv, grid);
+        if (!gx) { scheduler_fail(sv, "tick capture failed"); return; }
+        if (hipGraphLaunch(gx, sv->stream) != hipSuccess) { scheduler_fail(sv, "graph launch failed"); return; }
+        sv->ticks += kStepsPerTick;
         // read back the control blocks of the active slots
         for (size_t k = 0; k < sv->active.size(); ++k) {
             const int ci = sv->active[k]->ctrl_index;
@@ -1293,13 +1353,23 @@ void scheduler_main(cteno_server *sv) {
             ServerSlot &sl = *sv->active[k];
             const Ctrl &c = sv->h_ctrl[sl.ctrl_index];
             if (!c.done) { ++k; continue; }
-            cteno_status rc = retire(sv, sl, c);
+            std::vector<double> result;
+            const cteno_status rc = c.nonphysical ? CTENO_ERR_NONPHYSICAL : retire(sv, sl, result);
+            const std::string err = c.nonphysical ? "non-physical state (density or pressure <= 0, or NaN)" : g_err;
             std::lock_guard<std::mutex> lk(sv->mu);
-            if (rc != CTENO_OK) {
-                sl.req->state = REQ_FAILED;
-                sl.req->fail_status = rc;
-                sl.req->err = g_err;
-                sl.req->t_done = Clock::now();
+            ServerRequest &rq = *sl.req;
+            rq.steps = c.step;
+            rq.t_end = c.t;
+            rq.fallbacks = (int64_t)c.fallbacks;
+            rq.hm = HostMesh();
+            rq.t_done = Clock::now();
+            if (rc == CTENO_OK) {
+                rq.result = std::move(result);
+                rq.state = REQ_DONE;
+            } else {
+                rq.state = REQ_FAILED;
+                rq.fail_status = rc;
+                rq.err = err;
             }
             sv->cell_stages += sl.dm.N * 3 * c.step;
             sv->fallbacks += (int64_t)c.fallbacks;
@@ -1308,6 +1378,7 @@ void scheduler_main(cteno_server *sv) {
             sv->n_finished++;
             sv->active.erase(sv->active.begin() + k);
             dirty = true;
+            sv->cv_budget.notify_all();
             sv->cv_done.notify_all();
         }
     }
@@ -1354,22 +1425,20 @@ extern "C" cteno_status cteno_server_create(cteno_ctx *ctx, const cteno_scheme *
     p.gamma = scheme->gamma; p.lam1p = scheme->lambda1_prime; p.ct = scheme->c_t; p.eps = scheme->eps;
     p.positivity = scheme->positivity;
     make_ref_tables(p.r, p.tab);
-    // capture one batched step
-    hipGraph_t g = nullptr;
     HIP_TRY(hipStreamSynchronize(sv->stream));
-    HIP_TRY(hipStreamBeginCapture(sv->stream, hipStreamCaptureModeThreadLocal));
-    hipError_t e = launch_batch_step(sv->proto, sv->d_table.as<BatchSlot>(), sv->d_nslots.as<int>(), max_slots,
-                                     sv->max_blocks, sv->stream);
-    hipError_t e2 = hipStreamEndCapture(sv->stream, &g);
-    if (e != hipSuccess) return fail(CTENO_ERR_DEVICE, std::string("capture: ") + hipGetErrorString(e));
-    HIP_TRY(e2);
-    HIP_TRY(hipGraphInstantiate(&sv->graph, g, nullptr, nullptr, 0));
-    (void)hipGraphDestroy(g);
-    cteno_server *raw = sv.release();
-    // several mesh builders, each with a share of the host threads
+    // several mesh builders, each with a share of the host threads, and two
+    // upload threads, each with a stream of its own (default priority)
+    constexpr int kUploaders = 2;
+    for (int k = 0; k < kUploaders; ++k) {
+        hipStream_t us = nullptr;
+        HIP_TRY(hipStreamCreateWithFlags(&us, hipStreamNonBlocking));
+        sv->upload_streams.push_back(us);
+    }
     const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
     const int nb = std::max(1, std::min(4, hw / 2));
+    cteno_server *raw = sv.release();
     for (int k = 0; k < nb; ++k) raw->builders.emplace_back(builder_main, raw, std::max(1, std::min(hw, 16) / nb));
+    for (int k = 0; k < kUploaders; ++k) raw->uploaders.emplace_back(uploader_main, raw, k);
     raw->scheduler = std::thread(scheduler_main, raw);
     *out = raw;
     return CTENO_OK;
@@ -1471,8 +1540,8 @@ extern "C" cteno_status cteno_server_request_info(cteno_server *sv, uint64_t tic
     const bool finished = rq.state == REQ_DONE || rq.state == REQ_FAILED;
     info->latency_s = finished ? sec(rq.t_submit, rq.t_done) : 0.0;
     info->build_s = sec(rq.t_submit, rq.t_built);
-    info->queue_s = sec(rq.t_built, rq.t_admit);
-    info->admit_s = sec(rq.t_admit, rq.t_running);
+    info->queue_s = sec(rq.t_built, rq.t_admit) + sec(rq.t_ready, rq.t_running);
+    info->admit_s = sec(rq.t_admit, rq.t_ready);
     info->run_s = finished ? sec(rq.t_running, rq.t_done) : 0.0;
     return CTENO_OK;
 }
@@ -1483,17 +1552,26 @@ extern "C" void cteno_server_destroy(cteno_server *sv) {
         std::lock_guard<std::mutex> lk(sv->mu);
         sv->stop = true;
         sv->to_build.clear();
-        sv->ready.clear();
+        sv->built.clear();
     }
     sv->cv_build.notify_all();
+    sv->cv_upload.notify_all();
+    sv->cv_budget.notify_all();
     sv->cv_sched.notify_all();
     for (auto &b : sv->builders)
         if (b.joinable()) b.join();
+    for (auto &u : sv->uploaders)
+        if (u.joinable()) u.join();
     if (sv->scheduler.joinable()) sv->scheduler.join();
     (void)hipSetDevice(sv->ctx->device);
     (void)hipStreamSynchronize(sv->stream);
+    for (hipStream_t us : sv->upload_streams) {
+        (void)hipStreamSynchronize(us);
+        (void)hipStreamDestroy(us);
+    }
+    sv->prepared.clear();
     sv->active.clear();
-    if (sv->graph) (void)hipGraphExecDestroy(sv->graph);
+    for (auto &kv : sv->graphs) (void)hipGraphExecDestroy(kv.second);
     if (sv->h_table) (void)hipHostFree(sv->h_table);
     if (sv->h_nslots) (void)hipHostFree(sv->h_nslots);
     if (sv->h_ctrl) (void)hipHostFree(sv->h_ctrl);
