@@ -183,14 +183,18 @@ __device__ __forceinline__ int find_slot(const BatchSlot *tab, int n, int64_t b)
 template <int R, int SCHEME, int GFORM>
 __global__ __launch_bounds__(256) void k_reconstruct_batch(const ReconArgs<float, (R + 1) * (R + 2) / 2 - 1> a,
                                                            const BatchSlot *tab, const int *n_slots, int stage) {
+    constexpr int K = (R + 1) * (R + 2) / 2 - 1;
     const int64_t b = blockIdx.x;
     const int s = find_slot(tab, *n_slots, b);
-    if (s < 0) return;
+    if (s < 0) return;                        // uniform across the block
     const BatchSlot &t = tab[s];
     if (t.ctrl->done) return;
+    __shared__ float ctab[recon_tab_size<K>()];
+    recon_tab_fill<float, K>(a, ctab);
+    __syncthreads();
     const int64_t i = (b - t.block0) * blockDim.x + threadIdx.x;
     if (i >= t.N) return;
-    const ReconPtrs<float> ptr{t.U[stage], t.slot, t.flags, t.P, t.FV, nullptr, nullptr, &t.ctrl->fallbacks};
+    const ReconPtrs<float> ptr{t.U[stage], t.slot, t.flags, t.P, t.FV, nullptr, nullptr, &t.ctrl->fallbacks, ctab};
     float out[3][2][4];
     recon_body<float, R, 4, SCHEME, GFORM, 0, 0>(a, ptr, i, out);
     store_row<float, 3 * 2 * 4>(ptr.FV + i * 3 * 2 * 4, &out[0][0][0]);

@@ -1,17 +1,17 @@
-// Fused SSP-RK3 stage of degree 2 and 3 for one arithmetic type;
-// instantiated per type by k_stage_f32.hip and k_stage_f64.hip.
+// Fused SSP-RK3 stage of degree 2 and 3 (FP32 reconstruction and fluxes,
+// instantiated by k_stage_f32.hip).
 //
 // k_stage (part 0), one lane per cell, 256-cell blocks: the reconstruction of
 // the block's cells (sec. 2.1-2.6) goes to LDS; after a block barrier each
 // cell evaluates the fluxes (sec. 2.7) of its faces whose neighbour lies in
 // the same block from LDS, and of its boundary faces, and -- when no face
 // leads to another block -- applies its RK stage at once.  A cell with a
-// face to another block stores its face values and its partial sum instead,
-// and k_stage_cross (part 1) adds the faces to other blocks and applies its
-// stage.  Both cells of a face evaluate the same flux from the same values
-// (LDS holds exactly the values the other cell computed), so the update
-// stays conservative to FP64 round-off.  The face values of cells whose
-// faces all stay inside their block never leave the chip.
+// face to another block stores the values of those faces and its partial
+// sum instead, and k_stage_cross (part 1) adds the faces to other blocks and
+// applies its stage.  Both cells of a face evaluate the same flux from the
+// same values (LDS holds exactly the values the other cell computed), so
+// the update stays conservative to FP64 round-off.  Face values of faces
+// inside a block never leave the chip.
 #pragma once
 #include "kernels_common.h"
 
@@ -23,6 +23,10 @@ __global__ __launch_bounds__(256) void k_stage(const ReconArgs<real, (R + 1) * (
     constexpr int NQ = 2, ROW = 3 * NQ * NV;
     __shared__ __align__(16) real lfv[256 * ROW];       // the block's face-point values
     __shared__ __align__(16) double lterm[256 * 3 * NV]; // owners' terms of the faces inside the block
+    constexpr int K = (R + 1) * (R + 2) / 2 - 1;
+    __shared__ real tab[recon_tab_size<K>()];
+    recon_tab_fill<real, K>(ra, tab);
+    __syncthreads();
     const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
     const int64_t i = blk * 256 + threadIdx.x;
     if (ra.done && *ra.done) return;           // uniform across the grid
@@ -34,7 +38,7 @@ __global__ __launch_bounds__(256) void k_stage(const ReconArgs<real, (R + 1) * (
     uint32_t code[3];
     double u0[NV], us[NV], ar = 1.0;
     if (live) {
-        const ReconPtrs<real> rp{ra.U, ra.slot, ra.flags, ra.P, nullptr, nullptr, ra.fr, ra.fb_count};
+        const ReconPtrs<real> rp{ra.U, ra.slot, ra.flags, ra.P, nullptr, nullptr, ra.fr, ra.fb_count, tab};
         recon_body<real, R, NV, SCHEME, GFORM, 0, VARS>(ra, rp, i, own);
         store_row<real, ROW>(lfv + threadIdx.x * ROW, &own[0][0][0]);
         // the flux phase's operands, requested before the barrier
@@ -96,7 +100,11 @@ __global__ __launch_bounds__(256) void k_stage(const ReconArgs<real, (R + 1) * (
         if (!deferred) {
             dtc = rk_apply<real, NV, PHYS>(fa, ptr, i, acc, nrm, u0, us, ar);
         } else {
-            store_row<real, ROW>(const_cast<real *>(fa.FV) + i * ROW, &own[0][0][0]);
+            // only the values of the faces to other blocks leave the chip
+#pragma unroll
+            for (int f = 0; f < 3; ++f)
+                if (kind[f] == 2)
+                    store_row<real, NQ * NV>(const_cast<real *>(fa.FV) + i * ROW + f * NQ * NV, &own[f][0][0]);
 #pragma unroll
             for (int v = 0; v < NV; ++v) fa.racc[i * NV + v] = acc[v];
         }
@@ -121,8 +129,6 @@ __global__ __launch_bounds__(256) void k_stage_cross(const FluxArgs<real> fa) {
         double acc[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) acc[v] = fa.racc[i * NV + v];
-        real own[3][NQ][NV];
-        load_row<real, ROW>(fa.FV + i * ROW, &own[0][0][0]);
         double nrm[3][3];
         bool bad = false;
 #pragma unroll
@@ -136,10 +142,12 @@ __global__ __launch_bounds__(256) void k_stage_cross(const FluxArgs<real> fa) {
             if ((j >> 8) == blk) continue;        // added by part 0
             const bool owner = (code & kNbOwner) != 0;
             const int g = (code >> 28) & 3;
-            real oth[NQ][NV];
+            // both sides' values of this face, as part 0 stored them
+            real mine[NQ][NV], oth[NQ][NV];
+            load_row<real, NQ * NV>(fa.FV + i * ROW + f * NQ * NV, &mine[0][0]);
             load_row<real, NQ * NV>(fa.FV + j * ROW + g * NQ * NV, &oth[0][0]);
             double term[NV];
-            face_term<real, NV, PHYS, NQ>(fa, own[f], oth, owner, false, nx, ny, len, term, bad);
+            face_term<real, NV, PHYS, NQ>(fa, mine, oth, owner, false, nx, ny, len, term, bad);
 #pragma unroll
             for (int v = 0; v < NV; ++v) acc[v] += term[v];
         }

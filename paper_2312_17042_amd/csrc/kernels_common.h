@@ -328,16 +328,41 @@ struct ReconPtrs {
     uint8_t *delta;
     const real *fr;         // face records (characteristic variables only)
     unsigned long long *fb; // cells that took the positivity fallback (may be null)
+    const real *tab;        // the block's LDS copy of the Gram matrix [K][K] and face basis [3][2][K]
 };
+
+// Entries of the reconstruction's constant table (Gram matrix, then face
+// basis values) and its LDS copy: lane 0 of the block writes it from the
+// kernel arguments; the caller synchronises the block before use.  In LDS
+// the FP32 constants cost no scalar registers in the epilogue, where they
+// would not fit beside the kernel's other scalars (the FP64 kernels read
+// them from the arguments: as vector registers they would cost a wave).
+template <int K>
+constexpr int recon_tab_size() { return K * K + 6 * K; }
+template <typename real, int K>
+__device__ __forceinline__ void recon_tab_fill(const ReconArgs<real, K> a, real *tab) {
+    if (std::is_same<real, float>::value && threadIdx.x == 0) {
+#pragma unroll
+        for (int p = 0; p < K; ++p)
+#pragma unroll
+            for (int q = 0; q < K; ++q) tab[p * K + q] = a.gram[p][q];
+#pragma unroll
+        for (int f = 0; f < 3; ++f)
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+#pragma unroll
+                for (int k = 0; k < K; ++k) tab[K * K + (f * 2 + q) * K + k] = a.basis[f][q][k];
+    }
+}
 
 // selection (or CWENO weights) of NV fields and their final coefficients,
 // in place: c1[K][NV] holds the p_1 coefficients on entry and the final
 // polynomial's on exit, cd[3][2][NV] the degree-1 directional ones; forced
 // (DMODE 2) points at the fields' forced selection bytes
 template <typename real, int K, int NV, int SCHEME, int GFORM, int DMODE, typename CD>
-__device__ __forceinline__ void finish_fields(const ReconArgs<real, K> a, real (&c1)[K][NV], const CD cd,
-                                              int fl, int adm, int st, real lams, real lratio, const uint8_t *forced,
-                                              int (&bits)[NV]) {
+__device__ __forceinline__ void finish_fields(const ReconArgs<real, K> a, const real *tab, real (&c1)[K][NV],
+                                              const CD cd, int fl, int adm, int st, real lams, real lratio,
+                                              const uint8_t *forced, int (&bits)[NV]) {
     if (DMODE == 2 && SCHEME != CTENO_SCHEME_CWENO) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) bits[v] = forced[v] & adm;
@@ -360,14 +385,16 @@ __device__ __forceinline__ void finish_fields(const ReconArgs<real, K> a, real (
             for (int v = 0; v < NV; ++v) rowp[v] = 0;
 #pragma unroll
             for (int q = SYM ? p : 0; q < K; ++q) {
-                const real g = a.gram[p][q];
+                const real g = std::is_same<real, float>::value ? tab[p * K + q] : a.gram[p][q];
 #pragma unroll
                 for (int v = 0; v < NV; ++v) rowp[v] += g * c1[q][v];
             }
 #pragma unroll
             for (int v = 0; v < NV; ++v) si[v][0] += c1[p][v] * rowp[v];
         }
-        const real g00 = a.gram[0][0], g01 = a.gram[0][1], g10 = a.gram[1][0], g11 = a.gram[1][1];
+        constexpr bool LT = std::is_same<real, float>::value;
+        const real g00 = LT ? tab[0] : a.gram[0][0], g01 = LT ? tab[1] : a.gram[0][1];
+        const real g10 = LT ? tab[K] : a.gram[1][0], g11 = LT ? tab[K + 1] : a.gram[1][1];
 #pragma unroll
         for (int q = 0; q < 3; ++q)
 #pragma unroll
@@ -691,11 +718,11 @@ __device__ __forceinline__ void recon_body(const ReconArgs<real, (R + 1) * (R + 
     if constexpr (VARS == 0) {
         int bits[NV];
         if constexpr (AD_LDS)
-            finish_fields<real, K, NV, SCHEME, GFORM, DMODE>(a, ao, CdLds<NV>{lad}, fl, adm, st, lams, lratio,
-                                                             ptr.delta + i * NV, bits);
+            finish_fields<real, K, NV, SCHEME, GFORM, DMODE>(a, ptr.tab, ao, CdLds<NV>{lad}, fl, adm, st, lams,
+                                                             lratio, ptr.delta + i * NV, bits);
         else
-            finish_fields<real, K, NV, SCHEME, GFORM, DMODE>(a, ao, CdRegs<real, NV>{ad}, fl, adm, st, lams, lratio,
-                                                             ptr.delta + i * NV, bits);
+            finish_fields<real, K, NV, SCHEME, GFORM, DMODE>(a, ptr.tab, ao, CdRegs<real, NV>{ad}, fl, adm, st,
+                                                             lams, lratio, ptr.delta + i * NV, bits);
 #pragma unroll
         for (int v = 0; v < NV; ++v) dbyte[v] = (uint8_t)bits[v];
         // face Gauss-point values
@@ -708,7 +735,8 @@ __device__ __forceinline__ void recon_body(const ReconArgs<real, (R + 1) * (R + 
                 for (int v = 0; v < NV; ++v) val[v] = 0;
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
-                    const real b = a.basis[f][q][k];
+                    const real b = std::is_same<real, float>::value ? ptr.tab[K * K + (f * 2 + q) * K + k]
+                                                                    : a.basis[f][q][k];
 #pragma unroll
                     for (int v = 0; v < NV; ++v) val[v] += b * ao[k][v];
                 }
@@ -764,8 +792,8 @@ __device__ __forceinline__ void recon_body(const ReconArgs<real, (R + 1) * (R + 
                         cd[s2][k][j] = x;
                     }
             int bits[4];
-            finish_fields<real, K, 4, SCHEME, GFORM, DMODE>(a, c1, CdRegs<real, 4>{cd}, fl, adm, st, lams, lratio,
-                                                            ptr.delta + (i * 3 + f) * 4, bits);
+            finish_fields<real, K, 4, SCHEME, GFORM, DMODE>(a, ptr.tab, c1, CdRegs<real, 4>{cd}, fl, adm, st, lams,
+                                                            lratio, ptr.delta + (i * 3 + f) * 4, bits);
 #pragma unroll
             for (int j = 0; j < 4; ++j) dbyte[f * 4 + j] = (uint8_t)bits[j];
 #pragma unroll
@@ -775,7 +803,8 @@ __device__ __forceinline__ void recon_body(const ReconArgs<real, (R + 1) * (R + 
                 for (int j = 0; j < 4; ++j) w[j] = 0;
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
-                    const real b = a.basis[f][q][k];
+                    const real b = std::is_same<real, float>::value ? ptr.tab[K * K + (f * 2 + q) * K + k]
+                                                                    : a.basis[f][q][k];
 #pragma unroll
                     for (int j = 0; j < 4; ++j) w[j] += b * c1[k][j];
                 }
