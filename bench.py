@@ -47,10 +47,11 @@ CELL_UPDATE_BYTES = 32 + 32 + 8
 # HBM bytes per cell and launch measured with the FETCH_SIZE / WRITE_SIZE
 # counters (scaled by the copy-kernel calibration), valid only for the
 # kernel sources they were taken on
-MEASURED_TRAFFIC = {"kernels_sha256_prefix": None,
-                    "bytes_per_cell": {"k_stage": None, "k_stage_cross": None,
-                                       "k_reconstruct_f32": None, "k_flux_f32": None,
-                                       "k_reconstruct_f64": None, "k_flux_f64": None}}
+MEASURED_TRAFFIC = {"kernels_sha256_prefix": "2a36b487e721139a",
+                    "source": "profiles/stage_vortex8M_hbm_counters.md",
+                    "bytes_per_cell": {"k_stage": 997.5, "k_stage_cross": 170.0,
+                                       "k_reconstruct_f32": 968.2, "k_flux_f32": 294.5,
+                                       "k_reconstruct_f64": 1811.3, "k_flux_f64": 555.0}}
 
 
 KERNEL_SOURCES = ("kernels_common.h", "k_recon.inl", "k_recon_ho.inl", "k_stage.inl", "k_recon_f32.hip",
