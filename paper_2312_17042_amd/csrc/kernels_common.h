@@ -335,8 +335,9 @@ struct ReconPtrs {
 // basis values) and its LDS copy: lane 0 of the block writes it from the
 // kernel arguments; the caller synchronises the block before use.  In LDS
 // the FP32 constants cost no scalar registers in the epilogue, where they
-// would not fit beside the kernel's other scalars (the FP64 kernels read
-// them from the arguments: as vector registers they would cost a wave).
+// would not fit beside the kernel's other scalars (FP64 and characteristic
+// variables read them from the arguments: as vector registers they would
+// cost a wave).
 template <int K>
 constexpr int recon_tab_size() { return K * K + 6 * K; }
 template <typename real, int K>
@@ -359,7 +360,7 @@ __device__ __forceinline__ void recon_tab_fill(const ReconArgs<real, K> a, real 
 // in place: c1[K][NV] holds the p_1 coefficients on entry and the final
 // polynomial's on exit, cd[3][2][NV] the degree-1 directional ones; forced
 // (DMODE 2) points at the fields' forced selection bytes
-template <typename real, int K, int NV, int SCHEME, int GFORM, int DMODE, typename CD>
+template <typename real, int K, int NV, int SCHEME, int GFORM, int DMODE, bool LT, typename CD>
 __device__ __forceinline__ void finish_fields(const ReconArgs<real, K> a, const real *tab, real (&c1)[K][NV],
                                               const CD cd, int fl, int adm, int st, real lams, real lratio,
                                               const uint8_t *forced, int (&bits)[NV]) {
@@ -385,14 +386,13 @@ __device__ __forceinline__ void finish_fields(const ReconArgs<real, K> a, const 
             for (int v = 0; v < NV; ++v) rowp[v] = 0;
 #pragma unroll
             for (int q = SYM ? p : 0; q < K; ++q) {
-                const real g = std::is_same<real, float>::value ? tab[p * K + q] : a.gram[p][q];
+                const real g = LT ? tab[p * K + q] : a.gram[p][q];
 #pragma unroll
                 for (int v = 0; v < NV; ++v) rowp[v] += g * c1[q][v];
             }
 #pragma unroll
             for (int v = 0; v < NV; ++v) si[v][0] += c1[p][v] * rowp[v];
         }
-        constexpr bool LT = std::is_same<real, float>::value;
         const real g00 = LT ? tab[0] : a.gram[0][0], g01 = LT ? tab[1] : a.gram[0][1];
         const real g10 = LT ? tab[K] : a.gram[1][0], g11 = LT ? tab[K + 1] : a.gram[1][1];
 #pragma unroll
@@ -498,6 +498,10 @@ __device__ __forceinline__ void recon_body(const ReconArgs<real, (R + 1) * (R + 
     // FP64: the directional coefficients wait in LDS until the epilogue
     // (registers for two waves per SIMD); 256 lanes per block
     constexpr bool AD_LDS = std::is_same<real, double>::value;
+    // FP32 in conserved variables reads the scheme constants from the block's
+    // LDS table; the others from the arguments (their epilogues would hold
+    // the loaded constants in vector registers and lose a wave per SIMD)
+    constexpr bool LTAB = std::is_same<real, float>::value && VARS == 0;
     double *lad = nullptr;
     if constexpr (AD_LDS) lad = ad_lds<NV>();
 #pragma unroll
@@ -718,11 +722,11 @@ __device__ __forceinline__ void recon_body(const ReconArgs<real, (R + 1) * (R + 
     if constexpr (VARS == 0) {
         int bits[NV];
         if constexpr (AD_LDS)
-            finish_fields<real, K, NV, SCHEME, GFORM, DMODE>(a, ptr.tab, ao, CdLds<NV>{lad}, fl, adm, st, lams,
-                                                             lratio, ptr.delta + i * NV, bits);
+            finish_fields<real, K, NV, SCHEME, GFORM, DMODE, LTAB>(a, ptr.tab, ao, CdLds<NV>{lad}, fl, adm, st,
+                                                                   lams, lratio, ptr.delta + i * NV, bits);
         else
-            finish_fields<real, K, NV, SCHEME, GFORM, DMODE>(a, ptr.tab, ao, CdRegs<real, NV>{ad}, fl, adm, st,
-                                                             lams, lratio, ptr.delta + i * NV, bits);
+            finish_fields<real, K, NV, SCHEME, GFORM, DMODE, LTAB>(a, ptr.tab, ao, CdRegs<real, NV>{ad}, fl, adm,
+                                                                   st, lams, lratio, ptr.delta + i * NV, bits);
 #pragma unroll
         for (int v = 0; v < NV; ++v) dbyte[v] = (uint8_t)bits[v];
         // face Gauss-point values
@@ -735,8 +739,7 @@ __device__ __forceinline__ void recon_body(const ReconArgs<real, (R + 1) * (R + 
                 for (int v = 0; v < NV; ++v) val[v] = 0;
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
-                    const real b = std::is_same<real, float>::value ? ptr.tab[K * K + (f * 2 + q) * K + k]
-                                                                    : a.basis[f][q][k];
+                    const real b = LTAB ? ptr.tab[K * K + (f * 2 + q) * K + k] : a.basis[f][q][k];
 #pragma unroll
                     for (int v = 0; v < NV; ++v) val[v] += b * ao[k][v];
                 }
@@ -792,8 +795,8 @@ __device__ __forceinline__ void recon_body(const ReconArgs<real, (R + 1) * (R + 
                         cd[s2][k][j] = x;
                     }
             int bits[4];
-            finish_fields<real, K, 4, SCHEME, GFORM, DMODE>(a, ptr.tab, c1, CdRegs<real, 4>{cd}, fl, adm, st, lams,
-                                                            lratio, ptr.delta + (i * 3 + f) * 4, bits);
+            finish_fields<real, K, 4, SCHEME, GFORM, DMODE, false>(a, ptr.tab, c1, CdRegs<real, 4>{cd}, fl, adm, st,
+                                                                   lams, lratio, ptr.delta + (i * 3 + f) * 4, bits);
 #pragma unroll
             for (int j = 0; j < 4; ++j) dbyte[f * 4 + j] = (uint8_t)bits[j];
 #pragma unroll
@@ -803,8 +806,7 @@ __device__ __forceinline__ void recon_body(const ReconArgs<real, (R + 1) * (R + 
                 for (int j = 0; j < 4; ++j) w[j] = 0;
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
-                    const real b = std::is_same<real, float>::value ? ptr.tab[K * K + (f * 2 + q) * K + k]
-                                                                    : a.basis[f][q][k];
+                    const real b = a.basis[f][q][k];
 #pragma unroll
                     for (int j = 0; j < 4; ++j) w[j] += b * c1[k][j];
                 }
