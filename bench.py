@@ -469,15 +469,12 @@ def main():
     N = mesh.n_cells
 
     res, split = {}, {}
-    # mixed precision through the fused stage kernels (the default), FP64
-    # through its reconstruction and flux kernels (the fused kernels are
-    # FP32 only), then mixed precision through the separate kernels for
-    # comparison
-    runs = [("mixed", T.MIXED, True, res)]
-    if not args.no_fp64:
-        runs.append(("fp64", T.FP64, False, res))
+    # both precisions through the fused stage kernels (the default), then
+    # through the separate reconstruction and flux kernels for comparison
+    precs = [("mixed", T.MIXED)] + ([] if args.no_fp64 else [("fp64", T.FP64)])
+    runs = [(name, prec, True, res) for name, prec in precs]
     if not args.no_split:
-        runs.append(("mixed", T.MIXED, False, split))
+        runs += [(name, prec, False, split) for name, prec in precs]
     for name, prec, fused, store in runs:
         ctx.set_fused_stage(fused)
         kernels = "fused stage kernels" if fused else "reconstruction + flux kernels"
@@ -570,15 +567,16 @@ def main():
     if "fp64" in res:
         f = res["fp64"]
         a0, a1 = kstats(f)
+        c0, c1 = stage_split_bytes("fp64")
         out["fp64"] = {"value": f["value"], "ms_per_step": 1e3 * f["elapsed"] / args.steps,
                        "graph_replay_value": N * 3 * args.steps / f["graph_elapsed"],
-                       "stage_kernels": "k_reconstruct + k_flux (FP64)",
-                       "reconstruct_ms": a0, "flux_rk_ms": a1,
-                       "reconstruct_GBs": gbs(RECON_BYTES["fp64"], a0),
-                       "reconstruct_frac": gbs(RECON_BYTES["fp64"], a0) / HBM_PEAK_GBS,
+                       "stage_kernels": "k_stage + k_stage_cross (FP64)",
+                       "stage_ms": a0, "cross_ms": a1,
+                       "k_stage_GBs": gbs(c0, a0), "k_stage_frac": gbs(c0, a0) / HBM_PEAK_GBS,
                        "stage_GBs": gbs(STAGE_BYTES["fp64"], a0 + a1),
                        "stage_frac": gbs(STAGE_BYTES["fp64"], a0 + a1) / HBM_PEAK_GBS,
-                       "bytes_per_cell": {"stage": STAGE_BYTES["fp64"], "reconstruct_share": RECON_BYTES["fp64"]}}
+                       "bytes_per_cell": {"stage": STAGE_BYTES["fp64"], "k_stage_share": c0,
+                                          "k_stage_cross_share": c1}}
         out["mixed_over_fp64"] = mx["value"] / f["value"]
     if split:
         out["split_kernels"] = {}

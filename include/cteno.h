@@ -177,15 +177,14 @@ cteno_status cteno_ctx_set_stream(cteno_ctx *ctx, void *stream);
 /* waits for the stream and reports pending device errors */
 cteno_status cteno_ctx_synchronize(cteno_ctx *ctx);
 const char *cteno_last_error(void);
-/* Stage kernels of degree 2 and 3 in mixed precision for RK stages and
-   marches (cteno_rk_stage, cteno_solve; FP64 stages always run the two
-   kernels): on = 1 (default), one fused kernel per stage reconstructs
-   each block of 256 cells into on-chip memory and evaluates the fluxes of
-   the faces inside the block there, and a second kernel finishes the cells
-   with faces to other blocks; on = 0, a reconstruction kernel writes all
-   face values to device memory and a flux kernel reads them back.  Results
-   agree to FP64 rounding (the fused path sums a cell's faces inside its
-   block first).  Synchronises. */
+/* Stage kernels of degree 2 and 3, in either precision, for RK stages and
+   marches (cteno_rk_stage, cteno_solve): on = 1 (default), one fused
+   kernel per stage reconstructs each block of 256 cells into on-chip
+   memory and evaluates the fluxes of the faces inside the block there, and
+   a second kernel finishes the cells with faces to other blocks; on = 0, a
+   reconstruction kernel writes all face values to device memory and a flux
+   kernel reads them back.  A stage's results agree to FP64 rounding (the
+   fused path sums a cell's faces inside its block first).  Synchronises. */
 cteno_status cteno_ctx_set_fused_stage(cteno_ctx *ctx, int32_t on);
 /* Per-kernel timing with HIP events on the context stream (off by default).
    kernel: 0 = reconstruction (the fused stage kernel when it runs), 1 =

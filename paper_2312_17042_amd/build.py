@@ -11,7 +11,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libcteno.so")
-SOURCES = ["k_recon_ho_f64.hip", "k_recon_ho_f32.hip", "k_stage_f32.hip", "k_recon_f64.hip",
+SOURCES = ["k_recon_ho_f64.hip", "k_recon_ho_f32.hip", "k_stage_f64.hip", "k_stage_f32.hip", "k_recon_f64.hip",
            "k_recon_f32.hip", "k_precompute.hip", "k_flux.hip", "mesh_builder.cpp", "runtime.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -52,8 +52,8 @@ static hipError_t flux_t(const DeviceMesh &m, const FluxLaunch &f, hipStream_t s
 
 hipError_t launch_stage(const DeviceMesh &m, bool fp32, const FluxLaunch &f, const int *done, int part,
                         hipStream_t st, unsigned long long *fb_count) {
-    if (!fp32) return hipErrorInvalidValue;      // FP64 stages run the separate kernels
-    return stage_fused<float>(m, f, done, part, st, fb_count);
+    return fp32 ? stage_fused<float>(m, f, done, part, st, fb_count)
+                : stage_fused<double>(m, f, done, part, st, fb_count);
 }
 
 hipError_t launch_flux(const DeviceMesh &m, bool fp32, const FluxLaunch &f, hipStream_t st) {
@@ -194,7 +194,8 @@ __global__ __launch_bounds__(256) void k_reconstruct_batch(const ReconArgs<float
     __syncthreads();
     const int64_t i = (b - t.block0) * blockDim.x + threadIdx.x;
     if (i >= t.N) return;
-    const ReconPtrs<float> ptr{t.U[stage], t.slot, t.flags, t.P, t.FV, nullptr, nullptr, &t.ctrl->fallbacks, ctab};
+    const ReconPtrs<float> ptr{t.U[stage], t.slot, t.flags, t.P, t.FV, nullptr, nullptr, &t.ctrl->fallbacks, ctab,
+                               nullptr};
     float out[3][2][4];
     recon_body<float, R, 4, SCHEME, GFORM, 0, 0>(a, ptr, i, out);
     store_row<float, 3 * 2 * 4>(ptr.FV + i * 3 * 2 * 4, &out[0][0][0]);

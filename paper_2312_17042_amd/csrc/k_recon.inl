@@ -13,13 +13,15 @@ template <typename real, int R, int NV, int SCHEME, int GFORM, int DMODE, int VA
 __global__ __launch_bounds__(256, (std::is_same<real, double>::value && VARS == 0 && DMODE != 2) ? 2 : 1)
 void k_reconstruct(const ReconArgs<real, (R + 1) * (R + 2) / 2 - 1> a) {
     constexpr int K = (R + 1) * (R + 2) / 2 - 1;
-    __shared__ real tab[recon_tab_size<K>()];
+    constexpr bool F64 = std::is_same<real, double>::value;
+    __shared__ real tab[F64 ? 1 : recon_tab_size<K>()];
+    __shared__ double lad[F64 ? 3 * 2 * NV * 256 : 1];   // FP64: directional coefficients
     recon_tab_fill<real, K>(a, tab);
     __syncthreads();
     const int64_t i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= a.N) return;
     if (a.done && *a.done) return;
-    const ReconPtrs<real> ptr{a.U, a.slot, a.flags, a.P, a.FV, a.delta, a.fr, a.fb_count, tab};
+    const ReconPtrs<real> ptr{a.U, a.slot, a.flags, a.P, a.FV, a.delta, a.fr, a.fb_count, tab, lad};
     real out[3][2][NV];
     recon_body<real, R, NV, SCHEME, GFORM, DMODE, VARS>(a, ptr, i, out);
     store_row<real, 3 * 2 * NV>(ptr.FV + i * 3 * 2 * NV, &out[0][0][0]);

@@ -1,5 +1,5 @@
-// Fused SSP-RK3 stage of degree 2 and 3 (FP32 reconstruction and fluxes,
-// instantiated by k_stage_f32.hip).
+// Fused SSP-RK3 stage of degree 2 and 3 for one arithmetic type;
+// instantiated per type by k_stage_f32.hip and k_stage_f64.hip.
 //
 // k_stage (part 0), one lane per cell, 256-cell blocks: the reconstruction of
 // the block's cells (sec. 2.1-2.6) goes to LDS; after a block barrier each
@@ -17,14 +17,20 @@
 
 namespace cteno {
 
+// FP64 in conserved variables is held to two waves per SIMD, like its
+// reconstruction kernel
 template <typename real, int R, int NV, int SCHEME, int GFORM, int VARS, int PHYS>
-__global__ __launch_bounds__(256) void k_stage(const ReconArgs<real, (R + 1) * (R + 2) / 2 - 1> ra,
-                                               const FluxArgs<real> fa) {
+__global__ __launch_bounds__(256, (std::is_same<real, double>::value && VARS == 0) ? 2 : 1)
+void k_stage(const ReconArgs<real, (R + 1) * (R + 2) / 2 - 1> ra, const FluxArgs<real> fa) {
     constexpr int NQ = 2, ROW = 3 * NQ * NV;
-    __shared__ __align__(16) real lfv[256 * ROW];       // the block's face-point values
+    constexpr bool F64 = std::is_same<real, double>::value;
+    // the block's face-point values; in FP64 the same space first holds the
+    // reconstruction's directional coefficients ([3][2][NV] x 256 doubles)
+    __shared__ __align__(16) real lfv[256 * ROW];
     __shared__ __align__(16) double lterm[256 * 3 * NV]; // owners' terms of the faces inside the block
     constexpr int K = (R + 1) * (R + 2) / 2 - 1;
-    __shared__ real tab[recon_tab_size<K>()];
+    __shared__ real tab[F64 ? 1 : recon_tab_size<K>()];
+    static_assert(!F64 || ROW == 3 * 2 * NV, "the face-value rows hold the directional coefficients");
     recon_tab_fill<real, K>(ra, tab);
     __syncthreads();
     const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
@@ -38,8 +44,12 @@ __global__ __launch_bounds__(256) void k_stage(const ReconArgs<real, (R + 1) * (
     uint32_t code[3];
     double u0[NV], us[NV], ar = 1.0;
     if (live) {
-        const ReconPtrs<real> rp{ra.U, ra.slot, ra.flags, ra.P, nullptr, nullptr, ra.fr, ra.fb_count, tab};
+        const ReconPtrs<real> rp{ra.U, ra.slot, ra.flags, ra.P, nullptr, nullptr, ra.fr, ra.fb_count, tab,
+                                 F64 ? reinterpret_cast<double *>(lfv) : nullptr};
         recon_body<real, R, NV, SCHEME, GFORM, 0, VARS>(ra, rp, i, own);
+    }
+    if constexpr (F64) __syncthreads();     // every lane is done with the coefficients in lfv
+    if (live) {
         store_row<real, ROW>(lfv + threadIdx.x * ROW, &own[0][0][0]);
         // the flux phase's operands, requested before the barrier
 #pragma unroll

@@ -117,7 +117,7 @@ struct FluxLaunch {
 };
 hipError_t launch_flux(const DeviceMesh &m, bool fp32, const FluxLaunch &f, hipStream_t st);
 
-// Fused SSP-RK3 stage of degree <= 3 in mixed precision (f.mode 2): part 0 reconstructs each
+// Fused SSP-RK3 stage of degree <= 3 (f.mode 2): part 0 reconstructs each
 // 256-cell block into LDS, evaluates the faces inside the block and updates
 // the cells whose faces all lie inside it; the others store their face
 // values and partial sums (f.racc), and part 1 finishes them with the faces
@@ -126,7 +126,7 @@ hipError_t launch_stage(const DeviceMesh &m, bool fp32, const FluxLaunch &f, con
                         hipStream_t st, unsigned long long *fb_count);
 template <typename real>
 hipError_t stage_fused(const DeviceMesh &m, const FluxLaunch &f, const int *done, int part, hipStream_t st,
-                       unsigned long long *fb_count);     // instantiated for float (k_stage_f32.hip)
+                       unsigned long long *fb_count);     // k_stage_f32.hip, k_stage_f64.hip
 
 // per-block minima of the CFL bound of state U into dt_part[blocks()], from the
 // face records of the stage kernels' precision (fp32) so a march's first step

@@ -329,6 +329,7 @@ struct ReconPtrs {
     const real *fr;         // face records (characteristic variables only)
     unsigned long long *fb; // cells that took the positivity fallback (may be null)
     const real *tab;        // the block's LDS copy of the Gram matrix [K][K] and face basis [3][2][K]
+    double *lad;            // FP64: the block's LDS space for directional coefficients, [3][2][NV] x 256
 };
 
 // Entries of the reconstruction's constant table (Gram matrix, then face
@@ -449,7 +450,8 @@ __device__ __forceinline__ void finish_fields(const ReconArgs<real, K> a, const 
 }
 
 // the degree-1 directional coefficients cd(q, c, v) of a cell: in registers,
-// or parked in LDS (FP64 reconstruction, 256 lanes per block)
+// or parked in LDS (FP64 reconstruction: the kernel provides [3][2][NV] x
+// 256 doubles of block-shared space, one column per lane)
 template <typename real, int NV>
 struct CdRegs {
     const real (&a)[3][2][NV];
@@ -462,14 +464,6 @@ struct CdLds {
         return p[((q * 2 + c) * NV + v) * 256 + threadIdx.x];
     }
 };
-
-// block-shared parking space of the FP64 reconstruction's directional
-// coefficients, [3][2][NV] x 256 lanes
-template <int NV>
-__device__ __forceinline__ double *ad_lds() {
-    __shared__ double lad[3 * 2 * NV * 256];
-    return lad;
-}
 
 // Reconstruction of cell i: its face Gauss-point values in out (and its
 // selection bytes, DMODE 1); the caller stores them
@@ -502,8 +496,7 @@ __device__ __forceinline__ void recon_body(const ReconArgs<real, (R + 1) * (R + 
     // LDS table; the others from the arguments (their epilogues would hold
     // the loaded constants in vector registers and lose a wave per SIMD)
     constexpr bool LTAB = std::is_same<real, float>::value && VARS == 0;
-    double *lad = nullptr;
-    if constexpr (AD_LDS) lad = ad_lds<NV>();
+    double *const lad = ptr.lad;
 #pragma unroll
     for (int k = 0; k < K; ++k)
 #pragma unroll

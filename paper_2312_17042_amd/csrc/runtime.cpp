@@ -812,10 +812,9 @@ extern "C" cteno_status cteno_residual(cteno_ctx *ctx, const cteno_mesh *m, cons
 }
 
 namespace {
-// The fused stage runs in mixed precision: in FP64 the reconstruction holds
-// one wave per SIMD, too few to hide the flux phase behind the block barrier
-// (measured slower than the two kernels), so FP64 keeps the separate kernels.
-bool use_fused(const cteno_ctx *ctx, const DeviceMesh &dm, bool f32) { return f32 && dm.fused && ctx->fused_stage; }
+// the fused stage kernels (degree <= 3, both precisions) unless the context
+// asks for the separate reconstruction and flux kernels
+bool use_fused(const cteno_ctx *ctx, const DeviceMesh &dm, bool) { return dm.fused && ctx->fused_stage; }
 
 // one SSP-RK3 stage on sol; dt from a device pointer or a host value
 hipError_t issue_stage(cteno_ctx *ctx, cteno_sol *s, bool f32, int stage, const double *dt_ptr, double dt_value,
