@@ -47,16 +47,17 @@ CELL_UPDATE_BYTES = 32 + 32 + 8
 # HBM bytes per cell and launch measured with the FETCH_SIZE / WRITE_SIZE
 # counters (scaled by the copy-kernel calibration), valid only for the
 # kernel sources they were taken on
-MEASURED_TRAFFIC = {"kernels_sha256_prefix": "2a36b487e721139a",
+MEASURED_TRAFFIC = {"kernels_sha256_prefix": "b803a74be9eee6dd",
                     "source": "profiles/stage_vortex8M_hbm_counters.md",
-                    "bytes_per_cell": {"k_stage": 997.5, "k_stage_cross": 170.0,
-                                       "k_reconstruct_f32": 968.2, "k_flux_f32": 294.5,
-                                       "k_reconstruct_f64": 1811.3, "k_flux_f64": 555.0}}
+                    "bytes_per_cell": {"k_stage_f32": 997.5, "k_stage_cross_f32": 170.0,
+                                       "k_stage_f64": 1814.9, "k_stage_cross_f64": 211.4,
+                                       "k_reconstruct_f32": 968.2, "k_flux_f32": 291.5,
+                                       "k_reconstruct_f64": 1811.3, "k_flux_f64": 554.9}}
 
 
 KERNEL_SOURCES = ("kernels_common.h", "k_recon.inl", "k_recon_ho.inl", "k_stage.inl", "k_recon_f32.hip",
                   "k_recon_f64.hip", "k_recon_ho_f32.hip", "k_recon_ho_f64.hip", "k_stage_f32.hip",
-                  "k_precompute.hip", "k_flux.hip")
+                  "k_stage_f64.hip", "k_precompute.hip", "k_flux.hip")
 
 
 def kernels_hash():
@@ -528,7 +529,7 @@ def main():
     stage_gbs = gbs(STAGE_BYTES["mixed"], t0 + t1)
     fresh = kernels_hash() == MEASURED_TRAFFIC["kernels_sha256_prefix"]
     measured = MEASURED_TRAFFIC["bytes_per_cell"] if fresh else None
-    traffic = measured["k_stage"] * N if fresh else None
+    traffic = measured["k_stage_f32"] * N if fresh else None
     out = {
         "metric": "cell-stage updates/s (mixed FP32 vs FP64) at stated error; serving p50/p99",
         "value": mx["value"],
