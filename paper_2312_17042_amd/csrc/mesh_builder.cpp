@@ -228,19 +228,29 @@ struct Builder {
         return true;
     }
 
+    // per-thread work space of the stencil search, reused from cell to cell
+    // (per-cell heap allocations would serialise the threads on the allocator)
+    struct StencilScratch {
+        std::vector<int32_t> stamp, S_, layer, next;
+        std::vector<std::pair<double, int>> rest, cand;
+        std::vector<int> sector;
+    };
+
     bool stencils() {
         cen.assign((size_t)N * M, -1);
         dir.assign((size_t)N * 3 * Md, -1);
         dirn.assign((size_t)N * 3, 0);
         int nt = nthreads_for(N);
-        std::vector<std::vector<int32_t>> stamps(nt);
+        std::vector<StencilScratch> scratch(nt);
         std::atomic<int64_t> bad{-1};
         parallel_for(N, [&](int64_t ii, int tid) {
             int i = (int)ii;
-            auto &st = stamps[tid];
+            StencilScratch &w = scratch[tid];
+            auto &st = w.stamp;
             if (st.empty()) st.assign(N, -1);
-            std::vector<int32_t> S_, layer{i}, next;
-            S_.reserve(M);
+            auto &S_ = w.S_, &layer = w.layer, &next = w.next;
+            S_.clear();
+            layer.assign(1, i);
             st[i] = i;
             while ((int)S_.size() < M) {
                 next.clear();
@@ -260,7 +270,8 @@ struct Builder {
                     layer = next;
                 } else {
                     int need = M - (int)S_.size();
-                    std::vector<std::pair<double, int>> rest;
+                    auto &rest = w.rest;
+                    rest.clear();
                     for (int j : next) {
                         bool isf = false;
                         for (int f = 0; f < 3; ++f) isf |= (fnb[3 * (size_t)i + f] == j);
@@ -278,7 +289,8 @@ struct Builder {
             std::copy(S_.begin(), S_.end(), cen.begin() + (size_t)i * M);
             // sectors
             const int32_t *t = tri.data() + 3 * (size_t)i;
-            std::vector<int> sector(M, -1);
+            auto &sector = w.sector;
+            sector.assign(M, -1);
             for (int a = 0; a < M; ++a) {
                 int j = S_[a], s = -1;
                 for (int f = 0; f < 3; ++f) if (fnb[3 * (size_t)i + f] == j) s = f;
@@ -299,7 +311,8 @@ struct Builder {
             for (int f = 0; f < 3; ++f) {
                 int nbf = fnb[3 * (size_t)i + f];
                 if (nbf < 0) continue;
-                std::vector<std::pair<double, int>> cand;
+                auto &cand = w.cand;
+                cand.clear();
                 for (int a = 0; a < M; ++a) {
                     if (sector[a] != f || S_[a] == nbf) continue;
                     int sx, sy; double dx, dy;
@@ -399,9 +412,11 @@ cteno_status build_host_mesh(const cteno_mesh_desc &d, const cteno_scheme &s, Ho
     hm.iperm.resize(N);
     for (int k = 0; k < N; ++k) hm.iperm[hm.perm[k]] = k;
 
-    hm.cen_user = b.cen;
-    hm.dir_user = b.dir;
-    hm.dirn_user = b.dirn;
+    // the stencils in caller order move to the host mesh (the slot layout
+    // below reads them there)
+    hm.cen_user = std::move(b.cen);
+    hm.dir_user = std::move(b.dir);
+    hm.dirn_user = std::move(b.dirn);
 
     const int64_t Np = pad64(N);
     const int SP = round_up(S, 4);
@@ -458,13 +473,15 @@ cteno_status build_host_mesh(const cteno_mesh_desc &d, const cteno_scheme &s, Ho
         }
         hm.area[k] = b.area[u];
         // slots: sector groups first, then the remaining central cells, then pads
-        const int32_t *cen = b.cen.data() + (size_t)u * M;
+        const int32_t *cen = hm.cen_user.data() + (size_t)u * M;
         const int Md = b.Md;
-        const int32_t *dr = b.dir.data() + (size_t)u * 3 * Md;
-        const int32_t *dn = b.dirn.data() + (size_t)u * 3;
-        std::vector<int> used(M, 0);
-        std::vector<int32_t> sl(S, -1);
-        std::vector<uint8_t> fl(S, 0);
+        const int32_t *dr = hm.dir_user.data() + (size_t)u * 3 * Md;
+        const int32_t *dn = hm.dirn_user.data() + (size_t)u * 3;
+        static_assert(2 * ((kMaxR + 1) * (kMaxR + 2) / 2 - 1) <= 64, "central stencils fit 64 slots");
+        int used[64] = {0};
+        int32_t sl[64];
+        uint8_t fl[64] = {0};
+        std::fill(sl, sl + S, -1);
         uint8_t adm = 0;
         for (int f = 0; f < 3; ++f) {
             if (dn[f] > 0) {
