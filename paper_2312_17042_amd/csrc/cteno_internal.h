@@ -29,9 +29,18 @@ inline int dims_M(int r) { return 2 * dims_K(r); }
 inline int dims_rd(int r) { return r <= 3 ? 1 : (r + 1) / 2; }
 inline int dims_Kd(int r) { return dims_K(dims_rd(r)); }
 inline int dims_Md(int r) { return 2 * dims_Kd(r); }
-// slots: the three directional groups of M_d slots first, then the rest of
-// the central stencil
-inline int dims_S(int r) { return dims_M(r) > 3 * dims_Md(r) ? dims_M(r) : 3 * dims_Md(r); }
+// Slots of a cell's stream.  Up to cubic (and at degree 6, where
+// 3 M_d = M): the three directional groups of M_d slots first (a group's
+// members, then other central cells or pads), then the rest of the central
+// stencil.  At degrees 4 and 5 (M < 3 M_d; the directional stencils, subsets
+// of the central one, hold at most M cells together): exactly the M central
+// cells, the members of the three directional stencils first, one stencil
+// after the other, then the central cells of no directional stencil.
+inline bool ho_var_groups(int r) { return r >= 4 && dims_M(r) < 3 * dims_Md(r); }
+inline int dims_S(int r) {
+    if (ho_var_groups(r)) return dims_M(r);
+    return dims_M(r) > 3 * dims_Md(r) ? dims_M(r) : 3 * dims_Md(r);
+}
 inline int dims_Nq(int r) { return (r + 2) / 2; }
 // r >= 4: every slot carries K central and K_d directional entries, padded
 // to a multiple of 4 so each slot is a whole number of 16-byte vectors
@@ -74,6 +83,11 @@ constexpr uint32_t kNbOwner = 0x40000000u;
 constexpr uint32_t kNbIndexMask = 0x0FFFFFFFu;
 // boundary faces: kind in bits 0-1; an inflow face's row in the inflow table in bits 2-29
 constexpr uint32_t kNbInflowMask = 0x0FFFFFFFu;
+// slot entries at degree >= 4: bits 0..27 the cell (internal index), bits
+// 28..29 the directional stencil (face 0..2) that holds it, 3 for none
+constexpr uint32_t kSlotIndexMask = 0x0FFFFFFFu;
+constexpr int kSlotGroupShift = 28;
+constexpr uint32_t kSlotNoGroup = 3u;
 
 // ---------------------------------------------------------------------------
 // host mesh builder output (all in internal order unless noted)

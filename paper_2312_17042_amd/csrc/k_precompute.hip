@@ -299,9 +299,11 @@ hipError_t launch_precompute(const DeviceMesh &m, const PrecomputeInputs &in, hi
 // ===========================================================================
 // orders 5 to 7 (r = 4..6)
 // ===========================================================================
-// The pseudo-inverse stream of a cell has S = 3 M_d slots (the three
-// directional groups cover the whole central stencil) of EPS entries: K
-// central, K_d directional, zero padding to a multiple of 4.  It is
+// The pseudo-inverse stream of a cell has S slots of EPS entries: K central,
+// K_d directional (those of the directional stencil that holds the slot's
+// cell; zero for a cell of none), zero padding to a multiple of 4.  At
+// degrees 4 and 5 the slots are exactly the M central cells; at degree 6
+// (M = 3 M_d) three groups of M_d slots, each group's members first.  It is
 // vector-tiled with tiles of CT = 64 / nv cells: the reconstruction runs one
 // lane per (cell, variable), so a wave covers CT cells and its lanes of one
 // cell read the same 16-byte vector.
@@ -339,7 +341,7 @@ struct PreHoArgs {
 template <int R>
 __global__ __launch_bounds__(256) void k_precompute_ho(const PreHoArgs<R> a) {
     using D = HoDims<R>;
-    constexpr int K = D::K, KD = D::KD, MD = D::MD, S = D::S, SP = D::SP, EPS = D::EPS, E = D::E;
+    constexpr int K = D::K, KD = D::KD, S = D::S, SP = D::SP, EPS = D::EPS, E = D::E;
     __shared__ double sA[4][K][64];       // central system, column-major, row = lane
     __shared__ double sD[4][KD][64];      // directional systems (disjoint rows)
     __shared__ double sH[4][3][K];        // central v0, beta, diag(R)
@@ -366,10 +368,14 @@ __global__ __launch_bounds__(256) void k_precompute_ho(const PreHoArgs<R> a) {
     double row[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) row[k] = 0.0;
+    // the slot's directional stencil (3: none); each stencil's rows are contiguous
+    int gl = (int)kSlotNoGroup;
     if (lane < S) {
         fl = a.slot_flag[tix(i, lane, S)];
+        const uint32_t se = (uint32_t)a.slot[avix(i, lane, SP, 4)];
+        gl = (int)(se >> kSlotGroupShift);
         if (fl & 1) {
-            const int64_t m = a.slot[avix(i, lane, SP, 4)];
+            const int64_t m = se & kSlotIndexMask;
             const double sx = a.slot_shift[tix(i, 2 * lane, 2 * S)] * a.Lx;
             const double sy = a.slot_shift[tix(i, 2 * lane + 1, 2 * S)] * a.Ly;
             double X[3], Y[3];
@@ -453,13 +459,20 @@ __global__ __launch_bounds__(256) void k_precompute_ho(const PreHoArgs<R> a) {
         if (lane < K) put(m * EPS + lane, rank_ok ? xo : 0.0);
     }
 
-    // directional systems: group s owns rows [s M_d, (s+1) M_d); its members
-    // come first, in directional-list order
+    // directional systems: stencil s owns the contiguous rows [base, base +
+    // n) of the slots that name it, in directional-list order (the other
+    // rows' directional entries stay zero from the stream's clearing)
     uint8_t flg = a.flags[i];
 #pragma unroll 1
     for (int s = 0; s < 3; ++s) {
-        const int base = s * MD;
-        const bool in = lane >= base && lane < base + MD;
+        const unsigned long long mk = __ballot(gl == s);
+        const int nmem = __popcll(mk);
+        if (nmem == 0) {                  // uniform: no stencil on this face
+            flg &= (uint8_t)~(1u << s);
+            continue;
+        }
+        const int base = __ffsll((long long)mk) - 1;
+        const bool in = gl == s;
         double dmax = 0.0;
 #pragma unroll 1
         for (int k = 0; k < KD; ++k) {
@@ -486,7 +499,7 @@ __global__ __launch_bounds__(256) void k_precompute_ho(const PreHoArgs<R> a) {
         for (int k = 0; k < KD; ++k) ok = ok && fabs(sHd[wv][s][2][k]) > 1e-12 * dmax;
         if (!ok) flg &= (uint8_t)~(1u << s);
 #pragma unroll 1
-        for (int t = 0; t < MD; ++t) {
+        for (int t = 0; t < nmem; ++t) {
             const int mrow = base + t;
             double b = lane == mrow ? wd : 0.0;
 #pragma unroll 1

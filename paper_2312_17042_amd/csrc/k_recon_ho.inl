@@ -136,13 +136,29 @@ __device__ __forceinline__ void ho_take(const real (&acc)[GF][VW][4], const real
     ((out[k] = ho_take1<real, VW, GF, e0 + k>(acc, acs, v)), ...);
 }
 
+// whether some lane of a quad holds a directional entry (e in [K, K + K_d))
+// at component c of its vector in round t
+template <int K, int KD, int VW>
+constexpr bool ho_dir_any(int t, int c) {
+    for (int u = 0; u < 4; ++u) {
+        const int e = (4 * t + u) * VW + c;
+        if (e >= K && e < K + KD) return true;
+    }
+    return false;
+}
+
 // a_opt = P_c d and a_s = P_s d for the four variables of a cell held by a
 // quad of lanes.  The lanes split each slot's stream instead of each reading
 // all of it: lane q loads the stream vectors q, q + 4, ... and accumulates
 // their coefficients for all four variables (the differences d come from
-// the variable lanes by DPP moves); at the end of each directional group
-// and of the loop the coefficients go to their variable lanes.  Every
-// coefficient sums its slots in slot order, as a lane per variable would.
+// the variable lanes by DPP moves); the coefficients go to their variable
+// lanes at the end (and, with fixed groups of M_d slots, at the end of each
+// group).  Every coefficient sums its slots in slot order, as a lane per
+// variable would.  With variable groups (degrees 4 and 5), where a slot's
+// directional stencil comes with its index, the positions that hold a
+// directional entry in some lane keep three sums, one per stencil: a
+// directional entry enters the sum of its slot's stencil only, a central
+// entry enters the first sum at every slot.
 // Where the slot ends in a partial round of four scalars (r = 4 and 6: one
 // float4 or two double2 vectors), lane q reads scalar q of it, so no lane
 // multiplies a vector it does not own.
@@ -151,6 +167,7 @@ __device__ __forceinline__ void ho_contract_quad(const ReconHoArgs<real> a, int6
                                                  real (&ao)[HoDims<R>::K], real (&ad)[3][HoDims<R>::KD]) {
     using D = HoDims<R>;
     constexpr int K = D::K, KD = D::KD, MD = D::MD, S = D::S, SP = D::SP, EPS = D::EPS, E = D::E;
+    constexpr bool VARG = D::VARG;
     constexpr int CT = 16;
     using V = typename Vec<real>::T;
     constexpr int VW = Vec<real>::W;
@@ -163,41 +180,53 @@ __device__ __forceinline__ void ho_contract_quad(const ReconHoArgs<real> a, int6
     const real *__restrict__ Pr =
         reinterpret_cast<const real *>(Pv) + ((4 * GF + v / VW) * CT) * VW + v % VW;
     const int32_t *__restrict__ Si = a.slot + (size_t)(i >> 6) * (SP / 4) * 256 + (i & 63) * 4;
-    real acc[GF][VW][4], acs[4];
+    // acc: central sums and (fixed groups) the current group's directional
+    // sums, or (variable groups) those of stencil 0; ag[0], ag[1]: those of
+    // stencils 1 and 2 (variable groups, directional positions only)
+    real acc[GF][VW][4], acs[4], ag[2][GF][VW][4], ags[2][4];
 #pragma unroll
     for (int t = 0; t < GF; ++t)
 #pragma unroll
         for (int c = 0; c < VW; ++c)
 #pragma unroll
-            for (int u = 0; u < 4; ++u) acc[t][c][u] = 0;
+            for (int u = 0; u < 4; ++u) acc[t][c][u] = ag[0][t][c][u] = ag[1][t][c][u] = 0;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) acs[u] = 0;
+    for (int u = 0; u < 4; ++u) acs[u] = ags[0][u] = ags[1][u] = 0;
     // this lane's entries that belong to a directional polynomial
-    bool keep[GF][VW];
+    bool isdir[GF][VW];
 #pragma unroll
     for (int t = 0; t < GF; ++t)
 #pragma unroll
         for (int c = 0; c < VW; ++c) {
             const int e = (4 * t + v) * VW + c;
-            keep[t][c] = !(e >= K && e < K + KD);
+            isdir[t][c] = e >= K && e < K + KD;
         }
     const int es = 4 * GF * VW + v;
-    const bool keeps = !(es >= K && es < K + KD);
+    const bool isdirs = es >= K && es < K + KD;
+    constexpr bool DIRS = SPREAD && 4 * GF * VW + 3 >= K && 4 * GF * VW < K + KD;
     V cur[GF], nxt[GF];
     real cs = 0, ns = 0;
 #pragma unroll
     for (int t = 0; t < GF; ++t) cur[t] = Pv[(4 * t + v) * CT];
     if constexpr (SPREAD) cs = Pr[0];
-    // neighbour averages GD slots ahead (a ring), the next index one more:
-    // four in FP32, where the dependent index -> average -> product chain
-    // bounds the order-7 kernel (-11 %); one in FP64, where the ring's
+    // neighbour averages GD slots ahead (a ring), the next slot entry one
+    // more: four in FP32, where the dependent index -> average -> product
+    // chain bounds the order-7 kernel (-11 %); one in FP64, where the ring's
     // registers would cost a wave per SIMD
     constexpr int GD = sizeof(real) == 4 ? 4 : 1;
-    auto slot_index = [&](int j) { const int jc = j < S ? j : S - 1; return Si[(jc >> 2) * 256 + (jc & 3)]; };
+    auto slot_entry = [&](int j) {
+        const int jc = j < S ? j : S - 1;
+        return (uint32_t)Si[(jc >> 2) * 256 + (jc & 3)];
+    };
     double ring[GD];
+    int gring[GD];                        // the slots' directional stencils
 #pragma unroll
-    for (int k = 0; k < GD; ++k) ring[k] = a.U[(int64_t)slot_index(k) * 4 + v];
-    int mnext = slot_index(GD);
+    for (int k = 0; k < GD; ++k) {
+        const uint32_t se = slot_entry(k);
+        ring[k] = a.U[(int64_t)(se & kSlotIndexMask) * 4 + v];
+        gring[k] = (int)(se >> kSlotGroupShift);
+    }
+    uint32_t snext = slot_entry(GD);
 #pragma unroll 1
     for (int j = 0; j < S; ++j) {
         const int jn = j + 1 < S ? j + 1 : j;
@@ -205,23 +234,49 @@ __device__ __forceinline__ void ho_contract_quad(const ReconHoArgs<real> a, int6
         for (int t = 0; t < GF; ++t) nxt[t] = Pv[(jn * SV + 4 * t + v) * CT];
         if constexpr (SPREAD) ns = Pr[(size_t)jn * SV * CT * VW];
         const double ucur = ring[0];
+        const int g = gring[0];
 #pragma unroll
-        for (int k = 0; k < GD - 1; ++k) ring[k] = ring[k + 1];
-        ring[GD - 1] = a.U[(int64_t)mnext * 4 + v];
-        mnext = slot_index(j + GD + 1);
+        for (int k = 0; k < GD - 1; ++k) { ring[k] = ring[k + 1]; gring[k] = gring[k + 1]; }
+        ring[GD - 1] = a.U[(int64_t)(snext & kSlotIndexMask) * 4 + v];
+        gring[GD - 1] = (int)(snext >> kSlotGroupShift);
+        snext = slot_entry(j + GD + 1);
         const real dv = (real)(ucur - U0);
         const real d[4] = {quad_bcast<0>(dv), quad_bcast<1>(dv), quad_bcast<2>(dv), quad_bcast<3>(dv)};
 #pragma unroll
         for (int t = 0; t < GF; ++t)
 #pragma unroll
-            for (int c = 0; c < VW; ++c)
+            for (int c = 0; c < VW; ++c) {
+                const real p = comp(cur[t], c);
+                if (VARG && ho_dir_any<K, KD, VW>(t, c)) {
+                    const real p0 = (isdir[t][c] && g != 0) ? (real)0 : p;
+                    const real p1 = g == 1 ? p : (real)0, p2 = g == 2 ? p : (real)0;
 #pragma unroll
-                for (int u = 0; u < 4; ++u) acc[t][c][u] += comp(cur[t], c) * d[u];
+                    for (int u = 0; u < 4; ++u) {
+                        acc[t][c][u] += p0 * d[u];
+                        ag[0][t][c][u] += p1 * d[u];
+                        ag[1][t][c][u] += p2 * d[u];
+                    }
+                } else {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) acc[t][c][u] += p * d[u];
+                }
+            }
         if constexpr (SPREAD) {
+            if constexpr (VARG && DIRS) {
+                const real p0 = (isdirs && g != 0) ? (real)0 : cs;
+                const real p1 = g == 1 ? cs : (real)0, p2 = g == 2 ? cs : (real)0;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) acs[u] += cs * d[u];
+                for (int u = 0; u < 4; ++u) {
+                    acs[u] += p0 * d[u];
+                    ags[0][u] += p1 * d[u];
+                    ags[1][u] += p2 * d[u];
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) acs[u] += cs * d[u];
+            }
         }
-        if (j % MD == MD - 1) {           // uniform: group j / MD is complete
+        if (!VARG && j % MD == MD - 1) {  // uniform: group j / MD is complete
             real x[KD];
             ho_take<real, VW, GF, K, KD>(acc, acs, v, x, std::make_integer_sequence<int, KD>{});
             const int s = j / MD;
@@ -240,13 +295,18 @@ __device__ __forceinline__ void ho_contract_quad(const ReconHoArgs<real> a, int6
 #pragma unroll
                 for (int c = 0; c < VW; ++c)
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) acc[t][c][u] = keep[t][c] ? acc[t][c][u] : (real)0;
+                    for (int u = 0; u < 4; ++u) acc[t][c][u] = isdir[t][c] ? (real)0 : acc[t][c][u];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) acs[u] = keeps ? acs[u] : (real)0;
+            for (int u = 0; u < 4; ++u) acs[u] = isdirs ? (real)0 : acs[u];
         }
 #pragma unroll
         for (int t = 0; t < GF; ++t) cur[t] = nxt[t];
         cs = ns;
+    }
+    if constexpr (VARG) {
+        ho_take<real, VW, GF, K, KD>(acc, acs, v, ad[0], std::make_integer_sequence<int, KD>{});
+        ho_take<real, VW, GF, K, KD>(ag[0], ags[0], v, ad[1], std::make_integer_sequence<int, KD>{});
+        ho_take<real, VW, GF, K, KD>(ag[1], ags[1], v, ad[2], std::make_integer_sequence<int, KD>{});
     }
     ho_take<real, VW, GF, 0, K>(acc, acs, v, ao, std::make_integer_sequence<int, K>{});
 }
@@ -272,8 +332,9 @@ __global__ __launch_bounds__(256) void k_reconstruct_ho(const ReconHoArgs<real> 
         ho_contract_quad<real, R>(a, i, v, U0, ao, ad);
     } else {
     // a_opt = P_c d and a_s = P_s d, slot by slot (one lane per cell); the
-    // next slot's stream vectors and index are requested before the current
-    // slot is used
+    // next slot's stream vectors and entry are requested before the current
+    // slot is used.  Variable groups: a slot's directional entries go to the
+    // sums of the stencil its entry names
     real adt[KD];
 #pragma unroll
     for (int k = 0; k < K; ++k) ao[k] = 0;
@@ -282,32 +343,44 @@ __global__ __launch_bounds__(256) void k_reconstruct_ho(const ReconHoArgs<real> 
     V cur[SV];
 #pragma unroll
     for (int g = 0; g < SV; ++g) cur[g] = Pv[g * CT];
-    int mcur = Si[0];
+    uint32_t scur = (uint32_t)Si[0];
 #pragma unroll 1
     for (int j = 0; j < S; ++j) {
         const int jn = j + 1 < S ? j + 1 : j;
         V nxt[SV];
 #pragma unroll
         for (int g = 0; g < SV; ++g) nxt[g] = Pv[(jn * SV + g) * CT];
-        const int mn = Si[(jn >> 2) * 256 + (jn & 3)];
-        const real d = (real)(a.U[(int64_t)mcur * NV + v] - U0);
+        const uint32_t sn = (uint32_t)Si[(jn >> 2) * 256 + (jn & 3)];
+        const real d = (real)(a.U[(int64_t)(scur & kSlotIndexMask) * NV + v] - U0);
 #pragma unroll
         for (int k = 0; k < K; ++k) ao[k] += comp(cur[k / VW], k % VW) * d;
+        if constexpr (D::VARG) {
+            const int gs = (int)(scur >> kSlotGroupShift);
+            const real d0 = gs == 0 ? d : (real)0, d1 = gs == 1 ? d : (real)0, d2 = gs == 2 ? d : (real)0;
 #pragma unroll
-        for (int k = 0; k < KD; ++k) adt[k] += comp(cur[(K + k) / VW], (K + k) % VW) * d;
-        if (j % MD == MD - 1) {           // uniform: group j / MD is complete
-            const int s = j / MD;
+            for (int k = 0; k < KD; ++k) {
+                const real p = comp(cur[(K + k) / VW], (K + k) % VW);
+                ad[0][k] += p * d0;
+                ad[1][k] += p * d1;
+                ad[2][k] += p * d2;
+            }
+        } else {
 #pragma unroll
-            for (int s2 = 0; s2 < 3; ++s2)
-                if (s2 == s)
+            for (int k = 0; k < KD; ++k) adt[k] += comp(cur[(K + k) / VW], (K + k) % VW) * d;
+            if (j % MD == MD - 1) {       // uniform: group j / MD is complete
+                const int s = j / MD;
 #pragma unroll
-                    for (int k = 0; k < KD; ++k) ad[s2][k] = adt[k];
+                for (int s2 = 0; s2 < 3; ++s2)
+                    if (s2 == s)
 #pragma unroll
-            for (int k = 0; k < KD; ++k) adt[k] = 0;
+                        for (int k = 0; k < KD; ++k) ad[s2][k] = adt[k];
+#pragma unroll
+                for (int k = 0; k < KD; ++k) adt[k] = 0;
+            }
         }
 #pragma unroll
         for (int g = 0; g < SV; ++g) cur[g] = nxt[g];
-        mcur = mn;
+        scur = sn;
     }
     }
 

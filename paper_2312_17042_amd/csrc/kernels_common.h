@@ -881,7 +881,12 @@ struct HoDims {
     static constexpr int RD = (R + 1) / 2;
     static constexpr int KD = (RD + 1) * (RD + 2) / 2 - 1;
     static constexpr int MD = 2 * KD;
-    static constexpr int S = 3 * MD;
+    static constexpr int M = 2 * K;
+    // variable groups (degrees 4 and 5): the slots are the M central cells,
+    // each directional stencil's members contiguous, their stencil in the
+    // slot entry; else three groups of M_d slots
+    static constexpr bool VARG = M < 3 * MD;
+    static constexpr int S = VARG ? M : 3 * MD;
     static constexpr int SP = (S + 3) / 4 * 4;
     static constexpr int EPS = (K + KD + 3) / 4 * 4;
     static constexpr int E = S * EPS;

@@ -420,6 +420,9 @@ cteno_status build_host_mesh(const cteno_mesh_desc &d, const cteno_scheme &s, Ho
 
     const int64_t Np = pad64(N);
     const int SP = round_up(S, 4);
+    // degree >= 4: slot entries carry the slot's directional stencil
+    const bool ho = s.degree >= 4, var_groups = ho_var_groups(s.degree);
+    static_assert(kMaxS <= 64, "slot tables fit 64 entries");
     hm.SP = SP;
     hm.slot.assign((size_t)Np * SP, 0);
     hm.slot_flag.assign((size_t)Np * S, 0);
@@ -457,11 +460,12 @@ cteno_status build_host_mesh(const cteno_mesh_desc &d, const cteno_scheme &s, Ho
     for (int k = 0; k < 3; ++k) hm.bline[k] = d.line[k];
 
     std::atomic<int64_t> nfaces{0}, nbnd{0};
-    std::atomic<int> ninad{0};
+    std::atomic<int> ninad{0}, overfull{0};
     parallel_for(Np, [&](int64_t k, int) {
         if (k >= N) {
             // padding cells: self slots, unit area, boundary faces; never written back
-            for (int j = 0; j < SP; ++j) hm.slot[avix(k, j, SP, 4)] = (int32_t)k;
+            for (int j = 0; j < SP; ++j)
+                hm.slot[avix(k, j, SP, 4)] = (int32_t)(k | (ho ? kSlotNoGroup << kSlotGroupShift : 0u));
             for (int f = 0; f < 3; ++f) put_face(k, f, 1.0, 0.0, 0.0, kNbBoundary | CTENO_TRANSMISSIVE);
             return;
         }
@@ -472,7 +476,9 @@ cteno_status build_host_mesh(const cteno_mesh_desc &d, const cteno_scheme &s, Ho
             hm.verts[tix(k, 2 * v + 1, 6)] = b.Y(t[v]);
         }
         hm.area[k] = b.area[u];
-        // slots: sector groups first, then the remaining central cells, then pads
+        // slots: sector groups first (fixed groups of M_d slots, or at
+        // degrees 4 and 5 one member after the other), then the remaining
+        // central cells, then pads
         const int32_t *cen = hm.cen_user.data() + (size_t)u * M;
         const int Md = b.Md;
         const int32_t *dr = hm.dir_user.data() + (size_t)u * 3 * Md;
@@ -481,14 +487,23 @@ cteno_status build_host_mesh(const cteno_mesh_desc &d, const cteno_scheme &s, Ho
         int used[64] = {0};
         int32_t sl[64];
         uint8_t fl[64] = {0};
+        uint32_t grp[64];   // degree >= 4: the directional stencil of each slot
         std::fill(sl, sl + S, -1);
+        std::fill(grp, grp + 64, kSlotNoGroup);
         uint8_t adm = 0;
+        int nd = 0;         // variable groups: slots taken by directional members
         for (int f = 0; f < 3; ++f) {
             if (dn[f] > 0) {
                 adm |= (uint8_t)(1 << f);
                 for (int a = 0; a < dn[f]; ++a) {
-                    sl[f * Md + a] = dr[f * Md + a];
-                    fl[f * Md + a] = 3;
+                    // (directional stencils are disjoint subsets of the
+                    // central one; a cell that neighbours another across two
+                    // faces could break that on a tiny periodic mesh)
+                    if (var_groups && nd >= S) { overfull++; break; }
+                    const int j = var_groups ? nd++ : f * Md + a;
+                    sl[j] = dr[f * Md + a];
+                    fl[j] = 3;
+                    grp[j] = (uint32_t)f;
                     for (int m = 0; m < M; ++m) if (cen[m] == dr[f * Md + a]) used[m] = 1;
                 }
             } else if (b.fnb[3 * (size_t)u + f] >= 0) {
@@ -505,12 +520,12 @@ cteno_status build_host_mesh(const cteno_mesh_desc &d, const cteno_scheme &s, Ho
         for (int j = 0; j < SP; ++j) {
             const int src = j < S ? sl[j] : -1;
             if (src < 0) {   // pad: the cell itself, zero weight
-                hm.slot[avix(k, j, SP, 4)] = (int32_t)k;
+                hm.slot[avix(k, j, SP, 4)] = (int32_t)(k | (ho ? kSlotNoGroup << kSlotGroupShift : 0u));
                 continue;
             }
             int sx, sy; double dx, dy;
             b.offset(u, src, sx, sy, dx, dy);
-            hm.slot[avix(k, j, SP, 4)] = hm.iperm[src];
+            hm.slot[avix(k, j, SP, 4)] = (int32_t)((uint32_t)hm.iperm[src] | (ho ? grp[j] << kSlotGroupShift : 0u));
             hm.slot_flag[tix(k, j, S)] = fl[j];
             hm.slot_shift[tix(k, 2 * j, 2 * S)] = (int8_t)sx;
             hm.slot_shift[tix(k, 2 * j + 1, 2 * S)] = (int8_t)sy;
@@ -561,6 +576,7 @@ cteno_status build_host_mesh(const cteno_mesh_desc &d, const cteno_scheme &s, Ho
     });
     hm.n_faces = nfaces;
     hm.n_boundary = nbnd;
+    if (overfull) { err = "directional stencils overlap (mesh too small)"; return CTENO_ERR_INVALID; }
     hm.n_inadmissible = ninad;
     return CTENO_OK;
 }

@@ -488,7 +488,10 @@ extern "C" cteno_status cteno_mesh_pinv(cteno_ctx *ctx, const cteno_mesh *m, int
         if (directional)
             std::fill(directional + (size_t)a * 3 * Kd * Md, directional + (size_t)(a + 1) * 3 * Kd * Md, 0.0);
         for (int j = 0; j < S; ++j) {
-            const int src_k = (int)slotd[(size_t)a * dm.SP + j];
+            // degree >= 4: the slot entry also names the slot's directional stencil
+            const uint32_t se = (uint32_t)(int64_t)slotd[(size_t)a * dm.SP + j];
+            const int src_k = hm.r >= 4 ? (int)(se & kSlotIndexMask) : (int)se;
+            const int grp = hm.r >= 4 ? (int)(se >> kSlotGroupShift) : (j < 3 * Md ? j / Md : 3);
             if (src_k == idx[a]) continue;   // padding slot (the cell itself)
             const int src_u = hm.perm[src_k];
             int cpos = -1;
@@ -498,8 +501,8 @@ extern "C" cteno_status cteno_mesh_pinv(cteno_ctx *ctx, const cteno_mesh *m, int
             const int off = hm.r >= 4 ? j * ho_slot_entries(hm.r) : pinv_offset(j, K);
             if (central)
                 for (int k = 0; k < K; ++k) central[((size_t)a * K + k) * M + cpos] = pe[(size_t)a * E + off + k];
-            if (j < 3 * Md && directional) {
-                const int s = j / Md;
+            if (grp < 3 && directional) {
+                const int s = grp;
                 int dpos = -1;
                 for (int q = 0; q < Md; ++q) if (dr[s * Md + q] == src_u) dpos = q;
                 if (dpos >= 0)

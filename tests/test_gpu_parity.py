@@ -69,6 +69,10 @@ CASES = {
                      dict(physics=O.EULER, scheme=O.CTENO, degree=4, lambda1_prime=1e15, positivity=1)),
     "vortex_r5_ctenoz": (lambda: W.vortex_case(20, seed=6),
                          dict(physics=O.EULER, scheme=O.CTENOZ, degree=5, lambda1_prime=1e4)),
+    # degree 5 with one lane per cell: the directional sums follow the
+    # stencil each slot names (degrees 4 and 5 lay out exactly M slots)
+    "advection_r5_cteno": (lambda: W.advection_case(20, seed=1),
+                           dict(physics=O.ADVECTION, scheme=O.CTENO, degree=5, lambda1_prime=1e15)),
     "advection_r6_cteno_lambda": (lambda: W.advection_case(20, seed=1),
                                   dict(physics=O.ADVECTION, scheme=O.CTENO, degree=6, lambda1_prime=1e15,
                                        gamma_form=O.GAMMA_LAMBDA)),
@@ -486,8 +490,8 @@ def test_nonphysical_state_is_reported(ctx):
     assert e.value.status == T.ERR_NONPHYSICAL
 
 
-@pytest.mark.parametrize("which", ["vortex_80k", "sod_1p28M", "vortex_8M", "vortex_2M_r4", "vortex_2M_r6",
-                                   "dmr_715k_r4"])
+@pytest.mark.parametrize("which", ["vortex_80k", "sod_1p28M", "vortex_8M", "vortex_2M_r4", "vortex_2M_r5",
+                                   "vortex_2M_r6", "dmr_715k_r4"])
 def test_full_size_sampled_parity(ctx, which):
     """Full configured sizes, one reconstruction and residual in the launch
     configuration of the time march; the oracle evaluates sampled cells.
