@@ -136,6 +136,22 @@ __device__ __forceinline__ void ho_take(const real (&acc)[GF][VW][4], const real
     ((out[k] = ho_take1<real, VW, GF, e0 + k>(acc, acs, v)), ...);
 }
 
+// an empty asm statement that takes x and gives it back, so that x is
+// computed here (not volatile: a volatile statement would count as a
+// possible store and turn the uniform table loads after it into vector loads)
+template <typename T>
+__device__ __forceinline__ void opaque(T &x) { asm("" : "+v"(x)); }
+__device__ __forceinline__ void opaque(float4 &x) {
+    float a = x.x, b = x.y, c = x.z, d = x.w;
+    opaque(a); opaque(b); opaque(c); opaque(d);
+    x = make_float4(a, b, c, d);
+}
+__device__ __forceinline__ void opaque(double2 &x) {
+    double a = x.x, b = x.y;
+    opaque(a); opaque(b);
+    x = make_double2(a, b);
+}
+
 // whether some lane of a quad holds a directional entry (e in [K, K + K_d))
 // at component c of its vector in round t
 template <int K, int KD, int VW>
@@ -204,76 +220,68 @@ __device__ __forceinline__ void ho_contract_quad(const ReconHoArgs<real> a, int6
     const int es = 4 * GF * VW + v;
     const bool isdirs = es >= K && es < K + KD;
     constexpr bool DIRS = SPREAD && 4 * GF * VW + 3 >= K && 4 * GF * VW < K + KD;
-    V cur[GF], nxt[GF];
-    real cs = 0, ns = 0;
+    // Slot j's stream vectors and neighbour averages are requested when slot
+    // j - 2 has been used and its entry when slot j - 4 has: the loop takes
+    // the slots in pairs with a buffer per slot of the pair, so that no load
+    // is waited for before its slot (a rotating buffer waits at the copy,
+    // and the compiler had turned the earlier rotating version into loads
+    // at the top of each slot, waited for at once).  The scheduling
+    // barriers keep each pair's loads behind the slot that frees the buffer.
+    static_assert(S % 2 == 0, "slots are taken in pairs (or one by one)");
+    auto ld_stream = [&](int j, V (&b)[GF], real &bs) {
+        const int jc = j < S ? j : S - 1;
 #pragma unroll
-    for (int t = 0; t < GF; ++t) cur[t] = Pv[(4 * t + v) * CT];
-    if constexpr (SPREAD) cs = Pr[0];
-    // neighbour averages GD slots ahead (a ring), the next slot entry one
-    // more: four in FP32, where the dependent index -> average -> product
-    // chain bounds the order-7 kernel (-11 %); one in FP64, where the ring's
-    // registers would cost a wave per SIMD
-    constexpr int GD = sizeof(real) == 4 ? 4 : 1;
-    auto slot_entry = [&](int j) {
+        for (int t = 0; t < GF; ++t) b[t] = Pv[(jc * SV + 4 * t + v) * CT];
+        if constexpr (SPREAD) bs = Pr[(size_t)jc * SV * CT * VW];
+    };
+    auto ld_entry = [&](int j) {
         const int jc = j < S ? j : S - 1;
         return (uint32_t)Si[(jc >> 2) * 256 + (jc & 3)];
     };
-    double ring[GD];
-    int gring[GD];                        // the slots' directional stencils
-#pragma unroll
-    for (int k = 0; k < GD; ++k) {
-        const uint32_t se = slot_entry(k);
-        ring[k] = a.U[(int64_t)(se & kSlotIndexMask) * 4 + v];
-        gring[k] = (int)(se >> kSlotGroupShift);
-    }
-    uint32_t snext = slot_entry(GD);
-#pragma unroll 1
-    for (int j = 0; j < S; ++j) {
-        const int jn = j + 1 < S ? j + 1 : j;
-#pragma unroll
-        for (int t = 0; t < GF; ++t) nxt[t] = Pv[(jn * SV + 4 * t + v) * CT];
-        if constexpr (SPREAD) ns = Pr[(size_t)jn * SV * CT * VW];
-        const double ucur = ring[0];
-        const int g = gring[0];
-#pragma unroll
-        for (int k = 0; k < GD - 1; ++k) { ring[k] = ring[k + 1]; gring[k] = gring[k + 1]; }
-        ring[GD - 1] = a.U[(int64_t)(snext & kSlotIndexMask) * 4 + v];
-        gring[GD - 1] = (int)(snext >> kSlotGroupShift);
-        snext = slot_entry(j + GD + 1);
-        const real dv = (real)(ucur - U0);
+    // (the lambdas take copies of the pointers they need: a reference to the
+    // argument struct would cost it its uniformity, and the scheme tables
+    // would move into vector registers)
+    const double *__restrict__ Ug = a.U;
+    auto ld_avg = [Ug, v](uint32_t se) { return Ug[(int64_t)(se & kSlotIndexMask) * 4 + v]; };
+    // one slot: differences of the quad's four variables, products with
+    // this lane's stream vectors (b, bs), group sums (g: the slot's stencil)
+    double uc = U0;                       // the cell's own average, loaded before the loop
+    opaque(uc);                           // (pending at the loop it would cost a full wait per pair)
+    auto slot_step = [&](const V (&b)[GF], real bs, double u, int g, int j) {
+        const real dv = (real)(u - uc);
         const real d[4] = {quad_bcast<0>(dv), quad_bcast<1>(dv), quad_bcast<2>(dv), quad_bcast<3>(dv)};
 #pragma unroll
         for (int t = 0; t < GF; ++t)
 #pragma unroll
             for (int c = 0; c < VW; ++c) {
-                const real p = comp(cur[t], c);
+                const real p = comp(b[t], c);
                 if (VARG && ho_dir_any<K, KD, VW>(t, c)) {
                     const real p0 = (isdir[t][c] && g != 0) ? (real)0 : p;
                     const real p1 = g == 1 ? p : (real)0, p2 = g == 2 ? p : (real)0;
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        acc[t][c][u] += p0 * d[u];
-                        ag[0][t][c][u] += p1 * d[u];
-                        ag[1][t][c][u] += p2 * d[u];
+                    for (int u4 = 0; u4 < 4; ++u4) {
+                        acc[t][c][u4] += p0 * d[u4];
+                        ag[0][t][c][u4] += p1 * d[u4];
+                        ag[1][t][c][u4] += p2 * d[u4];
                     }
                 } else {
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) acc[t][c][u] += p * d[u];
+                    for (int u4 = 0; u4 < 4; ++u4) acc[t][c][u4] += p * d[u4];
                 }
             }
         if constexpr (SPREAD) {
             if constexpr (VARG && DIRS) {
-                const real p0 = (isdirs && g != 0) ? (real)0 : cs;
-                const real p1 = g == 1 ? cs : (real)0, p2 = g == 2 ? cs : (real)0;
+                const real p0 = (isdirs && g != 0) ? (real)0 : bs;
+                const real p1 = g == 1 ? bs : (real)0, p2 = g == 2 ? bs : (real)0;
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    acs[u] += p0 * d[u];
-                    ags[0][u] += p1 * d[u];
-                    ags[1][u] += p2 * d[u];
+                for (int u4 = 0; u4 < 4; ++u4) {
+                    acs[u4] += p0 * d[u4];
+                    ags[0][u4] += p1 * d[u4];
+                    ags[1][u4] += p2 * d[u4];
                 }
             } else {
 #pragma unroll
-                for (int u = 0; u < 4; ++u) acs[u] += cs * d[u];
+                for (int u4 = 0; u4 < 4; ++u4) acs[u4] += bs * d[u4];
             }
         }
         if (!VARG && j % MD == MD - 1) {  // uniform: group j / MD is complete
@@ -295,13 +303,57 @@ __device__ __forceinline__ void ho_contract_quad(const ReconHoArgs<real> a, int6
 #pragma unroll
                 for (int c = 0; c < VW; ++c)
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) acc[t][c][u] = isdir[t][c] ? (real)0 : acc[t][c][u];
+                    for (int u4 = 0; u4 < 4; ++u4) acc[t][c][u4] = isdir[t][c] ? (real)0 : acc[t][c][u4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) acs[u] = isdirs ? (real)0 : acs[u];
+            for (int u4 = 0; u4 < 4; ++u4) acs[u4] = isdirs ? (real)0 : acs[u4];
         }
-#pragma unroll
-        for (int t = 0; t < GF; ++t) cur[t] = nxt[t];
-        cs = ns;
+    };
+    // FP64 at degree 6: one buffer (its second would cost a wave per SIMD)
+    constexpr bool PAIRS = !(sizeof(real) == 8 && R == 6);
+    V bA[GF], bB[GF];
+    real sA = 0, sB = 0;
+    ld_stream(0, bA, sA);
+    uint32_t eA = ld_entry(0), eB = ld_entry(1);
+    double uA = ld_avg(eA), uB = 0;
+    int gA = (int)(eA >> kSlotGroupShift), gB = 0;
+    if constexpr (PAIRS) {
+        ld_stream(1, bB, sB);
+        uB = ld_avg(eB);
+        gB = (int)(eB >> kSlotGroupShift);
+        eA = ld_entry(2);
+        eB = ld_entry(3);
+#pragma unroll 1
+        for (int j = 0; j < S; j += 2) {
+            slot_step(bA, sA, uA, gA, j);
+            __builtin_amdgcn_sched_barrier(0);
+            ld_stream(j + 2, bA, sA);
+            gA = (int)(eA >> kSlotGroupShift);
+            opaque(gA);                   // taken now: eA's register is free for the next entry
+            uA = ld_avg(eA);
+            eA = ld_entry(j + 4);
+            __builtin_amdgcn_sched_barrier(0);
+            slot_step(bB, sB, uB, gB, j + 1);
+            __builtin_amdgcn_sched_barrier(0);
+            ld_stream(j + 3, bB, sB);
+            gB = (int)(eB >> kSlotGroupShift);
+            opaque(gB);
+            uB = ld_avg(eB);
+            eB = ld_entry(j + 5);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    } else {
+        eA = eB;
+#pragma unroll 1
+        for (int j = 0; j < S; ++j) {
+            slot_step(bA, sA, uA, gA, j);
+            __builtin_amdgcn_sched_barrier(0);
+            ld_stream(j + 1, bA, sA);
+            gA = (int)(eA >> kSlotGroupShift);
+            opaque(gA);
+            uA = ld_avg(eA);
+            eA = ld_entry(j + 2);
+            __builtin_amdgcn_sched_barrier(0);
+        }
     }
     if constexpr (VARG) {
         ho_take<real, VW, GF, K, KD>(acc, acs, v, ad[0], std::make_integer_sequence<int, KD>{});
