@@ -47,12 +47,12 @@ CELL_UPDATE_BYTES = 32 + 32 + 8
 # HBM bytes per cell and launch measured with the FETCH_SIZE / WRITE_SIZE
 # counters (scaled by the copy-kernel calibration), valid only for the
 # kernel sources they were taken on
-MEASURED_TRAFFIC = {"kernels_sha256_prefix": "b803a74be9eee6dd",
+MEASURED_TRAFFIC = {"kernels_sha256_prefix": "a76193a47a75e837",
                     "source": "profiles/stage_vortex8M_hbm_counters.md",
-                    "bytes_per_cell": {"k_stage_f32": 997.5, "k_stage_cross_f32": 170.0,
-                                       "k_stage_f64": 1814.9, "k_stage_cross_f64": 211.4,
-                                       "k_reconstruct_f32": 968.2, "k_flux_f32": 291.5,
-                                       "k_reconstruct_f64": 1811.3, "k_flux_f64": 554.9}}
+                    "bytes_per_cell": {"k_stage_f32": 997.8, "k_stage_cross_f32": 170.0,
+                                       "k_stage_f64": 1815.3, "k_stage_cross_f64": 211.4,
+                                       "k_reconstruct_f32": 968.2, "k_flux_f32": 295.5,
+                                       "k_reconstruct_f64": 1811.3, "k_flux_f64": 555.2}}
 
 
 KERNEL_SOURCES = ("kernels_common.h", "k_recon.inl", "k_recon_ho.inl", "k_stage.inl", "k_recon_f32.hip",
