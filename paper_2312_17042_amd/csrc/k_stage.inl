@@ -6,12 +6,13 @@
 // cell evaluates the fluxes (sec. 2.7) of its faces whose neighbour lies in
 // the same block from LDS, and of its boundary faces, and -- when no face
 // leads to another block -- applies its RK stage at once.  A cell with a
-// face to another block stores the values of those faces and its partial
-// sum instead, and k_stage_cross (part 1) adds the faces to other blocks and
-// applies its stage.  Both cells of a face evaluate the same flux from the
-// same values (LDS holds exactly the values the other cell computed), so
-// the update stays conservative to FP64 round-off.  Face values of faces
-// inside a block never leave the chip.
+// face to another block (a cross cell) stores the values of those faces and
+// its stage state from the other faces instead, both by its rank among the
+// cross cells (so part 1 reads them contiguously), and k_stage_cross (part
+// 1) adds the faces to other blocks.  Both cells of a face evaluate the same
+// flux from the same values (LDS holds exactly the values the other cell
+// computed), so the update stays conservative to FP64 round-off.  Face
+// values of faces inside a block never leave the chip.
 #pragma once
 #include "kernels_common.h"
 
@@ -30,6 +31,7 @@ void k_stage(const ReconArgs<real, (R + 1) * (R + 2) / 2 - 1> ra, const FluxArgs
     __shared__ __align__(16) double lterm[256 * 3 * NV]; // owners' terms of the faces inside the block
     constexpr int K = (R + 1) * (R + 2) / 2 - 1;
     __shared__ real tab[F64 ? 1 : recon_tab_size<K>()];
+    __shared__ int wcross[4];                         // cross cells per wave
     static_assert(!F64 || ROW == 3 * 2 * NV, "the face-value rows hold the directional coefficients");
     recon_tab_fill<real, K>(ra, tab);
     __syncthreads();
@@ -84,17 +86,20 @@ void k_stage(const ReconArgs<real, (R + 1) * (R + 2) / 2 - 1> ra, const FluxArgs
             }
         }
     }
+    // a cross cell's rank among the block's cross cells (listed in ascending order)
+    const bool cross = live && (kind[0] == 2 || kind[1] == 2 || kind[2] == 2);
+    const unsigned long long cbal = __ballot(cross);
+    if ((threadIdx.x & 63) == 0) wcross[threadIdx.x >> 6] = __popcll(cbal);
     __syncthreads();
     double dtc = INFINITY;
     if (live) {
         double acc[NV], nrm[3][3];
 #pragma unroll
         for (int v = 0; v < NV; ++v) acc[v] = 0.0;
-        bool deferred = false;
 #pragma unroll
         for (int f = 0; f < 3; ++f) {
             nrm[f][0] = (double)nx[f]; nrm[f][1] = (double)ny[f]; nrm[f][2] = (double)len[f];
-            if (kind[f] == 2) { deferred = true; continue; }
+            if (kind[f] == 2) continue;
             if (kind[f] == 1) {
                 // the owner evaluated F(owner side, this side; owner normal):
                 // this cell's term is its exact negation
@@ -107,16 +112,24 @@ void k_stage(const ReconArgs<real, (R + 1) * (R + 2) / 2 - 1> ra, const FluxArgs
             for (int v = 0; v < NV; ++v) acc[v] += term[f][v];
         }
         if (bad && fa.nonphys) atomicOr(fa.nonphys, 1);
-        if (!deferred) {
+        if (!cross) {
             dtc = rk_apply<real, NV, PHYS>(fa, ptr, i, acc, nrm, u0, us, ar);
         } else {
+            const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+            int before = 0;
+#pragma unroll
+            for (int w = 0; w < 3; ++w) before += w < wv ? wcross[w] : 0;
+            const int64_t t = (int64_t)fa.xbase[blk] + before + __popcll(cbal & ((1ull << lane) - 1));
             // only the values of the faces to other blocks leave the chip
 #pragma unroll
             for (int f = 0; f < 3; ++f)
                 if (kind[f] == 2)
-                    store_row<real, NQ * NV>(const_cast<real *>(fa.FV) + i * ROW + f * NQ * NV, &own[f][0][0]);
+                    store_row<real, NQ * NV>(const_cast<real *>(fa.FV) + t * ROW + f * NQ * NV, &own[f][0][0]);
+            // the stage state from the faces inside the block; part 1 adds
+            // dt times the residual of the others with rk_weight
+            const double dt = ptr.dt_ptr ? *ptr.dt_ptr : fa.dt_value;
 #pragma unroll
-            for (int v = 0; v < NV; ++v) fa.racc[i * NV + v] = acc[v];
+            for (int v = 0; v < NV; ++v) fa.xpart[t * NV + v] = rk_value(fa.stage, u0[v], us[v], dt * (-acc[v] / ar));
         }
     }
     if (fa.dt_part) {
@@ -125,6 +138,8 @@ void k_stage(const ReconArgs<real, (R + 1) * (R + 2) / 2 - 1> ra, const FluxArgs
     }
 }
 
+// part 1: one lane per cross cell, in cross-cell order: the faces to other
+// blocks from both sides' stored values, added to the partial stage state
 template <typename real, int NV, int PHYS>
 __global__ __launch_bounds__(256) void k_stage_cross(const FluxArgs<real> fa) {
     constexpr int NQ = 2, ROW = 3 * NQ * NV;
@@ -133,36 +148,39 @@ __global__ __launch_bounds__(256) void k_stage_cross(const FluxArgs<real> fa) {
     double dtc = INFINITY;
     if (t < fa.n_cross) {
         const int64_t i = fa.xcells[t];
-        const int64_t blk = i >> 8;
         const FluxPtrs<real> ptr{fa.FV, fa.fr, fa.area, fa.Un, fa.Us, fa.Uout, fa.dt_ptr, nullptr, nullptr,
                                  fa.nonphys, fa.dt_part != nullptr};
         double acc[NV];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) acc[v] = fa.racc[i * NV + v];
+        for (int v = 0; v < NV; ++v) acc[v] = 0.0;
         double nrm[3][3];
         bool bad = false;
 #pragma unroll
         for (int f = 0; f < 3; ++f) {
             real nx, ny, len;
             uint32_t code;
-            face_record<real>(fa.fr, i, f, nx, ny, len, code);
+            face_record<real>(fa.xfr, t, f, nx, ny, len, code);
             nrm[f][0] = (double)nx; nrm[f][1] = (double)ny; nrm[f][2] = (double)len;
-            if (code & kNbBoundary) continue;
-            const int64_t j = code & kNbIndexMask;
-            if ((j >> 8) == blk) continue;        // added by part 0
+            const int tn = fa.xnb[t * 3 + f];
+            if (tn < 0) continue;                 // a boundary, or inside the block: in part 0's state
             const bool owner = (code & kNbOwner) != 0;
             const int g = (code >> 28) & 3;
             // both sides' values of this face, as part 0 stored them
             real mine[NQ][NV], oth[NQ][NV];
-            load_row<real, NQ * NV>(fa.FV + i * ROW + f * NQ * NV, &mine[0][0]);
-            load_row<real, NQ * NV>(fa.FV + j * ROW + g * NQ * NV, &oth[0][0]);
+            load_row<real, NQ * NV>(fa.FV + t * ROW + f * NQ * NV, &mine[0][0]);
+            load_row<real, NQ * NV>(fa.FV + (int64_t)tn * ROW + g * NQ * NV, &oth[0][0]);
             double term[NV];
             face_term<real, NV, PHYS, NQ>(fa, mine, oth, owner, false, nx, ny, len, term, bad);
 #pragma unroll
             for (int v = 0; v < NV; ++v) acc[v] += term[v];
         }
         if (bad && fa.nonphys) atomicOr(fa.nonphys, 1);
-        dtc = rk_update<real, NV, PHYS>(fa, ptr, i, acc, nrm);
+        const double dt = ptr.dt_ptr ? *ptr.dt_ptr : fa.dt_value;
+        const double ar = fa.xarea[t], w = rk_weight(fa.stage);
+        double un[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) un[v] = fa.xpart[t * NV + v] + w * (dt * (-acc[v] / ar));
+        dtc = rk_store<real, NV, PHYS>(fa, ptr, i, un, nrm, ar);
     }
     if (fa.dt_part) {
         const double bm = block_min(dtc);
@@ -216,7 +234,9 @@ static hipError_t stage_t(const DeviceMesh &m, const FluxLaunch &f, const int *d
 template <typename real>
 hipError_t stage_fused(const DeviceMesh &m, const FluxLaunch &f, const int *done, int part, hipStream_t st,
                        unsigned long long *fb_count) {
-    if (f.mode != 2 || m.r > 3 || m.tab.Nq != 2 || !f.racc || !f.FV) return hipErrorInvalidValue;
+    if (f.mode != 2 || m.r > 3 || m.tab.Nq != 2 || !f.xpart || !f.FV) return hipErrorInvalidValue;
+    const void *xfr = std::is_same<real, double>::value ? (const void *)m.xfr64 : (const void *)m.xfr32;
+    if (m.n_cross && (!m.xcells || !m.xbase || !m.xnb || !m.xarea || !xfr)) return hipErrorInvalidValue;
     if (part == 1) {
         if (m.n_cross == 0) return hipSuccess;
         FluxArgs<real> fa;

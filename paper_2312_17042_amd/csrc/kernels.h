@@ -61,9 +61,18 @@ struct DeviceMesh {
     float *htab32 = nullptr;       // the same in FP32
     RefTables tab;
     // fused stage (degree <= 3): cells with a face whose neighbour lies in
-    // another 256-cell block, ascending
+    // another 256-cell block ("cross cells"), ascending; per cross cell (in
+    // that order) the cross index of the neighbour across each face, -1
+    // where the face stays in the block or is a boundary, its area and its
+    // face records (tiled like fr32 / fr64); per block the number of cross
+    // cells in the blocks before it
     int32_t *xcells = nullptr;
     int64_t n_cross = 0;
+    int32_t *xbase = nullptr;      // [blocks() + 1]
+    int32_t *xnb = nullptr;        // [n_cross][3]
+    double *xarea = nullptr;       // [n_cross]
+    float *xfr32 = nullptr;        // [pad64(n_cross)][12], VW 4
+    double *xfr64 = nullptr;       // [pad64(n_cross)][12], VW 2
     bool fused = false;            // the march runs the fused stage kernels
     int64_t blocks() const { return (N + 255) / 256; }
     int64_t cross_blocks() const { return (n_cross + 255) / 256; }
@@ -113,15 +122,18 @@ struct FluxLaunch {
     int *nonphys = nullptr;      // non-physical flag when ctrl is null (may be null)
     double *dt_part = nullptr;   // per-block minima of the CFL bound (stage 2 of a march), or null
     double t_base = 0.0;         // time of the stage input when the march time is not on the device
-    double *racc = nullptr;      // fused stage: partial sums [Np][nv] of cells with faces to other blocks
+    // fused stage: [n_cross][nv] stage states of the cross cells from their
+    // faces inside the block (the faces to other blocks still to add)
+    double *xpart = nullptr;
 };
 hipError_t launch_flux(const DeviceMesh &m, bool fp32, const FluxLaunch &f, hipStream_t st);
 
 // Fused SSP-RK3 stage of degree <= 3 (f.mode 2): part 0 reconstructs each
 // 256-cell block into LDS, evaluates the faces inside the block and updates
-// the cells whose faces all lie inside it; the others store their face
-// values and partial sums (f.racc), and part 1 finishes them with the faces
-// to other blocks.  The two parts are launched in order, 0 then 1.
+// the cells whose faces all lie inside it; the others store the values of
+// their faces to other blocks (f.FV, by cross index) and their partial stage
+// states (f.xpart), and part 1 finishes them with the faces to other
+// blocks.  The two parts are launched in order, 0 then 1.
 hipError_t launch_stage(const DeviceMesh &m, bool fp32, const FluxLaunch &f, const int *done, int part,
                         hipStream_t st, unsigned long long *fb_count);
 template <typename real>

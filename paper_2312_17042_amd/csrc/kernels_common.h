@@ -1011,10 +1011,15 @@ struct FluxArgs {
     double t_base;          // time of the stage input when tctrl is null
     const Ctrl *tctrl;      // time march: the stage input's time is tctrl->t, its step *dt_ptr
     // fused stage: cells with a face whose neighbour lies in another
-    // 256-cell block finish in a second kernel from their partial sums
-    double *racc;           // [Np][NV] partial sums of those cells
-    const int32_t *xcells;  // their list, ascending
+    // 256-cell block (cross cells) finish in a second kernel from their
+    // partial stage states; their data in cross-cell order
+    double *xpart;          // [n_cross][NV] stage states from the faces inside the block
+    const int32_t *xcells;  // the cross cells, ascending
     int64_t n_cross;
+    const int32_t *xbase;   // [blocks + 1] cross cells before each block
+    const int32_t *xnb;     // [n_cross][3] the neighbour's cross index across a face to another block, else -1
+    const double *xarea;    // [n_cross]
+    const real *xfr;        // [n_cross] face records, tiled like fr
     int64_t part_off;       // offset of the second kernel's block minima in dt_part
 };
 
@@ -1045,9 +1050,14 @@ inline void fill_flux_args(const DeviceMesh &m, const FluxLaunch &f, FluxArgs<re
     for (int q = 0; q < 4; ++q) a.gq[q] = q < m.tab.Nq ? m.tab.gq[q] : 0.0;
     a.t_base = f.t_base;
     a.tctrl = f.ctrl && f.dt_ptr ? f.ctrl : nullptr;
-    a.racc = f.racc;
+    a.xpart = f.xpart;
     a.xcells = m.xcells;
     a.n_cross = m.n_cross;
+    a.xbase = m.xbase;
+    a.xnb = m.xnb;
+    a.xarea = m.xarea;
+    if constexpr (std::is_same<real, double>::value) a.xfr = m.xfr64;
+    else a.xfr = m.xfr32;
     a.part_off = m.blocks();
 }
 
@@ -1182,6 +1192,30 @@ __device__ __forceinline__ void rk_load(const FluxPtrs<real> ptr, int64_t i, dou
     }
 }
 
+// SSP-RK3 stage value from U^n, the stage input and dt times the residual
+__device__ __forceinline__ double rk_value(int stage, double u0, double us, double dtR) {
+    if (stage == 0) return us + dtR;
+    if (stage == 1) return 0.75 * u0 + 0.25 * (us + dtR);
+    return (1.0 / 3.0) * u0 + (2.0 / 3.0) * (us + dtR);
+}
+// the weight of dt times the residual in rk_value
+__device__ __forceinline__ double rk_weight(int stage) { return stage == 0 ? 1.0 : stage == 1 ? 0.25 : 2.0 / 3.0; }
+
+// writes the new state un of cell i; returns its CFL bound when requested, else +inf
+template <typename real, int NV, int PHYS>
+__device__ __forceinline__ double rk_store(const FluxArgs<real> a, const FluxPtrs<real> ptr, int64_t i,
+                                           const double (&un)[NV], const double (&nrm)[3][3], double ar) {
+    if constexpr (NV == 4) {
+        double2 *O2 = reinterpret_cast<double2 *>(ptr.Uout);
+        O2[2 * i] = make_double2(un[0], un[1]);
+        O2[2 * i + 1] = make_double2(un[2], un[3]);
+    } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) ptr.Uout[i * NV + v] = un[v];
+    }
+    return ptr.want_dt ? cell_dt_bound<NV, PHYS>(un, nrm, ar, a.gamma64, (double)a.ax, (double)a.ay) : INFINITY;
+}
+
 // SSP-RK3 stage of cell i from the sum acc of its outward face fluxes (the
 // residual is -acc / |V_i|) and its loaded operands: writes the new state;
 // returns its CFL bound when requested, else +inf
@@ -1192,23 +1226,8 @@ __device__ __forceinline__ double rk_apply(const FluxArgs<real> a, const FluxPtr
     const double dt = ptr.dt_ptr ? *ptr.dt_ptr : a.dt_value;
     double un[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        const double R = -acc[v] / ar;
-        double r;
-        if (a.stage == 0) r = us[v] + dt * R;
-        else if (a.stage == 1) r = 0.75 * u0[v] + 0.25 * (us[v] + dt * R);
-        else r = (1.0 / 3.0) * u0[v] + (2.0 / 3.0) * (us[v] + dt * R);
-        un[v] = r;
-    }
-    if constexpr (NV == 4) {
-        double2 *O2 = reinterpret_cast<double2 *>(ptr.Uout);
-        O2[2 * i] = make_double2(un[0], un[1]);
-        O2[2 * i + 1] = make_double2(un[2], un[3]);
-    } else {
-#pragma unroll
-        for (int v = 0; v < NV; ++v) ptr.Uout[i * NV + v] = un[v];
-    }
-    return ptr.want_dt ? cell_dt_bound<NV, PHYS>(un, nrm, ar, a.gamma64, (double)a.ax, (double)a.ay) : INFINITY;
+    for (int v = 0; v < NV; ++v) un[v] = rk_value(a.stage, u0[v], us[v], dt * (-acc[v] / ar));
+    return rk_store<real, NV, PHYS>(a, ptr, i, un, nrm, ar);
 }
 
 template <typename real, int NV, int PHYS>

@@ -387,9 +387,47 @@ static cteno_status upload_device_mesh(cteno_ctx *ctx, hipStream_t st, HostMesh 
             }
         dm.n_cross = (int64_t)xc.size();
         if (dm.n_cross) {
+            // in cross-cell order: the neighbour's cross index across each
+            // face to another block, the area and the face records; per
+            // block the number of cross cells before it
+            const int64_t nx = dm.n_cross, nxp = pad64(nx), nb = dm.blocks();
+            std::vector<int32_t> xbase(nb + 1, 0), xidx(hm.N, -1), xnb(3 * nx, -1);
+            std::vector<double> xar(nx), xf64(keep_fr64 ? nxp * 12 : 0);
+            std::vector<float> xf32(dm.fr32 ? nxp * 12 : 0);
+            for (int64_t t = 0; t < nx; ++t) {
+                xbase[(xc[t] >> 8) + 1]++;
+                xidx[xc[t]] = (int32_t)t;
+            }
+            for (int64_t b = 0; b < nb; ++b) xbase[b + 1] += xbase[b];
+            for (int64_t t = 0; t < nx; ++t) {
+                const int64_t k = xc[t];
+                xar[t] = hm.area[k];
+                for (int f = 0; f < 3; ++f) {
+                    uint32_t code;
+                    std::memcpy(&code, &hm.fr32[avix(k, 4 * f + 3, 12, 4)], sizeof code);
+                    const int64_t j = code & kNbIndexMask;
+                    if (!(code & kNbBoundary) && (j >> 8) != (k >> 8)) xnb[3 * t + f] = xidx[j];
+                }
+                for (int e = 0; e < 12; ++e) {
+                    if (!xf32.empty()) xf32[avix(t, e, 12, 4)] = hm.fr32[avix(k, e, 12, 4)];
+                    if (!xf64.empty()) xf64[avix(t, e, 12, 2)] = hm.fr64[avix(k, e, 12, 2)];
+                }
+            }
             dm.xcells = alloc_T(int32_t, xc.size());
-            if (!dm.xcells) return fail(CTENO_ERR_NOMEM, "device allocation failed");
+            dm.xbase = alloc_T(int32_t, xbase.size());
+            dm.xnb = alloc_T(int32_t, xnb.size());
+            dm.xarea = alloc_T(double, xar.size());
+            if (!xf32.empty()) dm.xfr32 = alloc_T(float, xf32.size());
+            if (!xf64.empty()) dm.xfr64 = alloc_T(double, xf64.size());
+            if (!dm.xcells || !dm.xbase || !dm.xnb || !dm.xarea || (!xf32.empty() && !dm.xfr32) ||
+                (!xf64.empty() && !dm.xfr64))
+                return fail(CTENO_ERR_NOMEM, "device allocation failed");
             HIP_TRY(h2d(dm.xcells, xc, st));
+            HIP_TRY(h2d(dm.xbase, xbase, st));
+            HIP_TRY(h2d(dm.xnb, xnb, st));
+            HIP_TRY(h2d(dm.xarea, xar, st));
+            if (!xf32.empty()) HIP_TRY(h2d(dm.xfr32, xf32, st));
+            if (!xf64.empty()) HIP_TRY(h2d(dm.xfr64, xf64, st));
             HIP_TRY(hipStreamSynchronize(st));
         }
     }
@@ -548,7 +586,7 @@ struct cteno_sol {
     DevBuf ctrl;              // Ctrl
     DevBuf dt_part;           // per-block minima of the CFL bound
     DevBuf status;            // SolStatus: fallback count, non-physical flag of stage calls
-    DevBuf racc;              // fused stage: partial sums of cells with faces to other blocks
+    DevBuf xpart;             // fused stage: partial stage states of the cross cells
     double t = 0.0;
     Ctrl *h_ctrl = nullptr;   // pinned host mirror
     hipGraphExec_t graph[2] = {nullptr, nullptr};
@@ -842,7 +880,7 @@ hipError_t issue_stage(cteno_ctx *ctx, cteno_sol *s, bool f32, int stage, const 
     fl.dt_part = dt_part;
     fl.t_base = s->t;
     if (use_fused(ctx, dm, f32)) {
-        fl.racc = s->racc.as<double>();
+        fl.xpart = s->xpart.as<double>();
         hipError_t e = timed(ctx, 0, [&] { return launch_stage(dm, f32, fl, done, 0, st, &ss->fallbacks); });
         if (e != hipSuccess) return e;
         return timed(ctx, 1, [&] { return launch_stage(dm, f32, fl, done, 1, st, &ss->fallbacks); });
@@ -852,13 +890,13 @@ hipError_t issue_stage(cteno_ctx *ctx, cteno_sol *s, bool f32, int stage, const 
     return timed(ctx, 1, [&] { return launch_flux(dm, f32, fl, st); });
 }
 
-// the work buffers a stage needs: face values, and the fused stage's partial sums
+// the work buffers a stage needs: face values, and the fused stage's partial states
 bool stage_buffers(cteno_ctx *ctx, cteno_sol *s, bool f32) {
     if (!s->fv(f32)) return false;
     const DeviceMesh &dm = s->mesh->dm;
-    if (use_fused(ctx, dm, f32) && !s->racc.p) {
-        s->racc = DevBuf(ctx, (size_t)dm.Np * dm.nv * sizeof(double));
-        if (!s->racc.p) return false;
+    if (use_fused(ctx, dm, f32) && !s->xpart.p) {
+        s->xpart = DevBuf(ctx, (size_t)std::max<int64_t>(dm.n_cross, 1) * dm.nv * sizeof(double));
+        if (!s->xpart.p) return false;
     }
     return true;
 }
