@@ -41,18 +41,19 @@ STAGE_BYTES = {"mixed": 950, "fp64": 1712}
 RECON_BYTES = {"mixed": 162 * 4 + 24 * 4 + 18 * 4 + 12 + 32, "fp64": 162 * 8 + 24 * 8 + 18 * 4 + 12 + 32}
 # the flux / residual / RK kernel's share: U^n, state write, area, geometry
 FLUX_BYTES = {k: STAGE_BYTES[k] - RECON_BYTES[k] for k in STAGE_BYTES}
-# a cell's RK update: U^n read, state write, area
-CELL_UPDATE_BYTES = 32 + 32 + 8
+# a cross cell's share of the second fused-stage kernel: its state write
+# (k_stage reads its U^n, stage input and area and stores its partial state)
+CROSS_UPDATE_BYTES = 32
 
 # HBM bytes per cell and launch measured with the FETCH_SIZE / WRITE_SIZE
 # counters (scaled by the copy-kernel calibration), valid only for the
 # kernel sources they were taken on
-MEASURED_TRAFFIC = {"kernels_sha256_prefix": "a76193a47a75e837",
+MEASURED_TRAFFIC = {"kernels_sha256_prefix": "71dca1d49faff704",
                     "source": "profiles/stage_vortex8M_hbm_counters.md",
-                    "bytes_per_cell": {"k_stage_f32": 997.8, "k_stage_cross_f32": 170.0,
-                                       "k_stage_f64": 1815.3, "k_stage_cross_f64": 211.4,
-                                       "k_reconstruct_f32": 968.2, "k_flux_f32": 295.5,
-                                       "k_reconstruct_f64": 1811.3, "k_flux_f64": 555.2}}
+                    "bytes_per_cell": {"k_stage_f32": 994.5, "k_stage_cross_f32": 90.7,
+                                       "k_stage_f64": 1812.4, "k_stage_cross_f64": 109.0,
+                                       "k_reconstruct_f32": 968.3, "k_flux_f32": 292.6,
+                                       "k_reconstruct_f64": 1811.3, "k_flux_f64": 554.5}}
 
 
 KERNEL_SOURCES = ("kernels_common.h", "k_recon.inl", "k_recon_ho.inl", "k_stage.inl", "k_recon_f32.hip",
@@ -517,10 +518,10 @@ def main():
     def gbs(nbytes, ms):
         return nbytes * N / (ms * 1e-3) / 1e9
 
-    # the fused stage: k_stage moves every cell's share but U^n, the state
-    # write and the area of the cells k_stage_cross finishes (x_cross of them)
+    # the fused stage: k_stage moves every cell's share but the state write
+    # of the cells k_stage_cross finishes (x_cross of them)
     def stage_split_bytes(prec):
-        cross = x_cross * CELL_UPDATE_BYTES
+        cross = x_cross * CROSS_UPDATE_BYTES
         return STAGE_BYTES[prec] - cross, cross
 
     t0, t1 = kstats(mx)
