@@ -231,7 +231,7 @@ struct Builder {
     // per-thread work space of the stencil search, reused from cell to cell
     // (per-cell heap allocations would serialise the threads on the allocator)
     struct StencilScratch {
-        std::vector<int32_t> stamp, S_, layer, next;
+        std::vector<int32_t> stamp, vstamp, S_, layer, next;
         std::vector<std::pair<double, int>> rest, cand;
         std::vector<int> sector;
     };
@@ -246,8 +246,9 @@ struct Builder {
         parallel_for(N, [&](int64_t ii, int tid) {
             int i = (int)ii;
             StencilScratch &w = scratch[tid];
-            auto &st = w.stamp;
+            auto &st = w.stamp, &vst = w.vstamp;
             if (st.empty()) st.assign(N, -1);
+            if (vst.empty()) vst.assign(nvert, -1);
             auto &S_ = w.S_, &layer = w.layer, &next = w.next;
             S_.clear();
             layer.assign(1, i);
@@ -257,6 +258,9 @@ struct Builder {
                 for (int c : layer)
                     for (int k = 0; k < 3; ++k) {
                         int v = canon[tri[3 * (size_t)c + k]];
+                        // a vertex expanded for an earlier layer has no unvisited cells
+                        if (vst[v] == i) continue;
+                        vst[v] = i;
                         for (int p = v2c_off[v]; p < v2c_off[v + 1]; ++p) {
                             int j = v2c[p];
                             if (st[j] == i) continue;
@@ -281,11 +285,18 @@ struct Builder {
                         offset(i, j, sx, sy, dx, dy);
                         rest.push_back({dx * dx + dy * dy, j});
                     }
-                    std::sort(rest.begin(), rest.end());
+                    // the `need` nearest, in (d2, id) order
+                    std::partial_sort(rest.begin(), rest.begin() + need, rest.end());
                     for (int a = 0; a < need; ++a) S_.push_back(rest[a].second);
                 }
             }
-            std::sort(S_.begin(), S_.end());
+            // ascending ids (insertion sort: at most 54 entries)
+            for (size_t a = 1; a < S_.size(); ++a) {
+                const int32_t x = S_[a];
+                size_t b = a;
+                for (; b > 0 && S_[b - 1] > x; --b) S_[b] = S_[b - 1];
+                S_[b] = x;
+            }
             std::copy(S_.begin(), S_.end(), cen.begin() + (size_t)i * M);
             // sectors
             const int32_t *t = tri.data() + 3 * (size_t)i;
