@@ -232,8 +232,7 @@ struct Builder {
     // (per-cell heap allocations would serialise the threads on the allocator)
     struct StencilScratch {
         std::vector<int32_t> stamp, vstamp, S_, layer, next;
-        std::vector<std::pair<double, int>> rest, cand;
-        std::vector<int> sector;
+        std::vector<std::pair<double, int>> rest, cand3[3];
     };
 
     bool stencils() {
@@ -300,37 +299,31 @@ struct Builder {
             std::copy(S_.begin(), S_.end(), cen.begin() + (size_t)i * M);
             // sectors
             const int32_t *t = tri.data() + 3 * (size_t)i;
-            auto &sector = w.sector;
-            sector.assign(M, -1);
+            // the members of each sector other than the face neighbours, with
+            // their squared offsets
+            double px[3], py[3];                      // vertices relative to the centroid
+            for (int f = 0; f < 3; ++f) { px[f] = X(t[f]) - cx[i]; py[f] = Y(t[f]) - cy[i]; }
+            for (auto &c : w.cand3) c.clear();
             for (int a = 0; a < M; ++a) {
-                int j = S_[a], s = -1;
-                for (int f = 0; f < 3; ++f) if (fnb[3 * (size_t)i + f] == j) s = f;
-                if (s < 0) {
-                    int sx, sy; double qx, qy;
-                    offset(i, j, sx, sy, qx, qy);
-                    for (int f = 0; f < 3; ++f) {
-                        double ux = X(t[f]) - cx[i], uy = Y(t[f]) - cy[i];
-                        int g = (f + 1) % 3;
-                        double wx = X(t[g]) - cx[i], wy = Y(t[g]) - cy[i];
-                        double c1 = ux * qy - uy * qx;
-                        double c2 = qx * wy - qy * wx;
-                        if (c1 >= 0.0 && c2 > 0.0) { s = f; break; }
-                    }
+                const int j = S_[a];
+                bool isf = false;
+                for (int f = 0; f < 3; ++f) isf |= fnb[3 * (size_t)i + f] == j;
+                if (isf) continue;                    // each face neighbour leads its own face's stencil
+                int sx, sy; double qx, qy;
+                offset(i, j, sx, sy, qx, qy);
+                for (int f = 0; f < 3; ++f) {
+                    const int g = (f + 1) % 3;
+                    double c1 = px[f] * qy - py[f] * qx;
+                    double c2 = qx * py[g] - qy * px[g];
+                    if (c1 >= 0.0 && c2 > 0.0) { w.cand3[f].push_back({qx * qx + qy * qy, j}); break; }
                 }
-                sector[a] = s;
             }
             for (int f = 0; f < 3; ++f) {
                 int nbf = fnb[3 * (size_t)i + f];
                 if (nbf < 0) continue;
-                auto &cand = w.cand;
-                cand.clear();
-                for (int a = 0; a < M; ++a) {
-                    if (sector[a] != f || S_[a] == nbf) continue;
-                    int sx, sy; double dx, dy;
-                    offset(i, S_[a], sx, sy, dx, dy);
-                    cand.push_back({dx * dx + dy * dy, S_[a]});
-                }
-                std::sort(cand.begin(), cand.end());
+                auto &cand = w.cand3[f];
+                const size_t take = std::min(cand.size(), (size_t)(Md - 1));
+                std::partial_sort(cand.begin(), cand.begin() + take, cand.end());
                 int32_t *out = dir.data() + ((size_t)i * 3 + f) * Md;
                 int n = 0;
                 out[n++] = nbf;
