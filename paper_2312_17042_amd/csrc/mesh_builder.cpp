@@ -463,9 +463,12 @@ cteno_status build_host_mesh(const cteno_mesh_desc &d, const cteno_scheme &s, Ho
     for (int v = 0; v < 4; ++v) { hm.bst[0][v] = d.behind[v]; hm.bst[1][v] = d.ahead[v]; }
     for (int k = 0; k < 3; ++k) hm.bline[k] = d.line[k];
 
-    std::atomic<int64_t> nfaces{0}, nbnd{0};
-    std::atomic<int> ninad{0}, overfull{0};
-    parallel_for(Np, [&](int64_t k, int) {
+    // per-thread counts (shared atomic counters made the threads contend for
+    // one cache line at every face)
+    struct alignas(64) Counts { int64_t faces = 0, bnd = 0; int inad = 0, over = 0; };
+    std::vector<Counts> cnt(nthreads_for(Np));
+    parallel_for(Np, [&](int64_t k, int tid) {
+        Counts &c = cnt[tid];
         if (k >= N) {
             // padding cells: self slots, unit area, boundary faces; never written back
             for (int j = 0; j < SP; ++j)
@@ -503,7 +506,7 @@ cteno_status build_host_mesh(const cteno_mesh_desc &d, const cteno_scheme &s, Ho
                     // (directional stencils are disjoint subsets of the
                     // central one; a cell that neighbours another across two
                     // faces could break that on a tiny periodic mesh)
-                    if (var_groups && nd >= S) { overfull++; break; }
+                    if (var_groups && nd >= S) { c.over++; break; }
                     const int j = var_groups ? nd++ : f * Md + a;
                     sl[j] = dr[f * Md + a];
                     fl[j] = 3;
@@ -511,7 +514,7 @@ cteno_status build_host_mesh(const cteno_mesh_desc &d, const cteno_scheme &s, Ho
                     for (int m = 0; m < M; ++m) if (cen[m] == dr[f * Md + a]) used[m] = 1;
                 }
             } else if (b.fnb[3 * (size_t)u + f] >= 0) {
-                ninad++;
+                c.inad++;
             }
         }
         int m = 0;
@@ -562,8 +565,8 @@ cteno_status build_host_mesh(const cteno_mesh_desc &d, const cteno_scheme &s, Ho
                     e[3] = b.Y(vb) - b.Y(va);
                     code |= (uint32_t)row << 2;
                 }
-                nbnd++;
-                nfaces++;
+                c.bnd++;
+                c.faces++;
             } else {
                 int kj = hm.iperm[j];
                 int g = b.fnbf[3 * (size_t)u + f];
@@ -573,11 +576,14 @@ cteno_status build_host_mesh(const cteno_mesh_desc &d, const cteno_scheme &s, Ho
                 if (owner) edge_normal(u, f, nx, ny, len);
                 else { edge_normal(j, g, nx, ny, len); nx = -nx; ny = -ny; }
                 code = (uint32_t)kj | ((uint32_t)g << 28) | (owner ? kNbOwner : 0u);
-                if (owner) nfaces++;
+                if (owner) c.faces++;
             }
             put_face(k, f, nx, ny, len, code);
         }
     });
+    int64_t nfaces = 0, nbnd = 0;
+    int ninad = 0, overfull = 0;
+    for (const Counts &c : cnt) { nfaces += c.faces; nbnd += c.bnd; ninad += c.inad; overfull += c.over; }
     hm.n_faces = nfaces;
     hm.n_boundary = nbnd;
     if (overfull) { err = "directional stencils overlap (mesh too small)"; return CTENO_ERR_INVALID; }
