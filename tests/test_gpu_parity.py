@@ -490,6 +490,38 @@ def test_nonphysical_state_is_reported(ctx):
     assert e.value.status == T.ERR_NONPHYSICAL
 
 
+@pytest.mark.parametrize("case,degree", [("vortex", 3), ("sod", 3), ("sod", 4), ("vortex", 5), ("vortex", 6)])
+def test_mesh_counts_match_the_oracle(ctx, case, degree):
+    """The mesh handle's counts against the oracle's geometry and stencils:
+    faces and boundary faces, inadmissible interior faces (directional
+    stencil with fewer than K_d + 1 cells), slots per cell (max(M, 3 M_d) up
+    to cubic and at degree 6, M at degrees 4 and 5) and, in the caller's
+    cell order, the cells with a face to another 256-cell block."""
+    if case == "vortex":
+        mesh, _ = W.vortex_case(24, seed=2)
+    else:
+        mesh, _ = W.sod_case(48, 12, seed=3)
+    m = T.Mesh.from_workload(ctx, mesh, physics=O.EULER, scheme=O.CTENO, degree=degree, precision=T.BOTH,
+                             reorder=0)
+    o = O.Oracle.from_mesh(mesh, physics=O.EULER, scheme=O.CTENO, degree=degree)
+    nb = o.geometry()["nbr"]
+    _, _, cnt = o.stencils()
+    info = m.info
+    N = mesh.n_cells
+    assert info.n_cells == N
+    assert info.n_boundary_faces == int((nb < 0).sum())
+    assert info.n_faces == int((nb >= 0).sum()) // 2 + int((nb < 0).sum())
+    assert info.n_inadmissible == int(((nb >= 0) & (cnt == 0)).sum())
+    K = (degree + 1) * (degree + 2) // 2 - 1
+    kd = (degree + 1) // 2 if degree >= 4 else 1
+    Md = 2 * ((kd + 1) * (kd + 2) // 2 - 1)
+    assert info.slots == (2 * K if degree in (4, 5) else max(2 * K, 3 * Md))
+    cells = np.arange(N)[:, None]
+    cross = ((nb >= 0) & (nb // 256 != cells // 256)).any(axis=1)
+    assert info.n_cross_cells == (int(cross.sum()) if degree <= 3 else 0)
+    m.close()
+
+
 @pytest.mark.parametrize("which", ["vortex_80k", "sod_1p28M", "vortex_8M", "vortex_2M_r4", "vortex_2M_r5",
                                    "vortex_2M_r6", "dmr_715k_r4"])
 def test_full_size_sampled_parity(ctx, which):
