@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <memory>
+#include <utility>
 #include <string>
 #include <vector>
 
@@ -89,6 +91,21 @@ constexpr uint32_t kSlotIndexMask = 0x0FFFFFFFu;
 constexpr int kSlotGroupShift = 28;
 constexpr uint32_t kSlotNoGroup = 3u;
 
+// allocator whose new elements are left uninitialised (default-initialised):
+// for arrays that the parallel mesh layout writes in full, so that no serial
+// zero fill runs first
+template <typename T>
+struct NoInitAlloc : std::allocator<T> {
+    template <typename U> struct rebind { using other = NoInitAlloc<U>; };
+    NoInitAlloc() = default;
+    template <typename U> NoInitAlloc(const NoInitAlloc<U> &) noexcept {}
+    template <typename U> void construct(U *p) noexcept { ::new (static_cast<void *>(p)) U; }
+    template <typename U, typename... A> void construct(U *p, A &&...a) {
+        ::new (static_cast<void *>(p)) U(std::forward<A>(a)...);
+    }
+};
+template <typename T> using raw_vector = std::vector<T, NoInitAlloc<T>>;
+
 // ---------------------------------------------------------------------------
 // host mesh builder output (all in internal order unless noted)
 // ---------------------------------------------------------------------------
@@ -106,15 +123,15 @@ struct HostMesh {
     std::vector<int32_t> dirn_user;    // [N][3]
     // internal-order device inputs
     int SP = 0;                        // slots padded to a multiple of 4
-    std::vector<int32_t> slot;         // vector-tiled [SP] (VW 4): internal cell index (self for pads)
-    std::vector<uint8_t> slot_flag;    // tiled [S]: bit0 central member, bit1 directional member
-    std::vector<int8_t> slot_shift;    // tiled [2*S]: periodic image shift (x then y)
-    std::vector<uint8_t> flags;        // [Npad]: bit s = directional stencil of face s admissible
-    std::vector<double> verts;         // tiled [6]: CCW vertex coordinates x0,y0,x1,y1,x2,y2
+    raw_vector<int32_t> slot;          // vector-tiled [SP] (VW 4): internal cell index (self for pads)
+    raw_vector<uint8_t> slot_flag;     // tiled [S]: bit0 central member, bit1 directional member
+    raw_vector<int8_t> slot_shift;     // tiled [2*S]: periodic image shift (x then y)
+    raw_vector<uint8_t> flags;         // [Npad]: bit s = directional stencil of face s admissible
+    raw_vector<double> verts;          // tiled [6]: CCW vertex coordinates x0,y0,x1,y1,x2,y2
     // face records: per local face (nx, ny, |A|, neighbour code), vector-tiled
-    std::vector<double> fr64;          // [12] entries, VW 2; code stored in the low bits of the double
-    std::vector<float> fr32;           // [12] entries, VW 4; code stored as the float's bits
-    std::vector<double> area;          // [Npad]
+    raw_vector<double> fr64;           // [12] entries, VW 2; code stored in the low bits of the double
+    raw_vector<float> fr32;            // [12] entries, VW 4; code stored as the float's bits
+    raw_vector<double> area;           // [Npad]
     // inflow faces: first vertex (x, y) and edge vector, rows in internal cell order
     std::vector<double> bface;         // [n_inflow][4]
     double bst[2][4] = {};             // prescribed states behind / ahead of the moving line

@@ -428,14 +428,16 @@ cteno_status build_host_mesh(const cteno_mesh_desc &d, const cteno_scheme &s, Ho
     const bool ho = s.degree >= 4, var_groups = ho_var_groups(s.degree);
     static_assert(kMaxS <= 64, "slot tables fit 64 entries");
     hm.SP = SP;
-    hm.slot.assign((size_t)Np * SP, 0);
-    hm.slot_flag.assign((size_t)Np * S, 0);
-    hm.slot_shift.assign((size_t)Np * 2 * S, 0);
-    hm.flags.assign(Np, 0);
-    hm.verts.assign((size_t)Np * 6, 0.0);
-    hm.fr64.assign((size_t)Np * 12, 0.0);
-    hm.fr32.assign((size_t)Np * 12, 0.0f);
-    hm.area.assign(Np, 1.0);
+    // every entry of these is written by the layout below (first touch by
+    // its threads)
+    hm.slot.resize((size_t)Np * SP);
+    hm.slot_flag.resize((size_t)Np * S);
+    hm.slot_shift.resize((size_t)Np * 2 * S);
+    hm.flags.resize(Np);
+    hm.verts.resize((size_t)Np * 6);
+    hm.fr64.resize((size_t)Np * 12);
+    hm.fr32.resize((size_t)Np * 12);
+    hm.area.resize(Np);
 
     auto put_face = [&](int64_t k, int f, double nx, double ny, double len, uint32_t code) {
         hm.fr64[avix(k, 4 * f + 0, 12, 2)] = nx;
@@ -473,6 +475,14 @@ cteno_status build_host_mesh(const cteno_mesh_desc &d, const cteno_scheme &s, Ho
             // padding cells: self slots, unit area, boundary faces; never written back
             for (int j = 0; j < SP; ++j)
                 hm.slot[avix(k, j, SP, 4)] = (int32_t)(k | (ho ? kSlotNoGroup << kSlotGroupShift : 0u));
+            for (int j = 0; j < S; ++j) {
+                hm.slot_flag[tix(k, j, S)] = 0;
+                hm.slot_shift[tix(k, 2 * j, 2 * S)] = 0;
+                hm.slot_shift[tix(k, 2 * j + 1, 2 * S)] = 0;
+            }
+            hm.flags[k] = 0;
+            for (int e = 0; e < 6; ++e) hm.verts[tix(k, e, 6)] = 0.0;
+            hm.area[k] = 1.0;
             for (int f = 0; f < 3; ++f) put_face(k, f, 1.0, 0.0, 0.0, kNbBoundary | CTENO_TRANSMISSIVE);
             return;
         }
@@ -528,6 +538,11 @@ cteno_status build_host_mesh(const cteno_mesh_desc &d, const cteno_scheme &s, Ho
             const int src = j < S ? sl[j] : -1;
             if (src < 0) {   // pad: the cell itself, zero weight
                 hm.slot[avix(k, j, SP, 4)] = (int32_t)(k | (ho ? kSlotNoGroup << kSlotGroupShift : 0u));
+                if (j < S) {
+                    hm.slot_flag[tix(k, j, S)] = 0;
+                    hm.slot_shift[tix(k, 2 * j, 2 * S)] = 0;
+                    hm.slot_shift[tix(k, 2 * j + 1, 2 * S)] = 0;
+                }
                 continue;
             }
             int sx, sy; double dx, dy;

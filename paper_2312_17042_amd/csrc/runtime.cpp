@@ -230,8 +230,8 @@ struct cteno_mesh {
 };
 
 namespace {
-template <class T>
-hipError_t h2d(T *dst, const std::vector<T> &src, hipStream_t st) {
+template <class T, class A>
+hipError_t h2d(T *dst, const std::vector<T, A> &src, hipStream_t st) {
     return hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, st);
 }
 }  // namespace
