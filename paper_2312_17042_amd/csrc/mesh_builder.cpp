@@ -273,20 +273,35 @@ struct Builder {
                     layer = next;
                 } else {
                     int need = M - (int)S_.size();
-                    auto &rest = w.rest;
-                    rest.clear();
-                    for (int j : next) {
+                    auto is_face_nb = [&](int j) {
                         bool isf = false;
                         for (int f = 0; f < 3; ++f) isf |= (fnb[3 * (size_t)i + f] == j);
-                        if (isf && need > 0) { S_.push_back(j); --need; continue; }
-                        if (isf) continue;
-                        int sx, sy; double dx, dy;
-                        offset(i, j, sx, sy, dx, dy);
-                        rest.push_back({dx * dx + dy * dy, j});
-                    }
-                    // the `need` nearest, in (d2, id) order
-                    std::partial_sort(rest.begin(), rest.begin() + need, rest.end());
-                    for (int a = 0; a < need; ++a) S_.push_back(rest[a].second);
+                        return isf;
+                    };
+                    for (int j : next)
+                        if (need > 0 && is_face_nb(j)) { S_.push_back(j); --need; }
+                    // the `need` nearest of the others in (d2, id) order, by
+                    // insertion into a short sorted list (once it is full, most
+                    // candidates fail the first comparison)
+                    auto &best = w.rest;
+                    best.resize(std::max(need, 1));
+                    int nbest = 0;
+                    if (need > 0)
+                        for (int j : next) {
+                            if (is_face_nb(j)) continue;
+                            int sx, sy; double dx, dy;
+                            offset(i, j, sx, sy, dx, dy);
+                            const std::pair<double, int> x{dx * dx + dy * dy, j};
+                            if (nbest == need) {
+                                if (!(x < best[need - 1])) continue;
+                            } else {
+                                ++nbest;
+                            }
+                            int p = nbest - 1;
+                            for (; p > 0 && x < best[p - 1]; --p) best[p] = best[p - 1];
+                            best[p] = x;
+                        }
+                    for (int a = 0; a < nbest; ++a) S_.push_back(best[a].second);
                 }
             }
             // ascending ids (insertion sort: at most 54 entries)
