@@ -141,16 +141,6 @@ __device__ __forceinline__ void ho_take(const real (&acc)[GF][VW][4], const real
 // possible store and turn the uniform table loads after it into vector loads)
 template <typename T>
 __device__ __forceinline__ void opaque(T &x) { asm("" : "+v"(x)); }
-__device__ __forceinline__ void opaque(float4 &x) {
-    float a = x.x, b = x.y, c = x.z, d = x.w;
-    opaque(a); opaque(b); opaque(c); opaque(d);
-    x = make_float4(a, b, c, d);
-}
-__device__ __forceinline__ void opaque(double2 &x) {
-    double a = x.x, b = x.y;
-    opaque(a); opaque(b);
-    x = make_double2(a, b);
-}
 
 // whether some lane of a quad holds a directional entry (e in [K, K + K_d))
 // at component c of its vector in round t
@@ -238,9 +228,6 @@ __device__ __forceinline__ void ho_contract_quad(const ReconHoArgs<real> a, int6
         const int jc = j < S ? j : S - 1;
         return (uint32_t)Si[(jc >> 2) * 256 + (jc & 3)];
     };
-    // (the lambdas take copies of the pointers they need: a reference to the
-    // argument struct would cost it its uniformity, and the scheme tables
-    // would move into vector registers)
     const double *__restrict__ Ug = a.U;
     auto ld_avg = [Ug, v](uint32_t se) { return Ug[(int64_t)(se & kSlotIndexMask) * 4 + v]; };
     // one slot: differences of the quad's four variables, products with
