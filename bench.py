@@ -48,11 +48,11 @@ CROSS_UPDATE_BYTES = 32
 # HBM bytes per cell and launch measured with the FETCH_SIZE / WRITE_SIZE
 # counters (scaled by the copy-kernel calibration), valid only for the
 # kernel sources they were taken on
-MEASURED_TRAFFIC = {"kernels_sha256_prefix": "71dca1d49faff704",
+MEASURED_TRAFFIC = {"kernels_sha256_prefix": "002632cd235042d6",
                     "source": "profiles/stage_vortex8M_hbm_counters.md",
                     "bytes_per_cell": {"k_stage_f32": 994.5, "k_stage_cross_f32": 90.7,
-                                       "k_stage_f64": 1812.4, "k_stage_cross_f64": 109.0,
-                                       "k_reconstruct_f32": 968.3, "k_flux_f32": 292.6,
+                                       "k_stage_f64": 1812.3, "k_stage_cross_f64": 108.9,
+                                       "k_reconstruct_f32": 968.2, "k_flux_f32": 291.6,
                                        "k_reconstruct_f64": 1811.3, "k_flux_f64": 554.5}}
 
 
