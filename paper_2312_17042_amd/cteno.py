@@ -212,10 +212,6 @@ def _close_all():
 atexit.register(_close_all)
 
 
-def _finalizing() -> bool:
-    return sys.is_finalizing()
-
-
 class Context:
     """A library context on one device.  allocator="torch" (default) routes
     every device allocation of the library through torch's caching
@@ -246,8 +242,11 @@ class Context:
             self.h = None
         _live_contexts.discard(self)
 
-    def __del__(self):
-        if not _finalizing():
+    def __del__(self, _is_finalizing=sys.is_finalizing):
+        # (the default argument keeps the check reachable once interpreter
+        # shutdown has cleared this module's globals; the exit handler has
+        # closed every live handle by then)
+        if getattr(self, "h", None) and not _is_finalizing():
             self.close()
 
     def synchronize(self):
@@ -316,8 +315,11 @@ class Mesh:
                 lib().cteno_mesh_destroy(self.h)
             self.h = None
 
-    def __del__(self):
-        if not _finalizing():
+    def __del__(self, _is_finalizing=sys.is_finalizing):
+        # (the default argument keeps the check reachable once interpreter
+        # shutdown has cleared this module's globals; the exit handler has
+        # closed every live handle by then)
+        if getattr(self, "h", None) and not _is_finalizing():
             self.close()
 
     def stencils(self):
@@ -370,8 +372,11 @@ class Solution:
                 lib().cteno_sol_destroy(self.h)
             self.h = None
 
-    def __del__(self):
-        if not _finalizing():
+    def __del__(self, _is_finalizing=sys.is_finalizing):
+        # (the default argument keeps the check reachable once interpreter
+        # shutdown has cleared this module's globals; the exit handler has
+        # closed every live handle by then)
+        if getattr(self, "h", None) and not _is_finalizing():
             self.close()
 
     def set(self, u, t=0.0):
@@ -460,8 +465,11 @@ class Server:
                 lib().cteno_server_destroy(self.h)
             self.h = None
 
-    def __del__(self):
-        if not _finalizing():
+    def __del__(self, _is_finalizing=sys.is_finalizing):
+        # (the default argument keeps the check reachable once interpreter
+        # shutdown has cleared this module's globals; the exit handler has
+        # closed every live handle by then)
+        if getattr(self, "h", None) and not _is_finalizing():
             self.close()
 
     def submit(self, mesh, u0, n_steps: int, cfl: float = 0.3) -> int:

@@ -64,7 +64,8 @@ def test_hipmalloc_context_still_works():
 def test_exit_with_live_handles_is_clean():
     """A child process leaves a context, a mesh, a solution mid-use and a
     server with queued work to interpreter exit: the binding closes them
-    children-first before the runtime goes, and the process exits 0."""
+    children-first before the runtime goes, and the process exits 0 with
+    no finaliser error."""
     code = textwrap.dedent(f"""
         import sys
         sys.path.insert(0, {ROOT!r})
@@ -83,3 +84,5 @@ def test_exit_with_live_handles_is_clean():
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=240)
     assert r.returncode == 0, (r.returncode, r.stdout[-2000:], r.stderr[-2000:])
     assert "child ready" in r.stdout
+    # and no finaliser raised on the way out
+    assert "Traceback" not in r.stderr and "Exception ignored" not in r.stderr, r.stderr[-2000:]
