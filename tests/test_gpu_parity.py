@@ -730,6 +730,36 @@ def test_flips_are_counted(ctx):
     assert total > 0
 
 
+@pytest.mark.parametrize("nx,ny", [(10, 10), (8, 16), (6, 22)])
+def test_fused_stage_at_block_edges(ctx, nx, ny):
+    """Meshes of 200, 256 and 264 cells: one partial 256-cell block, one
+    full block (no cell has a face to another block, so the second fused
+    kernel has nothing to do), and a second block of 8 cells.  The fused
+    FP64 march equals the separate kernels' and the oracle's to 1e-12."""
+    mesh = W.split_jitter_mesh(nx, ny, (0.0, 10.0, 0.0, 10.0), seed=9)
+    u0 = W.cell_average(mesh, W.isentropic_vortex(0.0, 5.0, (5.0, 5.0), (10.0, 10.0)), n=4)
+    N = mesh.n_cells
+    kw = dict(physics=O.EULER, scheme=O.CTENOZ, degree=3, lambda1_prime=1e4)
+    m = T.Mesh.from_workload(ctx, mesh, precision=T.BOTH, **kw)
+    assert (m.info.n_cross_cells == 0) == (N <= 256)
+    o = O.Oracle.from_mesh(mesh, **kw)
+    steps = 6
+    uo, so, _ = o.solve(u0, 10.0, cfl=0.3, max_steps=steps)
+    out = {}
+    for fused in (True, False):
+        ctx.set_fused_stage(fused)
+        try:
+            s = T.Solution(m, u0)
+            assert s.solve(t_final=10.0, max_steps=steps, cfl=0.3, precision=T.FP64) == so
+            out[fused], _ = s.download()
+            s.close()
+        finally:
+            ctx.set_fused_stage(True)
+    assert relerr_var(out[True], out[False], axis_v=0) < 1e-12
+    assert relerr_var(out[True], uo, axis_v=0) < 1e-12
+    m.close()
+
+
 @pytest.mark.parametrize("name", ["advection_r2_cteno", "vortex_r3_ctenoz", "density_r2_ctenoz", "dmr_r3_cteno_char",
                                   "vortex_r3_ctenoz_scaled"])
 def test_fused_stage_matches_split_kernels(ctx, name):
