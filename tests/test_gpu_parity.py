@@ -67,6 +67,10 @@ CASES = {
                           dict(physics=O.EULER, scheme=O.CTENOZ, degree=4, lambda1_prime=1e4)),
     "sod_r4_cteno": (lambda: W.sod_case(48, 12, seed=3),
                      dict(physics=O.EULER, scheme=O.CTENO, degree=4, lambda1_prime=1e15, positivity=1)),
+    # degree 5 next to walls: the stencils of boundary faces are
+    # inadmissible, so the slots of the remaining stencils start elsewhere
+    "sod_r5_cteno": (lambda: W.sod_case(48, 12, seed=3),
+                     dict(physics=O.EULER, scheme=O.CTENO, degree=5, lambda1_prime=1e15, positivity=1)),
     "vortex_r5_ctenoz": (lambda: W.vortex_case(20, seed=6),
                          dict(physics=O.EULER, scheme=O.CTENOZ, degree=5, lambda1_prime=1e4)),
     # degree 5 with one lane per cell: the directional sums follow the
